@@ -1,0 +1,284 @@
+"""FP64 CPU oracle for the DGSEM relaxation-model-1 NSK solver (test infrastructure).
+
+This package is the reference the HIP library is checked against.  It is
+used only by ``tests/``, by ``__graft_entry__.smoke()`` and by the CPU
+baseline leg of ``bench.py``; the product path never imports it.  It shares
+no code with the HIP library: the C source ``nskr_oracle.c`` has its own
+basis, metrics, thermodynamics, fluxes, walls, time integration and
+reductions, each written from the paper (arXiv 2208.05310, Sec. 2-3).
+
+Pinned by ``tests/test_oracle_*.py`` against values the paper prints
+(Tables 1, 2, 4), closed forms, DGSEM invariants (exactness, free-stream
+preservation, conservation), the relaxation ODE, a convergence study on an
+isentropic vortex (ideal-gas reduction) and a manufactured solution of the
+full system, and a dense brute-force re-implementation on a tiny mesh.
+The wall fluxes beyond those invariants are "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nskr_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+
+def build() -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, OpenMP over elements)."""
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+           "-Wall", "-Wextra", "-o", _SO + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("gam", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("cfl", ctypes.c_double)]
+
+
+class Box(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("len", ctypes.c_double * 3), ("periodic", ctypes.c_int * 3),
+                ("side_kind", ctypes.c_int * 6), ("side_twall", ctypes.c_double * 6),
+                ("side_theta", ctypes.c_double * 6), ("curve_amp", ctypes.c_double)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        build()
+    L = ctypes.CDLL(_SO)
+    d, i, vp = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+    sig = {
+        "orc_create": (vp, [ctypes.POINTER(Params), ctypes.POINTER(Box), ctypes.c_char_p, i]),
+        "orc_destroy": (None, [vp]),
+        "orc_nnodes": (ctypes.c_long, [vp]),
+        "orc_nelems": (i, [vp]),
+        "orc_node_coords": (None, [vp, _D]),
+        "orc_metrics": (None, [vp, _D, _D, _D]),
+        "orc_rhs": (None, [vp, _D, _D]),
+        "orc_lift1": (None, [vp, _D, _D]),
+        "orc_lift2": (None, [vp, _D, _D]),
+        "orc_dt": (d, [vp, _D]),
+        "orc_rk_step": (None, [vp, _D, _D, d, d]),
+        "orc_run": (None, [vp, _D, _D, d, d, i]),
+        "orc_init_droplets": (i, [vp, d, i, _D, _D, d, _D, _D]),
+        "orc_reduce": (None, [vp, _D, _D]),
+        "orc_maxwell": (i, [d, d, d, d, _D, _D, _D]),
+        "orc_spinodal": (i, [d, d, d, d, _D, _D]),
+        "orc_rho_of_p": (d, [d, d, d, d, d, i]),
+        "orc_sigma": (d, [d, d, d, d, d]),
+        "orc_sigma_panels": (d, [d, d, d, d, d, i]),
+        "orc_sigma_gauss15": (d, [d, d, d, d, d]),
+        "orc_dpsiwall_dc": (d, [d, d, d, d, d]),
+        "orc_psiwall": (d, [d, d, d, d, d]),
+        "orc_basis": (None, [i, _D, _D, _D, _D, _D, _D]),
+        "orc_lobatto": (None, [i, _D]),
+        "orc_rk_coeffs": (None, [_D, _D, _D]),
+        "orc_pressure": (d, [d, d, d, d, d]),
+        "orc_cs2": (d, [d, d, d, d, d, d]),
+        "orc_chempot": (d, [d, d, d, d, d]),
+        "orc_set_threads": (None, [i]),
+        "orc_get_threads": (i, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+def make_params(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.01, kappa=1.0 / 150.0,
+                gam=1e-4, alpha=100.0, beta=1000.0, cfl=0.9) -> Params:
+    return Params(R, a, b, cv, mu, kappa, gam, alpha, beta, cfl)
+
+
+def make_box(N, n, lo=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
+             side_kind=(0,) * 6, side_twall=(0.0,) * 6, side_theta=(90.0,) * 6,
+             curve_amp=0.0) -> Box:
+    return Box(int(N), (ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo),
+               (ctypes.c_double * 3)(*length), (ctypes.c_int * 3)(*periodic),
+               (ctypes.c_int * 6)(*side_kind), (ctypes.c_double * 6)(*side_twall),
+               (ctypes.c_double * 6)(*side_theta), float(curve_amp))
+
+
+class Oracle:
+    """One discretised problem (mesh + parameters) on the CPU in FP64."""
+
+    def __init__(self, params: Params, box: Box, threads: int | None = None):
+        L = lib()
+        if threads is not None:
+            L.orc_set_threads(int(threads))
+        err = ctypes.create_string_buffer(256)
+        self.params, self.box = params, box
+        self._c = L.orc_create(ctypes.byref(params), ctypes.byref(box), err, 256)
+        if not self._c:
+            raise ValueError(err.value.decode())
+        self.N = box.N
+        self.nnodes = int(L.orc_nnodes(self._c))
+        self.nelems = int(L.orc_nelems(self._c))
+
+    def __del__(self):
+        if getattr(self, "_c", None):
+            lib().orc_destroy(self._c)
+            self._c = None
+
+    def state(self) -> np.ndarray:
+        return np.zeros((6, self.nnodes))
+
+    def coords(self) -> np.ndarray:
+        x = np.zeros((3, self.nnodes))
+        lib().orc_node_coords(self._c, _ptr(x))
+        return x
+
+    def metrics(self):
+        P = self.N + 1
+        Ja = np.zeros((9, self.nnodes))
+        J = np.zeros(self.nnodes)
+        nv = np.zeros((3, self.nelems * 6 * P * P))
+        lib().orc_metrics(self._c, _ptr(Ja), _ptr(J), _ptr(nv))
+        return Ja, J, nv.reshape(3, self.nelems, 6, P * P)
+
+    def rhs(self, U: np.ndarray) -> np.ndarray:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        Ut = np.zeros_like(U)
+        lib().orc_rhs(self._c, _ptr(U), _ptr(Ut))
+        return Ut
+
+    def lift1(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        q = np.zeros((15, self.nnodes))
+        lib().orc_lift1(self._c, _ptr(U), _ptr(q))
+        return q
+
+    def lift2(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        o = np.zeros((5, self.nnodes))
+        lib().orc_lift2(self._c, _ptr(U), _ptr(o))
+        return o
+
+    def dt(self, U) -> float:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        return float(lib().orc_dt(self._c, _ptr(U)))
+
+    def rk_step(self, U, R, t, dt):
+        lib().orc_rk_step(self._c, _ptr(U), _ptr(R), float(t), float(dt))
+
+    def run(self, U, R, t, dt, nsteps):
+        lib().orc_run(self._c, _ptr(U), _ptr(R), float(t), float(dt), int(nsteps))
+
+    def init_droplets(self, T0, centres, radii, width, noise=None) -> np.ndarray:
+        U = self.state()
+        cen = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
+        rad = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
+        nz = None
+        if noise is not None:
+            nz = np.ascontiguousarray(noise, dtype=np.float64)
+            assert nz.size == self.nnodes
+        rc = lib().orc_init_droplets(self._c, float(T0), int(rad.size), _ptr(cen), _ptr(rad),
+                                     float(width), _ptr(nz) if nz is not None else None, _ptr(U))
+        if rc != 0:
+            raise ValueError("init failed (supercritical temperature?)")
+        return U
+
+    def reduce(self, U) -> np.ndarray:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        out = np.zeros(20)
+        lib().orc_reduce(self._c, _ptr(U), _ptr(out))
+        return out
+
+
+# ---- thermodynamics and 1D operators ------------------------------------
+def maxwell(T, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    rv, rl, ps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    if not lib().orc_maxwell(R, a, b, T, ctypes.byref(rv), ctypes.byref(rl), ctypes.byref(ps)):
+        raise ValueError("supercritical")
+    return rv.value, rl.value, ps.value
+
+
+def spinodal(T, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    v, l = ctypes.c_double(), ctypes.c_double()
+    if not lib().orc_spinodal(R, a, b, T, ctypes.byref(v), ctypes.byref(l)):
+        raise ValueError("supercritical")
+    return v.value, l.value
+
+
+def rho_of_p(T, p, branch, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    return lib().orc_rho_of_p(R, a, b, T, p, int(branch))
+
+
+def sigma(T, gam=1e-4, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, panels=None):
+    if panels is None:
+        return lib().orc_sigma(R, a, b, T, gam)
+    return lib().orc_sigma_panels(R, a, b, T, gam, int(panels))
+
+
+def sigma_gauss15(T, gam=1e-4, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    return lib().orc_sigma_gauss15(R, a, b, T, gam)
+
+
+def dpsiwall_dc(c, rv, rl, sig, costh):
+    return lib().orc_dpsiwall_dc(c, rv, rl, sig, costh)
+
+
+def psiwall(c, rv, rl, ssv, ssl):
+    return lib().orc_psiwall(c, rv, rl, ssv, ssl)
+
+
+def pressure(rho, T, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    return lib().orc_pressure(R, a, b, rho, T)
+
+
+def cs2(rho, T, cv=5.0, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    return lib().orc_cs2(R, a, b, cv, rho, T)
+
+
+def chempot(rho, T, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
+    return lib().orc_chempot(R, a, b, rho, T)
+
+
+def basis(N):
+    P = N + 1
+    x, w, lm, lp = (np.zeros(P) for _ in range(4))
+    D, Dh = np.zeros((P, P)), np.zeros((P, P))
+    lib().orc_basis(int(N), _ptr(x), _ptr(w), _ptr(D), _ptr(Dh), _ptr(lm), _ptr(lp))
+    return x, w, D, Dh, lm, lp
+
+
+def lobatto(N):
+    x = np.zeros(N + 1)
+    lib().orc_lobatto(int(N), _ptr(x))
+    return x
+
+
+def rk_coeffs():
+    A, B, C = np.zeros(5), np.zeros(5), np.zeros(5)
+    lib().orc_rk_coeffs(_ptr(A), _ptr(B), _ptr(C))
+    return A, B, C
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().orc_get_threads())

@@ -1,0 +1,161 @@
+"""Seeded synthetic workloads: mesh sizes, parameters, droplet layouts, noise.
+
+This module holds inputs only -- no arithmetic of the method.  Both the HIP
+path and the CPU oracle are driven from the same descriptions, and each side
+builds its own mesh, metrics, Maxwell states and initial state from them.
+
+Workload shapes follow the paper's droplet set-ups (tanh droplet profile of
+Sec. 4.1.1/4.2, the sessile configuration of Sec. 4.4) at the sizes of the
+benchmark configurations.  Fluid properties default to Table 1
+(gamma_K = 1e-4, mu = 0.01, k = 1/150, c_v = 5) with the reduced van der
+Waals constants of Sec. 2.1; Korteweg and relaxation parameters default to
+alpha = 100, beta = 1000 (the values the paper uses most for bulk cases).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+# Reduced van der Waals constants (Sec. 2.1) and Table 1 fluid properties.
+TABLE1 = dict(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.01, kappa=1.0 / 150.0,
+              gam=1e-4, alpha=100.0, beta=1000.0, cfl=0.9)
+
+# Box side kinds: 0 periodic / none, 1 no-slip isothermal wall with a static
+# contact angle, 2 slip adiabatic neutral wall.
+PERIODIC, NOSLIP_CA, SLIP = 0, 1, 2
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    N: int
+    n: tuple
+    length: tuple = (1.0, 1.0, 1.0)
+    periodic: tuple = (1, 1, 1)
+    side_kind: tuple = (0, 0, 0, 0, 0, 0)
+    side_twall: tuple = (0.0,) * 6
+    side_theta: tuple = (90.0,) * 6
+    T0: float = 0.85
+    centres: tuple = ((0.5, 0.5, 0.5),)
+    radii: tuple = (0.25,)
+    width: float = 0.05
+    steps: int = 20
+    noise_seed: int | None = 1
+    noise_amp: float = 1e-6
+    params: dict = field(default_factory=lambda: dict(TABLE1))
+    curve_amp: float = 0.0
+
+    @property
+    def nelems(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def nnodes(self) -> int:
+        return self.nelems * (self.N + 1) ** 3
+
+    def noise(self) -> np.ndarray | None:
+        """Uniform noise U(-amp, amp) on rho, one value per node in the
+        state order [element][k][j][i] (numpy PCG64 with the workload seed)."""
+        if self.noise_seed is None:
+            return None
+        rng = np.random.default_rng(self.noise_seed)
+        return rng.uniform(-self.noise_amp, self.noise_amp, self.nnodes)
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+def _periodic_dist(a, b, length, periodic):
+    d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    L = np.asarray(length, dtype=np.float64)
+    per = np.asarray(periodic, dtype=bool)
+    d = np.where(per, d - L * np.round(d / L), d)
+    return float(np.sqrt(np.sum(d * d)))
+
+
+def random_droplets(seed, count, rmin, rmax, gap, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
+                    max_tries=100000):
+    """Droplet centres uniform in the box and radii uniform in [rmin, rmax],
+    sequential rejection until every pair is at least r_i + r_j + gap apart
+    (distances as minimum images along periodic axes)."""
+    rng = np.random.default_rng(seed)
+    centres, radii = [], []
+    tries = 0
+    while len(centres) < count:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("droplet placement did not converge")
+        c = rng.uniform(0.0, 1.0, 3) * np.asarray(length)
+        r = rng.uniform(rmin, rmax) if rmax > rmin else rmin
+        if all(_periodic_dist(c, c2, length, periodic) >= r + r2 + gap
+               for c2, r2 in zip(centres, radii)):
+            centres.append(tuple(float(v) for v in c))
+            radii.append(float(r))
+    return tuple(centres), tuple(radii)
+
+
+def c1() -> Workload:
+    """Periodic unit cube, 4^3 elements, N=3, one droplet r=0.25 at T=0.85."""
+    return Workload(name="droplet_periodic_4x4x4_N3", N=3, n=(4, 4, 4), steps=20, noise_seed=1)
+
+
+def c2() -> Workload:
+    """Periodic unit cube, 16^3 elements, N=4, two droplets r=0.15 at seeded
+    centres, T=0.85, beta=1e3; the FP64 throughput workload."""
+    cen, rad = random_droplets(2, 2, 0.15, 0.15, 0.20)
+    return Workload(name="two_droplets_periodic_16x16x16_N4", N=4, n=(16, 16, 16),
+                    centres=cen, radii=rad, T0=0.85, steps=200, noise_seed=12)
+
+
+def c3(n=32) -> Workload:
+    """Periodic unit cube, n^3 elements (32 for the full case), N=5, eight
+    droplets with radii in [0.05, 0.12] at T=0.9."""
+    cen, rad = random_droplets(3, 8, 0.05, 0.12, 0.10)
+    return Workload(name=f"eight_droplets_periodic_{n}x{n}x{n}_N5", N=5, n=(n, n, n),
+                    centres=cen, radii=rad, T0=0.9, steps=500, noise_seed=13)
+
+
+def c4(scale=1) -> Workload:
+    """Box (0,1)x(0,1)x(0,0.5), 48x48x24 elements at N=3 (divided by
+    ``scale``), periodic in x and y, no-slip isothermal wall at T=0.9 with a
+    60 degree contact angle at z=0, slip adiabatic wall at z=0.5; a
+    hemispherical droplet r=0.2 on the wall, fluid at T=0.85."""
+    n = (48 // scale, 48 // scale, 24 // scale)
+    return Workload(name=f"sessile_wall_{n[0]}x{n[1]}x{n[2]}_N3", N=3, n=n,
+                    length=(1.0, 1.0, 0.5), periodic=(1, 1, 0),
+                    side_kind=(0, 0, 0, 0, NOSLIP_CA, SLIP),
+                    side_twall=(0.0, 0.0, 0.0, 0.0, 0.9, 0.0),
+                    side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 90.0),
+                    T0=0.85, centres=((0.5, 0.5, 0.0),), radii=(0.2,), steps=1000,
+                    noise_seed=14)
+
+
+def serving_stream(seed=5, count=256, rate=50.0):
+    """Poisson request stream: arrival times (exponential gaps at ``rate``/s)
+    and per-request workload descriptions.  Each request draws its grid from
+    {4^3, 8^3, 12^3, 16^3}, N from {2,3,4,5}, T from U[0.80, 0.95] and either a
+    periodic droplet (r=0.25) or a wall box with a hemispherical droplet
+    (r=0.2) and a contact angle from U[45, 135] degrees; 200 RK steps each."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    reqs = []
+    for k in range(count):
+        g = int(rng.choice([4, 8, 12, 16]))
+        N = int(rng.choice([2, 3, 4, 5]))
+        T = float(rng.uniform(0.80, 0.95))
+        wall = bool(rng.integers(0, 2))
+        theta = float(rng.uniform(45.0, 135.0))
+        nseed = int(rng.integers(0, 2**31 - 1))
+        if wall:
+            w = Workload(name=f"req{k}_wall_{g}_N{N}", N=N, n=(g, g, g), periodic=(1, 1, 0),
+                         side_kind=(0, 0, 0, 0, NOSLIP_CA, SLIP),
+                         side_twall=(0.0, 0.0, 0.0, 0.0, T, 0.0),
+                         side_theta=(90.0, 90.0, 90.0, 90.0, theta, 90.0),
+                         T0=T, centres=((0.5, 0.5, 0.0),), radii=(0.2,), steps=200,
+                         noise_seed=nseed)
+        else:
+            w = Workload(name=f"req{k}_periodic_{g}_N{N}", N=N, n=(g, g, g), T0=T,
+                         centres=((0.5, 0.5, 0.5),), radii=(0.25,), steps=200, noise_seed=nseed)
+        reqs.append((float(t[k]), w))
+    return reqs

@@ -1,0 +1,297 @@
+"""Pins of the oracle's DGSEM operator against what the method fixes:
+polynomial exactness of the BR1 liftings, free-stream preservation, discrete
+mass conservation, the relaxation ODE of a uniform state, equivariance under
+axis permutations and reflections, and closed-form wall-flux integrals."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+R, A, B, CV = 8.0 / 3.0, 3.0, 1.0 / 3.0, 5.0
+
+
+def make(N, n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), kinds=(0,) * 6, tw=(0.0,) * 6,
+         th=(90.0,) * 6, amp=0.0, **pk):
+    p = oracle.make_params(**pk)
+    b = oracle.make_box(N, n, (0.0, 0.0, 0.0), length, periodic, kinds, tw, th, amp)
+    return oracle.Oracle(p, b)
+
+
+def conserved(o, rho, u, T, c):
+    """Conserved state with temperature T, using the oracle's lifted grad c for the
+    gradient energy of eq. totalenergyalpha."""
+    pr = o.params
+    U = np.zeros((6, o.nnodes))
+    U[0] = rho
+    U[1:4] = rho * u
+    U[5] = c
+    q = o.lift1(U)
+    g2 = q[12] ** 2 + q[13] ** 2 + q[14] ** 2
+    U[4] = (rho * (pr.R * pr.cv * T - pr.a * rho) + 0.5 * rho * np.sum(u * u, axis=0)
+            + 0.5 * pr.alpha * (rho - c) ** 2 + 0.5 * pr.gam * g2)
+    return U
+
+
+def quad_weights(o):
+    x, w, *_ = oracle.basis(o.N)
+    P = o.N + 1
+    w3 = (w[None, None, :] * w[None, :, None] * w[:, None, None]).reshape(-1)
+    _, J, _ = o.metrics()
+    return np.tile(w3, o.nelems) * J
+
+
+# ---------------------------------------------------------------- exactness
+def test_lift1_exact_for_polynomial_density_and_order_parameter():
+    # BR1 pass 1 (Sec. 3.1) reproduces the gradient of a global polynomial of degree <= N
+    # per direction: continuous traces make the central face value exact; walls use rho-.
+    N = 4
+    o = make(N, (3, 2, 2), (1.5, 1.0, 0.7), (0, 0, 0), (2,) * 6)
+    x, y, z = o.coords()
+    rho = 1.0 + 0.1 * x - 0.05 * y ** 2 + 0.02 * x * y * z + 0.01 * z ** 4 - 0.003 * x ** 3 * y
+    c = 0.9 + 0.03 * x ** 2 * z + 0.01 * y ** 3
+    U = np.zeros((6, o.nnodes))
+    U[0], U[5], U[4] = rho, c, 3.0
+    q = o.lift1(U)
+    grho = [0.1 + 0.02 * y * z - 0.009 * x ** 2 * y, -0.1 * y + 0.02 * x * z - 0.003 * x ** 3,
+            0.02 * x * y + 0.04 * z ** 3]
+    gc = [0.06 * x * z, 0.03 * y ** 2, 0.03 * x ** 2]
+    for m in range(3):
+        assert np.max(np.abs(q[m] - grho[m])) < 1e-12
+        assert np.max(np.abs(q[12 + m] - gc[m])) < 1e-12
+
+
+def test_lift1_exact_for_velocity_vanishing_on_noslip_walls():
+    # u = 0 on the no-slip walls is the wall value u* = 0, so the lifting is exact for
+    # polynomial velocities that vanish there (constant density).
+    N = 4
+    o = make(N, (2, 2, 2), (1.0, 1.0, 1.0), (0, 0, 0), (1,) * 6, tw=(0.85,) * 6)
+    x, y, z = o.coords()
+    b = x * (1 - x) * y * (1 - y) * z * (1 - z)
+    u = np.stack([b, 2 * b, -b])
+    db = [(1 - 2 * x) * y * (1 - y) * z * (1 - z), x * (1 - x) * (1 - 2 * y) * z * (1 - z),
+          x * (1 - x) * y * (1 - y) * (1 - 2 * z)]
+    U = np.zeros((6, o.nnodes))
+    U[0], U[5], U[4] = 1.3, 1.3, 4.0
+    U[1:4] = 1.3 * u
+    q = o.lift1(U)
+    for j, s in enumerate((1.0, 2.0, -1.0)):
+        for i in range(3):
+            assert np.max(np.abs(q[3 + 3 * j + i] - s * db[i])) < 1e-12
+
+
+def test_divergence_lifting_exact():
+    # Divergence lifting of the lifted grad c (reading of Delta c): exact for a polynomial
+    # c with zero normal derivative on slip walls, where the wall flux is 0.
+    N = 4
+    Lx, Ly, Lz = 1.5, 1.0, 0.7
+    o = make(N, (3, 2, 2), (Lx, Ly, Lz), (0, 0, 0), (2,) * 6)
+    x, y, z = o.coords()
+
+    def bump(t, L):
+        return t ** 2 * (t - L) ** 2 / L ** 4
+
+    def bump2(t, L):
+        return (12 * t ** 2 - 12 * t * L + 2 * L ** 2) / L ** 4
+
+    c = 1.0 + 0.1 * bump(x, Lx) + 0.2 * bump(y, Ly) - 0.15 * bump(z, Lz)
+    lap = 0.1 * bump2(x, Lx) + 0.2 * bump2(y, Ly) - 0.15 * bump2(z, Lz)
+    U = conserved(o, np.full(o.nnodes, 1.0), np.zeros((3, o.nnodes)), 0.9, c)
+    l2 = o.lift2(U)
+    assert np.max(np.abs(l2[4] - lap)) < 1e-11
+
+
+# ------------------------------------------------------------ free stream
+STATE = dict(rho=1.2, u=(0.3, -0.2, 0.1), T=0.9)
+
+
+@pytest.mark.parametrize("N,amp", [(3, 0.0), (4, 0.0), (3, 0.05), (4, 0.05), (5, 0.05)])
+def test_free_stream_periodic(N, amp):
+    # A constant state is an exact steady solution: requires discrete metric identities
+    # (curl-form metrics on curved meshes) and consistent fluxes.
+    o = make(N, (3, 3, 3), amp=amp)
+    rho = np.full(o.nnodes, STATE["rho"])
+    u = np.tile(np.array(STATE["u"])[:, None], (1, o.nnodes))
+    U = conserved(o, rho, u, STATE["T"], rho.copy())
+    Ut = o.rhs(U)
+    # Bound: round-off of the order-parameter diffusion gamma beta div(grad c) of a
+    # constant, ~ eps |c| (N^2/h)^2 gamma beta, reaches 1e-12 at N = 5 on 3^3 elements.
+    assert np.max(np.abs(Ut)) < 5e-12
+
+
+@pytest.mark.parametrize("amp", [0.0, 0.05])
+def test_free_stream_at_rest_with_walls(amp):
+    # Fluid at rest at the wall temperature, neutral contact angle: steady with both wall
+    # kinds (no-slip isothermal at 90 degrees on z-, slip adiabatic on z+).
+    o = make(3, (3, 3, 2), (1.0, 1.0, 0.5), (1, 1, 0), (0, 0, 0, 0, 1, 2), tw=(0, 0, 0, 0, 0.9, 0),
+             th=(90.0,) * 6, amp=amp)
+    rho = np.full(o.nnodes, 1.2)
+    U = conserved(o, rho, np.zeros((3, o.nnodes)), 0.9, rho.copy())
+    assert np.max(np.abs(o.rhs(U))) < 5e-12  # same round-off bound as above
+
+
+# ------------------------------------------------------------ conservation
+def droplet_state(o, centre, r=0.25, T=0.85, vel=True, seed=3):
+    x, y, z = o.coords()
+    rng = np.random.default_rng(seed)
+    U = o.init_droplets(T, [centre], [r], 0.05, rng.uniform(-1e-3, 1e-3, o.nnodes))
+    if vel:
+        rho = U[0]
+        u = np.stack([0.05 * np.sin(2 * np.pi * y), 0.04 * np.cos(2 * np.pi * z), 0.03 * np.sin(2 * np.pi * x)])
+        U[1:4] = rho * u
+        U[4] += 0.5 * rho * np.sum(u * u, axis=0)
+    return U
+
+
+def test_mass_conservation_periodic():
+    o = make(3, (4, 4, 4))
+    U = droplet_state(o, (0.4, 0.55, 0.5))
+    W = quad_weights(o)
+    Ut = o.rhs(U)
+    assert abs(W @ Ut[0]) <= 1e-14 * (W @ np.abs(Ut[0]))
+
+
+def test_mass_conservation_walls_and_curved():
+    o = make(3, (3, 3, 3), (1.0, 1.0, 0.5), (1, 1, 0), (0, 0, 0, 0, 1, 2),
+             tw=(0, 0, 0, 0, 0.9, 0), th=(0, 0, 0, 0, 60.0, 0), amp=0.03)
+    U = droplet_state(o, (0.5, 0.5, 0.0), r=0.2)
+    W = quad_weights(o)
+    Ut = o.rhs(U)
+    assert abs(W @ Ut[0]) <= 1e-14 * (W @ np.abs(Ut[0]))
+    m0 = W @ U[0]
+    dt = o.dt(U)
+    R_ = np.zeros_like(U)
+    o.run(U, R_, 0.0, dt, 10)
+    assert abs(W @ U[0] - m0) <= 1e-14 * m0
+
+
+# ------------------------------------------------------------ relaxation ODE
+def test_uniform_relaxation_follows_stability_polynomial():
+    # Uniform state with c0 != rho: only the source alpha beta (rho - c) acts, so the RK
+    # scheme multiplies c - rho by its stability polynomial P(-alpha beta dt) each step;
+    # rho, momentum and rho e stay constant.
+    o = make(3, (2, 2, 2))
+    pr = o.params
+    rho = np.full(o.nnodes, 1.0)
+    c = np.full(o.nnodes, 1.001)
+    U = conserved(o, rho, np.zeros((3, o.nnodes)), 0.9, c)
+    U0 = U.copy()
+    A_, B_, _ = oracle.rk_coeffs()
+    # stability polynomial from the 2N recursion applied to y' = lam y
+    dt = 2e-5
+    z = -pr.alpha * pr.beta * dt
+    y, r = 1.0, 0.0
+    for s in range(5):
+        r = (A_[s] * r if s else 0.0) + z * y
+        y = y + B_[s] * r
+    P = y
+    Pz = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24 + 0.005 * z ** 5
+    assert abs(P - Pz) < 1e-5 * abs(z) ** 5 + 1e-15
+    R_ = np.zeros_like(U)
+    nsteps = 10
+    o.run(U, R_, 0.0, dt, nsteps)
+    expect = 0.001 * P ** nsteps
+    assert np.max(np.abs((U[5] - U[0]) - expect)) < 1e-13
+    assert np.max(np.abs(U[0] - U0[0])) < 1e-14
+    assert np.max(np.abs(U[1:4])) < 1e-14
+    assert np.max(np.abs(U[4] - U0[4])) < 1e-12
+
+
+# ------------------------------------------------------------ equivariance
+def permute_state(U, n, P, axes):
+    """Relabel coordinates: new axis d is old axis axes[d]."""
+    E = n[0] * n[1] * n[2]
+    V = U.reshape(6, n[2], n[1], n[0], P, P, P)  # [v][ez][ey][ex][k][j][i]
+    # array axes order (z,y,x) for elements and nodes; build permutation
+    old_pos = {0: 2, 1: 1, 2: 0}
+    perm_e = [old_pos[axes[2]], old_pos[axes[1]], old_pos[axes[0]]]
+    perm = [0] + [1 + p for p in perm_e] + [4 + p for p in perm_e]
+    W = np.transpose(V, perm).copy()
+    out = W.reshape(6, E * P ** 3).copy()
+    mom = U[1:4].copy()
+    Wm = np.transpose(mom.reshape(3, n[2], n[1], n[0], P, P, P), [0] + perm[1:]).reshape(3, -1)
+    for d in range(3):
+        out[1 + d] = Wm[axes[d]]
+    return out
+
+
+@pytest.mark.parametrize("axes", [(1, 0, 2), (2, 1, 0), (1, 2, 0)])
+def test_axis_permutation_equivariance(axes):
+    # L(perm U) = perm L(U) on a cube mesh: catches transposed indices, wrong face/normal
+    # pairing and direction-dependent mistakes anywhere in the operator.
+    n, N = (3, 3, 3), 3
+    o = make(N, n)
+    U = droplet_state(o, (0.4, 0.55, 0.47))
+    lhs = o.rhs(permute_state(U, n, N + 1, axes))
+    rhs = permute_state(o.rhs(U), n, N + 1, axes)
+    scale = np.max(np.abs(rhs), axis=1, keepdims=True)
+    assert np.max(np.abs(lhs - rhs) / scale) < 1e-12
+
+
+def reflect_z(U, n, P):
+    V = U.reshape(6, n[2], n[1], n[0], P, P, P)[:, ::-1, :, :, ::-1, :, :].reshape(6, -1).copy()
+    V[3] = -V[3]
+    return V
+
+
+def test_reflection_equivariance_between_two_walls():
+    # Two identical walls (no-slip, contact angle 60 degrees, T_w = 0.9) at z = 0 and z = Lz:
+    # mirroring z maps solutions to solutions, which pins the wall normal orientation on
+    # both sides of the box.
+    n, N = (2, 2, 3), 3
+    o = make(N, n, (1.0, 1.0, 0.6), (1, 1, 0), (0, 0, 0, 0, 1, 1), tw=(0, 0, 0, 0, 0.9, 0.9),
+             th=(0, 0, 0, 0, 60.0, 60.0))
+    U = droplet_state(o, (0.45, 0.5, 0.1), r=0.2)
+    lhs = o.rhs(reflect_z(U, n, N + 1))
+    rhs = reflect_z(o.rhs(U), n, N + 1)
+    scale = np.max(np.abs(rhs), axis=1, keepdims=True)
+    assert np.max(np.abs(lhs - rhs) / scale) < 1e-12
+
+
+# ------------------------------------------------------------ wall integrals
+@pytest.mark.parametrize("theta", [45.0, 60.0, 90.0, 120.0])
+def test_contact_angle_wall_c_flux_integral(theta):
+    # Uniform fluid at rest with c = rho: the only change of int c is the wall flux of the
+    # order parameter, gamma beta g per unit area, g = -(1/gamma) dpsi_Gamma/dc
+    # (eq. bc_contactangle_alpha); wetting walls (theta < 90) attract liquid.
+    Tw = 0.9
+    o = make(3, (2, 2, 2), (1.0, 1.0, 0.5), (1, 1, 0), (0, 0, 0, 0, 1, 2), tw=(0, 0, 0, 0, Tw, 0),
+             th=(0, 0, 0, 0, theta, 0))
+    pr = o.params
+    c0 = 1.0
+    rho = np.full(o.nnodes, c0)
+    U = conserved(o, rho, np.zeros((3, o.nnodes)), Tw, rho.copy())
+    W = quad_weights(o)
+    Ut = o.rhs(U)
+    rv, rl, _ = oracle.maxwell(Tw)
+    sig = oracle.sigma(Tw, pr.gam)
+    g = -oracle.dpsiwall_dc(c0, rv, rl, sig, math.cos(math.radians(theta))) / pr.gam
+    expect = pr.gam * pr.beta * g * 1.0  # wall area 1
+    got = W @ Ut[5]
+    assert abs(got - expect) < 1e-12 * max(1.0, abs(expect))
+    if theta < 90:
+        assert got > 0
+    assert abs(W @ Ut[0]) < 1e-13
+    assert abs(W @ Ut[4]) < 1e-12
+
+
+def test_hot_isothermal_wall_heats_fluid():
+    # Fluid at T = 0.85 against a wall at T_w = 0.9: energy flows in (heat flux k grad T . n).
+    o = make(3, (2, 2, 2), (1.0, 1.0, 0.5), (1, 1, 0), (0, 0, 0, 0, 1, 2), tw=(0, 0, 0, 0, 0.9, 0))
+    rho = np.full(o.nnodes, 0.4)
+    U = conserved(o, rho, np.zeros((3, o.nnodes)), 0.85, rho.copy())
+    W = quad_weights(o)
+    assert W @ o.rhs(U)[4] > 0.0
+    o2 = make(3, (2, 2, 2), (1.0, 1.0, 0.5), (1, 1, 0), (0, 0, 0, 0, 1, 2), tw=(0, 0, 0, 0, 0.8, 0))
+    U2 = conserved(o2, rho, np.zeros((3, o2.nnodes)), 0.85, rho.copy())
+    assert W @ o2.rhs(U2)[4] < 0.0
+
+
+def test_init_recovers_temperature():
+    o = make(4, (3, 3, 3))
+    U = o.init_droplets(0.85, [(0.5, 0.5, 0.5)], [0.25], 0.05, None)
+    T = o.lift2(U)[0]
+    assert np.max(np.abs(T - 0.85)) < 1e-13
+    rv, rl, _ = oracle.maxwell(0.85)
+    assert abs(U[0].min() - rv) < 1e-3 and abs(U[0].max() - rl) < 1e-2
