@@ -1,0 +1,165 @@
+#!/usr/bin/env python
+"""Throughput of the DGSEM right-hand side + low-storage RK4 step of relaxation
+model 1 (van der Waals NSK) on one MI355X.
+
+A step is one full 5-stage RK4 step (every stage: BR1 lifting passes,
+temperature recovery, volume and surface integrals, wall and contact-angle
+fluxes, relaxation sources, register update) over the whole mesh, on a seeded
+synthetic droplet state resident in HBM.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-stage updates/s FP64 vs FP32-mixed at stated error; batched p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+
+
+def kernel_words_per_node(N):
+    """Algorithmic words moved per volume node by each kernel of one stage:
+    every array the kernel must read or write, each counted once; F = 6/(N+1)
+    own face points per node (neighbour traces are read once per side)."""
+    F = 6.0 / (N + 1)
+    return {
+        "prolong": 6 + 5 * F,             # U in; primitive traces out
+        "lift1": 22 + 9 * F,              # U, nbr traces in; grad(15), T, traces(4) out
+        "lift2": 23 + 21 * F,             # T, grad c, grad u, U, traces(own+nbr 4) in; gradT, lapc, flux traces(13) out
+        "update": 44 + 31 * F,            # U, R, grads(19), T, flux traces(own+nbr 13) in; U, R, traces(5) out
+    }
+
+
+def stage_words_per_node(N):
+    k = kernel_words_per_node(N)
+    return k["lift1"] + k["lift2"] + k["update"]
+
+
+def survey_bytes_model(N, word):
+    """B_floor (state and register read+write) and B_3phase of the BR1
+    three-phase byte model, per node-stage."""
+    F = 6.0 / (N + 1)
+    return 24 * word, (24 + 12 + 2 * F * 35 + 38) * word
+
+
+def cpu_baseline(w, budget_s=15.0):
+    import numpy as np
+
+    import oracle
+    p = oracle.make_params(**w.params)
+    b = oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
+                        w.side_theta)
+    o = oracle.Oracle(p, b)
+    U = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise())
+    dt = o.dt(U)
+    R = np.zeros_like(U)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.rk_step(U, R, 0.0, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 50:
+            break
+    return {"value": o.nnodes * 5 * steps / el, "unit": "node-stage updates/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"{w.name}: {steps} full RK4 step(s) of the FP64 C oracle on the whole mesh "
+                      f"({o.nnodes} nodes), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2208_05310_amd import workloads as wl
+    from paper_2208_05310_amd.nskr import init_workload, solver_for
+
+    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4}[args.workload]()
+    s = solver_for(w, args.precision)
+    U = init_workload(s, w)
+    R = s.new_state()
+    dt = s.dt(U)
+    stream = torch.cuda.current_stream()
+    s.rk_steps(U, R, dt, args.warmup, stream)
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-kernel HIP events recorded by the library on this stream
+    s.set_profiling(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    s.rk_steps(U, R, dt, args.steps, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile(stream)
+    s.set_profiling(False)
+    wall = t1 - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    sums = s.reduce(U)  # health check of the final state (raises on non-finite)
+    nn = s.nnodes
+    value = nn * 5 * args.steps / wall
+    word = 8 if args.precision == "fp64" else 4
+    words = kernel_words_per_node(w.N)
+    kern = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt and k in words:
+            avg = ms / cnt
+            kern[k] = {"avg_us": 1e3 * avg, "launches": cnt,
+                       "alg_bytes_per_launch": words[k] * word * nn,
+                       "achieved_GBs": words[k] * word * nn / (avg * 1e-3) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+    ach = kern[dom]["achieved_GBs"]
+    floor_b, b3 = survey_bytes_model(w.N, word)
+    stage_b = stage_words_per_node(w.N) * word
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic: seeded droplet state (tanh profiles at Maxwell densities, uniform noise 1e-6)",
+        "config": {"workload": w.name, "elements": w.nelems, "N": w.N, "nodes": nn,
+                   "precision": args.precision, "alpha": w.params["alpha"], "beta": w.params["beta"],
+                   "T0": w.T0, "dt": dt, "rk": "5-stage 2N RK4(3)5"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM_GBS, "traffic": None},
+        "kernels": kern,
+        "stage_model": {"design_bytes_per_node_stage": stage_b,
+                        "design_GBs": value * stage_b / 1e9,
+                        "B_3phase_bytes": b3, "B_3phase_GBs": value * b3 / 1e9,
+                        "B_floor_bytes": floor_b, "B_floor_GBs": value * floor_b / 1e9},
+        "gpu_event_ms": gpu_ms,
+        "final_mass": sums[0],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

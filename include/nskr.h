@@ -1,0 +1,219 @@
+/*
+ * nskr.h -- C ABI of the MI355X (gfx950) library for the DGSEM right-hand side
+ * and low-storage Runge-Kutta update of relaxation model 1 of the
+ * non-isothermal Navier-Stokes-Korteweg equations with a van der Waals
+ * equation of state (Keim, Munz, Rohde, arXiv 2208.05310).
+ *
+ * The system (Sec. 2.3.2, flux and source vectors of relaxation model 1) is
+ *   U_t + div(F^C(U) - F^V(U, grad U, lap c)) = S(U, grad U),
+ *   U = (rho, rho u, rho v, rho w, rho e, c),
+ * discretised as in Sec. 3.1: nodal DGSEM on Legendre-Gauss nodes with
+ * collocated quadrature, Rusanov face flux for F^C, BR1 lifting for the
+ * gradients, point-wise sources, explicit low-storage RK4.  Walls follow the
+ * relaxation-model boundary conditions of Sec. 2.4 (eq. bc_nsk_alpha) with the
+ * cubic wall energy (eq. helmfreesurftot_derivative), enforced weakly through
+ * the face flux (Sec. 3.2).
+ *
+ * Conventions
+ *  - Every call returns an int status (NSKR_OK = 0).  Arguments are validated
+ *    before anything is enqueued.  After NSKR_E_HIP the context is poisoned
+ *    and later calls return NSKR_E_STATE until nskr_destroy.
+ *  - A context is not thread-safe: one host thread per context.
+ *  - State buffers U, R, U_t are caller-owned device memory (e.g. torch
+ *    tensors), contiguous, structure-of-arrays [6][nelems][(N+1)^3] with the
+ *    node index i + (N+1)(j + (N+1)k), i along the first reference direction.
+ *    Element type is double for precision 0 (FP64) and float for precision 1
+ *    (FP32-mixed).
+ *  - Work is enqueued on the caller's stream and is asynchronous, except for
+ *    the calls documented as synchronising (they return host values).
+ *  - Only compute on the device: there is no CPU fallback.  If the device
+ *    code is unavailable, nskr_create fails with NSKR_E_HIP.
+ */
+#ifndef NSKR_H
+#define NSKR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSKR_ABI_VERSION 1
+
+enum {
+    NSKR_OK = 0,
+    NSKR_E_ARG = 1,          /* invalid argument; nothing enqueued          */
+    NSKR_E_STATE = 2,        /* call out of order or context poisoned       */
+    NSKR_E_NOMEM = 3,        /* device allocation failed                    */
+    NSKR_E_HIP = 4,          /* a HIP runtime call failed                   */
+    NSKR_E_NONFINITE = 5,    /* non-finite or out-of-range state detected   */
+    NSKR_E_UNSUPPORTED = 6   /* valid request this build does not implement */
+};
+
+typedef struct nskr_ctx nskr_ctx;
+typedef void *nskr_stream; /* a hipStream_t; NULL is the default stream */
+
+/* Physical and numerical parameters.  R, a, b: reduced van der Waals
+ * constants (Sec. 2.1: 8/3, 3, 1/3); cv: c_v; mu: viscosity (Stokes
+ * hypothesis); kappa: heat conductivity; gam: capillarity gamma_K; alpha:
+ * Korteweg parameter; beta: relaxation parameter (Sec. 2.3.2); cfl: CFL number
+ * (0.9, Sec. 4).  precision: 0 = FP64 everywhere; 1 = FP32-mixed (FP32 state
+ * and bulk arithmetic; temperature recovery, pressure and sound speed in FP64;
+ * time-step and integral reductions in FP64). */
+typedef struct {
+    double R, a, b, cv, mu, kappa, gam, alpha, beta, cfl;
+    int precision;
+    int reserved;
+} nskr_params;
+
+/* Wall boundary condition (Sec. 2.4, eq. bc_nsk_alpha with gamma_1 = gamma_4 =
+ * 0).  kind 1: impermeable no-slip isothermal wall at twall with a static
+ * contact angle theta_deg (cubic wall energy, eq. helmfreesurftot_derivative,
+ * Maxwell states and sigma_vl evaluated at twall).  kind 2: slip adiabatic wall
+ * with neutral wetting (zero contact-angle flux, zero tangential traction). */
+typedef struct {
+    int kind;
+    double twall;
+    double theta_deg;
+} nskr_bc;
+
+/* Hexahedral mesh (Sec. 3.1).  Every element must be a parallelepiped (affine
+ * map from the reference cube); corners[e][v][3] with v = i + 2j + 4k, i along
+ * the first reference direction.  Faces: 0 = xi^1 = -1, 1 = +1, 2/3 = xi^2,
+ * 4/5 = xi^3.  nbr[e][f] = neighbour element or -1 on a wall; nbr_face[e][f]
+ * = the neighbour's face, which must be the opposite face f^1 with identical
+ * face-point ordering (structured conforming meshes, periodic wrap allowed);
+ * bc[e][f] = 0 for interior faces, else a 1-based index into bcs.  All arrays
+ * are host memory; the library copies them. */
+typedef struct {
+    int nelems;
+    const double *corners;
+    const int *nbr;
+    const int *nbr_face;
+    const int *bc;
+    int nbcs;
+    const nskr_bc *bcs;
+} nskr_mesh;
+
+/* Droplet initial condition: rho = rho_v + sum_j (rho_l - rho_v)/2 (1 +
+ * tanh((r_j - d_j)/width)) with the Maxwell densities at T0 (the tanh profile
+ * of Sec. 4.1.1/4.2 with its width given directly), d_j the distance to centre
+ * j, taken as the minimum image along the axes flagged periodic (box extent
+ * length[]); u = 0; c = rho; rho e from eq. totalenergyalpha with the lifted
+ * grad c, so that the recovered temperature is T0.  centres: ndrop x 3,
+ * radii: ndrop, host memory. */
+typedef struct {
+    double T0;
+    int ndrop;
+    const double *centres;
+    const double *radii;
+    double width;
+    double length[3];
+    int periodic[3];
+} nskr_init;
+
+/* Integrals returned by nskr_reduce (Gauss quadrature with the Jacobian, FP64
+ * accumulation in a fixed order). */
+enum {
+    NSKR_SUM_MASS = 0, NSKR_SUM_MOMX = 1, NSKR_SUM_MOMY = 2, NSKR_SUM_MOMZ = 3,
+    NSKR_SUM_ENERGY = 4, NSKR_SUM_C = 5, NSKR_SUM_KINETIC = 6,
+    NSKR_SUM_GRADIENT_ENERGY = 7, /* gamma/2 |grad c|^2                 */
+    NSKR_SUM_RELAX_ENERGY = 8,    /* alpha/2 (rho - c)^2                */
+    NSKR_SUM_RHO_MINUS_C_SQ = 9,  /* (rho - c)^2                        */
+    NSKR_SUM_MIN_RHO = 10, NSKR_SUM_MAX_RHO = 11,
+    NSKR_SUM_MIN_T = 12, NSKR_SUM_MAX_T = 13,
+    NSKR_CNT_NONFINITE = 14, NSKR_CNT_RHO_RANGE = 15, NSKR_CNT_T_NONPOS = 16,
+    NSKR_CNT_CS2_NEG = 17,
+    NSKR_SUM_ENTROPY = 18,        /* -int rho eta, eta = R c_v ln T - R ln(b rho/(1-b rho)) */
+    NSKR_SUM_VOLUME = 19,
+    NSKR_NSUMS = 20
+};
+
+/* ABI version (NSKR_ABI_VERSION). */
+int nskr_version(void);
+
+/* Create a context for polynomial degree N (2..5) on HIP device `device`.
+ * No device memory is allocated yet.  Errors: NSKR_E_ARG (N out of range,
+ * negative mu, kappa, gam, alpha or beta, b < 0, cv <= 0, R <= 0, cfl <= 0,
+ * precision not 0/1, out == NULL); NSKR_E_HIP (device missing or no device code
+ * for it). */
+int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out);
+
+/* Free library-owned device memory and the context.  Never frees caller
+ * buffers.  Safe on NULL. */
+int nskr_destroy(nskr_ctx *ctx);
+
+/* Upload the mesh: per-element metric terms (Ja^d_m = J d xi^d/d x_m and J,
+ * exact for affine elements), outward face normals and surface elements,
+ * connectivity and per-wall constants (Maxwell states, sigma_vl of
+ * eq. surftenscoef read with the factor sqrt(2 gamma)); allocates the
+ * library's scratch (lifted gradients, face traces).  May be called again to
+ * replace the mesh.  Errors: NSKR_E_ARG (null arrays, element not a
+ * parallelepiped or J <= 0, neighbour indices out of range or not reciprocal,
+ * wall face without a bc or bc index out of range, wall kind not 1/2,
+ * supercritical wall temperature); NSKR_E_UNSUPPORTED (neighbour face not the
+ * opposite face); NSKR_E_NOMEM; NSKR_E_HIP.  Synchronises the stream. */
+int nskr_mesh_upload(nskr_ctx *ctx, const nskr_mesh *m, nskr_stream s);
+
+/* Number of values in one state buffer: 6 nelems (N+1)^3.
+ * Errors: NSKR_E_STATE before a mesh is uploaded. */
+int nskr_state_size(const nskr_ctx *ctx, size_t *nvalues);
+
+/* Bytes of library-owned device memory for the current mesh. */
+int nskr_device_bytes(const nskr_ctx *ctx, size_t *bytes);
+
+/* Write the droplet initial state into U (see nskr_init).  noise: host array
+ * of nelems (N+1)^3 doubles added to rho in node order (before c = rho), or
+ * NULL.  Errors: NSKR_E_ARG (null U or ic, ndrop < 0, width <= 0, T0 not below
+ * the critical temperature). */
+int nskr_init_droplets(nskr_ctx *ctx, const nskr_init *ic, const double *noise, void *U, nskr_stream s);
+
+/* U_t = L(U), the semi-discrete operator (Sec. 3.1).  Asynchronous.
+ * Errors: NSKR_E_STATE, NSKR_E_ARG (null or aliasing buffers), NSKR_E_HIP. */
+int nskr_rhs(nskr_ctx *ctx, const void *U, void *Ut, nskr_stream s);
+
+/* Sub-operators for verification.  nskr_lift1 writes the BR1 gradients of
+ * (rho, u, v, w, c): q[15][nelems (N+1)^3], field 3k+m = d w_k / d x_m.
+ * nskr_lift2 writes out[5][...] = temperature, its lifted gradient (3) and
+ * the divergence lifting of grad c (lap c).  Same element type as U. */
+int nskr_lift1(nskr_ctx *ctx, const void *U, void *q, nskr_stream s);
+int nskr_lift2(nskr_ctx *ctx, const void *U, void *out, nskr_stream s);
+
+/* Stable time step (FP64): min of the advective limit CFL T_N 2 / max_nodes
+ * sum_d (|u . Ja^d| + c~ |Ja^d|)/J and the parabolic/source limit
+ * CFL 4.6567 / (alpha beta + RHO_N nu_max max_nodes sum_d (|Ja^d|/(2J))^2),
+ * nu_max = max(4 mu/(3 rho), kappa/(rho R cv), gam beta), c~ = sqrt(|c_s^2|),
+ * T_N and RHO_N the 1D stability constants of the RK scheme.  Synchronises s.
+ * Errors: NSKR_E_NONFINITE if a rate is not finite (dt not written). */
+int nskr_dt(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
+
+/* nsteps steps of the 5-stage 2N-storage RK4(3)5 of Carpenter & Kennedy
+ * (the low-storage fourth-order scheme family cited in Sec. 3.1): per stage
+ * R <- A_s R + dt L(U) (assigned at stage 1, so R needs no initialisation),
+ * U <- U + B_s R.  Asynchronous.  Errors: NSKR_E_ARG (dt not positive and
+ * finite, nsteps < 0, null or aliasing buffers), NSKR_E_STATE, NSKR_E_HIP. */
+int nskr_rk_steps(nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, nskr_stream s);
+
+/* Integrals and counters (the NSKR_SUM_* indices) into out[NSKR_NSUMS].
+ * Synchronises s.  Returns NSKR_E_NONFINITE (out still filled) when a
+ * non-finite value, rho outside (0, 1/b) or T <= 0 is found. */
+int nskr_reduce(nskr_ctx *ctx, const void *U, double *out, nskr_stream s);
+
+/* Per-kernel timing with HIP events recorded on the caller's stream around
+ * every kernel launch of this context (off by default).  Kernel kinds:
+ * 0 prolong, 1 lift1, 2 lift2, 3 update, 4 reductions/init.  nskr_profile
+ * synchronises s, then writes the accumulated milliseconds and launch counts
+ * of each kind (arrays of length NSKR_NKINDS) and resets them. */
+#define NSKR_NKINDS 5
+int nskr_set_profiling(nskr_ctx *ctx, int on);
+int nskr_profile(nskr_ctx *ctx, double *ms, long *count, nskr_stream s);
+
+/* Message of the last failing call on this context (static storage valid
+ * until the next call); a generic message for ctx == NULL. */
+const char *nskr_last_error(const nskr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSKR_H */

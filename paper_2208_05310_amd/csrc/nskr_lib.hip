@@ -1,0 +1,993 @@
+// nskr_lib.hip -- host side of the gfx950 library behind include/nskr.h:
+// argument validation, mesh and metric upload, per-wall constants, launch
+// sequences of the DGSEM stages, the low-storage RK loop, the FP64 time-step
+// and integral reductions, and the droplet initialisation.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/nskr.h"
+#include "nskr_kernels.hpp"
+
+using namespace nskr;
+
+// ------------------------------------------------------------------ context
+struct nskr_ctx {
+    nskr_params p;
+    int N = 0, P = 0, device = 0;
+    bool poisoned = false;
+    std::string err;
+    // mesh
+    int E = 0;
+    size_t NN = 0, NF = 0;
+    int *d_nbr = nullptr, *d_bcid = nullptr;
+    double *d_emet = nullptr, *d_fmet = nullptr, *d_egeo = nullptr;
+    BcDev *d_bcs = nullptr;
+    std::vector<double> h_emet;  // host copy of the element metrics (weights for reductions)
+    // scratch (element type of the precision)
+    void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
+    double *d_part = nullptr;    // reduction partials
+    double *d_out = nullptr;     // final reduction values (device)
+    double *d_noise = nullptr;   // init noise
+    double *d_drop = nullptr;    // init droplets
+    size_t bytes = 0;
+    Basis bas;
+    Phys ph;
+    // optional per-kernel event timing
+    bool prof = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> prof_events;
+    std::vector<hipEvent_t> event_pool;
+};
+
+// Event pair around one kernel launch when profiling is on.
+struct KernelTimer {
+    nskr_ctx *c;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    static hipEvent_t take(nskr_ctx *c)
+    {
+        if (!c->event_pool.empty()) {
+            hipEvent_t e = c->event_pool.back();
+            c->event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    KernelTimer(nskr_ctx *c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_)
+    {
+        if (!c->prof) return;
+        a = take(c);
+        b = take(c);
+        if (a) (void)hipEventRecord(a, s);
+    }
+    ~KernelTimer()
+    {
+        if (!c->prof || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        c->prof_events.push_back({kind, {a, b}});
+    }
+};
+
+static const char *g_null_msg = "nskr: null context";
+
+static int fail(nskr_ctx *c, int code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(c, x)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) {                                                         \
+            (c)->poisoned = true;                                                       \
+            return fail((c), NSKR_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+        }                                                                               \
+    } while (0)
+
+struct DeviceGuard {
+    int old = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&old) != hipSuccess) old = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (old >= 0) (void)hipSetDevice(old);
+    }
+};
+
+// ------------------------------------------------------------ host numerics
+// Legendre-Gauss nodes/weights, Lagrange face values and the weak derivative
+// matrix, computed in extended precision and rounded once.
+typedef long double ld;
+
+static void legendre_ld(int n, ld x, ld &Pn, ld &dPn)
+{
+    ld p0 = 1, p1 = x;
+    if (n == 0) { Pn = 1; dPn = 0; return; }
+    for (int k = 2; k <= n; ++k) {
+        ld p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    Pn = p1;
+    dPn = n * (x * p1 - p0) / (x * x - 1);  // derivative identity of Legendre polynomials
+}
+
+static void make_basis(int N, Basis &b)
+{
+    const int P = N + 1;
+    ld x[8], w[8];
+    for (int i = 0; i < P; ++i) {
+        // Chebyshev-Gauss initial guess, Newton on P_{N+1}
+        ld xi = -cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (P + 0.5L));
+        for (int it = 0; it < 60; ++it) {
+            ld Pn, dP;
+            legendre_ld(P, xi, Pn, dP);
+            ld dx = Pn / dP;
+            xi -= dx;
+            if (fabsl(dx) < 1e-21L) break;
+        }
+        ld Pn, dP;
+        legendre_ld(P, xi, Pn, dP);
+        x[i] = xi;
+        w[i] = 2 / ((1 - xi * xi) * dP * dP);
+    }
+    // barycentric weights
+    ld lam[8];
+    for (int j = 0; j < P; ++j) {
+        ld prod = 1;
+        for (int k = 0; k < P; ++k)
+            if (k != j) prod *= x[j] - x[k];
+        lam[j] = 1 / prod;
+    }
+    ld D[8][8];
+    for (int i = 0; i < P; ++i) {
+        ld s = 0;
+        for (int j = 0; j < P; ++j) {
+            if (i == j) continue;
+            D[i][j] = lam[j] / (lam[i] * (x[i] - x[j]));
+            s += D[i][j];
+        }
+        D[i][i] = -s;
+    }
+    memset(&b, 0, sizeof(b));
+    for (int i = 0; i < P; ++i)
+        for (int l = 0; l < P; ++l) b.Dh[i * P + l] = (double)(-(w[l] / w[i]) * D[l][i]);
+    for (int j = 0; j < P; ++j) {
+        // l_j(+-1) from the barycentric form of the second kind
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            ld xe = sgn ? 1.0L : -1.0L, num = 0, den = 0;
+            for (int k = 0; k < P; ++k) {
+                ld t = lam[k] / (xe - x[k]);
+                den += t;
+                if (k == j) num = t;
+            }
+            ld val = num / den;
+            b.L[sgn][j] = (double)val;
+            b.Lh[sgn][j] = (double)(val / w[j]);
+        }
+        b.w[j] = (double)w[j];
+        b.x[j] = (double)x[j];
+    }
+}
+
+// van der Waals thermodynamics on the host (Sec. 2.1), extended precision.
+struct Vdw {
+    ld R, a, b;
+    ld p(ld r, ld T) const { return r * R * T / (1 - b * r) - a * r * r; }
+    ld dp(ld r, ld T) const { return R * T / ((1 - b * r) * (1 - b * r)) - 2 * a * r; }
+    ld mu(ld r, ld T) const { return R * T * logl(b * r / (1 - b * r)) + R * T / (1 - b * r) - 2 * a * r; }
+    ld dmu(ld r, ld T) const { return dp(r, T) / r; }  // d mu / d rho = (dp/drho) / rho
+    ld psi_nl(ld r, ld T) const { return r * R * T * logl(b * r / (1 - b * r)) - a * r * r; }
+};
+
+// Maxwell states: Newton on p(rv) = p(rl), mu(rv) = mu(rl), started from the
+// two spinodal densities pushed outwards, with a step-halving guard that keeps
+// both iterates on their branches.
+static bool maxwell_host(const Vdw &v, ld T, ld &rv, ld &rl)
+{
+    // spinodal: zeros of dp/drho; bracket them by scanning
+    const ld rmax = 1 / v.b;
+    ld sv = -1, sl = -1, prev = v.dp(rmax * 1e-6L, T);
+    const int n = 20000;
+    for (int k = 1; k < n; ++k) {
+        ld r = rmax * k / n, d = v.dp(r, T);
+        if (prev > 0 && d <= 0 && sv < 0) sv = r;
+        if (prev < 0 && d >= 0 && sv > 0 && sl < 0) sl = r;
+        prev = d;
+    }
+    if (sv < 0 || sl < 0) return false;
+    rv = 0.5L * sv;
+    rl = 0.5L * (sl + rmax);
+    for (int it = 0; it < 200; ++it) {
+        ld f1 = v.p(rv, T) - v.p(rl, T), f2 = v.mu(rv, T) - v.mu(rl, T);
+        ld a11 = v.dp(rv, T), a12 = -v.dp(rl, T), a21 = v.dmu(rv, T), a22 = -v.dmu(rl, T);
+        ld det = a11 * a22 - a12 * a21;
+        ld dv = (f1 * a22 - a12 * f2) / det, dl = (a11 * f2 - a21 * f1) / det;
+        ld s = 1;
+        while (s > 1e-6L && (rv - s * dv <= 0 || rv - s * dv >= sv || rl - s * dl <= sl || rl - s * dl >= rmax)) s *= 0.5L;
+        rv -= s * dv;
+        rl -= s * dl;
+        if (fabsl(dv) < 1e-19L * rv && fabsl(dl) < 1e-19L * rl) break;
+    }
+    return fabsl(v.p(rv, T) - v.p(rl, T)) < 1e-14L && fabsl(v.mu(rv, T) - v.mu(rl, T)) < 1e-13L;
+}
+
+// Surface tension of eq. surftenscoef with the prefactor sqrt(2 gamma):
+// composite 16-point Gauss-Legendre over 48 panels of [rv, rl].
+static ld sigma_host(const Vdw &v, ld T, ld gam, ld rv, ld rl)
+{
+    Basis b16;
+    (void)b16;
+    const int m = 16;
+    ld x[16], w[16];
+    for (int i = 0; i < m; ++i) {
+        ld xi = -cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (m + 0.5L));
+        for (int it = 0; it < 60; ++it) {
+            ld Pn, dP;
+            legendre_ld(m, xi, Pn, dP);
+            ld dx = Pn / dP;
+            xi -= dx;
+            if (fabsl(dx) < 1e-21L) break;
+        }
+        ld Pn, dP;
+        legendre_ld(m, xi, Pn, dP);
+        x[i] = xi;
+        w[i] = 2 / ((1 - xi * xi) * dP * dP);
+    }
+    const ld muv = v.mu(rv, T), psiv = v.psi_nl(rv, T);
+    const int panels = 48;
+    const ld h = (rl - rv) / panels;
+    ld I = 0;
+    for (int k = 0; k < panels; ++k) {
+        ld A = rv + k * h;
+        for (int i = 0; i < m; ++i) {
+            ld r = A + 0.5L * h * (x[i] + 1);
+            ld d = v.psi_nl(r, T) - (psiv + (r - rv) * muv);
+            I += 0.5L * h * w[i] * (d > 0 ? sqrtl(d) : 0);
+        }
+    }
+    return sqrtl(2 * gam) * I;
+}
+
+// ------------------------------------------------- RK and time-step constants
+// 5-stage 2N-storage RK4(3)5, Carpenter & Kennedy (1994).
+static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+// 1D stability constants (periodic Gauss DGSEM spectra under the scheme's
+// stability polynomial), index N: advective dt a / h and diffusive spectral
+// radius at h = 1; stability interval on the negative real axis.
+static const double kTN[6] = {0, 0, 0.3521, 0.2200, 0.1523, 0.1126};
+static const double kRhoN[6] = {0, 0, 64.8, 176.2, 387.0, 745.2};
+static const double kRkReal = 4.6567;
+
+// ------------------------------------------------------------ extra kernels
+struct RateArgs {
+    MeshDev mesh; Phys ph; size_t NN; double *part; int nblk;
+};
+
+template <int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, RateArgs a)
+{
+    using G = Tile<P>;
+    __shared__ double sr[3][kBlock];
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le;
+    const size_t g = (size_t)e0 * G::n3 + t;
+    double r0 = 0, r1 = 0, r2 = 0;
+    if (t < G::NV && e < a.mesh.E) {
+        double rho = U[g], m0 = U[a.NN + g], m1 = U[2 * a.NN + g], m2 = U[3 * a.NN + g];
+        double E = U[4 * a.NN + g], c = U[5 * a.NN + g];
+        double Tn = temperature(a.ph, rho, m0, m1, m2, E, c, Q[12 * a.NN + g], Q[13 * a.NN + g], Q[14 * a.NN + g]);
+        double p, cs2;
+        eos(a.ph, rho, Tn, p, cs2);
+        double cs = sqrt(fabs(cs2));
+        const double *em = a.mesh.emet + (size_t)e * 10;
+        double iJ = 1.0 / em[9];
+        for (int d = 0; d < 3; ++d) {
+            const double *Ja = em + 3 * d;
+            double nJ = sqrt(Ja[0] * Ja[0] + Ja[1] * Ja[1] + Ja[2] * Ja[2]);
+            r0 += (fabs(m0 * Ja[0] + m1 * Ja[1] + m2 * Ja[2]) / rho + cs * nJ) * iJ;
+            double h = 0.5 * nJ * iJ;
+            r1 += h * h;
+        }
+        r2 = fmax(fmax(4.0 * a.ph.mu / (3.0 * rho), a.ph.kappa / (rho * a.ph.R * a.ph.cv)), a.ph.gam * a.ph.beta);
+        if (!isfinite(r0) || !isfinite(r2)) r0 = r2 = INFINITY;
+    }
+    sr[0][t] = r0; sr[1][t] = r1; sr[2][t] = r2;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < 3; ++k) sr[k][t] = fmax(sr[k][t], sr[k][t + s]);
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < 3; ++k) a.part[(size_t)k * a.nblk + blockIdx.x] = sr[k][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_final(const double *part, int nblk, int nval, double *out)
+{
+    __shared__ double s[kBlock];
+    for (int k = 0; k < nval; ++k) {
+        double m = 0;
+        for (int b = threadIdx.x; b < nblk; b += kBlock) m = fmax(m, part[(size_t)k * nblk + b]);
+        s[threadIdx.x] = m;
+        __syncthreads();
+        for (int st = kBlock / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + st]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = s[0];
+        __syncthreads();
+    }
+}
+
+// Integrals: kinds 0 = sum, 1 = min, 2 = max for the NSKR_SUM_* slots.
+__device__ __forceinline__ int sum_kind(int k) { return k == 10 || k == 12 ? 1 : (k == 11 || k == 13 ? 2 : 0); }
+
+template <int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_integrals(const T *U, const T *Q, RateArgs a, Basis bas)
+{
+    using G = Tile<P>;
+    __shared__ double sr[NSKR_NSUMS][kBlock];
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le, nd = t - le * G::n3;
+    const size_t g = (size_t)e0 * G::n3 + t;
+    double v[NSKR_NSUMS];
+    for (int k = 0; k < NSKR_NSUMS; ++k) v[k] = 0.0;
+    v[10] = v[12] = INFINITY;
+    v[11] = v[13] = -INFINITY;
+    if (t < G::NV && e < a.mesh.E) {
+        const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
+        const double wJ = bas.w[i] * bas.w[j] * bas.w[k] * a.mesh.emet[(size_t)e * 10 + 9];
+        double u[6];
+        bool bad = false;
+        for (int q = 0; q < 6; ++q) {
+            u[q] = (double)U[q * a.NN + g];
+            if (!isfinite(u[q])) bad = true;
+        }
+        if (bad) {
+            v[14] = 1.0;
+        } else {
+            const double q0 = Q[12 * a.NN + g], q1 = Q[13 * a.NN + g], q2 = Q[14 * a.NN + g];
+            const double rho = u[0];
+            const double Tn = temperature(a.ph, rho, u[1], u[2], u[3], u[4], u[5], q0, q1, q2);
+            double p, cs2;
+            eos(a.ph, rho, Tn, p, cs2);
+            if (!(rho > 0.0 && rho * a.ph.b < 1.0)) v[15] = 1.0;
+            if (!(Tn > 0.0)) v[16] = 1.0;
+            if (cs2 < 0.0) v[17] = 1.0;
+            const double g2 = q0 * q0 + q1 * q1 + q2 * q2;
+            v[0] = wJ * rho;
+            v[1] = wJ * u[1];
+            v[2] = wJ * u[2];
+            v[3] = wJ * u[3];
+            v[4] = wJ * u[4];
+            v[5] = wJ * u[5];
+            v[6] = wJ * 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / rho;
+            v[7] = wJ * 0.5 * a.ph.gam * g2;
+            v[8] = wJ * 0.5 * a.ph.alpha * (rho - u[5]) * (rho - u[5]);
+            v[9] = wJ * (rho - u[5]) * (rho - u[5]);
+            v[10] = v[11] = rho;
+            v[12] = v[13] = Tn;
+            if (a.ph.b > 0.0 && Tn > 0.0 && rho > 0.0 && rho * a.ph.b < 1.0)
+                v[18] = -wJ * rho * (a.ph.R * a.ph.cv * log(Tn) - a.ph.R * log(a.ph.b * rho / (1.0 - a.ph.b * rho)));
+            v[19] = wJ;
+        }
+    }
+    for (int k = 0; k < NSKR_NSUMS; ++k) sr[k][t] = v[k];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int k = 0; k < NSKR_NSUMS; ++k) {
+                const int kd = sum_kind(k);
+                const double x = sr[k][t], y = sr[k][t + s];
+                sr[k][t] = kd == 0 ? x + y : (kd == 1 ? fmin(x, y) : fmax(x, y));
+            }
+        __syncthreads();
+    }
+    if (t == 0)
+        for (int k = 0; k < NSKR_NSUMS; ++k) a.part[(size_t)k * a.nblk + blockIdx.x] = sr[k][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_integrals_final(const double *part, int nblk, double *out)
+{
+    __shared__ double s[kBlock];
+    for (int k = 0; k < NSKR_NSUMS; ++k) {
+        const int kd = sum_kind(k);
+        double m = kd == 0 ? 0.0 : (kd == 1 ? INFINITY : -INFINITY);
+        for (int b = threadIdx.x; b < nblk; b += kBlock) {
+            const double x = part[(size_t)k * nblk + b];
+            m = kd == 0 ? m + x : (kd == 1 ? fmin(m, x) : fmax(m, x));
+        }
+        s[threadIdx.x] = m;
+        __syncthreads();
+        for (int st = kBlock / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) {
+                const double x = s[threadIdx.x], y = s[threadIdx.x + st];
+                s[threadIdx.x] = kd == 0 ? x + y : (kd == 1 ? fmin(x, y) : fmax(x, y));
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[k] = s[0];
+        __syncthreads();
+    }
+}
+
+struct InitArgs {
+    MeshDev mesh; Basis bas; size_t NN; const double *drop; int ndrop; double width, rv, rl;
+    double len[3]; int per[3]; const double *noise;
+};
+
+template <int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_init_rho(T *U, InitArgs a)
+{
+    using G = Tile<P>;
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le, nd = t - le * G::n3;
+    if (t >= G::NV || e >= a.mesh.E) return;
+    const size_t g = (size_t)e0 * G::n3 + t;
+    const int idx[3] = {nd % P, (nd / P) % P, nd / (P * P)};
+    const double *eg = a.mesh.egeo + (size_t)e * 12;
+    double x[3];
+    for (int m = 0; m < 3; ++m) {
+        double s = eg[m];
+        for (int d = 0; d < 3; ++d) s += eg[3 + 3 * d + m] * 0.5 * (a.bas.x[idx[d]] + 1.0);
+        x[m] = s;
+    }
+    double rho = a.rv;
+    for (int jd = 0; jd < a.ndrop; ++jd) {
+        double d2 = 0;
+        for (int m = 0; m < 3; ++m) {
+            double dx = x[m] - a.drop[4 * jd + m];
+            if (a.per[m]) dx -= a.len[m] * rint(dx / a.len[m]);
+            d2 += dx * dx;
+        }
+        rho += 0.5 * (a.rl - a.rv) * (1.0 + tanh((a.drop[4 * jd + 3] - sqrt(d2)) / a.width));
+    }
+    if (a.noise) rho += a.noise[g];
+    U[g] = T(rho);
+    U[a.NN + g] = T(0);
+    U[2 * a.NN + g] = T(0);
+    U[3 * a.NN + g] = T(0);
+    U[4 * a.NN + g] = T(0);
+    U[5 * a.NN + g] = T(rho);
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_init_energy(T *U, const T *Q, int E, size_t NN, Phys ph, double T0)
+{
+    using G = Tile<P>;
+    const int t = threadIdx.x;
+    const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le;
+    if (t >= G::NV || e >= E) return;
+    const size_t g = (size_t)e0 * G::n3 + t;
+    const double rho = U[g];
+    const double q0 = Q[12 * NN + g], q1 = Q[13 * NN + g], q2 = Q[14 * NN + g];
+    U[4 * NN + g] = T(rho * (ph.R * ph.cv * T0 - ph.a * rho) + 0.5 * ph.gam * (q0 * q0 + q1 * q1 + q2 * q2));
+}
+
+// ------------------------------------------------------------ launch layer
+template <int P, typename T> struct Impl {
+    using G = Tile<P>;
+    static int nblk(const nskr_ctx *c) { return (c->E + G::EPB - 1) / G::EPB; }
+
+    static MeshDev mesh(const nskr_ctx *c)
+    {
+        MeshDev m;
+        m.E = c->E; m.nbr = c->d_nbr; m.bcid = c->d_bcid; m.emet = c->d_emet; m.fmet = c->d_fmet;
+        m.egeo = c->d_egeo; m.bcs = c->d_bcs;
+        return m;
+    }
+
+    static void prolong(nskr_ctx *c, const T *U, hipStream_t s)
+    {
+        ProlongArgs<T> a{U, (T *)c->d_TU, mesh(c), c->bas, c->NN};
+        KernelTimer kt(c, 0, s);
+        hipLaunchKernelGGL((k_prolong<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+    }
+    static void lift1(nskr_ctx *c, const T *U, hipStream_t s)
+    {
+        Lift1Args<T> a{U, (const T *)c->d_TU, (T *)c->d_Q, (T *)c->d_TH, (T *)c->d_T2, mesh(c), c->ph, c->bas, c->NN};
+        KernelTimer kt(c, 1, s);
+        hipLaunchKernelGGL((k_lift1<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+    }
+    static void lift2(nskr_ctx *c, const T *U, hipStream_t s)
+    {
+        Lift2Args<T> a{U, (const T *)c->d_Q, (const T *)c->d_TH, (const T *)c->d_T2, (T *)c->d_G2, (T *)c->d_TF,
+                       mesh(c), c->ph, c->bas, c->NN};
+        KernelTimer kt(c, 2, s);
+        hipLaunchKernelGGL((k_lift2<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+    }
+    static void update(nskr_ctx *c, T *U, T *R, T *Ut, int mode, int first, double A, double B, double dt,
+                       hipStream_t s)
+    {
+        UpdateArgs<T> a{U, R, Ut, (const T *)c->d_Q, (const T *)c->d_TH, (const T *)c->d_G2, (const T *)c->d_TF,
+                        (T *)c->d_TU, mesh(c), c->ph, c->bas, c->NN, mode, first, A, B, dt};
+        KernelTimer kt(c, 3, s);
+        hipLaunchKernelGGL((k_update<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+    }
+    static int rhs(nskr_ctx *c, const void *U, void *Ut, hipStream_t s)
+    {
+        prolong(c, (const T *)U, s);
+        lift1(c, (const T *)U, s);
+        lift2(c, (const T *)U, s);
+        update(c, (T *)U, nullptr, (T *)Ut, 0, 0, 0, 0, 0, s);
+        HIPCHK(c, hipGetLastError());
+        return NSKR_OK;
+    }
+    static int rk(nskr_ctx *c, void *Uv, void *Rv, double dt, int nsteps, hipStream_t s)
+    {
+        T *U = (T *)Uv, *R = (T *)Rv;
+        if (nsteps == 0) return NSKR_OK;
+        prolong(c, U, s);
+        for (int n = 0; n < nsteps; ++n)
+            for (int st = 0; st < 5; ++st) {
+                lift1(c, U, s);
+                lift2(c, U, s);
+                update(c, U, R, nullptr, 1, st == 0, kRkA[st], kRkB[st], dt, s);
+            }
+        HIPCHK(c, hipGetLastError());
+        return NSKR_OK;
+    }
+    static int lift1_out(nskr_ctx *c, const void *U, void *q, hipStream_t s)
+    {
+        prolong(c, (const T *)U, s);
+        lift1(c, (const T *)U, s);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(q, c->d_Q, sizeof(T) * 15 * c->NN, hipMemcpyDeviceToDevice, s));
+        return NSKR_OK;
+    }
+    static int lift2_out(nskr_ctx *c, const void *U, void *o, hipStream_t s)
+    {
+        prolong(c, (const T *)U, s);
+        lift1(c, (const T *)U, s);
+        lift2(c, (const T *)U, s);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(o, c->d_TH, sizeof(T) * c->NN, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync((T *)o + c->NN, c->d_G2, sizeof(T) * 4 * c->NN, hipMemcpyDeviceToDevice, s));
+        return NSKR_OK;
+    }
+    static int dt(nskr_ctx *c, const void *U, double *out3, hipStream_t s)
+    {
+        prolong(c, (const T *)U, s);
+        lift1(c, (const T *)U, s);
+        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk(c)};
+        hipLaunchKernelGGL((k_dt_rates<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, (const T *)U,
+                           (const T *)c->d_Q, a);
+        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk(c), 3, c->d_out);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(out3, c->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return NSKR_OK;
+    }
+    static int reduce(nskr_ctx *c, const void *U, double *out, hipStream_t s)
+    {
+        prolong(c, (const T *)U, s);
+        lift1(c, (const T *)U, s);
+        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk(c)};
+        hipLaunchKernelGGL((k_integrals<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, (const T *)U,
+                           (const T *)c->d_Q, a, c->bas);
+        hipLaunchKernelGGL(k_integrals_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk(c),
+                           c->d_out);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(out, c->d_out, NSKR_NSUMS * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return NSKR_OK;
+    }
+    static int init(nskr_ctx *c, const InitArgs &ia, double T0, void *Uv, hipStream_t s)
+    {
+        T *U = (T *)Uv;
+        hipLaunchKernelGGL((k_init_rho<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, U, ia);
+        prolong(c, U, s);
+        lift1(c, U, s);
+        hipLaunchKernelGGL((k_init_energy<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, U, (const T *)c->d_Q, c->E,
+                           c->NN, c->ph, T0);
+        HIPCHK(c, hipGetLastError());
+        return NSKR_OK;
+    }
+};
+
+template <typename F> static int dispatch(const nskr_ctx *c, F &&f)
+{
+    const bool dbl = c->p.precision == 0;
+    switch (c->N) {
+    case 2: return dbl ? f(Impl<3, double>()) : f(Impl<3, float>());
+    case 3: return dbl ? f(Impl<4, double>()) : f(Impl<4, float>());
+    case 4: return dbl ? f(Impl<5, double>()) : f(Impl<5, float>());
+    case 5: return dbl ? f(Impl<6, double>()) : f(Impl<6, float>());
+    }
+    return NSKR_E_ARG;
+}
+
+static int elem_per_block(int N)
+{
+    const int n3 = (N + 1) * (N + 1) * (N + 1);
+    return kBlock / n3;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+int nskr_version(void) { return NSKR_ABI_VERSION; }
+
+int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
+{
+    if (!out || !p) return NSKR_E_ARG;
+    *out = nullptr;
+    if (N < 2 || N > 5) return NSKR_E_ARG;
+    if (!(p->mu >= 0) || !(p->kappa >= 0) || !(p->gam >= 0) || !(p->alpha >= 0) || !(p->beta >= 0) ||
+        !(p->b >= 0) || !(p->cv > 0) || !(p->R > 0) || !(p->cfl > 0) || !(p->a >= 0))
+        return NSKR_E_ARG;
+    if (p->precision != 0 && p->precision != 1) return NSKR_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NSKR_E_HIP;
+    // make sure the device code for this GPU is present
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(&k_update<4, double>)) != hipSuccess)
+        return NSKR_E_HIP;
+    nskr_ctx *c = new nskr_ctx();
+    c->p = *p;
+    c->N = N;
+    c->P = N + 1;
+    c->device = device;
+    make_basis(N, c->bas);
+    c->ph.R = p->R; c->ph.a = p->a; c->ph.b = p->b; c->ph.cv = p->cv; c->ph.mu = p->mu;
+    c->ph.kappa = p->kappa; c->ph.gam = p->gam; c->ph.alpha = p->alpha; c->ph.beta = p->beta;
+    c->ph.inv_Rcv = 1.0 / (p->R * p->cv);
+    c->ph.cs_fac = (1.0 + 1.0 / p->cv) * p->R;
+    *out = c;
+    return NSKR_OK;
+}
+
+static void free_mesh(nskr_ctx *c)
+{
+    void *ptrs[] = {c->d_nbr, c->d_bcid, c->d_emet, c->d_fmet, c->d_egeo, c->d_bcs, c->d_Q, c->d_TH,
+                    c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    c->d_nbr = c->d_bcid = nullptr;
+    c->d_emet = c->d_fmet = c->d_egeo = nullptr;
+    c->d_bcs = nullptr;
+    c->d_Q = c->d_TH = c->d_G2 = c->d_T2 = c->d_TF = c->d_TU = nullptr;
+    c->d_part = c->d_out = c->d_noise = c->d_drop = nullptr;
+    c->E = 0;
+    c->NN = c->NF = 0;
+    c->bytes = 0;
+}
+
+int nskr_destroy(nskr_ctx *c)
+{
+    if (!c) return NSKR_OK;
+    {
+        DeviceGuard g(c->device);
+        free_mesh(c);
+        for (auto &pe : c->prof_events) {
+            (void)hipEventDestroy(pe.second.first);
+            (void)hipEventDestroy(pe.second.second);
+        }
+        for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    }
+    delete c;
+    return NSKR_OK;
+}
+
+static int dalloc(nskr_ctx *c, void **p, size_t bytes)
+{
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return fail(c, NSKR_E_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    c->bytes += bytes;
+    return NSKR_OK;
+}
+
+int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
+{
+    if (!c) return NSKR_E_ARG;
+    if (c->poisoned) return fail(c, NSKR_E_STATE, "context poisoned by an earlier HIP error");
+    if (!m || m->nelems <= 0 || !m->corners || !m->nbr || !m->nbr_face || !m->bc)
+        return fail(c, NSKR_E_ARG, "mesh arrays missing or nelems <= 0");
+    if (m->nbcs < 0 || (m->nbcs > 0 && !m->bcs)) return fail(c, NSKR_E_ARG, "bad wall table");
+    const int E = m->nelems;
+    // validate connectivity
+    for (int e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int nb = m->nbr[e * 6 + f], bc = m->bc[e * 6 + f];
+            if (nb >= E || nb < -1) return fail(c, NSKR_E_ARG, "neighbour index out of range");
+            if (nb >= 0) {
+                if (m->nbr_face[e * 6 + f] != (f ^ 1))
+                    return fail(c, NSKR_E_UNSUPPORTED, "only opposite-face connectivity with identical ordering");
+                if (m->nbr[nb * 6 + (f ^ 1)] != e) return fail(c, NSKR_E_ARG, "connectivity not reciprocal");
+                if (bc != 0) return fail(c, NSKR_E_ARG, "interior face with a wall index");
+            } else {
+                if (bc < 1 || bc > m->nbcs) return fail(c, NSKR_E_ARG, "wall face without a valid wall index");
+                const int kind = m->bcs[bc - 1].kind;
+                if (kind != 1 && kind != 2) return fail(c, NSKR_E_ARG, "wall kind must be 1 or 2");
+            }
+        }
+    // per-element affine metrics
+    std::vector<double> emet((size_t)E * 10), fmet((size_t)E * 24), egeo((size_t)E * 12);
+    for (int e = 0; e < E; ++e) {
+        const double *cr = m->corners + (size_t)e * 24;
+        double a[3][3];  // edge vectors a_d = x(v_d) - x(0), v_d = 1, 2, 4
+        const int vd[3] = {1, 2, 4};
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 3; ++k) a[d][k] = cr[3 * vd[d] + k] - cr[k];
+        double scale = 0;
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(a[d][k]));
+        for (int v = 0; v < 8; ++v) {
+            const int ii = v & 1, jj = (v >> 1) & 1, kk = (v >> 2) & 1;
+            for (int k = 0; k < 3; ++k) {
+                double x = cr[k] + ii * a[0][k] + jj * a[1][k] + kk * a[2][k];
+                if (fabs(x - cr[3 * v + k]) > 1e-12 * scale)
+                    return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " is not a parallelepiped");
+            }
+        }
+        // dx/dxi^d = a_d / 2; Ja^1 = (a_2 x a_3)/4, Ja^2 = (a_3 x a_1)/4, Ja^3 = (a_1 x a_2)/4
+        for (int d = 0; d < 3; ++d) {
+            const double *u = a[(d + 1) % 3], *w = a[(d + 2) % 3];
+            emet[(size_t)e * 10 + 3 * d + 0] = 0.25 * (u[1] * w[2] - u[2] * w[1]);
+            emet[(size_t)e * 10 + 3 * d + 1] = 0.25 * (u[2] * w[0] - u[0] * w[2]);
+            emet[(size_t)e * 10 + 3 * d + 2] = 0.25 * (u[0] * w[1] - u[1] * w[0]);
+        }
+        const double J = 0.125 * (a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                                  a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                                  a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]));
+        if (!(J > 0)) return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " has J <= 0");
+        emet[(size_t)e * 10 + 9] = J;
+        for (int d = 0; d < 3; ++d) {
+            const double *Ja = &emet[(size_t)e * 10 + 3 * d];
+            const double nrm = sqrt(Ja[0] * Ja[0] + Ja[1] * Ja[1] + Ja[2] * Ja[2]);
+            for (int s = 0; s < 2; ++s) {
+                double *fm = &fmet[((size_t)e * 6 + 2 * d + s) * 4];
+                const double sg = s ? 1.0 : -1.0;
+                for (int k = 0; k < 3; ++k) fm[k] = sg * Ja[k] / nrm;
+                fm[3] = nrm;
+            }
+        }
+        for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + k] = cr[k];
+        for (int d = 0; d < 3; ++d)
+            for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + 3 + 3 * d + k] = a[d][k];
+    }
+    // wall constants
+    std::vector<BcDev> bcs(m->nbcs > 0 ? m->nbcs : 1);
+    Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
+    for (int k = 0; k < m->nbcs; ++k) {
+        BcDev &b = bcs[k];
+        memset(&b, 0, sizeof(b));
+        b.kind = m->bcs[k].kind;
+        b.twall = m->bcs[k].twall;
+        if (b.kind == 1) {
+            ld rv, rl;
+            if (!(m->bcs[k].twall > 0) || !maxwell_host(vdw, (ld)m->bcs[k].twall, rv, rl))
+                return fail(c, NSKR_E_ARG, "wall temperature must be subcritical and positive");
+            ld sig = sigma_host(vdw, (ld)m->bcs[k].twall, (ld)c->p.gam, rv, rl);
+            ld d = rl - rv;
+            ld ct = cosl((ld)m->bcs[k].theta_deg * 3.14159265358979323846264338327950288L / 180);
+            b.rv = (double)rv;
+            b.rl = (double)rl;
+            // g = -(1/gamma) dpsi_Gamma/dc = -6 sigma cos(theta) / (gamma (rl - rv)^3) (c - rl)(c - rv)
+            b.gcoef = c->p.gam > 0 ? (double)(-6 * sig * ct / ((ld)c->p.gam * d * d * d)) : 0.0;
+        }
+    }
+    DeviceGuard guard(c->device);
+    hipStream_t s = (hipStream_t)sv;
+    free_mesh(c);
+    c->E = E;
+    const int n3 = c->P * c->P * c->P, n2 = c->P * c->P;
+    c->NN = (size_t)E * n3;
+    c->NF = (size_t)E * 6 * n2;
+    const size_t ts = c->p.precision == 0 ? sizeof(double) : sizeof(float);
+    const int nblk = (E + elem_per_block(c->N) - 1) / elem_per_block(c->N);
+    int rc = NSKR_OK;
+    if ((rc = dalloc(c, (void **)&c->d_nbr, sizeof(int) * E * 6)) ||
+        (rc = dalloc(c, (void **)&c->d_bcid, sizeof(int) * E * 6)) ||
+        (rc = dalloc(c, (void **)&c->d_emet, sizeof(double) * emet.size())) ||
+        (rc = dalloc(c, (void **)&c->d_fmet, sizeof(double) * fmet.size())) ||
+        (rc = dalloc(c, (void **)&c->d_egeo, sizeof(double) * egeo.size())) ||
+        (rc = dalloc(c, (void **)&c->d_bcs, sizeof(BcDev) * bcs.size())) ||
+        (rc = dalloc(c, &c->d_Q, ts * 15 * c->NN)) || (rc = dalloc(c, &c->d_TH, ts * c->NN)) ||
+        (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * 4 * c->NF)) ||
+        (rc = dalloc(c, &c->d_TF, ts * 13 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 5 * c->NF)) ||
+        (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
+        (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS))) {
+        free_mesh(c);
+        return rc;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_nbr, m->nbr, sizeof(int) * E * 6, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_bcid, m->bc, sizeof(int) * E * 6, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_emet, emet.data(), sizeof(double) * emet.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_fmet, fmet.data(), sizeof(double) * fmet.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_egeo, egeo.data(), sizeof(double) * egeo.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d_bcs, bcs.data(), sizeof(BcDev) * bcs.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->h_emet.swap(emet);
+    return NSKR_OK;
+}
+
+int nskr_state_size(const nskr_ctx *c, size_t *n)
+{
+    if (!c || !n) return NSKR_E_ARG;
+    if (c->E == 0) return NSKR_E_STATE;
+    *n = 6 * c->NN;
+    return NSKR_OK;
+}
+
+int nskr_device_bytes(const nskr_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return NSKR_E_ARG;
+    *bytes = c->bytes;
+    return NSKR_OK;
+}
+
+static int ready(nskr_ctx *c)
+{
+    if (!c) return NSKR_E_ARG;
+    if (c->poisoned) return fail(c, NSKR_E_STATE, "context poisoned by an earlier HIP error");
+    if (c->E == 0) return fail(c, NSKR_E_STATE, "no mesh uploaded");
+    return NSKR_OK;
+}
+
+int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, void *U, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!ic || !U || ic->ndrop < 0 || !(ic->width > 0) || (ic->ndrop > 0 && (!ic->centres || !ic->radii)))
+        return fail(c, NSKR_E_ARG, "bad initial condition");
+    for (int k = 0; k < 3; ++k)
+        if (ic->periodic[k] && !(ic->length[k] > 0)) return fail(c, NSKR_E_ARG, "periodic axis needs a length");
+    Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
+    ld rv, rl;
+    if (!(ic->T0 > 0) || !maxwell_host(vdw, (ld)ic->T0, rv, rl))
+        return fail(c, NSKR_E_ARG, "T0 must be positive and subcritical");
+    DeviceGuard guard(c->device);
+    hipStream_t s = (hipStream_t)sv;
+    if (c->d_drop) { (void)hipFree(c->d_drop); c->d_drop = nullptr; }
+    if (c->d_noise) { (void)hipFree(c->d_noise); c->d_noise = nullptr; }
+    std::vector<double> drop(4 * (size_t)(ic->ndrop > 0 ? ic->ndrop : 1), 0.0);
+    for (int j = 0; j < ic->ndrop; ++j) {
+        for (int k = 0; k < 3; ++k) drop[4 * j + k] = ic->centres[3 * j + k];
+        drop[4 * j + 3] = ic->radii[j];
+    }
+    if (hipMalloc((void **)&c->d_drop, sizeof(double) * drop.size()) != hipSuccess)
+        return fail(c, NSKR_E_NOMEM, "droplet table allocation failed");
+    HIPCHK(c, hipMemcpyAsync(c->d_drop, drop.data(), sizeof(double) * drop.size(), hipMemcpyHostToDevice, s));
+    if (noise) {
+        if (hipMalloc((void **)&c->d_noise, sizeof(double) * c->NN) != hipSuccess)
+            return fail(c, NSKR_E_NOMEM, "noise allocation failed");
+        HIPCHK(c, hipMemcpyAsync(c->d_noise, noise, sizeof(double) * c->NN, hipMemcpyHostToDevice, s));
+    }
+    InitArgs ia;
+    ia.mesh = Impl<4, double>::mesh(c);
+    ia.bas = c->bas;
+    ia.NN = c->NN;
+    ia.drop = c->d_drop;
+    ia.ndrop = ic->ndrop;
+    ia.width = ic->width;
+    ia.rv = (double)rv;
+    ia.rl = (double)rl;
+    for (int k = 0; k < 3; ++k) { ia.len[k] = ic->length[k]; ia.per[k] = ic->periodic[k]; }
+    ia.noise = c->d_noise;
+    rc = dispatch(c, [&](auto impl) { return decltype(impl)::init(c, ia, ic->T0, U, s); });
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(s));  // the host-side tables are freed on the next call
+    return NSKR_OK;
+}
+
+int nskr_rhs(nskr_ctx *c, const void *U, void *Ut, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !Ut || U == Ut) return fail(c, NSKR_E_ARG, "null or aliasing state buffers");
+    DeviceGuard guard(c->device);
+    return dispatch(c, [&](auto impl) { return decltype(impl)::rhs(c, U, Ut, (hipStream_t)sv); });
+}
+
+int nskr_lift1(nskr_ctx *c, const void *U, void *q, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !q || U == q) return fail(c, NSKR_E_ARG, "null or aliasing buffers");
+    DeviceGuard guard(c->device);
+    return dispatch(c, [&](auto impl) { return decltype(impl)::lift1_out(c, U, q, (hipStream_t)sv); });
+}
+
+int nskr_lift2(nskr_ctx *c, const void *U, void *o, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !o || U == o) return fail(c, NSKR_E_ARG, "null or aliasing buffers");
+    DeviceGuard guard(c->device);
+    return dispatch(c, [&](auto impl) { return decltype(impl)::lift2_out(c, U, o, (hipStream_t)sv); });
+}
+
+int nskr_dt(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !dt) return fail(c, NSKR_E_ARG, "null argument");
+    DeviceGuard guard(c->device);
+    double r[3];
+    rc = dispatch(c, [&](auto impl) { return decltype(impl)::dt(c, U, r, (hipStream_t)sv); });
+    if (rc) return rc;
+    if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !(r[0] > 0))
+        return fail(c, NSKR_E_NONFINITE, "non-finite wave speed or diffusivity");
+    const double dt_adv = c->p.cfl * kTN[c->N] * 2.0 / r[0];
+    const double den = c->p.alpha * c->p.beta + kRhoN[c->N] * r[2] * r[1];
+    const double dt_par = den > 0 ? c->p.cfl * kRkReal / den : INFINITY;
+    *dt = dt_adv < dt_par ? dt_adv : dt_par;
+    return NSKR_OK;
+}
+
+int nskr_rk_steps(nskr_ctx *c, void *U, void *R, double dt, int nsteps, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !R || U == R) return fail(c, NSKR_E_ARG, "null or aliasing state buffers");
+    if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, NSKR_E_ARG, "dt must be positive and finite");
+    DeviceGuard guard(c->device);
+    return dispatch(c, [&](auto impl) { return decltype(impl)::rk(c, U, R, dt, nsteps, (hipStream_t)sv); });
+}
+
+int nskr_reduce(nskr_ctx *c, const void *U, double *out, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !out) return fail(c, NSKR_E_ARG, "null argument");
+    DeviceGuard guard(c->device);
+    rc = dispatch(c, [&](auto impl) { return decltype(impl)::reduce(c, U, out, (hipStream_t)sv); });
+    if (rc) return rc;
+    if (out[NSKR_CNT_NONFINITE] > 0 || out[NSKR_CNT_RHO_RANGE] > 0 || out[NSKR_CNT_T_NONPOS] > 0)
+        return fail(c, NSKR_E_NONFINITE, "non-finite or out-of-range state");
+    return NSKR_OK;
+}
+
+int nskr_set_profiling(nskr_ctx *c, int on)
+{
+    if (!c) return NSKR_E_ARG;
+    c->prof = on != 0;
+    return NSKR_OK;
+}
+
+int nskr_profile(nskr_ctx *c, double *ms, long *count, nskr_stream sv)
+{
+    if (!c || !ms || !count) return NSKR_E_ARG;
+    DeviceGuard guard(c->device);
+    for (int k = 0; k < NSKR_NKINDS; ++k) { ms[k] = 0.0; count[k] = 0; }
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)sv));
+    for (auto &pe : c->prof_events) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventSynchronize(pe.second.second));
+        HIPCHK(c, hipEventElapsedTime(&t, pe.second.first, pe.second.second));
+        ms[pe.first] += t;
+        count[pe.first] += 1;
+        c->event_pool.push_back(pe.second.first);
+        c->event_pool.push_back(pe.second.second);
+    }
+    c->prof_events.clear();
+    return NSKR_OK;
+}
+
+const char *nskr_last_error(const nskr_ctx *c)
+{
+    if (!c) return g_null_msg;
+    return c->err.c_str();
+}
+
+}  // extern "C"

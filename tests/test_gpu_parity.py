@@ -1,0 +1,305 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 CPU oracle.
+
+Bar: per conserved field, max |gpu - oracle| / max(|oracle|_inf, s_f) <= 1e-12,
+with s_f = |rho|_inf |c~|_inf for the momenta of a state (they start at zero)
+and s_f = 0 otherwise.  Inputs are the same seeded workloads on both sides;
+the oracle computes its own initial state, the GPU computes its own too (the
+initial-state test compares them), and the operator tests start both sides
+from the oracle's state.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from helpers import oracle_for, oracle_init
+from paper_2208_05310_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def gpu_solver(w, precision="fp64"):
+    from paper_2208_05310_amd.nskr import solver_for
+    return solver_for(w, precision)
+
+
+def to_gpu(torch, a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda:0")
+
+
+def rel_err(g, o, floor=None):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    out = []
+    for f in range(o.shape[0]):
+        scale = np.max(np.abs(o[f]))
+        if floor is not None:
+            scale = max(scale, floor[f])
+        out.append(np.max(np.abs(g[f] - o[f])) / scale if scale > 0 else np.max(np.abs(g[f])))
+    return np.array(out)
+
+
+def grouped_err(g, o, groups):
+    """Max error of each field relative to the max-norm of its group (the three
+    components of a gradient or of a vector are normalised together)."""
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    out = np.zeros(o.shape[0])
+    for grp in groups:
+        scale = max(np.max(np.abs(o[f])) for f in grp)
+        for f in grp:
+            out[f] = np.max(np.abs(g[f] - o[f])) / scale
+    return out
+
+
+def rhs_term_scale(o, U, params):
+    """Per-field scale of the largest term entering U_t.  The momentum source
+    alpha rho (grad c - grad rho) is a difference of two terms of size
+    alpha |rho| |grad rho| (about 2500 for these droplets against |U_t| ~ 20), so
+    the round-off of U_t for momentum and energy is set by that term, not by
+    the result."""
+    q = o.lift1(U)
+    sm = params["alpha"] * np.max(np.abs(U[0])) * np.max(np.abs(q[0:3]))
+    umax = np.max(np.abs(U[1:4] / U[0]))
+    Ut = o.rhs(U)
+    sc = np.max(np.abs(Ut), axis=1)
+    sc[1:4] = max(sm, np.max(sc[1:4]))
+    sc[4] = max(sc[4], sm * umax)
+    return sc, Ut
+
+
+def state_floor(o_state, params):
+    rho = o_state[0]
+    T = 0.9
+    cs = math.sqrt(abs((1 + 1 / params["cv"]) * params["R"] * T / (1 - params["b"] * rho.max()) ** 2))
+    s = np.max(np.abs(rho)) * cs
+    return [0.0, s, s, s, 0.0, 0.0]
+
+
+def small_cases():
+    base = wl.c1()
+    return [
+        base,                                                            # C1: 4^3, N=3
+        base.with_(name="ragged_3x3x3_N2", N=2, n=(3, 3, 3)),            # 27 elems, 9 per block
+        base.with_(name="ragged_3x3x3_N3", N=3, n=(3, 3, 3)),            # 27 elems, 4 per block
+        base.with_(name="ragged_3x3x3_N4", N=4, n=(3, 3, 3)),            # 27 elems, 2 per block
+        base.with_(name="ragged_2x2x3_N5", N=5, n=(2, 2, 3), length=(1.0, 1.0, 1.5)),
+        wl.c4(scale=8).with_(name="wall_6x6x3_N3"),                      # no-slip CA + slip walls
+        wl.c4(scale=8).with_(name="wall_6x6x3_N4_theta120", N=4,
+                             side_theta=(90.0, 90.0, 90.0, 90.0, 120.0, 90.0)),
+        wl.c4(scale=12).with_(name="wall_4x4x2_N2_hot", N=2, T0=0.8),
+    ]
+
+
+CASES = small_cases()
+IDS = [w.name for w in CASES]
+
+
+def perturbed_state(o, w, seed=7):
+    """Droplet state plus a smooth velocity field, so every flux term is active."""
+    U = oracle_init(o, w)
+    x, y, z = o.coords()
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0, 2 * np.pi, 3)
+    u = np.stack([0.05 * np.sin(2 * np.pi * y + ph[0]), 0.04 * np.cos(2 * np.pi * x + ph[1]),
+                  0.03 * np.sin(2 * np.pi * x + ph[2]) * (z if not w.periodic[2] else 1.0)])
+    if not w.periodic[2]:
+        u[2] *= z * (w.length[2] - z)  # no normal flow through the walls
+    U[1:4] = U[0] * u
+    U[4] += 0.5 * U[0] * np.sum(u * u, axis=0)
+    # non-uniform temperature (about +-0.02) and c != rho, so that grad T and the
+    # relaxation sources are not round-off
+    pr = w.params
+    U[4] += U[0] * pr["R"] * pr["cv"] * 0.02 * np.sin(2 * np.pi * (x + 2 * z) + ph[1])
+    U[5] = U[0] + 0.01 * np.sin(2 * np.pi * (x + y) + ph[2])
+    return U
+
+
+@pytest.mark.parametrize("w", CASES, ids=IDS)
+def test_lift1_parity(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] lift1 {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    q = torch.empty((15, s.nnodes), dtype=torch.float64, device="cuda:0")
+    s.lift1(to_gpu(torch, U), q)
+    torch.cuda.synchronize()
+    # gradients are compared as tensors: each component relative to the largest
+    # component of the same variable's gradient (some components vanish exactly)
+    err = grouped_err(q.cpu().numpy(), o.lift1(U), [[3 * k, 3 * k + 1, 3 * k + 2] for k in range(5)])
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("w", CASES, ids=IDS)
+def test_lift2_parity(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] lift2 {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    out = torch.empty((5, s.nnodes), dtype=torch.float64, device="cuda:0")
+    s.lift2(to_gpu(torch, U), out)
+    torch.cuda.synchronize()
+    err = grouped_err(out.cpu().numpy(), o.lift2(U), [[0], [1, 2, 3], [4]])
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("w", CASES, ids=IDS)
+def test_rhs_parity(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] rhs {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    Ut = s.new_state()
+    s.rhs(to_gpu(torch, U), Ut)
+    torch.cuda.synchronize()
+    scale, Uto = rhs_term_scale(o, U, w.params)
+    err = np.max(np.abs(Ut.cpu().numpy() - Uto), axis=1) / scale
+    print("rhs errors per field (term scale)", err, flush=True)
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("w", CASES, ids=IDS)
+def test_init_parity(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] init {w.name}", flush=True)
+    o = oracle_for(w)
+    Uo = oracle_init(o, w)
+    s = gpu_solver(w)
+    from paper_2208_05310_amd.nskr import init_workload
+    Ug = init_workload(s, w)
+    torch.cuda.synchronize()
+    err = rel_err(Ug.cpu().numpy(), Uo)
+    assert np.all(err[[0, 4, 5]] <= TOL), err
+    assert np.all(Ug[1:4].abs().max().item() == 0.0)
+
+
+@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[3]], ids=[IDS[0], IDS[5], IDS[3]])
+def test_dt_parity(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] dt {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    dg = s.dt(to_gpu(torch, U))
+    do = o.dt(U)
+    assert abs(dg - do) <= 1e-14 * do, (dg, do)
+
+
+@pytest.mark.parametrize("w", [CASES[0], CASES[5]], ids=[IDS[0], IDS[5]])
+def test_reduce_parity(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] reduce {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    rg = s.reduce(to_gpu(torch, U))
+    ro = o.reduce(U)
+    scale = np.maximum(np.abs(ro), 1e-300)
+    # sums: relative 1e-13 (different summation order); extrema and counters: exact-ish
+    for k in range(20):
+        if k in (1, 2, 3):
+            assert abs(rg[k] - ro[k]) <= 1e-13 * max(abs(ro[0]), 1.0), (k, rg[k], ro[k])
+        else:
+            assert abs(rg[k] - ro[k]) <= 1e-13 * scale[k] + 1e-300, (k, rg[k], ro[k])
+
+
+@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[4]], ids=[IDS[0], IDS[5], IDS[4]])
+def test_rk_steps_parity(torch_cuda, w):
+    """Fixed number of RK steps with the oracle's step-0 dt on both sides."""
+    torch = torch_cuda
+    nsteps = 20 if w.name.startswith("droplet") else 10
+    print(f"[case] rk {w.name} steps={nsteps}", flush=True)
+    o = oracle_for(w)
+    U = oracle_init(o, w)
+    dt = o.dt(U)
+    s = gpu_solver(w)
+    Ug = to_gpu(torch, U)
+    Rg = s.new_state()
+    s.rk_steps(Ug, Rg, dt, nsteps)
+    torch.cuda.synchronize()
+    R = np.zeros_like(U)
+    o.run(U, R, 0.0, dt, nsteps)
+    err = rel_err(Ug.cpu().numpy(), U, state_floor(U, w.params))
+    print("errors per field", err, flush=True)
+    assert np.all(err <= TOL), err
+
+
+def test_rk_split_equals_joined(torch_cuda):
+    """10 + 10 steps equal 20 steps bit for bit (the register is re-assigned at
+    stage 1, and traces are rebuilt at the start of each call)."""
+    torch = torch_cuda
+    w = CASES[0]
+    s = gpu_solver(w)
+    from paper_2208_05310_amd.nskr import init_workload
+    U1 = init_workload(s, w)
+    U2 = U1.clone()
+    R1, R2 = s.new_state(), s.new_state()
+    dt = s.dt(U1)
+    s.rk_steps(U1, R1, dt, 20)
+    s.rk_steps(U2, R2, dt, 10)
+    R2.fill_(float("nan"))
+    s.rk_steps(U2, R2, dt, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+
+
+def test_full_size_bench_workload_parity(torch_cuda):
+    """The benchmark workload at full size (16^3 elements, N = 4, 512000 nodes),
+    same kernels and launch configuration as bench.py: GPU initial state and two
+    RK steps against the oracle's."""
+    torch = torch_cuda
+    w = wl.c2()
+    print(f"[case] full-size {w.name}", flush=True)
+    from paper_2208_05310_amd.nskr import init_workload
+    s = gpu_solver(w)
+    Ug = init_workload(s, w)
+    dt = s.dt(Ug)
+    Rg = s.new_state()
+    o = oracle_for(w)
+    Uo = oracle_init(o, w)
+    dto = o.dt(Uo)
+    assert abs(dt - dto) <= 1e-14 * dto
+    err0 = rel_err(Ug.cpu().numpy(), Uo)
+    assert np.all(err0[[0, 4, 5]] <= TOL), err0
+    s.rk_steps(Ug, Rg, dto, 2)
+    torch.cuda.synchronize()
+    Ro = np.zeros_like(Uo)
+    o.run(Uo, Ro, 0.0, dto, 2)
+    err = rel_err(Ug.cpu().numpy(), Uo, state_floor(Uo, w.params))
+    print("errors per field", err, flush=True)
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("w", [CASES[0], CASES[5]], ids=[IDS[0], IDS[5]])
+def test_fp32_mixed_accuracy(torch_cuda, w):
+    """FP32-mixed form (FP32 state and bulk arithmetic, FP64 temperature/EoS,
+    dt and integrals) against the FP64 oracle after 20 steps: relative density
+    error (max-norm) at most 1e-5."""
+    torch = torch_cuda
+    print(f"[case] fp32-mixed {w.name}", flush=True)
+    o = oracle_for(w)
+    U = oracle_init(o, w)
+    dt = o.dt(U)
+    s = gpu_solver(w, "fp32_mixed")
+    Ug = to_gpu(torch, U, torch.float32)
+    Rg = s.new_state()
+    s.rk_steps(Ug, Rg, dt, 20)
+    torch.cuda.synchronize()
+    R = np.zeros_like(U)
+    o.run(U, R, 0.0, dt, 20)
+    err = rel_err(Ug.double().cpu().numpy(), U, state_floor(U, w.params))
+    print("fp32-mixed errors per field", err, flush=True)
+    assert err[0] <= 1e-5, err
+    assert np.all(err <= 1e-4), err
