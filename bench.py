@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
@@ -90,6 +92,13 @@ def main():
     from paper_2208_05310_amd import workloads as wl
     from paper_2208_05310_amd.nskr import init_workload, solver_for
 
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4}[args.workload]()
     s = solver_for(w, args.precision)
     U = init_workload(s, w)
