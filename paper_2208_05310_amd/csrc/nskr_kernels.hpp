@@ -98,6 +98,7 @@ __device__ __forceinline__ void eos(const Phys &ph, double rho, double T, double
 // Local state at a point for the flux evaluation.
 template <typename T> struct Pt {
     T rho, m[3], E, c;    // conserved
+    T ir;                 // 1 / rho
     T p;                  // pressure
     T gu[3][3];           // gu[j][i] = d u_j / d x_i
     T gT[3], gc[3], lapc; // grad T, grad c, lap c
@@ -111,7 +112,7 @@ template <typename T> struct Pt {
 template <typename T>
 __device__ __forceinline__ void flux_dot(const Phys &ph, const Pt<T> &s, const T v[3], T out[6])
 {
-    const T ir = T(1) / s.rho;
+    const T ir = s.ir;
     const T u0 = s.m[0] * ir, u1 = s.m[1] * ir, u2 = s.m[2] * ir;
     const T mv = s.m[0] * v[0] + s.m[1] * v[1] + s.m[2] * v[2];
     const T uv = mv * ir;
@@ -146,7 +147,7 @@ __device__ __forceinline__ void flux_dot(const Phys &ph, const Pt<T> &s, const T
 template <typename T>
 __device__ __forceinline__ void source(const Phys &ph, const Pt<T> &s, const T grho[3], T S[6])
 {
-    const T ir = T(1) / s.rho;
+    const T ir = s.ir;
     const T u[3] = {s.m[0] * ir, s.m[1] * ir, s.m[2] * ir};
     const T div = s.gu[0][0] + s.gu[1][1] + s.gu[2][2];
     const T al = T(ph.alpha);
@@ -184,7 +185,7 @@ template <typename T>
 __device__ __forceinline__ void wall_flux(const Phys &ph, const BcDev &bc, const Pt<T> &s, double T_face,
                                           const T n[3], T out[6])
 {
-    const T ir = T(1) / s.rho;
+    const T ir = s.ir;
     const T mn = s.m[0] * n[0] + s.m[1] * n[1] + s.m[2] * n[2];
     const T un = mn * ir;
     double pd, cs2;
@@ -253,31 +254,39 @@ __device__ __forceinline__ void load_basis(const Basis &b, double *sDh, double *
     }
 }
 
-// Face point task -> (local element, face, face point, neighbour-side info).
-template <int P> struct FaceTask {
-    int le, f, fp, d, s, p, q;
-    __device__ __forceinline__ FaceTask(int task)
+// Line task: the line of P nodes through face point (p,q) along direction d
+// of local element le; it carries the two face points of faces 2d (xi^d = -1)
+// and 2d+1 (+1), so each LDS value of the line is read once for both faces.
+template <int P> struct LineTask {
+    int le, d, fp, p, q;
+    __device__ __forceinline__ LineTask(int task)
     {
-        le = task / (6 * P * P);
-        int r = task - le * 6 * P * P;
-        f = r / (P * P);
-        fp = r - f * P * P;
-        d = f >> 1;
-        s = f & 1;
+        le = task / (3 * P * P);
+        const int r = task - le * 3 * P * P;
+        d = r / (P * P);
+        fp = r - d * P * P;
         p = fp % P;
         q = fp / P;
     }
 };
 
-// Prolongation of an LDS field of one element to a face point.
+// Prolongation of one LDS field of an element to both faces of a line.
 template <int P, typename T>
-__device__ __forceinline__ T prolong(const T *s, int base, const double *sL, const FaceTask<P> &ft)
+__device__ __forceinline__ void prolong2(const T *s, int base, const double *sL, const LineTask<P> &lt, T &vm,
+                                         T &vp)
 {
-    T acc = T(0);
+    T am = T(0), ap = T(0);
 #pragma unroll
-    for (int l = 0; l < P; ++l) acc += T(sL[ft.s * P + l]) * s[base + line_node<P>(ft.d, l, ft.p, ft.q)];
-    return acc;
+    for (int l = 0; l < P; ++l) {
+        const T v = s[base + line_node<P>(lt.d, l, lt.p, lt.q)];
+        am += T(sL[l]) * v;
+        ap += T(sL[P + l]) * v;
+    }
+    vm = am;
+    vp = ap;
 }
+
+template <int P> __device__ __forceinline__ constexpr int n_lines() { return Tile<P>::EPB * 3 * P * P; }
 
 // ------------------------------------------------------------ k_prolong
 // Primitive face traces (rho, u, v, w, c) of the state, from the prolonged
@@ -293,27 +302,31 @@ __global__ __launch_bounds__(kBlock) void k_prolong(ProlongArgs<T> a)
     const int E = a.mesh.E;
     const int t = threadIdx.x;
     if (t < G::NV && e0 + t / G::n3 < E) {
-        size_t g = (size_t)e0 * G::n3 + t;
+        const size_t g = (size_t)e0 * G::n3 + t;
 #pragma unroll
         for (int v = 0; v < 6; ++v) sU[v][t] = a.U[v * a.NN + g];
     }
     __syncthreads();
     const size_t NF = (size_t)E * 6 * G::n2;
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int e = e0 + ft.le;
+    for (int task = t; task < n_lines<P>(); task += kBlock) {
+        LineTask<P> lt(task);
+        const int e = e0 + lt.le;
         if (e >= E) continue;
-        const int base = ft.le * G::n3;
-        T u6[6];
+        const int base = lt.le * G::n3;
+        T um[6], up[6];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) u6[v] = prolong<P>(sU[v], base, sL, ft);
-        const size_t o = ((size_t)e * 6 + ft.f) * G::n2 + ft.fp;
-        const T ir = T(1) / u6[0];
-        a.TU[0 * NF + o] = u6[0];
-        a.TU[1 * NF + o] = u6[1] * ir;
-        a.TU[2 * NF + o] = u6[2] * ir;
-        a.TU[3 * NF + o] = u6[3] * ir;
-        a.TU[4 * NF + o] = u6[5];
+        for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, um[v], up[v]);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const T *u6 = s ? up : um;
+            const size_t o = ((size_t)e * 6 + 2 * lt.d + s) * G::n2 + lt.fp;
+            const T ir = T(1) / u6[0];
+            a.TU[0 * NF + o] = u6[0];
+            a.TU[1 * NF + o] = u6[1] * ir;
+            a.TU[2 * NF + o] = u6[2] * ir;
+            a.TU[3 * NF + o] = u6[3] * ir;
+            a.TU[4 * NF + o] = u6[5];
+        }
     }
 }
 
@@ -322,6 +335,7 @@ template <int P, typename T>
 __global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
 {
     using G = Tile<P>;
+    static_assert(n_lines<P>() <= kBlock, "one line per thread");
     __shared__ T sU[6][G::NV];
     __shared__ T sW[5][G::NV];
     __shared__ T sS[5][G::NF];
@@ -334,6 +348,27 @@ __global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
     const int e = e0 + le;
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
+    const size_t NF = (size_t)E * 6 * G::n2;
+
+    // early loads: own nodes, and the neighbour traces of this thread's line
+    const LineTask<P> lt(t);
+    const int el = e0 + lt.le;
+    const bool lact = t < n_lines<P>() && el < E;
+    int nbm = -1, nbp = -1;
+    T wn[2][5];
+    if (lact) {
+        nbm = a.mesh.nbr[el * 6 + 2 * lt.d];
+        nbp = a.mesh.nbr[el * 6 + 2 * lt.d + 1];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int nb = s ? nbp : nbm;
+            if (nb >= 0) {
+                const size_t o = ((size_t)nb * 6 + (2 * lt.d + 1 - s)) * G::n2 + lt.fp;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) wn[s][k] = a.TU[k * NF + o];
+            }
+        }
+    }
     if (act) {
         T u6[6];
 #pragma unroll
@@ -346,38 +381,38 @@ __global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
         sW[4][t] = u6[5];
     }
     __syncthreads();
-    // face values w* of the BR1 lifting
-    const size_t NF = (size_t)E * 6 * G::n2;
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int ef = e0 + ft.le;
-        if (ef >= E) continue;
-        const int base = ft.le * G::n3;
-        T u6[6];
+    // face values w* of the BR1 lifting on both faces of the line
+    if (lact) {
+        T uf[2][6];
+        const int base = lt.le * G::n3;
 #pragma unroll
-        for (int v = 0; v < 6; ++v) u6[v] = prolong<P>(sU[v], base, sL, ft);
-        const T ir = T(1) / u6[0];
-        T w[5] = {u6[0], u6[1] * ir, u6[2] * ir, u6[3] * ir, u6[5]};
-        const int nb = a.mesh.nbr[ef * 6 + ft.f];
-        if (nb >= 0) {
-            const size_t o = ((size_t)nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
+        for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + a.TU[k * NF + o]);
-        } else {
-            const BcDev bc = a.mesh.bcs[a.mesh.bcid[ef * 6 + ft.f] - 1];
-            if (bc.kind == 1) {
-                w[1] = w[2] = w[3] = T(0);
+        for (int s = 0; s < 2; ++s) {
+            const int f = 2 * lt.d + s;
+            const T ir = T(1) / uf[s][0];
+            T w[5] = {uf[s][0], uf[s][1] * ir, uf[s][2] * ir, uf[s][3] * ir, uf[s][5]};
+            const int nb = s ? nbp : nbm;
+            if (nb >= 0) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + wn[s][k]);
             } else {
-                const double *fm = a.mesh.fmet + ((size_t)ef * 6 + ft.f) * 4;
-                const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
-                const T un = w[1] * n0 + w[2] * n1 + w[3] * n2;
-                w[1] -= un * n0;
-                w[2] -= un * n1;
-                w[3] -= un * n2;
+                const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                if (bc.kind == 1) {
+                    w[1] = w[2] = w[3] = T(0);
+                } else {
+                    const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
+                    const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+                    const T un = w[1] * n0 + w[2] * n1 + w[3] * n2;
+                    w[1] -= un * n0;
+                    w[2] -= un * n1;
+                    w[3] -= un * n2;
+                }
             }
-        }
+            const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) sS[k][task] = w[k];
+            for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
+        }
     }
     __syncthreads();
     // volume + surface: J q_m = sum_d Ja^d_m (Dhat w + lhat+ w*_+ - lhat- w*_-)
@@ -426,23 +461,24 @@ __global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
         sW[2][t] = qc[2];
     }
     __syncthreads();
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int ef = e0 + ft.le;
-        if (ef >= E) continue;
-        const int base = ft.le * G::n3;
-        T u6[6], q3[3];
+    if (lact) {
+        const int base = lt.le * G::n3;
+        T qf[2][3], uf[2][6];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) u6[v] = prolong<P>(sU[v], base, sL, ft);
+        for (int m = 0; m < 3; ++m) prolong2<P>(sW[m], base, sL, lt, qf[0][m], qf[1][m]);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) q3[m] = prolong<P>(sW[m], base, sL, ft);
-        const double Tf = temperature(a.ph, (double)u6[0], (double)u6[1], (double)u6[2], (double)u6[3],
-                                      (double)u6[4], (double)u6[5], (double)q3[0], (double)q3[1], (double)q3[2]);
-        const size_t o = ((size_t)ef * 6 + ft.f) * G::n2 + ft.fp;
-        a.T2[0 * NF + o] = q3[0];
-        a.T2[1 * NF + o] = q3[1];
-        a.T2[2 * NF + o] = q3[2];
-        a.T2[3 * NF + o] = T(Tf);
+        for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double Tf = temperature(a.ph, (double)uf[s][0], (double)uf[s][1], (double)uf[s][2], (double)uf[s][3],
+                                          (double)uf[s][4], (double)uf[s][5], (double)qf[s][0], (double)qf[s][1],
+                                          (double)qf[s][2]);
+            const size_t o = ((size_t)el * 6 + 2 * lt.d + s) * G::n2 + lt.fp;
+            a.T2[0 * NF + o] = qf[s][0];
+            a.T2[1 * NF + o] = qf[s][1];
+            a.T2[2 * NF + o] = qf[s][2];
+            a.T2[3 * NF + o] = T(Tf);
+        }
     }
 }
 
@@ -464,6 +500,29 @@ __global__ __launch_bounds__(kBlock) void k_lift2(Lift2Args<T> a)
     const int e = e0 + le;
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
+    const size_t NF = (size_t)E * 6 * G::n2;
+
+    // early loads: own and neighbour traces of grad c and T on this thread's line
+    const LineTask<P> lt(t);
+    const int el = e0 + lt.le;
+    const bool lact = t < n_lines<P>() && el < E;
+    int nb2[2] = {-1, -1};
+    T own[2][4], oth[2][4];
+    if (lact) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int f = 2 * lt.d + s;
+            const size_t o = ((size_t)el * 6 + f) * G::n2 + lt.fp;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) own[s][k] = a.T2[k * NF + o];
+            nb2[s] = a.mesh.nbr[el * 6 + f];
+            if (nb2[s] >= 0) {
+                const size_t on = ((size_t)nb2[s] * 6 + (f ^ 1)) * G::n2 + lt.fp;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) oth[s][k] = a.T2[k * NF + on];
+            }
+        }
+    }
     if (act) {
         sA[0][t] = a.TH[g];
 #pragma unroll
@@ -474,36 +533,35 @@ __global__ __launch_bounds__(kBlock) void k_lift2(Lift2Args<T> a)
         for (int r = 0; r < 9; ++r) sGu[r][t] = a.Q[(3 + r) * a.NN + g];
     }
     __syncthreads();
-    const size_t NF = (size_t)E * 6 * G::n2;
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int ef = e0 + ft.le;
-        if (ef >= E) continue;
-        const size_t o = ((size_t)ef * 6 + ft.f) * G::n2 + ft.fp;
-        const double *fm = a.mesh.fmet + ((size_t)ef * 6 + ft.f) * 4;
-        const T Tm = a.T2[3 * NF + o];
-        const int nb = a.mesh.nbr[ef * 6 + ft.f];
-        T Ts, Fs;
-        if (nb >= 0) {
-            const size_t on = ((size_t)nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
-            Ts = T(0.5) * (Tm + a.T2[3 * NF + on]);
-            T acc = T(0);
+    if (lact) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) acc += T(0.5) * (a.T2[m * NF + o] + a.T2[m * NF + on]) * T(fm[m] * fm[3]);
-            Fs = acc;
-        } else {
-            const BcDev bc = a.mesh.bcs[a.mesh.bcid[ef * 6 + ft.f] - 1];
-            if (bc.kind == 1) {
-                Ts = T(bc.twall);
-                const T c = prolong<P>(sU[5], ft.le * G::n3, sL, ft);
-                Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
+        for (int s = 0; s < 2; ++s) {
+            const int f = 2 * lt.d + s;
+            const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
+            T Ts, Fs;
+            if (nb2[s] >= 0) {
+                Ts = T(0.5) * (own[s][3] + oth[s][3]);
+                T acc = T(0);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) acc += T(0.5) * (own[s][m] + oth[s][m]) * T(fm[m] * fm[3]);
+                Fs = acc;
             } else {
-                Ts = Tm;
-                Fs = T(0);
+                const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                if (bc.kind == 1) {
+                    Ts = T(bc.twall);
+                    T cm, cp;
+                    prolong2<P>(sU[5], lt.le * G::n3, sL, lt, cm, cp);
+                    const T c = s ? cp : cm;
+                    Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
+                } else {
+                    Ts = own[s][3];
+                    Fs = T(0);
+                }
             }
+            const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
+            sTs[slot] = Ts;
+            sFs[slot] = Fs;
         }
-        sTs[task] = Ts;
-        sFs[task] = Fs;
     }
     __syncthreads();
     T gT[3] = {T(0), T(0), T(0)}, lap = T(0);
@@ -555,55 +613,122 @@ __global__ __launch_bounds__(kBlock) void k_lift2(Lift2Args<T> a)
         sA[3][t] = lap;
     }
     __syncthreads();
-    // own-face flux traces: G = (F^C - F^V).n, wave speed, state; walls: the
-    // complete wall flux in G.
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int ef = e0 + ft.le;
-        if (ef >= E) continue;
-        const int base = ft.le * G::n3;
-        const size_t o = ((size_t)ef * 6 + ft.f) * G::n2 + ft.fp;
-        const double *fm = a.mesh.fmet + ((size_t)ef * 6 + ft.f) * 4;
-        Pt<T> s;
-        s.rho = prolong<P>(sU[0], base, sL, ft);
-        s.m[0] = prolong<P>(sU[1], base, sL, ft);
-        s.m[1] = prolong<P>(sU[2], base, sL, ft);
-        s.m[2] = prolong<P>(sU[3], base, sL, ft);
-        s.E = prolong<P>(sU[4], base, sL, ft);
-        s.c = prolong<P>(sU[5], base, sL, ft);
+    // own-face flux traces on both faces of the line: G = (F^C - F^V).n, wave
+    // speed, state; on walls the complete wall flux in G.
+    if (lact) {
+        const int base = lt.le * G::n3;
+        // One face at a time, and each field group folded into the six flux
+        // components as soon as it is prolonged, so few values stay live.
+#pragma unroll 1
+        for (int s = 0; s < 2; ++s) {
+            const double *Lf = sL + s * P;
+            auto pro = [&](const T *fld) {
+                T acc = T(0);
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-            for (int ii = 0; ii < 3; ++ii) s.gu[jj][ii] = prolong<P>(sGu[3 * jj + ii], base, sL, ft);
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            s.gT[m] = prolong<P>(sA[m], base, sL, ft);
-            s.gc[m] = a.T2[m * NF + o];
+                for (int l = 0; l < P; ++l) acc += T(Lf[l]) * fld[base + line_node<P>(lt.d, l, lt.p, lt.q)];
+                return acc;
+            };
+            const int f = 2 * lt.d + s;
+            const size_t o = ((size_t)el * 6 + f) * G::n2 + lt.fp;
+            const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
+            const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+            const bool wall = nb2[s] < 0;
+            const int kind = wall ? a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind : 0;
+            // state and convective part
+            const T rho = pro(sU[0]), m0 = pro(sU[1]), m1 = pro(sU[2]), m2 = pro(sU[3]);
+            const T E = pro(sU[4]), c = pro(sU[5]);
+            const T ir = T(1) / rho;
+            const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
+            const T mn = m0 * n0 + m1 * n1 + m2 * n2;
+            const T un = mn * ir;
+            const double Tf = (double)a.T2[3 * NF + o];
+            double pd, cs2;
+            eos(a.ph, (double)rho, Tf, pd, cs2);
+            const T p = T(pd);
+            const T lam = fabs(un) + T(sqrt(fabs(cs2)));
+            T G0, G1, G2_, G3, G4, G5;
+            if (!wall) {
+                G0 = mn;
+                G1 = m0 * un + p * n0;
+                G2_ = m1 * un + p * n1;
+                G3 = m2 * un + p * n2;
+                G4 = (E + p) * un;
+                G5 = c * un;
+            } else if (kind == 1) {  // mirrored ghost, all velocity components
+                G0 = T(0);
+                G1 = m0 * un + p * n0 + lam * m0;
+                G2_ = m1 * un + p * n1 + lam * m1;
+                G3 = m2 * un + p * n2 + lam * m2;
+                G4 = T(0);
+                G5 = T(0);
+            } else {                 // mirrored normal velocity only
+                const T q = mn * un + p + lam * mn;
+                G0 = T(0);
+                G1 = q * n0;
+                G2_ = q * n1;
+                G3 = q * n2;
+                G4 = T(0);
+                G5 = T(0);
+            }
+            // viscous stress tau n = mu ((grad u + grad u^T) n - 2/3 div u n)
+            T div, tn0, tn1, tn2;
+            {
+                const T g00 = pro(sGu[0]), g01 = pro(sGu[1]), g02 = pro(sGu[2]);
+                const T g10 = pro(sGu[3]), g11 = pro(sGu[4]), g12 = pro(sGu[5]);
+                const T g20 = pro(sGu[6]), g21 = pro(sGu[7]), g22 = pro(sGu[8]);
+                div = g00 + g11 + g22;
+                const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
+                tn0 = mu * ((g00 + g00) * n0 + (g01 + g10) * n1 + (g02 + g20) * n2 - td * n0);
+                tn1 = mu * ((g10 + g01) * n0 + (g11 + g11) * n1 + (g12 + g21) * n2 - td * n1);
+                tn2 = mu * ((g20 + g02) * n0 + (g21 + g12) * n1 + (g22 + g22) * n2 - td * n2);
+            }
+            if (!wall) {
+                G1 -= tn0;
+                G2_ -= tn1;
+                G3 -= tn2;
+                G4 -= tn0 * u0 + tn1 * u1 + tn2 * u2;
+            } else if (kind == 1) {
+                G1 -= tn0;
+                G2_ -= tn1;
+                G3 -= tn2;
+            } else {
+                const T tnn = tn0 * n0 + tn1 * n1 + tn2 * n2;
+                G1 -= tnn * n0;
+                G2_ -= tnn * n1;
+                G3 -= tnn * n2;
+            }
+            // heat flux
+            if (kind != 2) {
+                const T gTn = pro(sA[0]) * n0 + pro(sA[1]) * n1 + pro(sA[2]) * n2;
+                G4 -= T(a.ph.kappa) * gTn;
+            }
+            // order-parameter terms of j_e and F^V_c
+            if (!wall) {
+                const T gcn = a.T2[0 * NF + o] * n0 + a.T2[1 * NF + o] * n1 + a.T2[2 * NF + o] * n2;
+                const T lapc = pro(sA[3]);
+                const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
+                G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;
+                G5 -= T(a.ph.gam * a.ph.beta) * gcn;
+                a.TF[6 * NF + o] = lam;
+                a.TF[7 * NF + o] = rho;
+                a.TF[8 * NF + o] = m0;
+                a.TF[9 * NF + o] = m1;
+                a.TF[10 * NF + o] = m2;
+                a.TF[11 * NF + o] = E;
+                a.TF[12 * NF + o] = c;
+            } else if (kind == 1) {
+                const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                const T g = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv));
+                G4 += T(a.ph.gam) * c * g * div;
+                G5 -= T(a.ph.gam * a.ph.beta) * g;
+            }
+            a.TF[0 * NF + o] = G0;
+            a.TF[1 * NF + o] = G1;
+            a.TF[2 * NF + o] = G2_;
+            a.TF[3 * NF + o] = G3;
+            a.TF[4 * NF + o] = G4;
+            a.TF[5 * NF + o] = G5;
         }
-        s.lapc = prolong<P>(sA[3], base, sL, ft);
-        const double Tf = (double)a.T2[3 * NF + o];
-        double pd, cs2;
-        eos(a.ph, (double)s.rho, Tf, pd, cs2);
-        s.p = T(pd);
-        const T n[3] = {T(fm[0]), T(fm[1]), T(fm[2])};
-        T out[6];
-        const int nb = a.mesh.nbr[ef * 6 + ft.f];
-        if (nb >= 0) {
-            flux_dot(a.ph, s, n, out);
-            const T un = (s.m[0] * n[0] + s.m[1] * n[1] + s.m[2] * n[2]) / s.rho;
-            a.TF[6 * NF + o] = fabs(un) + T(sqrt(fabs(cs2)));
-            a.TF[7 * NF + o] = s.rho;
-            a.TF[8 * NF + o] = s.m[0];
-            a.TF[9 * NF + o] = s.m[1];
-            a.TF[10 * NF + o] = s.m[2];
-            a.TF[11 * NF + o] = s.E;
-            a.TF[12 * NF + o] = s.c;
-        } else {
-            const BcDev bc = a.mesh.bcs[a.mesh.bcid[ef * 6 + ft.f] - 1];
-            wall_flux(a.ph, bc, s, Tf, n, out);
-        }
-#pragma unroll
-        for (int v = 0; v < 6; ++v) a.TF[v * NF + o] = out[v];
     }
 }
 
@@ -625,33 +750,10 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
     const size_t g = (size_t)e0 * G::n3 + t;
     const size_t NF = (size_t)E * 6 * G::n2;
 
-    // surface flux (F* . n) dS per face point
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int ef = e0 + ft.le;
-        if (ef >= E) continue;
-        const size_t o = ((size_t)ef * 6 + ft.f) * G::n2 + ft.fp;
-        const T dS = T(a.mesh.fmet[((size_t)ef * 6 + ft.f) * 4 + 3]);
-        const int nb = a.mesh.nbr[ef * 6 + ft.f];
-        if (nb >= 0) {
-            const size_t on = ((size_t)nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
-            const T lm = a.TF[6 * NF + o], lp = a.TF[6 * NF + on];
-            const T lam = lm > lp ? lm : lp;
-#pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                const T Fn = T(0.5) * (a.TF[v * NF + o] - a.TF[v * NF + on]) -
-                             T(0.5) * lam * (a.TF[(7 + v) * NF + on] - a.TF[(7 + v) * NF + o]);
-                sFs[v][task] = Fn * dS;
-            }
-        } else {
-#pragma unroll
-            for (int v = 0; v < 6; ++v) sFs[v][task] = a.TF[v * NF + o] * dS;
-        }
-    }
-
-    // point-wise fluxes and source
+    // node data first (consumed after the face fluxes), then the face loads
     Pt<T> s;
-    T S[6], Ft[3][6], Ja[9], iJ = T(0);
+    T grho[3];
+    double Tn = 0.0;
     if (act) {
         s.rho = a.U[0 * a.NN + g];
         s.m[0] = a.U[1 * a.NN + g];
@@ -659,7 +761,6 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
         s.m[2] = a.U[3 * a.NN + g];
         s.E = a.U[4 * a.NN + g];
         s.c = a.U[5 * a.NN + g];
-        T grho[3];
 #pragma unroll
         for (int m = 0; m < 3; ++m) grho[m] = a.Q[m * a.NN + g];
 #pragma unroll
@@ -672,26 +773,59 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
             s.gT[m] = a.G2[m * a.NN + g];
         }
         s.lapc = a.G2[3 * a.NN + g];
+        Tn = (double)a.TH[g];
+    }
+    // surface flux (F* . n) dS on both faces of this thread's line
+    const LineTask<P> lt(t);
+    const int el = e0 + lt.le;
+    if (t < n_lines<P>() && el < E) {
+#pragma unroll 1
+        for (int sd = 0; sd < 2; ++sd) {
+            const int f = 2 * lt.d + sd;
+            const size_t o = ((size_t)el * 6 + f) * G::n2 + lt.fp;
+            const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+            const int nb = a.mesh.nbr[el * 6 + f];
+            const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
+            if (nb >= 0) {
+                const size_t on = ((size_t)nb * 6 + (f ^ 1)) * G::n2 + lt.fp;
+                const T lm = a.TF[6 * NF + o], lp = a.TF[6 * NF + on];
+                const T lam = lm > lp ? lm : lp;
+#pragma unroll
+                for (int v = 0; v < 6; ++v) {
+                    const T Fn = T(0.5) * (a.TF[v * NF + o] - a.TF[v * NF + on]) -
+                                 T(0.5) * lam * (a.TF[(7 + v) * NF + on] - a.TF[(7 + v) * NF + o]);
+                    sFs[v][slot] = Fn * dS;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < 6; ++v) sFs[v][slot] = a.TF[v * NF + o] * dS;
+            }
+        }
+    }
+
+    // point-wise source; contravariant fluxes one direction at a time
+    T S[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, iJ = T(0);
+    if (act) {
         double pd, cs2;
-        eos(a.ph, (double)s.rho, (double)a.TH[g], pd, cs2);
+        eos(a.ph, (double)s.rho, Tn, pd, cs2);
         s.p = T(pd);
-        const double *em = a.mesh.emet + (size_t)e * 10;
-#pragma unroll
-        for (int r = 0; r < 9; ++r) Ja[r] = T(em[r]);
-        iJ = T(1.0 / em[9]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) flux_dot(a.ph, s, &Ja[3 * d], Ft[d]);
+        s.ir = T(1) / s.rho;
+        iJ = T(1.0 / a.mesh.emet[(size_t)e * 10 + 9]);
         source(a.ph, s, grho, S);
     }
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
     const int base = le * G::n3;
-#pragma unroll
+#pragma unroll 1
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
         if (act) {
+            const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
+            const T Jd[3] = {T(em[0]), T(em[1]), T(em[2])};
+            T Fd[6];
+            flux_dot(a.ph, s, Jd, Fd);
 #pragma unroll
-            for (int v = 0; v < 6; ++v) sF[v][t] = Ft[d][v];
+            for (int v = 0; v < 6; ++v) sF[v][t] = Fd[v];
         }
         __syncthreads();
         if (act) {
@@ -734,31 +868,33 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
     __syncthreads();
     if (act) {
         const T A = T(a.A), B = T(a.B), dt = T(a.dt);
+        T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            T r = a.first ? dt * Ut[v] : A * a.R[v * a.NN + g] + dt * Ut[v];
+            const T r = a.first ? dt * Ut[v] : A * a.R[v * a.NN + g] + dt * Ut[v];
             a.R[v * a.NN + g] = r;
-            T u = a.U[v * a.NN + g] + B * r;
+            const T u = u6[v] + B * r;
             a.U[v * a.NN + g] = u;
             sF[v][t] = u;
         }
     }
     __syncthreads();
-    for (int task = t; task < G::NF; task += kBlock) {
-        FaceTask<P> ft(task);
-        const int ef = e0 + ft.le;
-        if (ef >= E) continue;
-        const int b2 = ft.le * G::n3;
-        T u6[6];
+    if (t < n_lines<P>() && el < E) {
+        const int b2 = lt.le * G::n3;
+        T um[6], up[6];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) u6[v] = prolong<P>(sF[v], b2, sL, ft);
-        const size_t o = ((size_t)ef * 6 + ft.f) * G::n2 + ft.fp;
-        const T ir = T(1) / u6[0];
-        a.TU[0 * NF + o] = u6[0];
-        a.TU[1 * NF + o] = u6[1] * ir;
-        a.TU[2 * NF + o] = u6[2] * ir;
-        a.TU[3 * NF + o] = u6[3] * ir;
-        a.TU[4 * NF + o] = u6[5];
+        for (int v = 0; v < 6; ++v) prolong2<P>(sF[v], b2, sL, lt, um[v], up[v]);
+#pragma unroll
+        for (int sd = 0; sd < 2; ++sd) {
+            const T *u6 = sd ? up : um;
+            const size_t o = ((size_t)el * 6 + 2 * lt.d + sd) * G::n2 + lt.fp;
+            const T ir = T(1) / u6[0];
+            a.TU[0 * NF + o] = u6[0];
+            a.TU[1 * NF + o] = u6[1] * ir;
+            a.TU[2 * NF + o] = u6[2] * ir;
+            a.TU[3 * NF + o] = u6[3] * ir;
+            a.TU[4 * NF + o] = u6[5];
+        }
     }
 }
 
