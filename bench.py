@@ -70,6 +70,28 @@ def cpu_baseline(w, budget_s=15.0):
                       f"({o.nnodes} nodes), {el:.1f} s"}
 
 
+def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_active_nodes=4_000_000):
+    """Continuous batching of the seeded Poisson request stream (FP32-mixed,
+    graph-captured batched kernels, autotuned tiles) against the same requests
+    solved one at a time with the FP64 single-instance path."""
+    from paper_2208_05310_amd import autotune, serving
+    from paper_2208_05310_amd import workloads as wl
+    reqs = wl.serving_stream(seed=5, count=nreq, rate=50.0)
+    pairs = sorted({(w.N, "fp32_mixed") for _, w in reqs})
+    t0 = time.perf_counter()
+    table = autotune.tune(pairs, path=None)
+    t_tune = time.perf_counter() - t0
+    stats, _ = serving.serve(reqs, int(budget_gb * 2**30), "fp32_mixed", table, log=log,
+                             max_active_nodes=max_active_nodes)
+    out = {"batched_fp32_mixed": stats, "tiles": {k: v["threads"] for k, v in table.items()},
+           "autotune_s": t_tune, "budget_GiB": budget_gb}
+    if sequential:
+        seq, _ = serving.serve_sequential(reqs, "fp64")
+        out["one_at_a_time_fp64"] = seq
+        out["speedup_throughput"] = stats["node_stage_updates_per_s"] / seq["node_stage_updates_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,7 +100,12 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--serving", action="store_true", help="run only the request-stream serving measurement")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -92,6 +119,17 @@ def main():
     from paper_2208_05310_amd import workloads as wl
     from paper_2208_05310_amd.nskr import init_workload, solver_for
 
+    if args.serving:
+        res = serving_bench(args.serving_requests, log=lambda m: None, max_active_nodes=args.serving_max_nodes)
+        b, q = res["batched_fp32_mixed"], res.get("one_at_a_time_fp64")
+        print(json.dumps({"metric": "batched p50/p99 time-to-solution and aggregate node-stage updates/s",
+                          "value": b["node_stage_updates_per_s"], "unit": "node-stage updates/s",
+                          "p50_s": b["p50_s"], "p99_s": b["p99_s"], "n_gpus": 1, "higher_is_better": True,
+                          "data": "synthetic: seeded Poisson stream of droplet solves",
+                          "config": {"workload": f"serving_stream_{args.serving_requests}_requests_rate50"},
+                          "serving": res}), flush=True)
+        return
+
     if args.copy_calibration_mb > 0:
         n = args.copy_calibration_mb * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda:0")
@@ -100,41 +138,50 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4}[args.workload]()
-    s = solver_for(w, args.precision)
-    U = init_workload(s, w)
-    R = s.new_state()
-    dt = s.dt(U)
     stream = torch.cuda.current_stream()
-    s.rk_steps(U, R, dt, args.warmup, stream)
-    torch.cuda.synchronize()
 
-    # timed region: K steps, per-kernel HIP events recorded by the library on this stream
-    s.set_profiling(True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    s.rk_steps(U, R, dt, args.steps, stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = s.profile(stream)
-    s.set_profiling(False)
-    wall = t1 - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    def timed_run(precision, U0=None):
+        """Warm-up + K timed steps; returns throughput, per-kernel data, final state."""
+        s = solver_for(w, precision)
+        if U0 is None:
+            U = init_workload(s, w)
+        else:
+            U = U0.to(s.dtype).clone()
+        R = s.new_state()
+        s.rk_steps(U, R, dt, args.warmup, stream)
+        torch.cuda.synchronize()
+        s.set_profiling(True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        s.rk_steps(U, R, dt, args.steps, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = s.profile(stream)
+        s.set_profiling(False)
+        wall = t1 - t0
+        word = 8 if precision == "fp64" else 4
+        words = kernel_words_per_node(w.N)
+        kern = {}
+        for k, (ms, cnt) in prof.items():
+            if cnt and k in words:
+                avg = ms / cnt
+                kern[k] = {"avg_us": 1e3 * avg, "launches": cnt,
+                           "alg_bytes_per_launch": words[k] * word * s.nnodes,
+                           "achieved_GBs": words[k] * word * s.nnodes / (avg * 1e-3) / 1e9}
+        sums = s.reduce(U)  # health check of the final state (raises on non-finite)
+        return {"value": s.nnodes * 5 * args.steps / wall, "wall": wall, "gpu_ms": ev0.elapsed_time(ev1),
+                "kern": kern, "nnodes": s.nnodes, "U": U, "mass": sums[0], "word": word}
 
-    sums = s.reduce(U)  # health check of the final state (raises on non-finite)
-    nn = s.nnodes
-    value = nn * 5 * args.steps / wall
-    word = 8 if args.precision == "fp64" else 4
-    words = kernel_words_per_node(w.N)
-    kern = {}
-    for k, (ms, cnt) in prof.items():
-        if cnt and k in words:
-            avg = ms / cnt
-            kern[k] = {"avg_us": 1e3 * avg, "launches": cnt,
-                       "alg_bytes_per_launch": words[k] * word * nn,
-                       "achieved_GBs": words[k] * word * nn / (avg * 1e-3) / 1e9}
+    s0 = solver_for(w, args.precision)
+    U0 = init_workload(s0, w)
+    dt = s0.dt(U0)
+    if args.precision == "fp64":
+        U0 = U0.double()
+    r = timed_run(args.precision, U0)
+    nn, value, kern, word = r["nnodes"], r["value"], r["kern"], r["word"]
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     ach = kern[dom]["achieved_GBs"]
     floor_b, b3 = survey_bytes_model(w.N, word)
@@ -146,7 +193,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * r["wall"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -162,9 +209,35 @@ def main():
                         "design_GBs": value * stage_b / 1e9,
                         "B_3phase_bytes": b3, "B_3phase_GBs": value * b3 / 1e9,
                         "B_floor_bytes": floor_b, "B_floor_GBs": value * floor_b / 1e9},
-        "gpu_event_ms": gpu_ms,
-        "final_mass": sums[0],
+        "gpu_event_ms": r["gpu_ms"],
+        "final_mass": r["mass"],
     }
+    if args.precision == "fp64" and not args.no_fp32:
+        # the FP32-mixed form on the same workload, initial state and dt: speed and error
+        r32 = timed_run("fp32_mixed", U0)
+        a, b_ = r32["U"][0].double(), r["U"][0]
+        k32 = r32["kern"]
+        d32 = max(k32, key=lambda k: k32[k]["avg_us"] * k32[k]["launches"])
+        out["fp32_mixed"] = {
+            "value": r32["value"], "speedup_vs_fp64": r32["value"] / value,
+            "rho_rel_max_err_vs_fp64": float((a - b_).abs().max() / b_.abs().max()),
+            "rho_rel_l2_err_vs_fp64": float((a - b_).norm() / b_.norm()),
+            "after_steps": args.warmup + args.steps,
+            "roofline": {"kernel": d32, "achieved": k32[d32]["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                         "frac": k32[d32]["achieved_GBs"] / PEAK_HBM_GBS},
+            "kernels": k32}
+    if not args.no_serving:
+        try:
+            res = serving_bench(args.serving_requests, max_active_nodes=args.serving_max_nodes)
+            bt, sq = res["batched_fp32_mixed"], res.get("one_at_a_time_fp64", {})
+            out["serving"] = {"requests": bt["requests"], "p50_s": bt["p50_s"], "p99_s": bt["p99_s"],
+                              "aggregate_node_stage_updates_per_s": bt["node_stage_updates_per_s"],
+                              "one_at_a_time_fp64": {k: sq.get(k) for k in ("p50_s", "p99_s",
+                                                                             "node_stage_updates_per_s")},
+                              "throughput_speedup": res.get("speedup_throughput"), "tiles": res["tiles"],
+                              "max_active_nodes": args.serving_max_nodes}
+        except Exception as e:  # reported, never hides the main measurement
+            out["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     print(json.dumps(out), flush=True)

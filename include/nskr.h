@@ -208,9 +208,58 @@ int nskr_reduce(nskr_ctx *ctx, const void *U, double *out, nskr_stream s);
 int nskr_set_profiling(nskr_ctx *ctx, int on);
 int nskr_profile(nskr_ctx *ctx, double *ms, long *count, nskr_stream s);
 
+/* Threads per workgroup of the stage kernels (256 or 512; a block must hold
+ * at least one element): the tile shape the autotuner chooses.  Results do not
+ * depend on it (every element's arithmetic is the same in any tile).
+ * Errors: NSKR_E_ARG for other values. */
+int nskr_set_block(nskr_ctx *ctx, int threads);
+int nskr_get_block(const nskr_ctx *ctx, int *threads);
+
 /* Message of the last failing call on this context (static storage valid
  * until the next call); a generic message for ctx == NULL. */
 const char *nskr_last_error(const nskr_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Batched execution of many independent instances (contexts), possibly with
+ * different degrees, meshes, parameters, precisions and time steps.  Each
+ * nskr_batch_step advances every active instance by one RK step: per group of
+ * equal (degree, precision, block size) one launch per stage kernel covers all
+ * member instances through a device table of instances and a block map, and
+ * the whole step is captured once into a HIP graph and replayed until the set
+ * of instances changes.  An instance's arithmetic is the same alone and in any
+ * mix, so its results are bitwise identical.
+ * ------------------------------------------------------------------------- */
+typedef struct nskr_batch nskr_batch;
+
+/* Batch on device `device` that admits instances while the sum of their
+ * library memory and two state buffers stays within budget_bytes. */
+int nskr_batch_create(int device, size_t budget_bytes, nskr_batch **out);
+int nskr_batch_destroy(nskr_batch *b);
+
+/* Capture steps into a HIP graph (default on).  Graph capture needs a stream
+ * other than the legacy default stream. */
+int nskr_batch_set_graph(nskr_batch *b, int on);
+
+/* Admit ctx (mesh uploaded) with caller-owned state U and register R (borrowed
+ * until retired), its time step dt and the number of steps to run.  Returns
+ * NSKR_E_NOMEM when the budget has no room now (not fatal: retry after a
+ * retirement); NSKR_E_ARG for bad arguments or an instance already admitted. */
+int nskr_batch_admit(nskr_batch *b, nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, int *slot);
+
+/* One RK step of every active instance on stream s (asynchronous).  Instances
+ * that reach their step count become finished and stop advancing. */
+int nskr_batch_step(nskr_batch *b, nskr_stream s);
+
+/* Finished slots (up to cap written to slots, total count in *n). */
+int nskr_batch_poll(nskr_batch *b, int *slots, int cap, int *n);
+
+/* Release a slot (finished or not); its buffers are the caller's again. */
+int nskr_batch_retire(nskr_batch *b, int slot);
+
+/* Budget in use, active instances, steps taken. */
+int nskr_batch_info(const nskr_batch *b, size_t *used_bytes, int *active, long *steps);
+
+const char *nskr_batch_last_error(const nskr_batch *b);
 
 #ifdef __cplusplus
 }

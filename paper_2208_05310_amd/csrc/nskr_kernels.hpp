@@ -62,9 +62,9 @@ struct MeshDev {
     const BcDev *bcs;
 };
 
-template <int P> struct Tile {
+template <int P, int BS = kBlock> struct Tile {
     static constexpr int n2 = P * P, n3 = P * P * P;
-    static constexpr int EPB = kBlock / n3;     // elements per block
+    static constexpr int EPB = BS / n3;         // elements per block
     static constexpr int NV = EPB * n3;         // active node threads
     static constexpr int NF = EPB * 6 * n2;     // face points per block
 };
@@ -222,25 +222,42 @@ __device__ __forceinline__ void wall_flux(const Phys &ph, const BcDev &bc, const
 }
 
 // ------------------------------------------------------------ kernel args
-template <typename T> struct ProlongArgs {
-    const T *U; T *TU; MeshDev mesh; Basis bas; size_t NN;
+// One problem instance as the kernels see it: caller state, library scratch,
+// mesh, physics and its own time step.
+template <typename T> struct Inst {
+    T *U, *R, *Ut;             // state, RK register, U_t output (rhs)
+    T *Q, *TH, *G2;            // grad(rho,u,c) [15], T, grad T + lap c [4]
+    T *T2, *TF, *TU;           // face traces: grad c + T [4], flux [13], primitives [5]
+    MeshDev mesh;
+    Phys ph;
+    size_t NN;                 // nodes of the instance
+    double dt;
 };
 
-template <typename T> struct Lift1Args {
-    const T *U; const T *TU; T *Q; T *TH; T *T2; MeshDev mesh; Phys ph; Basis bas; size_t NN;
-};
-
-template <typename T> struct Lift2Args {
-    const T *U; const T *Q; const T *TH; const T *T2; T *G2; T *TF; MeshDev mesh; Phys ph; Basis bas; size_t NN;
-};
-
-template <typename T> struct UpdateArgs {
-    T *U; T *R; T *Ut; const T *Q; const T *TH; const T *G2; const T *TF; T *TU;
-    MeshDev mesh; Phys ph; Basis bas; size_t NN;
-    int mode;        // 0: write U_t; 1: RK stage (update U, R, write traces)
+// Kernel argument: a single instance by value, or (BATCH) a device table of
+// instances with a block map (instance and first element of every block),
+// plus what is common to the launch.
+template <typename T> struct Launch {
+    Inst<T> one;
+    const Inst<T> *tab;
+    const int *blk_inst, *blk_e0;
+    Basis bas;
+    int mode;        // update: 0 write U_t; 1 RK stage (update U, R, write traces)
     int first;       // RK: assign R at the first stage
-    double A, B, dt; // RK coefficients of this stage
+    double A, B;     // RK coefficients of this stage
 };
+
+template <typename T, bool BATCH>
+__device__ __forceinline__ void instance_of(const Launch<T> &L, Inst<T> &a, int &e0, int epb)
+{
+    if (BATCH) {
+        a = L.tab[L.blk_inst[blockIdx.x]];
+        e0 = L.blk_e0[blockIdx.x];
+    } else {
+        a = L.one;
+        e0 = blockIdx.x * epb;
+    }
+}
 
 // Copy the basis into LDS (the rows each thread needs differ per lane).
 template <int P>
@@ -286,19 +303,21 @@ __device__ __forceinline__ void prolong2(const T *s, int base, const double *sL,
     vp = ap;
 }
 
-template <int P> __device__ __forceinline__ constexpr int n_lines() { return Tile<P>::EPB * 3 * P * P; }
+template <int P, int BS> __device__ __forceinline__ constexpr int n_lines() { return Tile<P, BS>::EPB * 3 * P * P; }
 
 // ------------------------------------------------------------ k_prolong
 // Primitive face traces (rho, u, v, w, c) of the state, from the prolonged
 // conserved variables.
-template <int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(ProlongArgs<T> a)
+template <int P, typename T, int BS, bool BATCH>
+__global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 {
-    using G = Tile<P>;
+    using G = Tile<P, BS>;
+    Inst<T> a;
+    int e0;
+    instance_of<T, BATCH>(L, a, e0, G::EPB);
     __shared__ T sU[6][G::NV];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
-    load_basis<P>(a.bas, sDh, sL, sLh);
-    const int e0 = blockIdx.x * G::EPB;
+    load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
     const int t = threadIdx.x;
     if (t < G::NV && e0 + t / G::n3 < E) {
@@ -308,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(ProlongArgs<T> a)
     }
     __syncthreads();
     const size_t NF = (size_t)E * 6 * G::n2;
-    for (int task = t; task < n_lines<P>(); task += kBlock) {
+    for (int task = t; task < n_lines<P, BS>(); task += BS) {
         LineTask<P> lt(task);
         const int e = e0 + lt.le;
         if (e >= E) continue;
@@ -331,18 +350,20 @@ __global__ __launch_bounds__(kBlock) void k_prolong(ProlongArgs<T> a)
 }
 
 // ------------------------------------------------------------ k_lift1
-template <int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
+template <int P, typename T, int BS, bool BATCH>
+__global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
 {
-    using G = Tile<P>;
-    static_assert(n_lines<P>() <= kBlock, "one line per thread");
+    using G = Tile<P, BS>;
+    Inst<T> a;
+    int e0;
+    instance_of<T, BATCH>(L, a, e0, G::EPB);
+    static_assert(n_lines<P, BS>() <= BS, "one line per thread");
     __shared__ T sU[6][G::NV];
     __shared__ T sW[5][G::NV];
     __shared__ T sS[5][G::NF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
-    load_basis<P>(a.bas, sDh, sL, sLh);
+    load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
-    const int e0 = blockIdx.x * G::EPB;
     const int t = threadIdx.x;
     const int le = t / G::n3, nd = t - le * G::n3;
     const int e = e0 + le;
@@ -353,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
     // early loads: own nodes, and the neighbour traces of this thread's line
     const LineTask<P> lt(t);
     const int el = e0 + lt.le;
-    const bool lact = t < n_lines<P>() && el < E;
+    const bool lact = t < n_lines<P, BS>() && el < E;
     int nbm = -1, nbp = -1;
     T wn[2][5];
     if (lact) {
@@ -483,18 +504,20 @@ __global__ __launch_bounds__(kBlock) void k_lift1(Lift1Args<T> a)
 }
 
 // ------------------------------------------------------------ k_lift2
-template <int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_lift2(Lift2Args<T> a)
+template <int P, typename T, int BS, bool BATCH>
+__global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 {
-    using G = Tile<P>;
+    using G = Tile<P, BS>;
+    Inst<T> a;
+    int e0;
+    instance_of<T, BATCH>(L, a, e0, G::EPB);
     __shared__ T sA[5][G::NV];     // T, grad c (3); then grad T (3), lap c
     __shared__ T sU[6][G::NV];
     __shared__ T sGu[9][G::NV];
     __shared__ T sTs[G::NF], sFs[G::NF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
-    load_basis<P>(a.bas, sDh, sL, sLh);
+    load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
-    const int e0 = blockIdx.x * G::EPB;
     const int t = threadIdx.x;
     const int le = t / G::n3, nd = t - le * G::n3;
     const int e = e0 + le;
@@ -505,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_lift2(Lift2Args<T> a)
     // early loads: own and neighbour traces of grad c and T on this thread's line
     const LineTask<P> lt(t);
     const int el = e0 + lt.le;
-    const bool lact = t < n_lines<P>() && el < E;
+    const bool lact = t < n_lines<P, BS>() && el < E;
     int nb2[2] = {-1, -1};
     T own[2][4], oth[2][4];
     if (lact) {
@@ -733,16 +756,18 @@ __global__ __launch_bounds__(kBlock) void k_lift2(Lift2Args<T> a)
 }
 
 // ------------------------------------------------------------ k_update
-template <int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
+template <int P, typename T, int BS, bool BATCH>
+__global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 {
-    using G = Tile<P>;
+    using G = Tile<P, BS>;
+    Inst<T> a;
+    int e0;
+    instance_of<T, BATCH>(L, a, e0, G::EPB);
     __shared__ T sF[6][G::NV];
     __shared__ T sFs[6][G::NF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
-    load_basis<P>(a.bas, sDh, sL, sLh);
+    load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
-    const int e0 = blockIdx.x * G::EPB;
     const int t = threadIdx.x;
     const int le = t / G::n3, nd = t - le * G::n3;
     const int e = e0 + le;
@@ -778,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
     // surface flux (F* . n) dS on both faces of this thread's line
     const LineTask<P> lt(t);
     const int el = e0 + lt.le;
-    if (t < n_lines<P>() && el < E) {
+    if (t < n_lines<P, BS>() && el < E) {
 #pragma unroll 1
         for (int sd = 0; sd < 2; ++sd) {
             const int f = 2 * lt.d + sd;
@@ -857,7 +882,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
     T Ut[6];
 #pragma unroll
     for (int v = 0; v < 6; ++v) Ut[v] = -acc[v] * iJ + S[v];
-    if (a.mode == 0) {
+    if (L.mode == 0) {
         if (act) {
 #pragma unroll
             for (int v = 0; v < 6; ++v) a.Ut[v * a.NN + g] = Ut[v];
@@ -867,11 +892,11 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
     // low-storage RK stage
     __syncthreads();
     if (act) {
-        const T A = T(a.A), B = T(a.B), dt = T(a.dt);
+        const T A = T(L.A), B = T(L.B), dt = T(a.dt);
         T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            const T r = a.first ? dt * Ut[v] : A * a.R[v * a.NN + g] + dt * Ut[v];
+            const T r = L.first ? dt * Ut[v] : A * a.R[v * a.NN + g] + dt * Ut[v];
             a.R[v * a.NN + g] = r;
             const T u = u6[v] + B * r;
             a.U[v * a.NN + g] = u;
@@ -879,7 +904,7 @@ __global__ __launch_bounds__(kBlock) void k_update(UpdateArgs<T> a)
         }
     }
     __syncthreads();
-    if (t < n_lines<P>() && el < E) {
+    if (t < n_lines<P, BS>() && el < E) {
         const int b2 = lt.le * G::n3;
         T um[6], up[6];
 #pragma unroll

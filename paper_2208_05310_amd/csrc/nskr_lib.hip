@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/nskr.h"
@@ -20,6 +21,7 @@ using namespace nskr;
 struct nskr_ctx {
     nskr_params p;
     int N = 0, P = 0, device = 0;
+    int bs = 256;               // threads per block of the stage kernels
     bool poisoned = false;
     std::string err;
     // mesh
@@ -482,9 +484,13 @@ __global__ __launch_bounds__(kBlock) void k_init_energy(T *U, const T *Q, int E,
 }
 
 // ------------------------------------------------------------ launch layer
-template <int P, typename T> struct Impl {
-    using G = Tile<P>;
+template <int P, typename T, int BS> struct Impl {
+    static constexpr int kP = P, kBS = BS;
+    using Real = T;
+    using G = Tile<P, BS>;
+    using G256 = Tile<P, kBlock>;
     static int nblk(const nskr_ctx *c) { return (c->E + G::EPB - 1) / G::EPB; }
+    static int nblk256(const nskr_ctx *c) { return (c->E + G256::EPB - 1) / G256::EPB; }
 
     static MeshDev mesh(const nskr_ctx *c)
     {
@@ -493,70 +499,118 @@ template <int P, typename T> struct Impl {
         m.egeo = c->d_egeo; m.bcs = c->d_bcs;
         return m;
     }
-
-    static void prolong(nskr_ctx *c, const T *U, hipStream_t s)
+    static Inst<T> inst(const nskr_ctx *c, const void *U, void *R, void *Ut, double dt)
     {
-        ProlongArgs<T> a{U, (T *)c->d_TU, mesh(c), c->bas, c->NN};
+        Inst<T> I;
+        I.U = (T *)U; I.R = (T *)R; I.Ut = (T *)Ut;
+        I.Q = (T *)c->d_Q; I.TH = (T *)c->d_TH; I.G2 = (T *)c->d_G2;
+        I.T2 = (T *)c->d_T2; I.TF = (T *)c->d_TF; I.TU = (T *)c->d_TU;
+        I.mesh = mesh(c); I.ph = c->ph; I.NN = c->NN; I.dt = dt;
+        return I;
+    }
+    static Launch<T> launch(const nskr_ctx *c, const Inst<T> &I)
+    {
+        Launch<T> L;
+        memset(&L, 0, sizeof(L));
+        L.one = I;
+        L.bas = c->bas;
+        return L;
+    }
+    // every stage kernel's static LDS fits the device's per-block limit
+    static int fits(int maxlds)
+    {
+        const void *fns[] = {reinterpret_cast<const void *>(&k_prolong<P, T, BS, false>),
+                             reinterpret_cast<const void *>(&k_lift1<P, T, BS, false>),
+                             reinterpret_cast<const void *>(&k_lift2<P, T, BS, false>),
+                             reinterpret_cast<const void *>(&k_update<P, T, BS, false>)};
+        for (const void *f : fns) {
+            hipFuncAttributes at;
+            if (hipFuncGetAttributes(&at, f) != hipSuccess) return 0;
+            if ((int)at.sharedSizeBytes > maxlds || at.maxThreadsPerBlock < BS) return 0;
+        }
+        return 1;
+    }
+    // single-instance launches
+    static void prolong(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
+    {
         KernelTimer kt(c, 0, s);
-        hipLaunchKernelGGL((k_prolong<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_prolong<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
     }
-    static void lift1(nskr_ctx *c, const T *U, hipStream_t s)
+    static void lift1(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        Lift1Args<T> a{U, (const T *)c->d_TU, (T *)c->d_Q, (T *)c->d_TH, (T *)c->d_T2, mesh(c), c->ph, c->bas, c->NN};
         KernelTimer kt(c, 1, s);
-        hipLaunchKernelGGL((k_lift1<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_lift1<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
     }
-    static void lift2(nskr_ctx *c, const T *U, hipStream_t s)
+    static void lift2(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        Lift2Args<T> a{U, (const T *)c->d_Q, (const T *)c->d_TH, (const T *)c->d_T2, (T *)c->d_G2, (T *)c->d_TF,
-                       mesh(c), c->ph, c->bas, c->NN};
         KernelTimer kt(c, 2, s);
-        hipLaunchKernelGGL((k_lift2<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_lift2<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
     }
-    static void update(nskr_ctx *c, T *U, T *R, T *Ut, int mode, int first, double A, double B, double dt,
-                       hipStream_t s)
+    static void update(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        UpdateArgs<T> a{U, R, Ut, (const T *)c->d_Q, (const T *)c->d_TH, (const T *)c->d_G2, (const T *)c->d_TF,
-                        (T *)c->d_TU, mesh(c), c->ph, c->bas, c->NN, mode, first, A, B, dt};
         KernelTimer kt(c, 3, s);
-        hipLaunchKernelGGL((k_update<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_update<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
     }
+    // batched launches over a group table
+    static void step_batched(const Launch<T> &L0, int nblocks, hipStream_t s)
+    {
+        Launch<T> L = L0;
+        hipLaunchKernelGGL((k_prolong<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
+        for (int st = 0; st < 5; ++st) {
+            L.mode = 1;
+            L.first = st == 0;
+            L.A = kRkA[st];
+            L.B = kRkB[st];
+            hipLaunchKernelGGL((k_lift1<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
+            hipLaunchKernelGGL((k_lift2<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
+            hipLaunchKernelGGL((k_update<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
+        }
+    }
+
     static int rhs(nskr_ctx *c, const void *U, void *Ut, hipStream_t s)
     {
-        prolong(c, (const T *)U, s);
-        lift1(c, (const T *)U, s);
-        lift2(c, (const T *)U, s);
-        update(c, (T *)U, nullptr, (T *)Ut, 0, 0, 0, 0, 0, s);
+        Launch<T> L = launch(c, inst(c, U, nullptr, Ut, 0.0));
+        L.mode = 0;
+        prolong(c, L, s);
+        lift1(c, L, s);
+        lift2(c, L, s);
+        update(c, L, s);
         HIPCHK(c, hipGetLastError());
         return NSKR_OK;
     }
-    static int rk(nskr_ctx *c, void *Uv, void *Rv, double dt, int nsteps, hipStream_t s)
+    static int rk(nskr_ctx *c, void *U, void *R, double dt, int nsteps, hipStream_t s)
     {
-        T *U = (T *)Uv, *R = (T *)Rv;
         if (nsteps == 0) return NSKR_OK;
-        prolong(c, U, s);
+        Launch<T> L = launch(c, inst(c, U, R, nullptr, dt));
+        prolong(c, L, s);
         for (int n = 0; n < nsteps; ++n)
             for (int st = 0; st < 5; ++st) {
-                lift1(c, U, s);
-                lift2(c, U, s);
-                update(c, U, R, nullptr, 1, st == 0, kRkA[st], kRkB[st], dt, s);
+                L.mode = 1;
+                L.first = st == 0;
+                L.A = kRkA[st];
+                L.B = kRkB[st];
+                lift1(c, L, s);
+                lift2(c, L, s);
+                update(c, L, s);
             }
         HIPCHK(c, hipGetLastError());
         return NSKR_OK;
     }
     static int lift1_out(nskr_ctx *c, const void *U, void *q, hipStream_t s)
     {
-        prolong(c, (const T *)U, s);
-        lift1(c, (const T *)U, s);
+        Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        prolong(c, L, s);
+        lift1(c, L, s);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(q, c->d_Q, sizeof(T) * 15 * c->NN, hipMemcpyDeviceToDevice, s));
         return NSKR_OK;
     }
     static int lift2_out(nskr_ctx *c, const void *U, void *o, hipStream_t s)
     {
-        prolong(c, (const T *)U, s);
-        lift1(c, (const T *)U, s);
-        lift2(c, (const T *)U, s);
+        Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        prolong(c, L, s);
+        lift1(c, L, s);
+        lift2(c, L, s);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(o, c->d_TH, sizeof(T) * c->NN, hipMemcpyDeviceToDevice, s));
         HIPCHK(c, hipMemcpyAsync((T *)o + c->NN, c->d_G2, sizeof(T) * 4 * c->NN, hipMemcpyDeviceToDevice, s));
@@ -564,12 +618,14 @@ template <int P, typename T> struct Impl {
     }
     static int dt(nskr_ctx *c, const void *U, double *out3, hipStream_t s)
     {
-        prolong(c, (const T *)U, s);
-        lift1(c, (const T *)U, s);
-        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk(c)};
-        hipLaunchKernelGGL((k_dt_rates<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, (const T *)U,
+        Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        prolong(c, L, s);
+        lift1(c, L, s);
+        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
+        hipLaunchKernelGGL((k_dt_rates<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a);
-        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk(c), 3, c->d_out);
+        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk256(c), 3,
+                           c->d_out);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(out3, c->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
@@ -577,12 +633,13 @@ template <int P, typename T> struct Impl {
     }
     static int reduce(nskr_ctx *c, const void *U, double *out, hipStream_t s)
     {
-        prolong(c, (const T *)U, s);
-        lift1(c, (const T *)U, s);
-        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk(c)};
-        hipLaunchKernelGGL((k_integrals<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, (const T *)U,
+        Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        prolong(c, L, s);
+        lift1(c, L, s);
+        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
+        hipLaunchKernelGGL((k_integrals<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a, c->bas);
-        hipLaunchKernelGGL(k_integrals_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk(c),
+        hipLaunchKernelGGL(k_integrals_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk256(c),
                            c->d_out);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(out, c->d_out, NSKR_NSUMS * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -592,25 +649,42 @@ template <int P, typename T> struct Impl {
     static int init(nskr_ctx *c, const InitArgs &ia, double T0, void *Uv, hipStream_t s)
     {
         T *U = (T *)Uv;
-        hipLaunchKernelGGL((k_init_rho<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, U, ia);
-        prolong(c, U, s);
-        lift1(c, U, s);
-        hipLaunchKernelGGL((k_init_energy<P, T>), dim3(nblk(c)), dim3(kBlock), 0, s, U, (const T *)c->d_Q, c->E,
+        hipLaunchKernelGGL((k_init_rho<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, U, ia);
+        Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        prolong(c, L, s);
+        lift1(c, L, s);
+        hipLaunchKernelGGL((k_init_energy<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, U, (const T *)c->d_Q, c->E,
                            c->NN, c->ph, T0);
         HIPCHK(c, hipGetLastError());
         return NSKR_OK;
     }
 };
 
+// Valid block sizes per degree: the block must hold at least one element and
+// one line task per thread.
+static bool block_ok(int N, int bs)
+{
+    const int P = N + 1, n3 = P * P * P;
+    if (bs != 256 && bs != 512) return false;
+    const int epb = bs / n3;
+    return epb >= 1 && epb * 3 * P * P <= bs;
+}
+
 template <typename F> static int dispatch(const nskr_ctx *c, F &&f)
 {
     const bool dbl = c->p.precision == 0;
+    const bool big = c->bs == 512;
+#define NSKR_CASE(NN, PP)                                                                  \
+    case NN:                                                                               \
+        if (dbl) return big ? f(Impl<PP, double, 512>()) : f(Impl<PP, double, 256>());     \
+        return big ? f(Impl<PP, float, 512>()) : f(Impl<PP, float, 256>());
     switch (c->N) {
-    case 2: return dbl ? f(Impl<3, double>()) : f(Impl<3, float>());
-    case 3: return dbl ? f(Impl<4, double>()) : f(Impl<4, float>());
-    case 4: return dbl ? f(Impl<5, double>()) : f(Impl<5, float>());
-    case 5: return dbl ? f(Impl<6, double>()) : f(Impl<6, float>());
+        NSKR_CASE(2, 3)
+        NSKR_CASE(3, 4)
+        NSKR_CASE(4, 5)
+        NSKR_CASE(5, 6)
     }
+#undef NSKR_CASE
     return NSKR_E_ARG;
 }
 
@@ -638,7 +712,7 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NSKR_E_HIP;
     // make sure the device code for this GPU is present
     hipFuncAttributes attr;
-    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(&k_update<4, double>)) != hipSuccess)
+    if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(&k_update<4, double, 256, false>)) != hipSuccess)
         return NSKR_E_HIP;
     nskr_ctx *c = new nskr_ctx();
     c->p = *p;
@@ -874,7 +948,7 @@ int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, vo
         HIPCHK(c, hipMemcpyAsync(c->d_noise, noise, sizeof(double) * c->NN, hipMemcpyHostToDevice, s));
     }
     InitArgs ia;
-    ia.mesh = Impl<4, double>::mesh(c);
+    ia.mesh = Impl<4, double, 256>::mesh(c);
     ia.bas = c->bas;
     ia.NN = c->NN;
     ia.drop = c->d_drop;
@@ -958,6 +1032,31 @@ int nskr_reduce(nskr_ctx *c, const void *U, double *out, nskr_stream sv)
     return NSKR_OK;
 }
 
+int nskr_set_block(nskr_ctx *c, int threads)
+{
+    if (!c) return NSKR_E_ARG;
+    if (!block_ok(c->N, threads)) return fail(c, NSKR_E_ARG, "block size must be 256 or 512 and hold an element");
+    DeviceGuard guard(c->device);
+    int maxlds = 0;
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+        return fail(c, NSKR_E_HIP, "cannot query the LDS limit");
+    const int old = c->bs;
+    c->bs = threads;
+    const int ok = dispatch(c, [&](auto impl) { return decltype(impl)::fits(maxlds); });
+    if (!ok) {
+        c->bs = old;
+        return fail(c, NSKR_E_UNSUPPORTED, "kernels of this block size exceed the device's LDS per block");
+    }
+    return NSKR_OK;
+}
+
+int nskr_get_block(const nskr_ctx *c, int *threads)
+{
+    if (!c || !threads) return NSKR_E_ARG;
+    *threads = c->bs;
+    return NSKR_OK;
+}
+
 int nskr_set_profiling(nskr_ctx *c, int on)
 {
     if (!c) return NSKR_E_ARG;
@@ -988,6 +1087,302 @@ const char *nskr_last_error(const nskr_ctx *c)
 {
     if (!c) return g_null_msg;
     return c->err.c_str();
+}
+
+// ------------------------------------------------------------------ batches
+}  // extern "C"
+
+struct BatchSlot {
+    nskr_ctx *c = nullptr;
+    void *U = nullptr, *R = nullptr;
+    double dt = 0.0;
+    int nsteps = 0, done = 0;
+    int state = 0;  // 0 free, 1 active, 2 finished (awaiting retire)
+    size_t bytes = 0;
+};
+
+struct BatchGroup {
+    int N = 0, prec = 0, bs = 0, nblocks = 0;
+    void *d_tab = nullptr;
+    int *d_bi = nullptr, *d_be = nullptr;
+    Basis bas;
+};
+
+struct nskr_batch {
+    int device = 0;
+    size_t budget = 0, used = 0;
+    std::vector<BatchSlot> slots;
+    std::vector<BatchGroup> groups;
+    bool dirty = true, use_graph = true, poisoned = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    long steps = 0;
+    std::string err;
+};
+
+static int bfail(nskr_batch *b, int code, const std::string &msg)
+{
+    b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, x)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (x);                                                             \
+        if (e_ != hipSuccess) {                                                          \
+            (b)->poisoned = true;                                                        \
+            return bfail((b), NSKR_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+        }                                                                                \
+    } while (0)
+
+static void batch_free_groups(nskr_batch *b)
+{
+    for (auto &g : b->groups) {
+        if (g.d_tab) (void)hipFree(g.d_tab);
+        if (g.d_bi) (void)hipFree(g.d_bi);
+        if (g.d_be) (void)hipFree(g.d_be);
+    }
+    b->groups.clear();
+    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+}
+
+template <int P, typename T, int BS>
+static int build_group(nskr_batch *b, BatchGroup &g, const std::vector<int> &members)
+{
+    using G = Tile<P, BS>;
+    std::vector<Inst<T>> tab;
+    std::vector<int> bi, be;
+    for (size_t k = 0; k < members.size(); ++k) {
+        BatchSlot &sl = b->slots[members[k]];
+        tab.push_back(Impl<P, T, BS>::inst(sl.c, sl.U, sl.R, nullptr, sl.dt));
+        const int nb = (sl.c->E + G::EPB - 1) / G::EPB;
+        for (int j = 0; j < nb; ++j) {
+            bi.push_back((int)k);
+            be.push_back(j * G::EPB);
+        }
+    }
+    g.nblocks = (int)bi.size();
+    g.bas = b->slots[members[0]].c->bas;
+    BHIPCHK(b, hipMalloc(&g.d_tab, sizeof(Inst<T>) * tab.size()));
+    BHIPCHK(b, hipMalloc((void **)&g.d_bi, sizeof(int) * bi.size()));
+    BHIPCHK(b, hipMalloc((void **)&g.d_be, sizeof(int) * be.size()));
+    BHIPCHK(b, hipMemcpy(g.d_tab, tab.data(), sizeof(Inst<T>) * tab.size(), hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(g.d_bi, bi.data(), sizeof(int) * bi.size(), hipMemcpyHostToDevice));
+    BHIPCHK(b, hipMemcpy(g.d_be, be.data(), sizeof(int) * be.size(), hipMemcpyHostToDevice));
+    return NSKR_OK;
+}
+
+template <int P, typename T, int BS> static void launch_group(const BatchGroup &g, hipStream_t s)
+{
+    Launch<T> L;
+    memset(&L, 0, sizeof(L));
+    L.tab = (const Inst<T> *)g.d_tab;
+    L.blk_inst = g.d_bi;
+    L.blk_e0 = g.d_be;
+    L.bas = g.bas;
+    Impl<P, T, BS>::step_batched(L, g.nblocks, s);
+}
+
+template <typename F> static int group_dispatch(int N, int prec, int bs, F &&f)
+{
+#define NSKR_GCASE(NN, PP)                                                                         \
+    case NN:                                                                                       \
+        if (prec == 0) return bs == 512 ? f(Impl<PP, double, 512>()) : f(Impl<PP, double, 256>()); \
+        return bs == 512 ? f(Impl<PP, float, 512>()) : f(Impl<PP, float, 256>());
+    switch (N) {
+        NSKR_GCASE(2, 3)
+        NSKR_GCASE(3, 4)
+        NSKR_GCASE(4, 5)
+        NSKR_GCASE(5, 6)
+    }
+#undef NSKR_GCASE
+    return NSKR_E_ARG;
+}
+
+static int batch_rebuild(nskr_batch *b)
+{
+    batch_free_groups(b);
+    // group active instances by (degree, precision, block size)
+    std::vector<std::vector<int>> members;
+    std::vector<BatchGroup> groups;
+    for (int i = 0; i < (int)b->slots.size(); ++i) {
+        const BatchSlot &sl = b->slots[i];
+        if (sl.state != 1) continue;
+        int gi = -1;
+        for (int k = 0; k < (int)groups.size(); ++k)
+            if (groups[k].N == sl.c->N && groups[k].prec == sl.c->p.precision && groups[k].bs == sl.c->bs) gi = k;
+        if (gi < 0) {
+            BatchGroup g;
+            g.N = sl.c->N;
+            g.prec = sl.c->p.precision;
+            g.bs = sl.c->bs;
+            groups.push_back(g);
+            members.emplace_back();
+            gi = (int)groups.size() - 1;
+        }
+        members[gi].push_back(i);
+    }
+    for (size_t k = 0; k < groups.size(); ++k) {
+        BatchGroup &g = groups[k];
+        int rc = group_dispatch(g.N, g.prec, g.bs, [&](auto impl) {
+            using I = decltype(impl);
+            return build_group<I::kP, typename I::Real, I::kBS>(b, g, members[k]);
+        });
+        b->groups.push_back(g);
+        if (rc) return rc;
+    }
+    b->dirty = false;
+    return NSKR_OK;
+}
+
+extern "C" {
+
+int nskr_batch_create(int device, size_t budget_bytes, nskr_batch **out)
+{
+    if (!out) return NSKR_E_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NSKR_E_HIP;
+    nskr_batch *b = new nskr_batch();
+    b->device = device;
+    b->budget = budget_bytes;
+    *out = b;
+    return NSKR_OK;
+}
+
+int nskr_batch_destroy(nskr_batch *b)
+{
+    if (!b) return NSKR_OK;
+    {
+        DeviceGuard g(b->device);
+        batch_free_groups(b);
+    }
+    delete b;
+    return NSKR_OK;
+}
+
+int nskr_batch_set_graph(nskr_batch *b, int on)
+{
+    if (!b) return NSKR_E_ARG;
+    if ((on != 0) != b->use_graph) {
+        b->use_graph = on != 0;
+        b->dirty = true;
+    }
+    return NSKR_OK;
+}
+
+int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, int nsteps, int *slot)
+{
+    if (!b || !c || !slot) return NSKR_E_ARG;
+    if (b->poisoned) return bfail(b, NSKR_E_STATE, "batch poisoned by an earlier HIP error");
+    if (c->poisoned || c->E == 0) return bfail(b, NSKR_E_STATE, "instance has no mesh or is poisoned");
+    if (c->device != b->device) return bfail(b, NSKR_E_ARG, "instance lives on another device");
+    if (!U || !R || U == R) return bfail(b, NSKR_E_ARG, "null or aliasing state buffers");
+    if (!(dt > 0) || !isfinite(dt) || nsteps < 1) return bfail(b, NSKR_E_ARG, "dt must be positive, nsteps >= 1");
+    for (const auto &sl : b->slots)
+        if (sl.state != 0 && sl.c == c) return bfail(b, NSKR_E_ARG, "instance already admitted");
+    const size_t ts = c->p.precision == 0 ? sizeof(double) : sizeof(float);
+    const size_t need = c->bytes + 2 * 6 * c->NN * ts;
+    if (b->used + need > b->budget) return bfail(b, NSKR_E_NOMEM, "no room in the memory budget now");
+    int k = -1;
+    for (int i = 0; i < (int)b->slots.size(); ++i)
+        if (b->slots[i].state == 0) { k = i; break; }
+    if (k < 0) {
+        b->slots.emplace_back();
+        k = (int)b->slots.size() - 1;
+    }
+    BatchSlot &sl = b->slots[k];
+    sl.c = c; sl.U = U; sl.R = R; sl.dt = dt; sl.nsteps = nsteps; sl.done = 0; sl.state = 1; sl.bytes = need;
+    b->used += need;
+    b->dirty = true;
+    *slot = k;
+    return NSKR_OK;
+}
+
+int nskr_batch_retire(nskr_batch *b, int slot)
+{
+    if (!b || slot < 0 || slot >= (int)b->slots.size() || b->slots[slot].state == 0) return NSKR_E_ARG;
+    BatchSlot &sl = b->slots[slot];
+    if (sl.state == 1) b->dirty = true;
+    b->used -= sl.bytes;
+    sl = BatchSlot();
+    return NSKR_OK;
+}
+
+int nskr_batch_step(nskr_batch *b, nskr_stream sv)
+{
+    if (!b) return NSKR_E_ARG;
+    if (b->poisoned) return bfail(b, NSKR_E_STATE, "batch poisoned by an earlier HIP error");
+    DeviceGuard guard(b->device);
+    hipStream_t s = (hipStream_t)sv;
+    int nact = 0;
+    for (const auto &sl : b->slots) nact += sl.state == 1;
+    if (nact == 0) return NSKR_OK;
+    if (b->dirty) {
+        BHIPCHK(b, hipStreamSynchronize(s));  // earlier replays may still read the old tables
+        int rc = batch_rebuild(b);
+        if (rc) return rc;
+    }
+    if (b->use_graph) {
+        if (!b->exec) {
+            BHIPCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (const auto &g : b->groups)
+                group_dispatch(g.N, g.prec, g.bs, [&](auto impl) {
+                    using I = decltype(impl);
+                    launch_group<I::kP, typename I::Real, I::kBS>(g, s);
+                    return 0;
+                });
+            BHIPCHK(b, hipStreamEndCapture(s, &b->graph));
+            BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        }
+        BHIPCHK(b, hipGraphLaunch(b->exec, s));
+    } else {
+        for (const auto &g : b->groups)
+            group_dispatch(g.N, g.prec, g.bs, [&](auto impl) {
+                using I = decltype(impl);
+                launch_group<I::kP, typename I::Real, I::kBS>(g, s);
+                return 0;
+            });
+        BHIPCHK(b, hipGetLastError());
+    }
+    b->steps++;
+    for (auto &sl : b->slots)
+        if (sl.state == 1 && ++sl.done >= sl.nsteps) {
+            sl.state = 2;
+            b->dirty = true;
+        }
+    return NSKR_OK;
+}
+
+int nskr_batch_poll(nskr_batch *b, int *slots, int cap, int *n)
+{
+    if (!b || !n || (cap > 0 && !slots)) return NSKR_E_ARG;
+    int k = 0;
+    for (int i = 0; i < (int)b->slots.size(); ++i)
+        if (b->slots[i].state == 2) {
+            if (k < cap) slots[k] = i;
+            ++k;
+        }
+    *n = k;
+    return NSKR_OK;
+}
+
+int nskr_batch_info(const nskr_batch *b, size_t *used_bytes, int *active, long *steps)
+{
+    if (!b) return NSKR_E_ARG;
+    int nact = 0;
+    for (const auto &sl : b->slots) nact += sl.state == 1;
+    if (used_bytes) *used_bytes = b->used;
+    if (active) *active = nact;
+    if (steps) *steps = b->steps;
+    return NSKR_OK;
+}
+
+const char *nskr_batch_last_error(const nskr_batch *b)
+{
+    if (!b) return "nskr: null batch";
+    return b->err.c_str();
 }
 
 }  // extern "C"

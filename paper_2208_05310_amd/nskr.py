@@ -22,7 +22,10 @@ SUM_NAMES = ["mass", "mom_x", "mom_y", "mom_z", "energy", "c", "kinetic", "gradi
 
 EXPORTS = ["nskr_version", "nskr_create", "nskr_destroy", "nskr_mesh_upload", "nskr_state_size",
            "nskr_device_bytes", "nskr_init_droplets", "nskr_rhs", "nskr_lift1", "nskr_lift2", "nskr_dt",
-           "nskr_rk_steps", "nskr_reduce", "nskr_set_profiling", "nskr_profile", "nskr_last_error"]
+           "nskr_rk_steps", "nskr_reduce", "nskr_set_profiling", "nskr_profile", "nskr_set_block",
+           "nskr_get_block", "nskr_last_error", "nskr_batch_create", "nskr_batch_destroy",
+           "nskr_batch_set_graph", "nskr_batch_admit", "nskr_batch_step", "nskr_batch_poll",
+           "nskr_batch_retire", "nskr_batch_info", "nskr_batch_last_error"]
 KERNEL_KINDS = ["prolong", "lift1", "lift2", "update", "other"]
 
 
@@ -83,7 +86,18 @@ def lib():
         "nskr_reduce": (i, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
         "nskr_set_profiling": (i, [vp, i]),
         "nskr_profile": (i, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), vp]),
+        "nskr_set_block": (i, [vp, i]),
+        "nskr_get_block": (i, [vp, ctypes.POINTER(i)]),
         "nskr_last_error": (ctypes.c_char_p, [vp]),
+        "nskr_batch_create": (i, [i, ctypes.c_size_t, ctypes.POINTER(vp)]),
+        "nskr_batch_destroy": (i, [vp]),
+        "nskr_batch_set_graph": (i, [vp, i]),
+        "nskr_batch_admit": (i, [vp, vp, vp, vp, d, i, ctypes.POINTER(i)]),
+        "nskr_batch_step": (i, [vp, vp]),
+        "nskr_batch_poll": (i, [vp, ctypes.POINTER(i), i, ctypes.POINTER(i)]),
+        "nskr_batch_retire": (i, [vp, i]),
+        "nskr_batch_info": (i, [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]),
+        "nskr_batch_last_error": (ctypes.c_char_p, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -265,6 +279,68 @@ class Solver:
         return vals
 
 
+class Batch:
+    """Many independent instances advanced together (one RK step per call),
+    grouped by degree/precision/block size, captured into a HIP graph."""
+
+    def __init__(self, budget_bytes: int, device: int = 0, graph: bool = True):
+        self.L = lib()
+        h = ctypes.c_void_p()
+        rc = self.L.nskr_batch_create(int(device), int(budget_bytes), ctypes.byref(h))
+        if rc != NSKR_OK:
+            raise NskrError(rc, "nskr_batch_create failed")
+        self._h = h
+        self.device = device
+        self.L.nskr_batch_set_graph(h, 1 if graph else 0)
+        self._held = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self.L.nskr_batch_destroy(h)
+            self._h = None
+
+    def _err(self, rc):
+        raise NskrError(rc, self.L.nskr_batch_last_error(self._h).decode())
+
+    def admit(self, solver: "Solver", U, R, dt: float, nsteps: int):
+        """Slot index, or None when the memory budget has no room now."""
+        slot = ctypes.c_int()
+        rc = self.L.nskr_batch_admit(self._h, solver._h, solver._state_ok(U), solver._state_ok(R), float(dt),
+                                     int(nsteps), ctypes.byref(slot))
+        if rc == NSKR_E_NOMEM:
+            return None
+        if rc != NSKR_OK:
+            self._err(rc)
+        self._held[slot.value] = (solver, U, R)
+        return slot.value
+
+    def step(self, stream):
+        rc = self.L.nskr_batch_step(self._h, _stream_ptr(stream))
+        if rc != NSKR_OK:
+            self._err(rc)
+
+    def poll(self):
+        n = ctypes.c_int()
+        cap = 4096
+        arr = (ctypes.c_int * cap)()
+        rc = self.L.nskr_batch_poll(self._h, arr, cap, ctypes.byref(n))
+        if rc != NSKR_OK:
+            self._err(rc)
+        return [arr[k] for k in range(min(n.value, cap))]
+
+    def retire(self, slot):
+        rc = self.L.nskr_batch_retire(self._h, int(slot))
+        if rc != NSKR_OK:
+            self._err(rc)
+        return self._held.pop(slot, None)
+
+    def info(self):
+        used, act, steps = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_long()
+        self.L.nskr_batch_info(self._h, ctypes.byref(used), ctypes.byref(act), ctypes.byref(steps))
+        return {"used_bytes": used.value, "active": act.value, "steps": steps.value}
+
+
 def _profile_methods():
     def set_profiling(self, on=True):
         self._check(self.L.nskr_set_profiling(self._h, 1 if on else 0))
@@ -275,8 +351,18 @@ def _profile_methods():
         self._check(self.L.nskr_profile(self._h, ms, cnt, _stream_ptr(stream)))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
 
+    def set_block(self, threads):
+        self._check(self.L.nskr_set_block(self._h, int(threads)))
+
+    def get_block(self):
+        v = ctypes.c_int()
+        self._check(self.L.nskr_get_block(self._h, ctypes.byref(v)))
+        return v.value
+
     Solver.set_profiling = set_profiling
     Solver.profile = profile
+    Solver.set_block = set_block
+    Solver.get_block = get_block
 
 
 _profile_methods()
