@@ -276,6 +276,7 @@ __device__ __forceinline__ void load_basis(const Basis &b, double *sDh, double *
 // and 2d+1 (+1), so each LDS value of the line is read once for both faces.
 template <int P> struct LineTask {
     int le, d, fp, p, q;
+    int off, str;  // node l of the line is off + l * str (element-local)
     __device__ __forceinline__ LineTask(int task)
     {
         le = task / (3 * P * P);
@@ -284,6 +285,9 @@ template <int P> struct LineTask {
         fp = r - d * P * P;
         p = fp % P;
         q = fp / P;
+        // d = 0: (l, p, q); d = 1: (p, l, q); d = 2: (p, q, l)
+        off = d == 0 ? P * fp : (d == 1 ? p + P * P * q : fp);
+        str = d == 0 ? 1 : (d == 1 ? P : P * P);
     }
 };
 
@@ -293,9 +297,10 @@ __device__ __forceinline__ void prolong2(const T *s, int base, const double *sL,
                                          T &vp)
 {
     T am = T(0), ap = T(0);
+    const T *ln = s + base + lt.off;
 #pragma unroll
     for (int l = 0; l < P; ++l) {
-        const T v = s[base + line_node<P>(lt.d, l, lt.p, lt.q)];
+        const T v = ln[l * lt.str];
         am += T(sL[l]) * v;
         ap += T(sL[P + l]) * v;
     }
@@ -304,6 +309,18 @@ __device__ __forceinline__ void prolong2(const T *s, int base, const double *sL,
 }
 
 template <int P, int BS> __device__ __forceinline__ constexpr int n_lines() { return Tile<P, BS>::EPB * 3 * P * P; }
+
+// Line task of thread t, or -1.  Every wave (on its own SIMD) gets an equal,
+// contiguous chunk of lines, so the heavy face phases use all SIMDs of the
+// workgroup and each wave's trace accesses stay contiguous.
+template <int P, int BS> __device__ __forceinline__ int line_of_thread(int t)
+{
+    constexpr int W = BS / 64;
+    constexpr int C = (n_lines<P, BS>() + W - 1) / W;
+    const int w = t >> 6, l = t & 63;
+    const int task = w * C + l;
+    return (l < C && task < n_lines<P, BS>()) ? task : -1;
+}
 
 // ------------------------------------------------------------ k_prolong
 // Primitive face traces (rho, u, v, w, c) of the state, from the prolonged
@@ -372,9 +389,10 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
     const size_t NF = (size_t)E * 6 * G::n2;
 
     // early loads: own nodes, and the neighbour traces of this thread's line
-    const LineTask<P> lt(t);
+    const int ltask = line_of_thread<P, BS>(t);
+    const LineTask<P> lt(ltask < 0 ? 0 : ltask);
     const int el = e0 + lt.le;
-    const bool lact = t < n_lines<P, BS>() && el < E;
+    const bool lact = ltask >= 0 && el < E;
     int nbm = -1, nbp = -1;
     T wn[2][5];
     if (lact) {
@@ -526,9 +544,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     const size_t NF = (size_t)E * 6 * G::n2;
 
     // early loads: own and neighbour traces of grad c and T on this thread's line
-    const LineTask<P> lt(t);
+    const int ltask = line_of_thread<P, BS>(t);
+    const LineTask<P> lt(ltask < 0 ? 0 : ltask);
     const int el = e0 + lt.le;
-    const bool lact = t < n_lines<P, BS>() && el < E;
+    const bool lact = ltask >= 0 && el < E;
     int nb2[2] = {-1, -1};
     T own[2][4], oth[2][4];
     if (lact) {
@@ -645,10 +664,11 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 #pragma unroll 1
         for (int s = 0; s < 2; ++s) {
             const double *Lf = sL + s * P;
+            const int lo = base + lt.off, ls = lt.str;
             auto pro = [&](const T *fld) {
                 T acc = T(0);
 #pragma unroll
-                for (int l = 0; l < P; ++l) acc += T(Lf[l]) * fld[base + line_node<P>(lt.d, l, lt.p, lt.q)];
+                for (int l = 0; l < P; ++l) acc += T(Lf[l]) * fld[lo + l * ls];
                 return acc;
             };
             const int f = 2 * lt.d + s;
@@ -658,8 +678,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const bool wall = nb2[s] < 0;
             const int kind = wall ? a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind : 0;
             // state and convective part
+            // scheduling barriers keep each field group's LDS loads next to the
+            // arithmetic that consumes them (otherwise all of them are hoisted
+            // and the register demand limits occupancy)
             const T rho = pro(sU[0]), m0 = pro(sU[1]), m1 = pro(sU[2]), m2 = pro(sU[3]);
             const T E = pro(sU[4]), c = pro(sU[5]);
+            __builtin_amdgcn_sched_barrier(0);
             const T ir = T(1) / rho;
             const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
             const T mn = m0 * n0 + m1 * n1 + m2 * n2;
@@ -695,6 +719,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             }
             // viscous stress tau n = mu ((grad u + grad u^T) n - 2/3 div u n)
             T div, tn0, tn1, tn2;
+            __builtin_amdgcn_sched_barrier(0);
             {
                 const T g00 = pro(sGu[0]), g01 = pro(sGu[1]), g02 = pro(sGu[2]);
                 const T g10 = pro(sGu[3]), g11 = pro(sGu[4]), g12 = pro(sGu[5]);
@@ -721,11 +746,13 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G3 -= tnn * n2;
             }
             // heat flux
+            __builtin_amdgcn_sched_barrier(0);
             if (kind != 2) {
                 const T gTn = pro(sA[0]) * n0 + pro(sA[1]) * n1 + pro(sA[2]) * n2;
                 G4 -= T(a.ph.kappa) * gTn;
             }
             // order-parameter terms of j_e and F^V_c
+            __builtin_amdgcn_sched_barrier(0);
             if (!wall) {
                 const T gcn = a.T2[0 * NF + o] * n0 + a.T2[1 * NF + o] * n1 + a.T2[2 * NF + o] * n2;
                 const T lapc = pro(sA[3]);
@@ -801,9 +828,11 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         Tn = (double)a.TH[g];
     }
     // surface flux (F* . n) dS on both faces of this thread's line
-    const LineTask<P> lt(t);
+    const int ltask = line_of_thread<P, BS>(t);
+    const LineTask<P> lt(ltask < 0 ? 0 : ltask);
     const int el = e0 + lt.le;
-    if (t < n_lines<P, BS>() && el < E) {
+    const bool lact = ltask >= 0 && el < E;
+    if (lact) {
 #pragma unroll 1
         for (int sd = 0; sd < 2; ++sd) {
             const int f = 2 * lt.d + sd;
@@ -904,7 +933,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         }
     }
     __syncthreads();
-    if (t < n_lines<P, BS>() && el < E) {
+    if (lact) {
         const int b2 = lt.le * G::n3;
         T um[6], up[6];
 #pragma unroll
