@@ -92,6 +92,72 @@ def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_activ
     return out
 
 
+def precision_study(n=32, steps=500, restriction=4):
+    """FP32-mixed vs FP64 on the eight-droplet N=5 case: both forms run the
+    same number of steps from the same initial state with the same dt; the
+    relative L2 and max errors of rho (and c) are reported, and on the n=4
+    restriction both GPU forms are also compared with the CPU oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2208_05310_amd import workloads as wl
+    from paper_2208_05310_amd.nskr import init_workload, solver_for
+
+    def run(w, prec, U0, dt, kahan=True):
+        s = solver_for(w, prec, kahan=kahan)
+        U = U0.to(s.dtype).clone()
+        R = s.new_state()
+        t0 = time.perf_counter()
+        s.rk_steps(U, R, dt, steps)
+        torch.cuda.synchronize()
+        return U.double(), time.perf_counter() - t0, s.reduce(U, check=False)
+
+    def errs(a, b):
+        out = {}
+        for name, k in (("rho", 0), ("c", 5)):
+            d = (a[k] - b[k])
+            out[f"{name}_rel_l2"] = float(d.norm() / b[k].norm())
+            out[f"{name}_rel_max"] = float(d.abs().max() / b[k].abs().max())
+        return out
+
+    res = {"steps": steps}
+    w = wl.c3(n)
+    s = solver_for(w, "fp64")
+    U0 = init_workload(s, w)
+    dt = s.dt(U0)
+    del s
+    U64, t64, sums64 = run(w, "fp64", U0, dt)
+    U32, t32, sums32 = run(w, "fp32_mixed", U0, dt)
+    U32p, t32p, _ = run(w, "fp32_mixed", U0, dt, kahan=False)
+    nn = U0.shape[1]
+    res["full"] = {"workload": w.name, "nodes": nn, "dt": dt, "fp64_s": t64, "fp32_mixed_s": t32,
+                   "speedup": t64 / t32, "fp32_vs_fp64": errs(U32, U64),
+                   "fp32_plain_update_s": t32p, "fp32_plain_update_vs_fp64": errs(U32p, U64),
+                   "mass_fp64": float(sums64[0]), "mass_fp32_mixed": float(sums32[0])}
+    # restriction: same droplets on the n=4 mesh, GPU forms vs the oracle
+    wr = wl.c3(restriction)
+    sr = solver_for(wr, "fp64")
+    Ur = init_workload(sr, wr)
+    dtr = sr.dt(Ur)
+    del sr
+    G64, _, _ = run(wr, "fp64", Ur, dtr)
+    G32, _, _ = run(wr, "fp32_mixed", Ur, dtr)
+    import oracle
+    p = oracle.make_params(**wr.params)
+    b = oracle.make_box(wr.N, wr.n, (0.0, 0.0, 0.0), wr.length, wr.periodic, wr.side_kind, wr.side_twall,
+                        wr.side_theta)
+    o = oracle.Oracle(p, b)
+    Uo = Ur.double().cpu().numpy().copy()
+    Ro = np.zeros_like(Uo)
+    t0 = time.perf_counter()
+    o.run(Uo, Ro, 0.0, dtr, steps)
+    to = time.perf_counter() - t0
+    Uo_t = torch.tensor(Uo, device=G64.device)
+    res["restriction"] = {"workload": wr.name, "nodes": int(Uo.shape[1]), "oracle_s": to,
+                          "fp64_vs_oracle": errs(G64, Uo_t), "fp32_mixed_vs_oracle": errs(G32, Uo_t)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +170,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serving", action="store_true", help="run only the request-stream serving measurement")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="FP32-mixed vs FP64 errors on the 32^3 N=5 case over 500 steps")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -119,6 +187,9 @@ def main():
     from paper_2208_05310_amd import workloads as wl
     from paper_2208_05310_amd.nskr import init_workload, solver_for
 
+    if args.precision_study:
+        print(json.dumps({"precision_study": precision_study()}), flush=True)
+        return
     if args.serving:
         res = serving_bench(args.serving_requests, log=lambda m: None, max_active_nodes=args.serving_max_nodes)
         b, q = res["batched_fp32_mixed"], res.get("one_at_a_time_fp64")
@@ -164,6 +235,8 @@ def main():
         wall = t1 - t0
         word = 8 if precision == "fp64" else 4
         words = kernel_words_per_node(w.N)
+        if precision == "fp32_mixed" and s.kahan:
+            words["update"] += 12  # compensation of the state update, read and written
         kern = {}
         for k, (ms, cnt) in prof.items():
             if cnt and k in words:
@@ -185,7 +258,7 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     ach = kern[dom]["achieved_GBs"]
     floor_b, b3 = survey_bytes_model(w.N, word)
-    stage_b = stage_words_per_node(w.N) * word
+    stage_b = (stage_words_per_node(w.N) + (12 if args.precision == "fp32_mixed" else 0)) * word
     out = {
         "metric": METRIC,
         "value": value,

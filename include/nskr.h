@@ -63,7 +63,8 @@ typedef void *nskr_stream; /* a hipStream_t; NULL is the default stream */
 typedef struct {
     double R, a, b, cv, mu, kappa, gam, alpha, beta, cfl;
     int precision;
-    int reserved;
+    int kahan;   /* FP32-mixed only: 1 = compensated (Kahan) state update, which
+                    carries the rounding error of U += B R from stage to stage */
 } nskr_params;
 
 /* Wall boundary condition (Sec. 2.4, eq. bc_nsk_alpha with gamma_1 = gamma_4 =

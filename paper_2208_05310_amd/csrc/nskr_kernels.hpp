@@ -226,6 +226,7 @@ __device__ __forceinline__ void wall_flux(const Phys &ph, const BcDev &bc, const
 // mesh, physics and its own time step.
 template <typename T> struct Inst {
     T *U, *R, *Ut;             // state, RK register, U_t output (rhs)
+    T *Ck;                     // compensation of the state update (FP32 Kahan), or null
     T *Q, *TH, *G2;            // grad(rho,u,c) [15], T, grad T + lap c [4]
     T *T2, *TF, *TU;           // face traces: grad c + T [4], flux [13], primitives [5]
     MeshDev mesh;
@@ -927,7 +928,16 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         for (int v = 0; v < 6; ++v) {
             const T r = L.first ? dt * Ut[v] : A * a.R[v * a.NN + g] + dt * Ut[v];
             a.R[v * a.NN + g] = r;
-            const T u = u6[v] + B * r;
+            T u;
+            if (a.Ck) {
+                // compensated summation: the low-order part lost by u6 + B r is
+                // kept in Ck and fed into the next stage's increment
+                const T y = B * r - a.Ck[v * a.NN + g];
+                u = u6[v] + y;
+                a.Ck[v * a.NN + g] = (u - u6[v]) - y;
+            } else {
+                u = u6[v] + B * r;
+            }
             a.U[v * a.NN + g] = u;
             sF[v][t] = u;
         }

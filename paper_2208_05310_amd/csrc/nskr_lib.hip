@@ -33,6 +33,7 @@ struct nskr_ctx {
     std::vector<double> h_emet;  // host copy of the element metrics (weights for reductions)
     // scratch (element type of the precision)
     void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
+    void *d_Ck = nullptr;        // Kahan compensation of the FP32 state update
     double *d_part = nullptr;    // reduction partials
     double *d_out = nullptr;     // final reduction values (device)
     double *d_noise = nullptr;   // init noise
@@ -483,6 +484,12 @@ __global__ __launch_bounds__(kBlock) void k_init_energy(T *U, const T *Q, int E,
     U[4 * NN + g] = T(rho * (ph.R * ph.cv * T0 - ph.a * rho) + 0.5 * ph.gam * (q0 * q0 + q1 * q1 + q2 * q2));
 }
 
+// Zero fill (used instead of a memset so that it can sit in captured graphs).
+template <typename T> __global__ __launch_bounds__(kBlock) void k_zero(T *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) p[i] = T(0);
+}
+
 // ------------------------------------------------------------ launch layer
 template <int P, typename T, int BS> struct Impl {
     static constexpr int kP = P, kBS = BS;
@@ -503,6 +510,7 @@ template <int P, typename T, int BS> struct Impl {
     {
         Inst<T> I;
         I.U = (T *)U; I.R = (T *)R; I.Ut = (T *)Ut;
+        I.Ck = (T *)c->d_Ck;
         I.Q = (T *)c->d_Q; I.TH = (T *)c->d_TH; I.G2 = (T *)c->d_G2;
         I.T2 = (T *)c->d_T2; I.TF = (T *)c->d_TF; I.TU = (T *)c->d_TU;
         I.mesh = mesh(c); I.ph = c->ph; I.NN = c->NN; I.dt = dt;
@@ -578,10 +586,18 @@ template <int P, typename T, int BS> struct Impl {
         HIPCHK(c, hipGetLastError());
         return NSKR_OK;
     }
+    static void zero_comp(nskr_ctx *c, hipStream_t s)
+    {
+        if (!c->d_Ck) return;
+        const size_t n = 6 * c->NN;
+        const unsigned grid = (unsigned)((n + kBlock - 1) / kBlock < 4096 ? (n + kBlock - 1) / kBlock : 4096);
+        hipLaunchKernelGGL((k_zero<T>), dim3(grid), dim3(kBlock), 0, s, (T *)c->d_Ck, n);
+    }
     static int rk(nskr_ctx *c, void *U, void *R, double dt, int nsteps, hipStream_t s)
     {
         if (nsteps == 0) return NSKR_OK;
         Launch<T> L = launch(c, inst(c, U, R, nullptr, dt));
+        zero_comp(c, s);
         prolong(c, L, s);
         for (int n = 0; n < nsteps; ++n)
             for (int st = 0; st < 5; ++st) {
@@ -708,6 +724,7 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
         !(p->b >= 0) || !(p->cv > 0) || !(p->R > 0) || !(p->cfl > 0) || !(p->a >= 0))
         return NSKR_E_ARG;
     if (p->precision != 0 && p->precision != 1) return NSKR_E_ARG;
+    if (p->kahan != 0 && p->kahan != 1) return NSKR_E_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NSKR_E_HIP;
     // make sure the device code for this GPU is present
@@ -731,13 +748,13 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
 static void free_mesh(nskr_ctx *c)
 {
     void *ptrs[] = {c->d_nbr, c->d_bcid, c->d_emet, c->d_fmet, c->d_egeo, c->d_bcs, c->d_Q, c->d_TH,
-                    c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop};
+                    c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop, c->d_Ck};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_nbr = c->d_bcid = nullptr;
     c->d_emet = c->d_fmet = c->d_egeo = nullptr;
     c->d_bcs = nullptr;
-    c->d_Q = c->d_TH = c->d_G2 = c->d_T2 = c->d_TF = c->d_TU = nullptr;
+    c->d_Q = c->d_TH = c->d_G2 = c->d_T2 = c->d_TF = c->d_TU = c->d_Ck = nullptr;
     c->d_part = c->d_out = c->d_noise = c->d_drop = nullptr;
     c->E = 0;
     c->NN = c->NF = 0;
@@ -880,7 +897,8 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * 4 * c->NF)) ||
         (rc = dalloc(c, &c->d_TF, ts * 13 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 5 * c->NF)) ||
         (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
-        (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS))) {
+        (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS)) ||
+        (c->p.precision == 1 && c->p.kahan && (rc = dalloc(c, &c->d_Ck, ts * 6 * c->NN)))) {
         free_mesh(c);
         return rc;
     }
@@ -1294,6 +1312,11 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     }
     BatchSlot &sl = b->slots[k];
     sl.c = c; sl.U = U; sl.R = R; sl.dt = dt; sl.nsteps = nsteps; sl.done = 0; sl.state = 1; sl.bytes = need;
+    if (c->d_Ck) {
+        DeviceGuard guard(b->device);
+        Impl<3, float, 256>::zero_comp(c, nullptr);
+        BHIPCHK(b, hipDeviceSynchronize());
+    }
     b->used += need;
     b->dirty = true;
     *slot = k;

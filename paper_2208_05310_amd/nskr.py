@@ -39,7 +39,7 @@ class Params(ctypes.Structure):
     _fields_ = [("R", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("gam", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("kahan", ctypes.c_int)]
 
 
 class Bc(ctypes.Structure):
@@ -165,14 +165,18 @@ def _stream_ptr(stream):
 class Solver:
     """One problem instance on one GPU: parameters, polynomial degree, mesh."""
 
-    def __init__(self, params: dict, N: int, precision: str = "fp64", device: int = 0):
+    def __init__(self, params: dict, N: int, precision: str = "fp64", device: int = 0, kahan: bool = True):
+        """precision: "fp64" or "fp32_mixed"; kahan (FP32-mixed only): compensated
+        state update."""
         self.L = lib()
         self.N = int(N)
         self.precision = precision
         self.device = int(device)
         prec = {"fp64": 0, "fp32_mixed": 1}[precision]
+        self.kahan = bool(kahan) and prec == 1
         p = Params(params["R"], params["a"], params["b"], params["cv"], params["mu"], params["kappa"],
-                   params["gam"], params["alpha"], params["beta"], params.get("cfl", 0.9), prec, 0)
+                   params["gam"], params["alpha"], params["beta"], params.get("cfl", 0.9), prec,
+                   1 if self.kahan else 0)
         self.params = dict(params)
         h = ctypes.c_void_p()
         rc = self.L.nskr_create(ctypes.byref(p), self.N, self.device, ctypes.byref(h))
@@ -368,9 +372,9 @@ def _profile_methods():
 _profile_methods()
 
 
-def solver_for(w, precision="fp64", device=0):
+def solver_for(w, precision="fp64", device=0, kahan=True):
     """Solver with the mesh of a workload description (paper_2208_05310_amd.workloads)."""
-    s = Solver(w.params, w.N, precision, device)
+    s = Solver(w.params, w.N, precision, device, kahan)
     s.upload_box(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta)
     return s
 

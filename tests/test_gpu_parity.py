@@ -303,3 +303,28 @@ def test_fp32_mixed_accuracy(torch_cuda, w):
     print("fp32-mixed errors per field", err, flush=True)
     assert err[0] <= 1e-5, err
     assert np.all(err <= 1e-4), err
+
+
+def test_fp32_compensated_update_reduces_error(torch_cuda):
+    """The compensated (Kahan) FP32 state update keeps the error against the
+    FP64 oracle below that of the plain FP32 update over 60 steps."""
+    torch = torch_cuda
+    w = CASES[0]
+    o = oracle_for(w)
+    U = oracle_init(o, w)
+    dt = o.dt(U)
+    from paper_2208_05310_amd.nskr import solver_for
+    out = {}
+    for kahan in (False, True):
+        s = solver_for(w, "fp32_mixed", kahan=kahan)
+        Ug = to_gpu(torch, U, torch.float32)
+        Rg = s.new_state()
+        s.rk_steps(Ug, Rg, dt, 60)
+        torch.cuda.synchronize()
+        out[kahan] = Ug.double().cpu().numpy()
+    R = np.zeros_like(U)
+    o.run(U, R, 0.0, dt, 60)
+    e_plain = rel_err(out[False], U)[0]
+    e_comp = rel_err(out[True], U)[0]
+    print("rho error plain", e_plain, "compensated", e_comp, flush=True)
+    assert e_comp < e_plain and e_comp <= 1e-5
