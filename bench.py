@@ -20,22 +20,50 @@ METRIC = "node-stage updates/s FP64 vs FP32-mixed at stated error; batched p50/p
 PEAK_HBM_GBS = 8000.0
 
 
+def progress(msg):
+    """One line per finished phase on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_words_per_node(N):
-    """Algorithmic words moved per volume node by each kernel of one stage:
-    every array the kernel must read or write, each counted once; F = 6/(N+1)
-    own face points per node (neighbour traces are read once per side)."""
+    """Algorithmic words per volume node for each kernel of one stage: every
+    array the kernel reads or writes, each element counted once (a face trace
+    that an element and its neighbour both read counts once); F = 6/(N+1)
+    face points per node."""
     F = 6.0 / (N + 1)
     return {
         "prolong": 6 + 5 * F,             # U in; primitive traces out
-        "lift1": 22 + 9 * F,              # U, nbr traces in; grad(15), T, traces(4) out
-        "lift2": 23 + 21 * F,             # T, grad c, grad u, U, traces(own+nbr 4) in; gradT, lapc, flux traces(13) out
-        "update": 44 + 31 * F,            # U, R, grads(19), T, flux traces(own+nbr 13) in; U, R, traces(5) out
+        "lift1": 22 + 9 * F,              # U, neighbour traces in; grad(15), T, traces(4) out
+        "lift2": 23 + 17 * F,             # T, grad c, grad u, U, traces(4) in; gradT, lapc, flux traces(13) out
+        "update": 44 + 18 * F,            # U, R, grads(19), T, flux traces(13) in; U, R, traces(5) out
     }
 
 
 def stage_words_per_node(N):
     k = kernel_words_per_node(N)
     return k["lift1"] + k["lift2"] + k["update"]
+
+
+TRAFFIC_TABLE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter table
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain device copy of known size), or None when the table has
+    no entry or was taken on kernels other than the ones built now."""
+    from paper_2208_05310_amd.build import kernel_fingerprint
+    try:
+        with open(TRAFFIC_TABLE) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if tab.get("kernel_fingerprint") != kernel_fingerprint():
+        return None
+    e = tab.get("entries", {}).get(f"{workload}/{precision}", {}).get(kernel)
+    if not e:
+        return None
+    return {"read": e["read_bytes"], "written": e["written_bytes"], "total": e["read_bytes"] + e["written_bytes"]}
 
 
 def survey_bytes_model(N, word):
@@ -81,18 +109,22 @@ def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_activ
     t0 = time.perf_counter()
     table = autotune.tune(pairs, path=None)
     t_tune = time.perf_counter() - t0
-    stats, _ = serving.serve(reqs, int(budget_gb * 2**30), "fp32_mixed", table, log=log,
+    stats, _ = serving.serve(reqs, int(budget_gb * 2**30), "fp32_mixed", table,
                              max_active_nodes=max_active_nodes)
+    if log:
+        log(f"serving batched: p50 {stats['p50_s']:.2f} s, p99 {stats['p99_s']:.2f} s")
     out = {"batched_fp32_mixed": stats, "tiles": {k: v["threads"] for k, v in table.items()},
            "autotune_s": t_tune, "budget_GiB": budget_gb}
     if sequential:
         seq, _ = serving.serve_sequential(reqs, "fp64")
+        if log:
+            log(f"serving one at a time: p50 {seq['p50_s']:.2f} s, p99 {seq['p99_s']:.2f} s")
         out["one_at_a_time_fp64"] = seq
         out["speedup_throughput"] = stats["node_stage_updates_per_s"] / seq["node_stage_updates_per_s"]
     return out
 
 
-def precision_study(n=32, steps=500, restriction=4):
+def precision_study(which="c3", steps=None, restriction=True):
     """FP32-mixed vs FP64 on the eight-droplet N=5 case: both forms run the
     same number of steps from the same initial state with the same dt; the
     relative L2 and max errors of rho (and c) are reported, and on the n=4
@@ -120,8 +152,9 @@ def precision_study(n=32, steps=500, restriction=4):
             out[f"{name}_rel_max"] = float(d.abs().max() / b[k].abs().max())
         return out
 
+    w = wl.c3() if which == "c3" else wl.c4()
+    steps = steps or w.steps
     res = {"steps": steps}
-    w = wl.c3(n)
     s = solver_for(w, "fp64")
     U0 = init_workload(s, w)
     dt = s.dt(U0)
@@ -134,8 +167,14 @@ def precision_study(n=32, steps=500, restriction=4):
                    "speedup": t64 / t32, "fp32_vs_fp64": errs(U32, U64),
                    "fp32_plain_update_s": t32p, "fp32_plain_update_vs_fp64": errs(U32p, U64),
                    "mass_fp64": float(sums64[0]), "mass_fp32_mixed": float(sums32[0])}
-    # restriction: same droplets on the n=4 mesh, GPU forms vs the oracle
-    wr = wl.c3(restriction)
+    res["full"]["fp64_sums"] = dict(zip(("mass", "energy", "min_rho", "max_rho", "min_T", "max_T"),
+                                       (float(sums64[i]) for i in (0, 4, 10, 11, 12, 13))))
+    res["full"]["fp32_mixed_sums"] = dict(zip(("mass", "energy", "min_rho", "max_rho", "min_T", "max_T"),
+                                             (float(sums32[i]) for i in (0, 4, 10, 11, 12, 13))))
+    if not restriction:
+        return res
+    # restriction: same set-up on a small mesh, GPU forms vs the oracle
+    wr = wl.c3(4) if which == "c3" else wl.c4(scale=8)
     sr = solver_for(wr, "fp64")
     Ur = init_workload(sr, wr)
     dtr = sr.dt(Ur)
@@ -170,8 +209,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serving", action="store_true", help="run only the request-stream serving measurement")
-    ap.add_argument("--precision-study", action="store_true",
-                    help="FP32-mixed vs FP64 errors on the 32^3 N=5 case over 500 steps")
+    ap.add_argument("--precision-study", choices=["c3", "c4"], default=None,
+                    help="FP32-mixed vs FP64 errors over the workload's full step count (c3: 32^3 N=5, "
+                         "500 steps; c4: sessile wall case, 1000 steps)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -188,10 +228,10 @@ def main():
     from paper_2208_05310_amd.nskr import init_workload, solver_for
 
     if args.precision_study:
-        print(json.dumps({"precision_study": precision_study()}), flush=True)
+        print(json.dumps({"precision_study": precision_study(args.precision_study)}), flush=True)
         return
     if args.serving:
-        res = serving_bench(args.serving_requests, log=lambda m: None, max_active_nodes=args.serving_max_nodes)
+        res = serving_bench(args.serving_requests, log=progress, max_active_nodes=args.serving_max_nodes)
         b, q = res["batched_fp32_mixed"], res.get("one_at_a_time_fp64")
         print(json.dumps({"metric": "batched p50/p99 time-to-solution and aggregate node-stage updates/s",
                           "value": b["node_stage_updates_per_s"], "unit": "node-stage updates/s",
@@ -221,18 +261,22 @@ def main():
         R = s.new_state()
         s.rk_steps(U, R, dt, args.warmup, stream)
         torch.cuda.synchronize()
-        s.set_profiling(True)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         ev0.record(stream)
         s.rk_steps(U, R, dt, args.steps, stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        wall = t1 - t0
+        # per-kernel times: the same K steps once more, each stage dispatch
+        # carrying its own event pair (kept out of the pass above: the events
+        # cost a few per cent of step time)
+        s.set_profiling(True)
+        s.rk_steps(U, R, dt, args.steps, stream)
+        torch.cuda.synchronize()
         prof = s.profile(stream)
         s.set_profiling(False)
-        wall = t1 - t0
         word = 8 if precision == "fp64" else 4
         words = kernel_words_per_node(w.N)
         if precision == "fp32_mixed" and s.kahan:
@@ -254,6 +298,7 @@ def main():
     if args.precision == "fp64":
         U0 = U0.double()
     r = timed_run(args.precision, U0)
+    progress(f"{w.name} {args.precision}: {r['value']:.4g} node-stage updates/s")
     nn, value, kern, word = r["nnodes"], r["value"], r["kern"], r["word"]
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     ach = kern[dom]["achieved_GBs"]
@@ -278,6 +323,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": ach / PEAK_HBM_GBS, "traffic": None},
         "kernels": kern,
+        "kernel_timing": "HIP event pair carried by each stage dispatch (start/stop of the kernel on the caller's "
+                         "stream) over a second pass of the same K steps right after the timed pass",
         "stage_model": {"design_bytes_per_node_stage": stage_b,
                         "design_GBs": value * stage_b / 1e9,
                         "B_3phase_bytes": b3, "B_3phase_GBs": value * b3 / 1e9,
@@ -285,9 +332,24 @@ def main():
         "gpu_event_ms": r["gpu_ms"],
         "final_mass": r["mass"],
     }
+    # measured HBM bytes per node-stage (lift1 + lift2 + update, counters)
+    trs = [measured_traffic(w.name, args.precision, k) for k in ("lift1", "lift2", "update")]
+    if all(trs):
+        mb = sum(t["total"] for t in trs) / nn
+        out["stage_model"]["measured_bytes_per_node_stage"] = mb
+        out["stage_model"]["measured_GBs"] = value * mb / 1e9
+        out["stage_model"]["measured_frac"] = value * mb / 1e9 / PEAK_HBM_GBS
+    tr = measured_traffic(w.name, args.precision, dom)
+    if tr:
+        alg = kern[dom]["alg_bytes_per_launch"]
+        out["roofline"]["traffic"] = tr["total"]
+        out["roofline"]["traffic_detail"] = {"unit": "bytes per launch", "read": tr["read"],
+                                             "written": tr["written"], "algorithmic": alg,
+                                             "ratio_to_algorithmic": tr["total"] / alg}
     if args.precision == "fp64" and not args.no_fp32:
         # the FP32-mixed form on the same workload, initial state and dt: speed and error
         r32 = timed_run("fp32_mixed", U0)
+        progress(f"{w.name} fp32_mixed: {r32['value']:.4g} node-stage updates/s")
         a, b_ = r32["U"][0].double(), r["U"][0]
         k32 = r32["kern"]
         d32 = max(k32, key=lambda k: k32[k]["avg_us"] * k32[k]["launches"])
@@ -295,13 +357,13 @@ def main():
             "value": r32["value"], "speedup_vs_fp64": r32["value"] / value,
             "rho_rel_max_err_vs_fp64": float((a - b_).abs().max() / b_.abs().max()),
             "rho_rel_l2_err_vs_fp64": float((a - b_).norm() / b_.norm()),
-            "after_steps": args.warmup + args.steps,
+            "after_steps": args.warmup + 2 * args.steps,
             "roofline": {"kernel": d32, "achieved": k32[d32]["achieved_GBs"], "peak": PEAK_HBM_GBS,
                          "frac": k32[d32]["achieved_GBs"] / PEAK_HBM_GBS},
             "kernels": k32}
     if not args.no_serving:
         try:
-            res = serving_bench(args.serving_requests, max_active_nodes=args.serving_max_nodes)
+            res = serving_bench(args.serving_requests, max_active_nodes=args.serving_max_nodes, log=progress)
             bt, sq = res["batched_fp32_mixed"], res.get("one_at_a_time_fp64", {})
             out["serving"] = {"requests": bt["requests"], "p50_s": bt["p50_s"], "p99_s": bt["p99_s"],
                               "aggregate_node_stage_updates_per_s": bt["node_stage_updates_per_s"],
@@ -313,6 +375,7 @@ def main():
             out["serving"] = {"error": repr(e)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        progress(f"cpu baseline: {out['cpu_baseline']['sample']}")
     print(json.dumps(out), flush=True)
 
 

@@ -248,7 +248,10 @@ int nskr_batch_set_graph(nskr_batch *b, int on);
 int nskr_batch_admit(nskr_batch *b, nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, int *slot);
 
 /* One RK step of every active instance on stream s (asynchronous).  Instances
- * that reach their step count become finished and stop advancing. */
+ * that reach their step count become finished and stop advancing.  The first
+ * step after an instance is admitted also prolongs its state to its faces
+ * (one direct launch before the graph); later steps take the face traces the
+ * previous step's last stage wrote, exactly as nskr_rk_steps does. */
 int nskr_batch_step(nskr_batch *b, nskr_stream s);
 
 /* Finished slots (up to cap written to slots, total count in *n). */

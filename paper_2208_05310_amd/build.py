@@ -1,6 +1,7 @@
 """Build the gfx950 shared library libnskr.so in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -15,6 +16,20 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+
+
+KERNELS = os.path.join(HERE, "csrc", "nskr_kernels.hpp")
+
+
+def kernel_fingerprint() -> str:
+    """sha256 over the device-kernel source and the compile flags: hardware
+    counters taken for one fingerprint say nothing about kernels built from
+    another."""
+    h = hashlib.sha256()
+    with open(KERNELS, "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(FLAGS).encode())
+    return h.hexdigest()
 
 
 def build(verbose: bool = False) -> str:

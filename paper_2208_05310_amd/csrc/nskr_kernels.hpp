@@ -248,12 +248,28 @@ template <typename T> struct Launch {
     double A, B;     // RK coefficients of this stage
 };
 
+// A pointer read from ordinary device memory is generic to the compiler,
+// which then emits flat loads and stores for everything addressed through it.
+// The instance table is read-only while a kernel runs, so read it through the
+// constant address space: pointers loaded from there are known to point to
+// global memory, and accesses through them compile to global loads and stores
+// exactly as for pointers passed by value in the kernel arguments.
+template <typename P> __device__ __forceinline__ P load_const(const P *p, int i)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const __attribute__((address_space(4))) P *)p)[i];
+#else
+    return p[i];  // host pass: the body is never run on the host
+#endif
+}
+
 template <typename T, bool BATCH>
 __device__ __forceinline__ void instance_of(const Launch<T> &L, Inst<T> &a, int &e0, int epb)
 {
     if (BATCH) {
-        a = L.tab[L.blk_inst[blockIdx.x]];
-        e0 = L.blk_e0[blockIdx.x];
+        const int k = load_const(L.blk_inst, blockIdx.x);
+        e0 = load_const(L.blk_e0, blockIdx.x);
+        a = load_const(L.tab, k);
     } else {
         a = L.one;
         e0 = blockIdx.x * epb;

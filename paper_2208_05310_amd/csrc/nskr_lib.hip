@@ -2,6 +2,7 @@
 // argument validation, mesh and metric upload, per-wall constants, launch
 // sequences of the DGSEM stages, the low-storage RK loop, the FP64 time-step
 // and integral reductions, and the droplet initialisation.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -47,37 +48,40 @@ struct nskr_ctx {
     std::vector<hipEvent_t> event_pool;
 };
 
-// Event pair around one kernel launch when profiling is on.
-struct KernelTimer {
-    nskr_ctx *c;
-    int kind;
-    hipStream_t s;
-    hipEvent_t a = nullptr, b = nullptr;
-    static hipEvent_t take(nskr_ctx *c)
-    {
-        if (!c->event_pool.empty()) {
-            hipEvent_t e = c->event_pool.back();
-            c->event_pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+// Events for per-kernel timing, reused across profile reads.
+static hipEvent_t take_event(nskr_ctx *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
         return e;
     }
-    KernelTimer(nskr_ctx *c_, int kind_, hipStream_t s_) : c(c_), kind(kind_), s(s_)
-    {
-        if (!c->prof) return;
-        a = take(c);
-        b = take(c);
-        if (a) (void)hipEventRecord(a, s);
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch one stage kernel.  With profiling on, the event pair rides on the
+// dispatch itself, so the recorded interval is the kernel's own begin-to-end
+// time (no dispatch gap, no marker packets between kernels).
+template <typename T>
+static void stage_launch(nskr_ctx *c, int kind, void (*kern)(Launch<T>), unsigned grid, unsigned block,
+                         hipStream_t s, const Launch<T> &L)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->prof) {
+        a = take_event(c);
+        b = take_event(c);
     }
-    ~KernelTimer()
-    {
-        if (!c->prof || !a || !b) return;
-        (void)hipEventRecord(b, s);
+    if (a && b) {
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, a, b, 0, L);
         c->prof_events.push_back({kind, {a, b}});
+        return;
     }
-};
+    if (a) c->event_pool.push_back(a);
+    if (b) c->event_pool.push_back(b);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, s, L);
+}
 
 static const char *g_null_msg = "nskr: null context";
 
@@ -541,29 +545,26 @@ template <int P, typename T, int BS> struct Impl {
     // single-instance launches
     static void prolong(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        KernelTimer kt(c, 0, s);
-        hipLaunchKernelGGL((k_prolong<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
+        stage_launch<T>(c, 0, &k_prolong<P, T, BS, false>, nblk(c), BS, s, L);
     }
     static void lift1(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        KernelTimer kt(c, 1, s);
-        hipLaunchKernelGGL((k_lift1<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
+        stage_launch<T>(c, 1, &k_lift1<P, T, BS, false>, nblk(c), BS, s, L);
     }
     static void lift2(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        KernelTimer kt(c, 2, s);
-        hipLaunchKernelGGL((k_lift2<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
+        stage_launch<T>(c, 2, &k_lift2<P, T, BS, false>, nblk(c), BS, s, L);
     }
     static void update(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        KernelTimer kt(c, 3, s);
-        hipLaunchKernelGGL((k_update<P, T, BS, false>), dim3(nblk(c)), dim3(BS), 0, s, L);
+        stage_launch<T>(c, 3, &k_update<P, T, BS, false>, nblk(c), BS, s, L);
     }
     // batched launches over a group table
+    // one RK step of every instance of a group; the face traces of the first
+    // stage come from the previous step's last update (or from prime())
     static void step_batched(const Launch<T> &L0, int nblocks, hipStream_t s)
     {
         Launch<T> L = L0;
-        hipLaunchKernelGGL((k_prolong<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
         for (int st = 0; st < 5; ++st) {
             L.mode = 1;
             L.first = st == 0;
@@ -575,6 +576,13 @@ template <int P, typename T, int BS> struct Impl {
         }
     }
 
+    // traces of a newly admitted batch instance (once, as at the start of rk())
+    static int prime(nskr_ctx *c, void *U, void *R, double dt, hipStream_t s)
+    {
+        Launch<T> L = launch(c, inst(c, U, R, nullptr, dt));
+        prolong(c, L, s);
+        return NSKR_OK;
+    }
     static int rhs(nskr_ctx *c, const void *U, void *Ut, hipStream_t s)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, Ut, 0.0));
@@ -1116,6 +1124,7 @@ struct BatchSlot {
     double dt = 0.0;
     int nsteps = 0, done = 0;
     int state = 0;  // 0 free, 1 active, 2 finished (awaiting retire)
+    bool fresh = true;  // face traces not yet prolonged
     size_t bytes = 0;
 };
 
@@ -1312,6 +1321,7 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     }
     BatchSlot &sl = b->slots[k];
     sl.c = c; sl.U = U; sl.R = R; sl.dt = dt; sl.nsteps = nsteps; sl.done = 0; sl.state = 1; sl.bytes = need;
+    sl.fresh = true;
     if (c->d_Ck) {
         DeviceGuard guard(b->device);
         Impl<3, float, 256>::zero_comp(c, nullptr);
@@ -1347,6 +1357,11 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
         int rc = batch_rebuild(b);
         if (rc) return rc;
     }
+    for (auto &sl : b->slots)
+        if (sl.state == 1 && sl.fresh) {
+            dispatch(sl.c, [&](auto impl) { return decltype(impl)::prime(sl.c, sl.U, sl.R, sl.dt, s); });
+            sl.fresh = false;
+        }
     if (b->use_graph) {
         if (!b->exec) {
             BHIPCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));

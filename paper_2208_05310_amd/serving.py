@@ -119,12 +119,15 @@ def serve(requests, budget_bytes, precision="fp32_mixed", table=None, keep_resul
     }, reqs
 
 
-def serve_sequential(requests, precision="fp64", time_scale=1.0, keep_results=False):
-    """Baseline: the same requests one at a time (arrival order, no batching),
-    each with the single-instance path; latencies include the queueing a
+def serve_sequential(requests, precision="fp64", time_scale=1.0, keep_results=False, graph=True):
+    """Baseline: the same requests one at a time in arrival order, each alone
+    in a batch of one (graph-replayed steps, so the baseline pays no more
+    launch overhead than the batched loop); latencies include the queueing a
     single server would impose on the same arrival clock."""
     import torch
     reqs = [Request(i, t * time_scale, w) for i, (t, w) in enumerate(requests)]
+    batch = Batch(1 << 62, graph=graph)
+    stream = torch.cuda.Stream()
     t_free = 0.0
     node_stages = 0
     t0 = time.perf_counter()
@@ -138,8 +141,13 @@ def serve_sequential(requests, precision="fp64", time_scale=1.0, keep_results=Fa
         U = init_workload(s, req.w)
         R = s.new_state()
         dt = s.dt(U)
-        s.rk_steps(U, R, dt, req.w.steps)
         torch.cuda.synchronize()
+        slot = batch.admit(s, U, R, dt, req.w.steps)
+        for _ in range(req.w.steps):
+            batch.step(stream)
+        stream.synchronize()
+        assert batch.poll() == [slot]
+        batch.retire(slot)
         service = time.perf_counter() - ts
         req.t_admit = start
         req.t_done = start + service
