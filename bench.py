@@ -32,10 +32,12 @@ def kernel_words_per_node(N):
     face points per node."""
     F = 6.0 / (N + 1)
     return {
-        "prolong": 6 + 5 * F,             # U in; primitive traces out
-        "lift1": 22 + 9 * F,              # U, neighbour traces in; grad(15), T, traces(4) out
-        "lift2": 23 + 17 * F,             # T, grad c, grad u, U, traces(4) in; gradT, lapc, flux traces(13) out
-        "update": 44 + 18 * F,            # U, R, grads(19), T, flux traces(13) in; U, R, traces(5) out
+        "prolong": 6 + 6 * F,             # U in; conserved traces out
+        "lift1": 6 + 5 * F,               # U, neighbour c traces in; grad c + T traces (4) out
+        "lift2": 10 + 16 * F,             # U, neighbour traces (rho, m, c: 5), grad c + T traces (4) in;
+                                          # grad T + lap c (4), flux + wave-speed traces (7) out
+        "update": 28 + 19 * F,            # U, R, grad T + lap c, neighbour conserved traces (6), flux traces (7)
+                                          # in; U, R, conserved traces (6) out
     }
 
 
@@ -214,6 +216,8 @@ def main():
                          "500 steps; c4: sessile wall case, 1000 steps)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
+    ap.add_argument("--threads", type=int, default=256, choices=[256, 512],
+                    help="workgroup size of the stage kernels")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -254,6 +258,7 @@ def main():
     def timed_run(precision, U0=None):
         """Warm-up + K timed steps; returns throughput, per-kernel data, final state."""
         s = solver_for(w, precision)
+        s.set_block(args.threads)
         if U0 is None:
             U = init_workload(s, w)
         else:
@@ -317,7 +322,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic: seeded droplet state (tanh profiles at Maxwell densities, uniform noise 1e-6)",
-        "config": {"workload": w.name, "elements": w.nelems, "N": w.N, "nodes": nn,
+        "config": {"workload": w.name, "elements": w.nelems, "N": w.N, "nodes": nn, "threads": args.threads,
                    "precision": args.precision, "alpha": w.params["alpha"], "beta": w.params["beta"],
                    "T0": w.T0, "dt": dt, "rk": "5-stage 2N RK4(3)5"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -3,24 +3,33 @@
 // equations with a van der Waals fluid (arXiv 2208.05310, Sec. 2.3.2, 2.4, 3).
 //
 // Execution model
-//   One workgroup of 256 threads owns EPB = 256 / (N+1)^3 elements; each
-//   thread owns one volume node.  Element tiles are staged in LDS for the 1D
-//   derivative sweeps along xi, eta, zeta; face work runs as a strided loop
-//   over the block's face points.  State is structure-of-arrays
-//   [var][element][node]; face traces are element-major [var][element][face]
-//   [point] so that each element writes its own six faces contiguously and
-//   reads its neighbour's face as one contiguous run.
+//   One workgroup of 256 (or 512) threads owns EPB = threads / (N+1)^3
+//   elements; each thread owns one volume node.  Element tiles are staged in
+//   LDS for the 1D derivative sweeps along xi, eta, zeta; face work runs as
+//   line tasks (one thread per grid line normal to a face pair).  State is
+//   structure-of-arrays [var][element][node]; face traces are element-major
+//   [var][element][face][point] so that each element writes its own six faces
+//   contiguously and reads its neighbour's face as one contiguous run.
 //
-// Phases of one stage (BR1 needs three neighbour exchanges):
-//   k_lift1  : U + neighbour primitive traces -> grad(rho,u,c) (15 fields), T
-//              at the nodes, and own-face traces of grad c and T.
-//   k_lift2  : T, grad c + neighbour traces -> grad T (3), lap c (1); then the
-//              own-face flux traces (normal flux, wave speed, state) or the
-//              complete wall flux on wall faces.
-//   k_update : volume integral of the contravariant fluxes, surface integral
+// Data flow of one stage (BR1 needs three neighbour exchanges).  Only what a
+// later kernel cannot rebuild from the state goes through memory: the lifted
+// gradients of the primitives are recomputed where they are needed from the
+// state and the neighbours' conserved face traces, which costs a few hundred
+// flops per node and saves their storage round trip.
+//   k_lift1  : U + neighbour c traces -> lifted grad c; own-face traces of
+//              grad c and of the face temperature (T2).
+//   k_lift2  : U + neighbour conserved traces -> lifted grad u, grad c, nodal
+//              T; with the T2 traces of both sides -> grad T, lap c (G2);
+//              then the own-face flux traces (normal flux, wave speed), or the
+//              complete wall flux on wall faces (TF).
+//   k_update : U + neighbour conserved traces -> all lifted gradients again;
+//              volume integral of the contravariant fluxes, surface integral
 //              of the Rusanov + central viscous face flux, point-wise source,
-//              Jacobian scaling, RK stage update, and the primitive face
+//              Jacobian scaling, RK stage update, and the conserved face
 //              traces of the new state for the next stage.
+// The conserved traces rotate over three buffers: stage s reads buffer b(s)
+// and writes b(s+1), b = 0 1 0 1 2 (0), so no kernel overwrites traces that
+// a neighbouring workgroup may still read.
 // Metric terms are per element (affine elements).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -227,8 +236,10 @@ __device__ __forceinline__ void wall_flux(const Phys &ph, const BcDev &bc, const
 template <typename T> struct Inst {
     T *U, *R, *Ut;             // state, RK register, U_t output (rhs)
     T *Ck;                     // compensation of the state update (FP32 Kahan), or null
-    T *Q, *TH, *G2;            // grad(rho,u,c) [15], T, grad T + lap c [4]
-    T *T2, *TF, *TU;           // face traces: grad c + T [4], flux [13], primitives [5]
+    T *Q, *TH;                 // grad(rho,u,c) [15] and T, for the API outputs only
+    T *G2;                     // grad T + lap c [4]
+    T *T2, *TF, *TU;           // face traces: grad c + T [4], flux + wave speed [7],
+                               // conserved state [3 buffers][6]
     MeshDev mesh;
     Phys ph;
     size_t NN;                 // nodes of the instance
@@ -245,6 +256,8 @@ template <typename T> struct Launch {
     Basis bas;
     int mode;        // update: 0 write U_t; 1 RK stage (update U, R, write traces)
     int first;       // RK: assign R at the first stage
+    int tb, tw;      // conserved-trace buffer read by this stage, written for the next
+    int full;        // k_lift1: also all lifted gradients and T at the nodes (API outputs)
     double A, B;     // RK coefficients of this stage
 };
 
@@ -325,6 +338,23 @@ __device__ __forceinline__ void prolong2(const T *s, int base, const double *sL,
     vp = ap;
 }
 
+// Face task: face point fp of face f of local element le, with the line of
+// the element that ends on it (node l of the line is off + l * str).
+template <int P> struct FaceTask {
+    int le, f, fp, off, str;
+    __device__ __forceinline__ FaceTask(int task)
+    {
+        constexpr int n2 = P * P;
+        le = task / (6 * n2);
+        const int r = task - le * 6 * n2;
+        f = r / n2;
+        fp = r - f * n2;
+        const int d = f >> 1, p = fp % P, q = fp / P;
+        off = d == 0 ? P * fp : (d == 1 ? p + P * P * q : fp);
+        str = d == 0 ? 1 : (d == 1 ? P : P * P);
+    }
+};
+
 template <int P, int BS> __device__ __forceinline__ constexpr int n_lines() { return Tile<P, BS>::EPB * 3 * P * P; }
 
 // Line task of thread t, or -1.  Every wave (on its own SIMD) gets an equal,
@@ -339,9 +369,110 @@ template <int P, int BS> __device__ __forceinline__ int line_of_thread(int t)
     return (l < C && task < n_lines<P, BS>()) ? task : -1;
 }
 
+// ------------------------------------------------------------ shared pieces
+// Primitive variables (rho, u, v, w, c) of a conserved state.
+template <typename T> __device__ __forceinline__ void primitives(const T u6[6], T w[5])
+{
+    const T ir = T(1) / u6[0];
+    w[0] = u6[0];
+    w[1] = u6[1] * ir;
+    w[2] = u6[2] * ir;
+    w[3] = u6[3] * ir;
+    w[4] = u6[5];
+}
+
+// BR1 face values of the primitives on a wall face: the interior values with
+// the velocity set to zero (no-slip) or stripped of its normal part (slip).
+template <typename T> __device__ __forceinline__ void wall_primitives(const MeshDev &m, int el, int f, T w[5])
+{
+    const BcDev bc = m.bcs[m.bcid[el * 6 + f] - 1];
+    if (bc.kind == 1) {
+        w[1] = w[2] = w[3] = T(0);
+    } else {
+        const double *fm = m.fmet + ((size_t)el * 6 + f) * 4;
+        const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+        const T un = w[1] * n0 + w[2] * n1 + w[3] * n2;
+        w[1] -= un * n0;
+        w[2] -= un * n1;
+        w[3] -= un * n2;
+    }
+}
+
+// BR1 lifted gradient of one field at element-local node (i, j, k):
+// J q_m = sum_d Ja^d_m (Dhat w + lhat(+1) w*_+ - lhat(-1) w*_-), from the node
+// values fw (element starting at base) and face values fs (element's face
+// points starting at fbase) in LDS.
+template <int P, typename T>
+__device__ __forceinline__ void lifted_grad(const T *fw, const T *fs, int base, int fbase, int i, int j, int k,
+                                            const double *sDh, const double *sLh, const T Ja[9], T iJ, T q[3])
+{
+    constexpr int n2 = P * P;
+    const int idx[3] = {i, j, k};
+    const int fpd[3] = {j + P * k, i + P * k, i + P * j};
+    T gd[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T acc = T(0);
+        const int id = idx[d];
+        const int p = d == 0 ? j : i, r = d == 2 ? j : k;
+#pragma unroll
+        for (int l = 0; l < P; ++l) acc += T(sDh[id * P + l]) * fw[base + line_node<P>(d, l, p, r)];
+        acc += T(sLh[P + id]) * fs[fbase + (2 * d + 1) * n2 + fpd[d]];
+        acc -= T(sLh[id]) * fs[fbase + (2 * d) * n2 + fpd[d]];
+        gd[d] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) q[m] = iJ * (Ja[m] * gd[0] + Ja[3 + m] * gd[1] + Ja[6 + m] * gd[2]);
+}
+
+// The same lifted gradient for NFLD consecutive LDS fields at once, sweeping
+// direction by direction so that only one row of Dhat is live: the reference
+// derivatives gd[f][d] first, then the metric transform.  Each (field,
+// direction) sum is formed exactly as in lifted_grad.
+template <int P, int NFLD, int NVS, int NFS, typename T>
+__device__ __forceinline__ void lifted_grads(const T (*fw)[NVS], const T (*fs)[NFS], int base, int fbase, int i, int j,
+                                             int k, const double *sDh, const double *sLh, T gd[NFLD][3])
+{
+    constexpr int n2 = P * P;
+    const int idx[3] = {i, j, k};
+    const int fpd[3] = {j + P * k, i + P * k, i + P * j};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int id = idx[d];
+        const int p = d == 0 ? j : i, r = d == 2 ? j : k;
+        T Dl[P];
+#pragma unroll
+        for (int l = 0; l < P; ++l) Dl[l] = T(sDh[id * P + l]);
+        const T lp = T(sLh[P + id]), lm = T(sLh[id]);
+#pragma unroll
+        for (int f = 0; f < NFLD; ++f) {
+            T acc = T(0);
+#pragma unroll
+            for (int l = 0; l < P; ++l) acc += Dl[l] * fw[f][base + line_node<P>(d, l, p, r)];
+            acc += lp * fs[f][fbase + (2 * d + 1) * n2 + fpd[d]];
+            acc -= lm * fs[f][fbase + (2 * d) * n2 + fpd[d]];
+            gd[f][d] = acc;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <typename T> __device__ __forceinline__ void to_physical(const T Ja[9], T iJ, const T gd[3], T q[3])
+{
+#pragma unroll
+    for (int m = 0; m < 3; ++m) q[m] = iJ * (Ja[m] * gd[0] + Ja[3 + m] * gd[1] + Ja[6 + m] * gd[2]);
+}
+
+template <typename T> __device__ __forceinline__ void element_metrics(const MeshDev &m, int e, T Ja[9], T &iJ)
+{
+    const double *em = m.emet + (size_t)e * 10;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) Ja[r] = T(em[r]);
+    iJ = T(1.0 / em[9]);
+}
+
 // ------------------------------------------------------------ k_prolong
-// Primitive face traces (rho, u, v, w, c) of the state, from the prolonged
-// conserved variables.
+// Conserved face traces of the state (into trace buffer L.tw).
 template <int P, typename T, int BS, bool BATCH>
 __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 {
@@ -361,6 +492,7 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
     }
     __syncthreads();
     const size_t NF = (size_t)E * 6 * G::n2;
+    T *TU = a.TU + (size_t)L.tw * 6 * NF;
     for (int task = t; task < n_lines<P, BS>(); task += BS) {
         LineTask<P> lt(task);
         const int e = e0 + lt.le;
@@ -371,19 +503,17 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
         for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, um[v], up[v]);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const T *u6 = s ? up : um;
             const size_t o = ((size_t)e * 6 + 2 * lt.d + s) * G::n2 + lt.fp;
-            const T ir = T(1) / u6[0];
-            a.TU[0 * NF + o] = u6[0];
-            a.TU[1 * NF + o] = u6[1] * ir;
-            a.TU[2 * NF + o] = u6[2] * ir;
-            a.TU[3 * NF + o] = u6[3] * ir;
-            a.TU[4 * NF + o] = u6[5];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) TU[v * NF + o] = s ? up[v] : um[v];
         }
     }
 }
 
 // ------------------------------------------------------------ k_lift1
+// Lifted grad c, and the own-face traces of grad c and of the face
+// temperature.  With L.full also every lifted gradient and the nodal
+// temperature (Q, TH) for the API outputs.
 template <int P, typename T, int BS, bool BATCH>
 __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
 {
@@ -404,6 +534,8 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
     const size_t NF = (size_t)E * 6 * G::n2;
+    const bool full = L.full != 0;
+    const T *TU = a.TU + (size_t)L.tb * 6 * NF;
 
     // early loads: own nodes, and the neighbour traces of this thread's line
     const int ltask = line_of_thread<P, BS>(t);
@@ -411,7 +543,7 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
     const int el = e0 + lt.le;
     const bool lact = ltask >= 0 && el < E;
     int nbm = -1, nbp = -1;
-    T wn[2][5];
+    T wn[2][6];
     if (lact) {
         nbm = a.mesh.nbr[el * 6 + 2 * lt.d];
         nbp = a.mesh.nbr[el * 6 + 2 * lt.d + 1];
@@ -420,94 +552,86 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
             const int nb = s ? nbp : nbm;
             if (nb >= 0) {
                 const size_t o = ((size_t)nb * 6 + (2 * lt.d + 1 - s)) * G::n2 + lt.fp;
+                if (full) {
 #pragma unroll
-                for (int k = 0; k < 5; ++k) wn[s][k] = a.TU[k * NF + o];
+                    for (int v = 0; v < 6; ++v)
+                        if (v != 4) wn[s][v] = TU[v * NF + o];
+                } else {
+                    wn[s][5] = TU[5 * NF + o];
+                }
             }
         }
     }
     if (act) {
-        T u6[6];
+        T u6[6], w[5];
 #pragma unroll
         for (int v = 0; v < 6; ++v) { u6[v] = a.U[v * a.NN + g]; sU[v][t] = u6[v]; }
-        const T ir = T(1) / u6[0];
-        sW[0][t] = u6[0];
-        sW[1][t] = u6[1] * ir;
-        sW[2][t] = u6[2] * ir;
-        sW[3][t] = u6[3] * ir;
-        sW[4][t] = u6[5];
+        primitives(u6, w);
+        if (full) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) sW[k][t] = w[k];
+        }
+        sW[4][t] = w[4];
     }
     __syncthreads();
-    // face values w* of the BR1 lifting on both faces of the line
+    // BR1 face values w* on both faces of the line
     if (lact) {
-        T uf[2][6];
         const int base = lt.le * G::n3;
+        T uf[2][6];
+        if (full) {
 #pragma unroll
-        for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
+            for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
+        } else {
+            prolong2<P>(sU[5], base, sL, lt, uf[0][5], uf[1][5]);
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int f = 2 * lt.d + s;
-            const T ir = T(1) / uf[s][0];
-            T w[5] = {uf[s][0], uf[s][1] * ir, uf[s][2] * ir, uf[s][3] * ir, uf[s][5]};
             const int nb = s ? nbp : nbm;
-            if (nb >= 0) {
-#pragma unroll
-                for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + wn[s][k]);
-            } else {
-                const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                if (bc.kind == 1) {
-                    w[1] = w[2] = w[3] = T(0);
-                } else {
-                    const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
-                    const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
-                    const T un = w[1] * n0 + w[2] * n1 + w[3] * n2;
-                    w[1] -= un * n0;
-                    w[2] -= un * n1;
-                    w[3] -= un * n2;
-                }
-            }
             const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
+            if (full) {
+                T w[5];
+                primitives(uf[s], w);
+                if (nb >= 0) {
+                    T v5[5];
+                    primitives(wn[s], v5);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
+                    for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + v5[k]);
+                } else {
+                    wall_primitives(a.mesh, el, f, w);
+                }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
+            } else {
+                sS[4][slot] = nb >= 0 ? T(0.5) * (uf[s][5] + wn[s][5]) : uf[s][5];
+            }
         }
     }
     __syncthreads();
-    // volume + surface: J q_m = sum_d Ja^d_m (Dhat w + lhat+ w*_+ - lhat- w*_-)
     T qc[3] = {T(0), T(0), T(0)};
     if (act) {
         const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
-        const int idx[3] = {i, j, k};
-        const int fpd[3] = {j + P * k, i + P * k, i + P * j};
-        const double *em = a.mesh.emet + (size_t)e * 10;
-        T Ja[9];
+        T Ja[9], iJ;
+        element_metrics(a.mesh, e, Ja, iJ);
+        const int base = le * G::n3, fbase = le * 6 * G::n2;
+        if (full) {
 #pragma unroll
-        for (int r = 0; r < 9; ++r) Ja[r] = T(em[r]);
-        const T iJ = T(1.0 / em[9]);
-        const int base = le * G::n3;
-        const int fbase = le * 6 * G::n2;
+            for (int w = 0; w < 4; ++w) {
+                T q[3];
+                lifted_grad<P>(sW[w], sS[w], base, fbase, i, j, k, sDh, sLh, Ja, iJ, q);
 #pragma unroll
-        for (int w = 0; w < 5; ++w) {
-            T gd[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                T acc = T(0);
-                const int id = idx[d];
-                const int p = d == 0 ? j : i, q = d == 2 ? j : k;
-#pragma unroll
-                for (int l = 0; l < P; ++l) acc += T(sDh[id * P + l]) * sW[w][base + line_node<P>(d, l, p, q)];
-                acc += T(sLh[P + id]) * sS[w][fbase + (2 * d + 1) * G::n2 + fpd[d]];
-                acc -= T(sLh[id]) * sS[w][fbase + (2 * d) * G::n2 + fpd[d]];
-                gd[d] = acc;
-            }
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const T q = iJ * (Ja[m] * gd[0] + Ja[3 + m] * gd[1] + Ja[6 + m] * gd[2]);
-                a.Q[(3 * w + m) * a.NN + g] = q;
-                if (w == 4) qc[m] = q;
+                for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[m];
             }
         }
-        const double Tn = temperature(a.ph, (double)sU[0][t], (double)sU[1][t], (double)sU[2][t], (double)sU[3][t],
-                                      (double)sU[4][t], (double)sU[5][t], (double)qc[0], (double)qc[1], (double)qc[2]);
-        a.TH[g] = T(Tn);
+        lifted_grad<P>(sW[4], sS[4], base, fbase, i, j, k, sDh, sLh, Ja, iJ, qc);
+        if (full) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) a.Q[(12 + m) * a.NN + g] = qc[m];
+            const double Tn = temperature(a.ph, (double)sU[0][t], (double)sU[1][t], (double)sU[2][t], (double)sU[3][t],
+                                          (double)sU[4][t], (double)sU[5][t], (double)qc[0], (double)qc[1],
+                                          (double)qc[2]);
+            a.TH[g] = T(Tn);
+        }
     }
     __syncthreads();
     // reuse sW[0..2] for grad c to prolong it to the faces
@@ -546,11 +670,17 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     Inst<T> a;
     int e0;
     instance_of<T, BATCH>(L, a, e0, G::EPB);
-    __shared__ T sA[5][G::NV];     // T, grad c (3); then grad T (3), lap c
+    // sX holds the primitives u, v, w, c [4][NV] and their BR1 face values
+    // [4][NF] while grad u and grad c are lifted, then grad u [9][NV]
+    constexpr int kX = 9 * G::NV > 4 * G::NV + 4 * G::NF ? 9 * G::NV : 4 * G::NV + 4 * G::NF;
+    __shared__ T sA[4][G::NV];     // T, grad c; then grad T, lap c
     __shared__ T sU[6][G::NV];
-    __shared__ T sGu[9][G::NV];
+    __shared__ T sX[kX];
     __shared__ T sTs[G::NF], sFs[G::NF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
+    T(*sW)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sX);
+    T(*sS)[G::NF] = reinterpret_cast<T(*)[G::NF]>(sX + 4 * G::NV);
+    T(*sGu)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sX);
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
     const int t = threadIdx.x;
@@ -559,80 +689,125 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
     const size_t NF = (size_t)E * 6 * G::n2;
+    const T *TU = a.TU + (size_t)L.tb * 6 * NF;
 
-    // early loads: own and neighbour traces of grad c and T on this thread's line
-    const int ltask = line_of_thread<P, BS>(t);
-    const LineTask<P> lt(ltask < 0 ? 0 : ltask);
-    const int el = e0 + lt.le;
-    const bool lact = ltask >= 0 && el < E;
-    int nb2[2] = {-1, -1};
-    T own[2][4], oth[2][4];
-    if (lact) {
+    // face work runs as face tasks (one face point per thread, a second round
+    // where the block has more face points than threads); the first round's
+    // traces are loaded before the node loads: the neighbour's conserved state
+    // (rho, m, c) and both sides' grad c and T
+    struct Tr {
+        int nb;
+        T own[4], oth[4], wn[6];
+    };
+    auto load_tr = [&](int task, Tr &r) {
+        const FaceTask<P> ft(task);
+        const int el = e0 + ft.le;
+        r.nb = -1;
+        if (el >= E) return;
+        const size_t o = ((size_t)el * 6 + ft.f) * G::n2 + ft.fp;
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int f = 2 * lt.d + s;
-            const size_t o = ((size_t)el * 6 + f) * G::n2 + lt.fp;
+        for (int k = 0; k < 4; ++k) r.own[k] = a.T2[k * NF + o];
+        r.nb = a.mesh.nbr[el * 6 + ft.f];
+        if (r.nb >= 0) {
+            const size_t on = ((size_t)r.nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) own[s][k] = a.T2[k * NF + o];
-            nb2[s] = a.mesh.nbr[el * 6 + f];
-            if (nb2[s] >= 0) {
-                const size_t on = ((size_t)nb2[s] * 6 + (f ^ 1)) * G::n2 + lt.fp;
+            for (int k = 0; k < 4; ++k) r.oth[k] = a.T2[k * NF + on];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) oth[s][k] = a.T2[k * NF + on];
-            }
+            for (int v = 0; v < 6; ++v)
+                if (v != 4) r.wn[v] = TU[v * NF + on];
         }
-    }
+    };
+    Tr tr0;
+    if (t < G::NF) load_tr(t, tr0);
     if (act) {
-        sA[0][t] = a.TH[g];
+        T u6[6], w[5];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) sA[1 + m][t] = a.Q[(12 + m) * a.NN + g];
+        for (int v = 0; v < 6; ++v) { u6[v] = a.U[v * a.NN + g]; sU[v][t] = u6[v]; }
+        primitives(u6, w);
 #pragma unroll
-        for (int v = 0; v < 6; ++v) sU[v][t] = a.U[v * a.NN + g];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) sGu[r][t] = a.Q[(3 + r) * a.NN + g];
+        for (int k = 0; k < 4; ++k) sW[k][t] = w[1 + k];
     }
     __syncthreads();
-    if (lact) {
+    // face values: BR1 w* of u, v, w, c; T* and (grad c)* . n dS of the second lifting
+    for (int task = t; task < G::NF; task += BS) {
+        const FaceTask<P> ft(task);
+        const int el = e0 + ft.le, f = ft.f;
+        if (el >= E) continue;
+        Tr tr;
+        if (task == t) tr = tr0; else load_tr(task, tr);
+        const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
+        const double *Lf = sL + (f & 1) * P;
+        const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
+        T uf[6];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int f = 2 * lt.d + s;
-            const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
-            T Ts, Fs;
-            if (nb2[s] >= 0) {
-                Ts = T(0.5) * (own[s][3] + oth[s][3]);
-                T acc = T(0);
+        for (int v = 0; v < 6; ++v) {
+            if (v == 4) continue;
+            T acc = T(0);
 #pragma unroll
-                for (int m = 0; m < 3; ++m) acc += T(0.5) * (own[s][m] + oth[s][m]) * T(fm[m] * fm[3]);
-                Fs = acc;
-            } else {
-                const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                if (bc.kind == 1) {
-                    Ts = T(bc.twall);
-                    T cm, cp;
-                    prolong2<P>(sU[5], lt.le * G::n3, sL, lt, cm, cp);
-                    const T c = s ? cp : cm;
-                    Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
-                } else {
-                    Ts = own[s][3];
-                    Fs = T(0);
-                }
-            }
-            const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
-            sTs[slot] = Ts;
-            sFs[slot] = Fs;
+            for (int l = 0; l < P; ++l) acc += T(Lf[l]) * sU[v][lo + l * ls];
+            uf[v] = acc;
         }
+        T w[5];
+        primitives(uf, w);
+        T Ts, Fs;
+        if (tr.nb >= 0) {
+            T v5[5];
+            primitives(tr.wn, v5);
+#pragma unroll
+            for (int k = 1; k < 5; ++k) w[k] = T(0.5) * (w[k] + v5[k]);
+            Ts = T(0.5) * (tr.own[3] + tr.oth[3]);
+            T acc = T(0);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) acc += T(0.5) * (tr.own[m] + tr.oth[m]) * T(fm[m] * fm[3]);
+            Fs = acc;
+        } else {
+            wall_primitives(a.mesh, el, f, w);
+            const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+            if (bc.kind == 1) {
+                Ts = T(bc.twall);
+                const T c = uf[5];
+                Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
+            } else {
+                Ts = tr.own[3];
+                Fs = T(0);
+            }
+        }
+        const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sS[k][slot] = w[1 + k];
+        sTs[slot] = Ts;
+        sFs[slot] = Fs;
     }
     __syncthreads();
+    // lifted grad u, grad c and the nodal temperature
+    T gu[9], gc[3];
+    double Tn = 0.0;
+    const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
+    T Ja[9], iJ = T(0);
+    if (act) {
+        T gd[4][3];
+        lifted_grads<P, 4>(sW, sS, le * G::n3, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
+        element_metrics(a.mesh, e, Ja, iJ);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) to_physical(Ja, iJ, gd[w], gu + 3 * w);
+        to_physical(Ja, iJ, gd[3], gc);
+        Tn = temperature(a.ph, (double)sU[0][t], (double)sU[1][t], (double)sU[2][t], (double)sU[3][t],
+                         (double)sU[4][t], (double)sU[5][t], (double)gc[0], (double)gc[1], (double)gc[2]);
+    }
+    __syncthreads();
+    if (act) {
+        sA[0][t] = T(Tn);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sA[1 + m][t] = gc[m];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) sGu[r][t] = gu[r];
+    }
+    __syncthreads();
+    // grad T (BR1 with T*) and lap c (divergence lifting of grad c)
     T gT[3] = {T(0), T(0), T(0)}, lap = T(0);
     if (act) {
-        const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
         const int idx[3] = {i, j, k};
         const int fpd[3] = {j + P * k, i + P * k, i + P * j};
-        const double *em = a.mesh.emet + (size_t)e * 10;
-        T Ja[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) Ja[r] = T(em[r]);
-        const T iJ = T(1.0 / em[9]);
         const int base = le * G::n3;
         const int fbase = le * 6 * G::n2;
         T gd[3], dl = T(0);
@@ -672,27 +847,27 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         sA[3][t] = lap;
     }
     __syncthreads();
-    // own-face flux traces on both faces of the line: G = (F^C - F^V).n, wave
-    // speed, state; on walls the complete wall flux in G.
-    if (lact) {
-        const int base = lt.le * G::n3;
-        // One face at a time, and each field group folded into the six flux
-        // components as soon as it is prolonged, so few values stay live.
-#pragma unroll 1
-        for (int s = 0; s < 2; ++s) {
-            const double *Lf = sL + s * P;
-            const int lo = base + lt.off, ls = lt.str;
+    // own-face flux traces, one face point per task: G = (F^C - F^V).n and
+    // the wave speed; on walls the complete wall flux in G.  Each field group
+    // is folded into the six flux components as soon as it is prolonged, so
+    // few values stay live.
+    for (int task = t; task < G::NF; task += BS) {
+        {
+            const FaceTask<P> ft(task);
+            const int el = e0 + ft.le, f = ft.f;
+            if (el >= E) continue;
+            const double *Lf = sL + (f & 1) * P;
+            const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
             auto pro = [&](const T *fld) {
                 T acc = T(0);
 #pragma unroll
                 for (int l = 0; l < P; ++l) acc += T(Lf[l]) * fld[lo + l * ls];
                 return acc;
             };
-            const int f = 2 * lt.d + s;
-            const size_t o = ((size_t)el * 6 + f) * G::n2 + lt.fp;
+            const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
             const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
             const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
-            const bool wall = nb2[s] < 0;
+            const bool wall = a.mesh.nbr[el * 6 + f] < 0;
             const int kind = wall ? a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind : 0;
             // state and convective part
             // scheduling barriers keep each field group's LDS loads next to the
@@ -777,12 +952,6 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * gcn;
                 a.TF[6 * NF + o] = lam;
-                a.TF[7 * NF + o] = rho;
-                a.TF[8 * NF + o] = m0;
-                a.TF[9 * NF + o] = m1;
-                a.TF[10 * NF + o] = m2;
-                a.TF[11 * NF + o] = E;
-                a.TF[12 * NF + o] = c;
             } else if (kind == 1) {
                 const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
                 const T g = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv));
@@ -807,8 +976,9 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     Inst<T> a;
     int e0;
     instance_of<T, BATCH>(L, a, e0, G::EPB);
-    __shared__ T sF[6][G::NV];
-    __shared__ T sFs[6][G::NF];
+    __shared__ T sF[6][G::NV];     // state; primitives; contravariant fluxes; new state
+    __shared__ T sS[5][G::NF];     // BR1 face values of the primitives
+    __shared__ T sFs[6][G::NF];    // surface flux (F* . n) dS
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
@@ -818,11 +988,9 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
     const size_t NF = (size_t)E * 6 * G::n2;
+    const T *TUr = a.TU + (size_t)L.tb * 6 * NF;
 
-    // node data first (consumed after the face fluxes), then the face loads
     Pt<T> s;
-    T grho[3];
-    double Tn = 0.0;
     if (act) {
         s.rho = a.U[0 * a.NN + g];
         s.m[0] = a.U[1 * a.NN + g];
@@ -831,62 +999,97 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         s.E = a.U[4 * a.NN + g];
         s.c = a.U[5 * a.NN + g];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) grho[m] = a.Q[m * a.NN + g];
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-            for (int ii = 0; ii < 3; ++ii) s.gu[jj][ii] = a.Q[(3 + 3 * jj + ii) * a.NN + g];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            s.gc[m] = a.Q[(12 + m) * a.NN + g];
-            s.gT[m] = a.G2[m * a.NN + g];
-        }
+        for (int m = 0; m < 3; ++m) s.gT[m] = a.G2[m * a.NN + g];
         s.lapc = a.G2[3 * a.NN + g];
-        Tn = (double)a.TH[g];
+        sF[0][t] = s.rho;
+        sF[1][t] = s.m[0];
+        sF[2][t] = s.m[1];
+        sF[3][t] = s.m[2];
+        sF[4][t] = s.E;
+        sF[5][t] = s.c;
     }
-    // surface flux (F* . n) dS on both faces of this thread's line
-    const int ltask = line_of_thread<P, BS>(t);
-    const LineTask<P> lt(ltask < 0 ? 0 : ltask);
-    const int el = e0 + lt.le;
-    const bool lact = ltask >= 0 && el < E;
-    if (lact) {
-#pragma unroll 1
-        for (int sd = 0; sd < 2; ++sd) {
-            const int f = 2 * lt.d + sd;
-            const size_t o = ((size_t)el * 6 + f) * G::n2 + lt.fp;
-            const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
-            const int nb = a.mesh.nbr[el * 6 + f];
-            const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
-            if (nb >= 0) {
-                const size_t on = ((size_t)nb * 6 + (f ^ 1)) * G::n2 + lt.fp;
-                const T lm = a.TF[6 * NF + o], lp = a.TF[6 * NF + on];
-                const T lam = lm > lp ? lm : lp;
+    __syncthreads();
+    // per face point (one per thread, a second round where the block has more
+    // face points than threads): BR1 face values of the primitives, and the
+    // Rusanov + central viscous flux (F* . n) dS from both sides' traces
+    for (int task = t; task < G::NF; task += BS) {
+        const FaceTask<P> ft(task);
+        const int el = e0 + ft.le, f = ft.f;
+        if (el >= E) continue;
+        const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
+        const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+        const int nb = a.mesh.nbr[el * 6 + f];
+        const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
+        const double *Lf = sL + (f & 1) * P;
+        const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
+        T uo[6];
 #pragma unroll
-                for (int v = 0; v < 6; ++v) {
-                    const T Fn = T(0.5) * (a.TF[v * NF + o] - a.TF[v * NF + on]) -
-                                 T(0.5) * lam * (a.TF[(7 + v) * NF + on] - a.TF[(7 + v) * NF + o]);
-                    sFs[v][slot] = Fn * dS;
-                }
-            } else {
+        for (int v = 0; v < 6; ++v) {
+            T acc = T(0);
 #pragma unroll
-                for (int v = 0; v < 6; ++v) sFs[v][slot] = a.TF[v * NF + o] * dS;
-            }
+            for (int l = 0; l < P; ++l) acc += T(Lf[l]) * sF[v][lo + l * ls];
+            uo[v] = acc;
         }
+        T w[5];
+        primitives(uo, w);
+        if (nb >= 0) {
+            const size_t on = ((size_t)nb * 6 + (f ^ 1)) * G::n2 + ft.fp;
+            T un6[6], wn[5];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) un6[v] = TUr[v * NF + on];
+            const T lm = a.TF[6 * NF + o], lp = a.TF[6 * NF + on];
+            const T lam = lm > lp ? lm : lp;
+#pragma unroll
+            for (int v = 0; v < 6; ++v) {
+                const T Fn = T(0.5) * (a.TF[v * NF + o] - a.TF[v * NF + on]) - T(0.5) * lam * (un6[v] - uo[v]);
+                sFs[v][slot] = Fn * dS;
+            }
+            primitives(un6, wn);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + wn[k]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 6; ++v) sFs[v][slot] = a.TF[v * NF + o] * dS;
+            wall_primitives(a.mesh, el, f, w);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
     }
-
-    // point-wise source; contravariant fluxes one direction at a time
-    T S[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, iJ = T(0);
+    __syncthreads();
+    // node values -> primitives, in place (the face prolongations are done)
     if (act) {
+        const T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
+        T w[5];
+        primitives(u6, w);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sF[k][t] = w[k];
+    }
+    __syncthreads();
+    // lifted gradients, temperature, pressure and the point-wise source
+    T S[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, iJ = T(0);
+    const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
+    const int base = le * G::n3;
+    if (act) {
+        T gd[5][3];
+        lifted_grads<P, 5>(sF, sS, base, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
+        T Ja[9], grho[3];
+        element_metrics(a.mesh, e, Ja, iJ);
+        to_physical(Ja, iJ, gd[0], grho);
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) to_physical(Ja, iJ, gd[1 + jj], s.gu[jj]);
+        to_physical(Ja, iJ, gd[4], s.gc);
+        // the temperature is held in the element type, as every stored field
+        const double Tn = (double)T(temperature(a.ph, (double)s.rho, (double)s.m[0], (double)s.m[1], (double)s.m[2],
+                                                (double)s.E, (double)s.c, (double)s.gc[0], (double)s.gc[1],
+                                                (double)s.gc[2]));
         double pd, cs2;
         eos(a.ph, (double)s.rho, Tn, pd, cs2);
         s.p = T(pd);
         s.ir = T(1) / s.rho;
-        iJ = T(1.0 / a.mesh.emet[(size_t)e * 10 + 9]);
         source(a.ph, s, grho, S);
     }
+    // contravariant fluxes one direction at a time
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-    const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
-    const int base = le * G::n3;
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
@@ -959,21 +1162,21 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         }
     }
     __syncthreads();
+    const int ltask = line_of_thread<P, BS>(t);
+    const LineTask<P> lt(ltask < 0 ? 0 : ltask);
+    const int el = e0 + lt.le;
+    const bool lact = ltask >= 0 && el < E;
     if (lact) {
+        T *TUw = a.TU + (size_t)L.tw * 6 * NF;
         const int b2 = lt.le * G::n3;
         T um[6], up[6];
 #pragma unroll
         for (int v = 0; v < 6; ++v) prolong2<P>(sF[v], b2, sL, lt, um[v], up[v]);
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd) {
-            const T *u6 = sd ? up : um;
             const size_t o = ((size_t)el * 6 + 2 * lt.d + sd) * G::n2 + lt.fp;
-            const T ir = T(1) / u6[0];
-            a.TU[0 * NF + o] = u6[0];
-            a.TU[1 * NF + o] = u6[1] * ir;
-            a.TU[2 * NF + o] = u6[2] * ir;
-            a.TU[3 * NF + o] = u6[3] * ir;
-            a.TU[4 * NF + o] = u6[5];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) TUw[v * NF + o] = sd ? up[v] : um[v];
         }
     }
 }

@@ -275,6 +275,10 @@ static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -24042679
 static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                                1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
+// Conserved face-trace buffer read by stage s and written for stage s+1: three
+// buffers so that no stage overwrites the buffer it reads, and the last stage
+// writes the buffer the next step's first stage reads (k_prolong fills 0).
+static const int kTraceBuf[6] = {0, 1, 0, 1, 2, 0};
 // 1D stability constants (periodic Gauss DGSEM spectra under the scheme's
 // stability polynomial), index N: advective dt a / h and diffusive spectral
 // radius at h = 1; stability interval on the negative real axis.
@@ -570,6 +574,8 @@ template <int P, typename T, int BS> struct Impl {
             L.first = st == 0;
             L.A = kRkA[st];
             L.B = kRkB[st];
+            L.tb = kTraceBuf[st];
+            L.tw = kTraceBuf[st + 1];
             hipLaunchKernelGGL((k_lift1<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
             hipLaunchKernelGGL((k_lift2<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
             hipLaunchKernelGGL((k_update<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
@@ -613,6 +619,8 @@ template <int P, typename T, int BS> struct Impl {
                 L.first = st == 0;
                 L.A = kRkA[st];
                 L.B = kRkB[st];
+                L.tb = kTraceBuf[st];
+                L.tw = kTraceBuf[st + 1];
                 lift1(c, L, s);
                 lift2(c, L, s);
                 update(c, L, s);
@@ -623,6 +631,7 @@ template <int P, typename T, int BS> struct Impl {
     static int lift1_out(nskr_ctx *c, const void *U, void *q, hipStream_t s)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
         HIPCHK(c, hipGetLastError());
@@ -632,6 +641,7 @@ template <int P, typename T, int BS> struct Impl {
     static int lift2_out(nskr_ctx *c, const void *U, void *o, hipStream_t s)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
         lift2(c, L, s);
@@ -643,6 +653,7 @@ template <int P, typename T, int BS> struct Impl {
     static int dt(nskr_ctx *c, const void *U, double *out3, hipStream_t s)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
         RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
@@ -658,6 +669,7 @@ template <int P, typename T, int BS> struct Impl {
     static int reduce(nskr_ctx *c, const void *U, double *out, hipStream_t s)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
         RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
@@ -675,6 +687,7 @@ template <int P, typename T, int BS> struct Impl {
         T *U = (T *)Uv;
         hipLaunchKernelGGL((k_init_rho<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, U, ia);
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
+        L.full = 1;
         prolong(c, L, s);
         lift1(c, L, s);
         hipLaunchKernelGGL((k_init_energy<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, U, (const T *)c->d_Q, c->E,
@@ -903,7 +916,7 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         (rc = dalloc(c, (void **)&c->d_bcs, sizeof(BcDev) * bcs.size())) ||
         (rc = dalloc(c, &c->d_Q, ts * 15 * c->NN)) || (rc = dalloc(c, &c->d_TH, ts * c->NN)) ||
         (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * 4 * c->NF)) ||
-        (rc = dalloc(c, &c->d_TF, ts * 13 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 5 * c->NF)) ||
+        (rc = dalloc(c, &c->d_TF, ts * 7 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 3 * 6 * c->NF)) ||
         (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
         (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS)) ||
         (c->p.precision == 1 && c->p.kahan && (rc = dalloc(c, &c->d_Ck, ts * 6 * c->NN)))) {
