@@ -255,13 +255,18 @@ def test_rk_split_equals_joined(torch_cuda):
     assert torch.equal(U1, U2)
 
 
-def test_full_size_bench_workload_parity(torch_cuda):
-    """The benchmark workload at full size (16^3 elements, N = 4, 512000 nodes),
-    same kernels and launch configuration as bench.py: GPU initial state and two
-    RK steps against the oracle's."""
+FULL = [("c2", 2), ("c3", 1), ("c4", 1)]
+
+
+@pytest.mark.parametrize("which,steps", FULL, ids=[f"{w}_{n}steps" for w, n in FULL])
+def test_full_size_workload_parity(torch_cuda, which, steps):
+    """The benchmark workloads at full size, same kernels and launch
+    configuration as bench.py: 16^3 N=4 (512000 nodes), 32^3 N=5 (7.08M
+    nodes) and the 48x48x24 N=3 wall box (3.54M nodes).  GPU initial state,
+    time step and RK steps against the oracle's, on every node."""
     torch = torch_cuda
-    w = wl.c2()
-    print(f"[case] full-size {w.name}", flush=True)
+    w = {"c2": wl.c2, "c3": wl.c3, "c4": wl.c4}[which]()
+    print(f"[case] full-size {w.name}, {steps} step(s)", flush=True)
     from paper_2208_05310_amd.nskr import init_workload
     s = gpu_solver(w)
     Ug = init_workload(s, w)
@@ -273,10 +278,10 @@ def test_full_size_bench_workload_parity(torch_cuda):
     assert abs(dt - dto) <= 1e-14 * dto
     err0 = rel_err(Ug.cpu().numpy(), Uo)
     assert np.all(err0[[0, 4, 5]] <= TOL), err0
-    s.rk_steps(Ug, Rg, dto, 2)
+    s.rk_steps(Ug, Rg, dto, steps)
     torch.cuda.synchronize()
     Ro = np.zeros_like(Uo)
-    o.run(Uo, Ro, 0.0, dto, 2)
+    o.run(Uo, Ro, 0.0, dto, steps)
     err = rel_err(Ug.cpu().numpy(), Uo, state_floor(Uo, w.params))
     print("errors per field", err, flush=True)
     assert np.all(err <= TOL), err
