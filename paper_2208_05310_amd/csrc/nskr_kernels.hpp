@@ -257,7 +257,7 @@ template <typename T> struct Launch {
     int mode;        // update: 0 write U_t; 1 RK stage (update U, R, write traces)
     int first;       // RK: assign R at the first stage
     int tb, tw;      // conserved-trace buffer read by this stage, written for the next
-    int full;        // k_lift1: also all lifted gradients and T at the nodes (API outputs)
+    int full;        // host side: launch the k_lift1 variant that also writes Q and TH
     double A, B;     // RK coefficients of this stage
 };
 
@@ -512,9 +512,9 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 
 // ------------------------------------------------------------ k_lift1
 // Lifted grad c, and the own-face traces of grad c and of the face
-// temperature.  With L.full also every lifted gradient and the nodal
-// temperature (Q, TH) for the API outputs.
-template <int P, typename T, int BS, bool BATCH>
+// temperature.  FULL: also every lifted gradient and the nodal temperature
+// (Q, TH) for the API outputs.
+template <int P, typename T, int BS, bool BATCH, bool FULL = false>
 __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
 {
     using G = Tile<P, BS>;
@@ -522,9 +522,12 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
     int e0;
     instance_of<T, BATCH>(L, a, e0, G::EPB);
     static_assert(n_lines<P, BS>() <= BS, "one line per thread");
+    // node values of the lifted primitives (c last; slots 0..2 later hold
+    // grad c) and their BR1 face values: all five with FULL, else c only
+    constexpr int NW = FULL ? 5 : 4, NS = FULL ? 5 : 1;
     __shared__ T sU[6][G::NV];
-    __shared__ T sW[5][G::NV];
-    __shared__ T sS[5][G::NF];
+    __shared__ T sW[NW][G::NV];
+    __shared__ T sS[NS][G::NF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
     const size_t NF = (size_t)E * 6 * G::n2;
-    const bool full = L.full != 0;
+    constexpr bool full = FULL;
     const T *TU = a.TU + (size_t)L.tb * 6 * NF;
 
     // early loads: own nodes, and the neighbour traces of this thread's line
@@ -571,7 +574,7 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
 #pragma unroll
             for (int k = 0; k < 4; ++k) sW[k][t] = w[k];
         }
-        sW[4][t] = w[4];
+        sW[NW - 1][t] = w[4];
     }
     __syncthreads();
     // BR1 face values w* on both faces of the line
@@ -601,9 +604,9 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
                     wall_primitives(a.mesh, el, f, w);
                 }
 #pragma unroll
-                for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
+                for (int k = 0; k < NS; ++k) sS[k][slot] = w[k];
             } else {
-                sS[4][slot] = nb >= 0 ? T(0.5) * (uf[s][5] + wn[s][5]) : uf[s][5];
+                sS[NS - 1][slot] = nb >= 0 ? T(0.5) * (uf[s][5] + wn[s][5]) : uf[s][5];
             }
         }
     }
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
                 for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[m];
             }
         }
-        lifted_grad<P>(sW[4], sS[4], base, fbase, i, j, k, sDh, sLh, Ja, iJ, qc);
+        lifted_grad<P>(sW[NW - 1], sS[NS - 1], base, fbase, i, j, k, sDh, sLh, Ja, iJ, qc);
         if (full) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) a.Q[(12 + m) * a.NN + g] = qc[m];

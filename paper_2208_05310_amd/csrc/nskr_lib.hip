@@ -537,6 +537,7 @@ template <int P, typename T, int BS> struct Impl {
     {
         const void *fns[] = {reinterpret_cast<const void *>(&k_prolong<P, T, BS, false>),
                              reinterpret_cast<const void *>(&k_lift1<P, T, BS, false>),
+                             reinterpret_cast<const void *>(&k_lift1<P, T, BS, false, true>),
                              reinterpret_cast<const void *>(&k_lift2<P, T, BS, false>),
                              reinterpret_cast<const void *>(&k_update<P, T, BS, false>)};
         for (const void *f : fns) {
@@ -553,7 +554,10 @@ template <int P, typename T, int BS> struct Impl {
     }
     static void lift1(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        stage_launch<T>(c, 1, &k_lift1<P, T, BS, false>, nblk(c), BS, s, L);
+        if (L.full)
+            stage_launch<T>(c, 1, &k_lift1<P, T, BS, false, true>, nblk(c), BS, s, L);
+        else
+            stage_launch<T>(c, 1, &k_lift1<P, T, BS, false>, nblk(c), BS, s, L);
     }
     static void lift2(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
