@@ -979,9 +979,15 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     Inst<T> a;
     int e0;
     instance_of<T, BATCH>(L, a, e0, G::EPB);
-    __shared__ T sF[6][G::NV];     // state; primitives; contravariant fluxes; new state
-    __shared__ T sS[5][G::NF];     // BR1 face values of the primitives
+    // sF: state; primitives; contravariant fluxes (even directions); new state.
+    // sB: BR1 face values of the primitives [5][NF], then the contravariant
+    // fluxes of the odd direction [6][NV].
+    constexpr int kB = 5 * G::NF > 6 * G::NV ? 5 * G::NF : 6 * G::NV;
+    __shared__ T sF[6][G::NV];
+    __shared__ T sB[kB];
     __shared__ T sFs[6][G::NF];    // surface flux (F* . n) dS
+    T(*sS)[G::NF] = reinterpret_cast<T(*)[G::NF]>(sB);
+    T(*sF2)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sB);
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
@@ -1091,29 +1097,37 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         s.ir = T(1) / s.rho;
         source(a.ph, s, grho, S);
     }
-    // contravariant fluxes one direction at a time
+    // volume integral sum_d Dhat_d (Ja^d . F): the contravariant fluxes of
+    // direction d go to buffer d & 1, so direction d+1 is written while
+    // direction d is read, one barrier per direction
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    auto put_flux = [&](int d, T (*buf)[G::NV]) {
+        const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
+        const T Jd[3] = {T(em[0]), T(em[1]), T(em[2])};
+        T Fd[6];
+        flux_dot(a.ph, s, Jd, Fd);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) buf[v][t] = Fd[v];
+    };
+    __syncthreads();
+    if (act) put_flux(0, sF);
 #pragma unroll 1
     for (int d = 0; d < 3; ++d) {
         __syncthreads();
         if (act) {
-            const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
-            const T Jd[3] = {T(em[0]), T(em[1]), T(em[2])};
-            T Fd[6];
-            flux_dot(a.ph, s, Jd, Fd);
-#pragma unroll
-            for (int v = 0; v < 6; ++v) sF[v][t] = Fd[v];
-        }
-        __syncthreads();
-        if (act) {
+            if (d < 2) put_flux(d + 1, (d & 1) ? sF : sF2);
+            __builtin_amdgcn_sched_barrier(0);
+            const T(*buf)[G::NV] = (d & 1) ? sF2 : sF;
+            // the line through this node along d, addressed branch-free:
+            // node l is lo + l * str
             const int id = d == 0 ? i : (d == 1 ? j : k);
-            const int p = d == 0 ? j : i, q = d == 2 ? j : k;
+            const int str = d == 0 ? 1 : (d == 1 ? P : P * P);
+            const int lo = base + nd - id * str;
 #pragma unroll
             for (int l = 0; l < P; ++l) {
-                const int n = base + line_node<P>(d, l, p, q);
                 const T D = T(sDh[id * P + l]);
 #pragma unroll
-                for (int v = 0; v < 6; ++v) acc[v] += D * sF[v][n];
+                for (int v = 0; v < 6; ++v) acc[v] += D * buf[v][lo + l * str];
             }
         }
     }
