@@ -843,11 +843,31 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         a.G2[3 * a.NN + g] = lap;
     }
     __syncthreads();
+    // per direction d, at the nodes: tau . n_d (3) and grad T . n_d with n_d
+    // the outward normal of face 2d+1 (face 2d has exactly -n_d on these
+    // affine elements), plus div u and lap c.  Their face values are the
+    // prolongations of these nodal values (n_d is constant on the face), so
+    // a face task prolongs 12 fields instead of 19.  Layout: direction 0 in
+    // sA, directions 1 and 2 and div u in sX (each thread overwrites only its
+    // own node's grad u, which it has read), lap c in sTs.
     if (act) {
-        sA[0][t] = gT[0];
-        sA[1][t] = gT[1];
-        sA[2][t] = gT[2];
-        sA[3][t] = lap;
+        T g[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) g[r] = sGu[r][t];
+        const T div = g[0] + g[4] + g[8];
+        const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double *fm = a.mesh.fmet + ((size_t)e * 6 + 2 * d + 1) * 4;
+            const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+            T *out = d == 0 ? &sA[0][0] : sX + (d - 1) * 4 * G::NV;
+            out[0 * G::NV + t] = mu * ((g[0] + g[0]) * n0 + (g[1] + g[3]) * n1 + (g[2] + g[6]) * n2 - td * n0);
+            out[1 * G::NV + t] = mu * ((g[3] + g[1]) * n0 + (g[4] + g[4]) * n1 + (g[5] + g[7]) * n2 - td * n1);
+            out[2 * G::NV + t] = mu * ((g[6] + g[2]) * n0 + (g[7] + g[5]) * n1 + (g[8] + g[8]) * n2 - td * n2);
+            out[3 * G::NV + t] = gT[0] * n0 + gT[1] * n1 + gT[2] * n2;
+        }
+        sX[8 * G::NV + t] = div;
+        sTs[t] = lap;
     }
     __syncthreads();
     // own-face flux traces, one face point per task: G = (F^C - F^V).n and
@@ -912,19 +932,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G4 = T(0);
                 G5 = T(0);
             }
-            // viscous stress tau n = mu ((grad u + grad u^T) n - 2/3 div u n)
-            T div, tn0, tn1, tn2;
+            // viscous traction tau n = mu ((grad u + grad u^T) n - 2/3 div u n)
             __builtin_amdgcn_sched_barrier(0);
-            {
-                const T g00 = pro(sGu[0]), g01 = pro(sGu[1]), g02 = pro(sGu[2]);
-                const T g10 = pro(sGu[3]), g11 = pro(sGu[4]), g12 = pro(sGu[5]);
-                const T g20 = pro(sGu[6]), g21 = pro(sGu[7]), g22 = pro(sGu[8]);
-                div = g00 + g11 + g22;
-                const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
-                tn0 = mu * ((g00 + g00) * n0 + (g01 + g10) * n1 + (g02 + g20) * n2 - td * n0);
-                tn1 = mu * ((g10 + g01) * n0 + (g11 + g11) * n1 + (g12 + g21) * n2 - td * n1);
-                tn2 = mu * ((g20 + g02) * n0 + (g21 + g12) * n1 + (g22 + g22) * n2 - td * n2);
-            }
+            const T sgn = (f & 1) ? T(1) : T(-1);
+            const T *nf = (f >> 1) == 0 ? &sA[0][0] : sX + ((f >> 1) - 1) * 4 * G::NV;
+            const T div = pro(sX + 8 * G::NV);
+            const T tn0 = sgn * pro(nf), tn1 = sgn * pro(nf + G::NV), tn2 = sgn * pro(nf + 2 * G::NV);
             if (!wall) {
                 G1 -= tn0;
                 G2_ -= tn1;
@@ -943,14 +956,14 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // heat flux
             __builtin_amdgcn_sched_barrier(0);
             if (kind != 2) {
-                const T gTn = pro(sA[0]) * n0 + pro(sA[1]) * n1 + pro(sA[2]) * n2;
+                const T gTn = sgn * pro(nf + 3 * G::NV);
                 G4 -= T(a.ph.kappa) * gTn;
             }
             // order-parameter terms of j_e and F^V_c
             __builtin_amdgcn_sched_barrier(0);
             if (!wall) {
                 const T gcn = a.T2[0 * NF + o] * n0 + a.T2[1 * NF + o] * n1 + a.T2[2 * NF + o] * n2;
-                const T lapc = pro(sA[3]);
+                const T lapc = pro(sTs);
                 const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * gcn;
