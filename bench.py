@@ -34,8 +34,8 @@ def kernel_words_per_node(N):
     return {
         "prolong": 6 + 6 * F,             # U in; conserved traces out
         "lift1": 6 + 5 * F,               # U, neighbour c traces in; grad c + T traces (4) out
-        "lift2": 10 + 16 * F,             # U, neighbour traces (rho, m, c: 5), grad c + T traces (4) in;
-                                          # grad T + lap c (4), flux + wave-speed traces (7) out
+        "lift2": 10 + 17 * F,             # U, conserved traces (own and neighbour: 6), grad c + T traces (4)
+                                          # in; grad T + lap c (4), flux + wave-speed traces (7) out
         "update": 28 + 19 * F,            # U, R, grad T + lap c, neighbour conserved traces (6), flux traces (7)
                                           # in; U, R, conserved traces (6) out
     }

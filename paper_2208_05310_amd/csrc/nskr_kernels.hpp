@@ -677,7 +677,6 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     // [4][NF] while grad u and grad c are lifted, then grad u [9][NV]
     constexpr int kX = 9 * G::NV > 4 * G::NV + 4 * G::NF ? 9 * G::NV : 4 * G::NV + 4 * G::NF;
     __shared__ T sA[4][G::NV];     // T, grad c; then grad T, lap c
-    __shared__ T sU[6][G::NV];
     __shared__ T sX[kX];
     __shared__ T sTs[G::NF], sFs[G::NF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
@@ -696,11 +695,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 
     // face work runs as face tasks (one face point per thread, a second round
     // where the block has more face points than threads); the first round's
-    // traces are loaded before the node loads: the neighbour's conserved state
-    // (rho, m, c) and both sides' grad c and T
+    // traces are loaded before the node loads: both sides' conserved state
+    // (rho, m, c; the own side's is the prolongation of the state, written by
+    // the previous stage) and both sides' grad c and T
     struct Tr {
         int nb;
-        T own[4], oth[4], wn[6];
+        T own[4], oth[4], wn[6], uo[6];
     };
     auto load_tr = [&](int task, Tr &r) {
         const FaceTask<P> ft(task);
@@ -710,6 +710,9 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         const size_t o = ((size_t)el * 6 + ft.f) * G::n2 + ft.fp;
 #pragma unroll
         for (int k = 0; k < 4; ++k) r.own[k] = a.T2[k * NF + o];
+#pragma unroll
+        for (int v = 0; v < 6; ++v)
+            if (v != 4) r.uo[v] = TU[v * NF + o];
         r.nb = a.mesh.nbr[el * 6 + ft.f];
         if (r.nb >= 0) {
             const size_t on = ((size_t)r.nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
@@ -722,11 +725,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     };
     Tr tr0;
     if (t < G::NF) load_tr(t, tr0);
+    T un[6];
     if (act) {
-        T u6[6], w[5];
+        T w[5];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) { u6[v] = a.U[v * a.NN + g]; sU[v][t] = u6[v]; }
-        primitives(u6, w);
+        for (int v = 0; v < 6; ++v) un[v] = a.U[v * a.NN + g];
+        primitives(un, w);
 #pragma unroll
         for (int k = 0; k < 4; ++k) sW[k][t] = w[1 + k];
     }
@@ -739,17 +743,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         Tr tr;
         if (task == t) tr = tr0; else load_tr(task, tr);
         const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
-        const double *Lf = sL + (f & 1) * P;
-        const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
-        T uf[6];
-#pragma unroll
-        for (int v = 0; v < 6; ++v) {
-            if (v == 4) continue;
-            T acc = T(0);
-#pragma unroll
-            for (int l = 0; l < P; ++l) acc += T(Lf[l]) * sU[v][lo + l * ls];
-            uf[v] = acc;
-        }
+        const T *uf = tr.uo;
         T w[5];
         primitives(uf, w);
         T Ts, Fs;
@@ -794,8 +788,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 #pragma unroll
         for (int w = 0; w < 3; ++w) to_physical(Ja, iJ, gd[w], gu + 3 * w);
         to_physical(Ja, iJ, gd[3], gc);
-        Tn = temperature(a.ph, (double)sU[0][t], (double)sU[1][t], (double)sU[2][t], (double)sU[3][t],
-                         (double)sU[4][t], (double)sU[5][t], (double)gc[0], (double)gc[1], (double)gc[2]);
+        Tn = temperature(a.ph, (double)un[0], (double)un[1], (double)un[2], (double)un[3], (double)un[4],
+                         (double)un[5], (double)gc[0], (double)gc[1], (double)gc[2]);
     }
     __syncthreads();
     if (act) {
@@ -896,8 +890,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // scheduling barriers keep each field group's LDS loads next to the
             // arithmetic that consumes them (otherwise all of them are hoisted
             // and the register demand limits occupancy)
-            const T rho = pro(sU[0]), m0 = pro(sU[1]), m1 = pro(sU[2]), m2 = pro(sU[3]);
-            const T E = pro(sU[4]), c = pro(sU[5]);
+            const T rho = TU[0 * NF + o], m0 = TU[1 * NF + o], m1 = TU[2 * NF + o], m2 = TU[3 * NF + o];
+            const T E = TU[4 * NF + o], c = TU[5 * NF + o];
             __builtin_amdgcn_sched_barrier(0);
             const T ir = T(1) / rho;
             const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
