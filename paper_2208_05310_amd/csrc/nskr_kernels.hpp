@@ -986,7 +986,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     Inst<T> a;
     int e0;
     instance_of<T, BATCH>(L, a, e0, G::EPB);
-    // sF: state; primitives; contravariant fluxes (even directions); new state.
+    // sF: primitives; contravariant fluxes (even directions); new state.
     // sB: BR1 face values of the primitives [5][NF], then the contravariant
     // fluxes of the odd direction [6][NV].
     constexpr int kB = 5 * G::NF > 6 * G::NV ? 5 * G::NF : 6 * G::NV;
@@ -1017,17 +1017,17 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 #pragma unroll
         for (int m = 0; m < 3; ++m) s.gT[m] = a.G2[m * a.NN + g];
         s.lapc = a.G2[3 * a.NN + g];
-        sF[0][t] = s.rho;
-        sF[1][t] = s.m[0];
-        sF[2][t] = s.m[1];
-        sF[3][t] = s.m[2];
-        sF[4][t] = s.E;
-        sF[5][t] = s.c;
+        const T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
+        T w[5];
+        primitives(u6, w);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sF[k][t] = w[k];
     }
-    __syncthreads();
     // per face point (one per thread, a second round where the block has more
     // face points than threads): BR1 face values of the primitives, and the
-    // Rusanov + central viscous flux (F* . n) dS from both sides' traces
+    // Rusanov + central viscous flux (F* . n) dS from both sides' traces (the
+    // own side's conserved trace is the prolongation of the current state,
+    // written by the previous stage)
     for (int task = t; task < G::NF; task += BS) {
         const FaceTask<P> ft(task);
         const int el = e0 + ft.le, f = ft.f;
@@ -1036,16 +1036,9 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
         const int nb = a.mesh.nbr[el * 6 + f];
         const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
-        const double *Lf = sL + (f & 1) * P;
-        const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
         T uo[6];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) {
-            T acc = T(0);
-#pragma unroll
-            for (int l = 0; l < P; ++l) acc += T(Lf[l]) * sF[v][lo + l * ls];
-            uo[v] = acc;
-        }
+        for (int v = 0; v < 6; ++v) uo[v] = TUr[v * NF + o];
         T w[5];
         primitives(uo, w);
         if (nb >= 0) {
@@ -1070,15 +1063,6 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         }
 #pragma unroll
         for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
-    }
-    __syncthreads();
-    // node values -> primitives, in place (the face prolongations are done)
-    if (act) {
-        const T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
-        T w[5];
-        primitives(u6, w);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) sF[k][t] = w[k];
     }
     __syncthreads();
     // lifted gradients, temperature, pressure and the point-wise source
