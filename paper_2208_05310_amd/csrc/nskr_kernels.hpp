@@ -89,10 +89,11 @@ template <int P> __device__ __forceinline__ int line_node(int d, int l, int p, i
 __device__ __forceinline__ double temperature(const Phys &ph, double rho, double m0, double m1, double m2,
                                               double E, double c, double q0, double q1, double q2)
 {
-    double kin = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho;
+    const double ir = 1.0 / rho;
+    double kin = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * ir;
     double rel = 0.5 * ph.alpha * (rho - c) * (rho - c);
     double grd = 0.5 * ph.gam * (q0 * q0 + q1 * q1 + q2 * q2);
-    return ((E - kin - rel - grd) / rho + ph.a * rho) * ph.inv_Rcv;
+    return ((E - kin - rel - grd) * ir + ph.a * rho) * ph.inv_Rcv;
 }
 
 // van der Waals pressure (eq. pressure) and isentropic sound speed squared
@@ -113,40 +114,34 @@ template <typename T> struct Pt {
     T gT[3], gc[3], lapc; // grad T, grad c, lap c
 };
 
-// (F^C - F^V) . v for an arbitrary vector v (unit normal on faces, the
-// contravariant metric row Ja^d in the volume), relaxation model 1
-// (eq. navierstokeskorteweg_p): F^V = (0, tau, tau u + j_e, gamma beta grad c),
-// tau = mu (grad u + grad u^T - 2/3 div u I), j_e = k grad T - gamma c grad c
-// div u + gamma grad c zeta, zeta = beta (gamma lap c + alpha (rho - c)).
+// Physical flux tensor of relaxation model 1 (eq. navierstokeskorteweg_p),
+// F[v][i] = (F^C - F^V)_v . e_i, so that (F^C - F^V) . w = sum_i F[v][i] w_i
+// for any vector w (the contravariant metric rows in the volume integral):
+// F^V = (0, tau, tau u + j_e, gamma beta grad c), tau = mu (grad u + grad u^T
+// - 2/3 div u I), j_e = k grad T - gamma c grad c div u + gamma grad c zeta,
+// zeta = beta (gamma lap c + alpha (rho - c)).
 template <typename T>
-__device__ __forceinline__ void flux_dot(const Phys &ph, const Pt<T> &s, const T v[3], T out[6])
+__device__ __forceinline__ void flux_tensor(const Phys &ph, const Pt<T> &s, T F[6][3])
 {
     const T ir = s.ir;
-    const T u0 = s.m[0] * ir, u1 = s.m[1] * ir, u2 = s.m[2] * ir;
-    const T mv = s.m[0] * v[0] + s.m[1] * v[1] + s.m[2] * v[2];
-    const T uv = mv * ir;
+    const T u[3] = {s.m[0] * ir, s.m[1] * ir, s.m[2] * ir};
     const T div = s.gu[0][0] + s.gu[1][1] + s.gu[2][2];
-    const T mu = T(ph.mu);
-    const T tdiv = T(2.0 / 3.0) * div;
-    // tau . v  (tau symmetric): (tau v)_j = mu sum_i (du_j/dx_i + du_i/dx_j) v_i - mu 2/3 div v_j
-    T tv[3];
+    const T mu = T(ph.mu), tdiv = T(2.0 / 3.0) * div;
+    T tau[3][3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        T acc = T(0);
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) acc += (s.gu[j][i] + s.gu[i][j]) * v[i];
-        tv[j] = mu * (acc - tdiv * v[j]);
-    }
-    const T gcv = s.gc[0] * v[0] + s.gc[1] * v[1] + s.gc[2] * v[2];
-    const T gTv = s.gT[0] * v[0] + s.gT[1] * v[1] + s.gT[2] * v[2];
+        for (int i = 0; i < 3; ++i) tau[j][i] = mu * (s.gu[j][i] + s.gu[i][j] - (i == j ? tdiv : T(0)));
     const T zeta = T(ph.beta) * (T(ph.gam) * s.lapc + T(ph.alpha) * (s.rho - s.c));
-    const T jev = T(ph.kappa) * gTv - T(ph.gam) * s.c * gcv * div + T(ph.gam) * gcv * zeta;
-    out[0] = mv;
-    out[1] = s.m[0] * uv + s.p * v[0] - tv[0];
-    out[2] = s.m[1] * uv + s.p * v[1] - tv[1];
-    out[3] = s.m[2] * uv + s.p * v[2] - tv[2];
-    out[4] = (s.E + s.p) * uv - (tv[0] * u0 + tv[1] * u1 + tv[2] * u2) - jev;
-    out[5] = s.c * uv - T(ph.gam * ph.beta) * gcv;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T je = T(ph.kappa) * s.gT[i] - T(ph.gam) * s.c * s.gc[i] * div + T(ph.gam) * s.gc[i] * zeta;
+        F[0][i] = s.m[i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) F[1 + j][i] = s.m[j] * u[i] + (i == j ? s.p : T(0)) - tau[j][i];
+        F[4][i] = (s.E + s.p) * u[i] - (tau[i][0] * u[0] + tau[i][1] * u[1] + tau[i][2] * u[2]) - je;
+        F[5][i] = s.c * u[i] - T(ph.gam * ph.beta) * s.gc[i];
+    }
 }
 
 // Non-conservative source of relaxation model 1, evaluated point-wise with the
@@ -1067,6 +1062,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     __syncthreads();
     // lifted gradients, temperature, pressure and the point-wise source
     T S[6] = {T(0), T(0), T(0), T(0), T(0), T(0)}, iJ = T(0);
+    T Fx[6][3];
     const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
     const int base = le * G::n3;
     if (act) {
@@ -1087,6 +1083,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         s.p = T(pd);
         s.ir = T(1) / s.rho;
         source(a.ph, s, grho, S);
+        flux_tensor(a.ph, s, Fx);
     }
     // volume integral sum_d Dhat_d (Ja^d . F): the contravariant fluxes of
     // direction d go to buffer d & 1, so direction d+1 is written while
@@ -1095,10 +1092,8 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     auto put_flux = [&](int d, T (*buf)[G::NV]) {
         const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
         const T Jd[3] = {T(em[0]), T(em[1]), T(em[2])};
-        T Fd[6];
-        flux_dot(a.ph, s, Jd, Fd);
 #pragma unroll
-        for (int v = 0; v < 6; ++v) buf[v][t] = Fd[v];
+        for (int v = 0; v < 6; ++v) buf[v][t] = Jd[0] * Fx[v][0] + Jd[1] * Fx[v][1] + Jd[2] * Fx[v][2];
     };
     __syncthreads();
     if (act) put_flux(0, sF);
