@@ -1001,6 +1001,38 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     const size_t NF = (size_t)E * 6 * G::n2;
     const T *TUr = a.TU + (size_t)L.tb * 6 * NF;
 
+    // face tasks (one face point per thread, a second round where the block
+    // has more face points than threads); the first round's traces are
+    // requested before the node loads so that both are in flight together
+    struct Tr {
+        int nb;
+        T uo[6], un[6], G[7], Gn[7];
+    };
+    auto load_tr = [&](int task, Tr &r) {
+        const FaceTask<P> ft(task);
+        const int el = e0 + ft.le;
+        r.nb = -1;
+        if (el >= E) return;
+        const size_t o = ((size_t)el * 6 + ft.f) * G::n2 + ft.fp;
+        r.nb = a.mesh.nbr[el * 6 + ft.f];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) r.uo[v] = TUr[v * NF + o];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) r.G[v] = a.TF[v * NF + o];
+        if (r.nb >= 0) {
+            const size_t on = ((size_t)r.nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
+            r.G[6] = a.TF[6 * NF + o];
+#pragma unroll
+            for (int v = 0; v < 7; ++v) r.Gn[v] = a.TF[v * NF + on];
+#pragma unroll
+            for (int v = 0; v < 6; ++v) r.un[v] = TUr[v * NF + on];
+        }
+    };
+    // (only where one round covers the block: holding a round's traces across
+    // the node loads costs too many registers otherwise)
+    constexpr bool kEarly = G::NF <= BS;
+    Tr tr0;
+    if (kEarly && t < G::NF) load_tr(t, tr0);
     Pt<T> s;
     if (act) {
         s.rho = a.U[0 * a.NN + g];
@@ -1009,51 +1041,40 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         s.m[2] = a.U[3 * a.NN + g];
         s.E = a.U[4 * a.NN + g];
         s.c = a.U[5 * a.NN + g];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) s.gT[m] = a.G2[m * a.NN + g];
-        s.lapc = a.G2[3 * a.NN + g];
         const T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
         T w[5];
         primitives(u6, w);
 #pragma unroll
         for (int k = 0; k < 5; ++k) sF[k][t] = w[k];
     }
-    // per face point (one per thread, a second round where the block has more
-    // face points than threads): BR1 face values of the primitives, and the
-    // Rusanov + central viscous flux (F* . n) dS from both sides' traces (the
-    // own side's conserved trace is the prolongation of the current state,
+    // per face point: BR1 face values of the primitives, and the Rusanov +
+    // central viscous flux (F* . n) dS from both sides' traces (the own
+    // side's conserved trace is the prolongation of the current state,
     // written by the previous stage)
     for (int task = t; task < G::NF; task += BS) {
         const FaceTask<P> ft(task);
         const int el = e0 + ft.le, f = ft.f;
         if (el >= E) continue;
-        const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
+        Tr tr;
+        if (kEarly) tr = tr0; else load_tr(task, tr);
         const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
-        const int nb = a.mesh.nbr[el * 6 + f];
         const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
-        T uo[6];
-#pragma unroll
-        for (int v = 0; v < 6; ++v) uo[v] = TUr[v * NF + o];
         T w[5];
-        primitives(uo, w);
-        if (nb >= 0) {
-            const size_t on = ((size_t)nb * 6 + (f ^ 1)) * G::n2 + ft.fp;
-            T un6[6], wn[5];
-#pragma unroll
-            for (int v = 0; v < 6; ++v) un6[v] = TUr[v * NF + on];
-            const T lm = a.TF[6 * NF + o], lp = a.TF[6 * NF + on];
-            const T lam = lm > lp ? lm : lp;
+        primitives(tr.uo, w);
+        if (tr.nb >= 0) {
+            T wn[5];
+            const T lam = tr.G[6] > tr.Gn[6] ? tr.G[6] : tr.Gn[6];
 #pragma unroll
             for (int v = 0; v < 6; ++v) {
-                const T Fn = T(0.5) * (a.TF[v * NF + o] - a.TF[v * NF + on]) - T(0.5) * lam * (un6[v] - uo[v]);
+                const T Fn = T(0.5) * (tr.G[v] - tr.Gn[v]) - T(0.5) * lam * (tr.un[v] - tr.uo[v]);
                 sFs[v][slot] = Fn * dS;
             }
-            primitives(un6, wn);
+            primitives(tr.un, wn);
 #pragma unroll
             for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + wn[k]);
         } else {
 #pragma unroll
-            for (int v = 0; v < 6; ++v) sFs[v][slot] = a.TF[v * NF + o] * dS;
+            for (int v = 0; v < 6; ++v) sFs[v][slot] = tr.G[v] * dS;
             wall_primitives(a.mesh, el, f, w);
         }
 #pragma unroll
@@ -1066,6 +1087,9 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
     const int base = le * G::n3;
     if (act) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) s.gT[m] = a.G2[m * a.NN + g];
+        s.lapc = a.G2[3 * a.NN + g];
         T gd[5][3];
         lifted_grads<P, 5>(sF, sS, base, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
         T Ja[9], grho[3];
