@@ -75,7 +75,10 @@ def survey_bytes_model(N, word):
     return 24 * word, (24 + 12 + 2 * F * 35 + 38) * word
 
 
-def cpu_baseline(w, budget_s=15.0):
+def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
+    """The FP64 C oracle on the host's cores (OpenMP over elements): full RK
+    steps on the whole workload mesh for about budget_s seconds, then the same
+    on one thread for about single_thread_s seconds."""
     import numpy as np
 
     import oracle
@@ -83,21 +86,34 @@ def cpu_baseline(w, budget_s=15.0):
     b = oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
                         w.side_theta)
     o = oracle.Oracle(p, b)
-    U = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise())
-    dt = o.dt(U)
-    R = np.zeros_like(U)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.rk_step(U, R, 0.0, dt)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or steps >= 50:
-            break
-    return {"value": o.nnodes * 5 * steps / el, "unit": "node-stage updates/s", "cores": oracle.get_threads(),
+    U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise())
+    dt = o.dt(U0)
+
+    def timed(budget, cap):
+        U = U0.copy()
+        R = np.zeros_like(U)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            o.rk_step(U, R, 0.0, dt)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget or steps >= cap:
+                return steps, el
+
+    cores = oracle.get_threads()
+    steps, el = timed(budget_s, 200)
+    oracle.set_threads(1)
+    try:
+        steps1, el1 = timed(single_thread_s, 50)
+    finally:
+        oracle.set_threads(cores)
+    return {"value": o.nnodes * 5 * steps / el, "unit": "node-stage updates/s", "cores": cores,
             "kind": "oracle",
             "sample": f"{w.name}: {steps} full RK4 step(s) of the FP64 C oracle on the whole mesh "
-                      f"({o.nnodes} nodes), {el:.1f} s"}
+                      f"({o.nnodes} nodes), {el:.1f} s",
+            "single_thread": {"value": o.nnodes * 5 * steps1 / el1, "cores": 1,
+                              "sample": f"{steps1} step(s), {el1:.1f} s"}}
 
 
 def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_active_nodes=4_000_000):
