@@ -86,7 +86,7 @@ def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
     b = oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
                         w.side_theta)
     o = oracle.Oracle(p, b)
-    U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise())
+    U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l)
     dt = o.dt(U0)
 
     def timed(budget, cap):
@@ -170,7 +170,7 @@ def precision_study(which="c3", steps=None, restriction=True):
             out[f"{name}_rel_max"] = float(d.abs().max() / b[k].abs().max())
         return out
 
-    w = wl.c3() if which == "c3" else wl.c4()
+    w = {"c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[which]()
     steps = steps or w.steps
     res = {"steps": steps}
     s = solver_for(w, "fp64")
@@ -192,7 +192,7 @@ def precision_study(which="c3", steps=None, restriction=True):
     if not restriction:
         return res
     # restriction: same set-up on a small mesh, GPU forms vs the oracle
-    wr = wl.c3(4) if which == "c3" else wl.c4(scale=8)
+    wr = {"c3": lambda: wl.c3(4), "c4": lambda: wl.c4(scale=8), "c5": lambda: wl.c5(scale=10)}[which]()
     sr = solver_for(wr, "fp64")
     Ur = init_workload(sr, wr)
     dtr = sr.dt(Ur)
@@ -220,16 +220,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c1 4^3 N=3 droplet; c2 16^3 N=4 two droplets (default); c3 32^3 N=5 eight "
+                         "droplets; c4 48x48x24 N=3 sessile wall box; c5 50^3 N=3 head-on collision")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serving", action="store_true", help="run only the request-stream serving measurement")
-    ap.add_argument("--precision-study", choices=["c3", "c4"], default=None,
+    ap.add_argument("--precision-study", choices=["c3", "c4", "c5"], default=None,
                     help="FP32-mixed vs FP64 errors over the workload's full step count (c3: 32^3 N=5, "
-                         "500 steps; c4: sessile wall case, 1000 steps)")
+                         "500 steps; c4: sessile wall case, 1000 steps; c5: head-on collision, 200 steps)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--threads", type=int, default=256, choices=[256, 512],
@@ -268,7 +270,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4}[args.workload]()
+    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[args.workload]()
     stream = torch.cuda.current_stream()
 
     def timed_run(precision, U0=None):

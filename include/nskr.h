@@ -97,12 +97,17 @@ typedef struct {
 } nskr_mesh;
 
 /* Droplet initial condition: rho = rho_v + sum_j (rho_l - rho_v)/2 (1 +
- * tanh((r_j - d_j)/width)) with the Maxwell densities at T0 (the tanh profile
- * of Sec. 4.1.1/4.2 with its width given directly), d_j the distance to centre
- * j, taken as the minimum image along the axes flagged periodic (box extent
- * length[]); u = 0; c = rho; rho e from eq. totalenergyalpha with the lifted
- * grad c, so that the recovered temperature is T0.  centres: ndrop x 3,
- * radii: ndrop, host memory. */
+ * tanh((r_j - d_j)/width)) (the tanh profiles of Sec. 4.1.1, 4.2 and 4.3 with
+ * their width given directly), d_j the distance to centre j, taken as the
+ * minimum image along the axes flagged periodic (box extent length[]);
+ * rho_v, rho_l are the Maxwell densities at T0 unless both fields below are
+ * positive (e.g. the Young-Laplace adjusted densities of the collision cases,
+ * Sec. 4.3, Table 5).  Velocity u = sum_j v_j (1 + tanh((r_j - d_j)/width))/2, each
+ * droplet carrying its own velocity v_j (zero when velocities is NULL);
+ * m = rho u; c = rho; rho e from eq. totalenergyalpha with the lifted grad c
+ * and the kinetic energy, so that the recovered temperature is T0.
+ * centres: ndrop x 3, radii: ndrop, velocities: ndrop x 3 or NULL; host
+ * memory. */
 typedef struct {
     double T0;
     int ndrop;
@@ -111,6 +116,8 @@ typedef struct {
     double width;
     double length[3];
     int periodic[3];
+    const double *velocities;
+    double rho_v, rho_l;
 } nskr_init;
 
 /* Integrals returned by nskr_reduce (Gauss quadrature with the Jacobian, FP64
@@ -164,9 +171,10 @@ int nskr_state_size(const nskr_ctx *ctx, size_t *nvalues);
 int nskr_device_bytes(const nskr_ctx *ctx, size_t *bytes);
 
 /* Write the droplet initial state into U (see nskr_init).  noise: host array
- * of nelems (N+1)^3 doubles added to rho in node order (before c = rho), or
- * NULL.  Errors: NSKR_E_ARG (null U or ic, ndrop < 0, width <= 0, T0 not below
- * the critical temperature). */
+ * of nelems (N+1)^3 doubles added to rho in node order (before c = rho and
+ * m = rho u), or NULL.  Errors: NSKR_E_ARG (null U or ic, ndrop < 0,
+ * width <= 0, T0 not below the critical temperature when the Maxwell
+ * densities are needed, densities outside (0, 1/b) or rho_l <= rho_v). */
 int nskr_init_droplets(nskr_ctx *ctx, const nskr_init *ic, const double *noise, void *U, nskr_stream s);
 
 /* U_t = L(U), the semi-discrete operator (Sec. 3.1).  Asynchronous.

@@ -8,7 +8,7 @@ basis, metrics, thermodynamics, fluxes, walls, time integration and
 reductions, each written from the paper (arXiv 2208.05310, Sec. 2-3).
 
 Pinned by ``tests/test_oracle_*.py`` against values the paper prints
-(Tables 1, 2, 4), closed forms, DGSEM invariants (exactness, free-stream
+(Tables 1, 2, 5), closed forms, DGSEM invariants (exactness, free-stream
 preservation, conservation), the relaxation ODE, a convergence study on an
 isentropic vortex (ideal-gas reduction) and a manufactured solution of the
 full system, and a dense brute-force re-implementation on a tiny mesh.
@@ -75,7 +75,7 @@ def lib():
         "orc_dt": (d, [vp, _D]),
         "orc_rk_step": (None, [vp, _D, _D, d, d]),
         "orc_run": (None, [vp, _D, _D, d, d, i]),
-        "orc_init_droplets": (i, [vp, d, i, _D, _D, d, _D, _D]),
+        "orc_init_droplets": (i, [vp, d, i, _D, _D, d, _D, _D, _D, d, d]),
         "orc_reduce": (None, [vp, _D, _D]),
         "orc_maxwell": (i, [d, d, d, d, _D, _D, _D]),
         "orc_spinodal": (i, [d, d, d, d, _D, _D]),
@@ -186,7 +186,8 @@ class Oracle:
     def run(self, U, R, t, dt, nsteps):
         lib().orc_run(self._c, _ptr(U), _ptr(R), float(t), float(dt), int(nsteps))
 
-    def init_droplets(self, T0, centres, radii, width, noise=None) -> np.ndarray:
+    def init_droplets(self, T0, centres, radii, width, noise=None, velocities=None, rho_v=0.0,
+                      rho_l=0.0) -> np.ndarray:
         U = self.state()
         cen = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
         rad = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
@@ -194,8 +195,13 @@ class Oracle:
         if noise is not None:
             nz = np.ascontiguousarray(noise, dtype=np.float64)
             assert nz.size == self.nnodes
+        vel = None
+        if velocities is not None:
+            vel = np.ascontiguousarray(np.asarray(velocities, dtype=np.float64).reshape(-1, 3))
+            assert vel.shape[0] == rad.size
         rc = lib().orc_init_droplets(self._c, float(T0), int(rad.size), _ptr(cen), _ptr(rad),
-                                     float(width), _ptr(nz) if nz is not None else None, _ptr(U))
+                                     float(width), _ptr(nz) if nz is not None else None, _ptr(U),
+                                     _ptr(vel) if vel is not None else None, float(rho_v), float(rho_l))
         if rc != 0:
             raise ValueError("init failed (supercritical temperature?)")
         return U

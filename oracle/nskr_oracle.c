@@ -1458,21 +1458,33 @@ double orc_dt(void *vc, const double *U)
 /* ------------------------------------------------------------------------ */
 
 /* Droplets: rho = rho_v + sum_j (rho_l - rho_v)/2 (1 + tanh((r_j - d_j)/w)),
- * the tanh profile of Sec. 4.1.1 and 4.2 with the width written directly,
- * distances as minimum images along periodic axes; Maxwell densities at T0;
- * plus the given per-node noise; c = rho; u = 0; rho e from
- * eq. totalenergyalpha with the lifted grad c, so the recovered temperature
- * is T0.  noise may be NULL. */
+ * the tanh profile of Sec. 4.1.1, 4.2 and 4.3 with the width written
+ * directly, distances as minimum images along periodic axes; rho_v, rho_l the
+ * Maxwell densities at T0 unless both rv_in and rl_in are positive (the
+ * Young-Laplace densities of the collision cases, Table 5); plus the given
+ * per-node noise; c = rho.  Velocity: each droplet j carries its velocity
+ * v_j (vel[3j..3j+2], or 0 when vel is NULL) weighted by its indicator
+ * (1 + tanh((r_j - d_j)/w))/2, so a droplet moves with v_j and the vapour far
+ * from it is at rest (the collision velocity field of Sec. 4.3 read as
+ * u_rel/2 per droplet); m = rho u.  rho e from eq. totalenergyalpha with the
+ * lifted grad c and the kinetic energy, so the recovered temperature is T0.
+ * noise and vel may be NULL. */
 int orc_init_droplets(void *vc, double T0, int nd, const double *cen, const double *rad,
-                      double width, const double *noise, double *U)
+                      double width, const double *noise, double *U, const double *vel, double rv_in,
+                      double rl_in)
 {
     orc_ctx *c = vc;
     const orc_params *pr = &c->pr;
     double rv, rl;
-    if (!orc_maxwell(pr->R, pr->a, pr->b, T0, &rv, &rl, NULL)) return -1;
+    if (rv_in > 0.0 && rl_in > 0.0) {
+        rv = rv_in;
+        rl = rl_in;
+    } else if (!orc_maxwell(pr->R, pr->a, pr->b, T0, &rv, &rl, NULL)) {
+        return -1;
+    }
     size_t nn = (size_t)c->E * c->n3;
     for (size_t a = 0; a < nn; ++a) {
-        double rho = rv;
+        double rho = rv, u[3] = {0.0, 0.0, 0.0};
         for (int j = 0; j < nd; ++j) {
             double d2 = 0.0;
             for (int m = 0; m < 3; ++m) {
@@ -1480,11 +1492,16 @@ int orc_init_droplets(void *vc, double T0, int nd, const double *cen, const doub
                 if (c->box.periodic[m]) dx -= c->box.len[m] * round(dx / c->box.len[m]);
                 d2 += dx * dx;
             }
-            rho += 0.5 * (rl - rv) * (1.0 + tanh((rad[j] - sqrt(d2)) / width));
+            double th = tanh((rad[j] - sqrt(d2)) / width);
+            rho += 0.5 * (rl - rv) * (1.0 + th);
+            if (vel)
+                for (int m = 0; m < 3; ++m) u[m] += vel[3 * j + m] * 0.5 * (1.0 + th);
         }
         if (noise) rho += noise[a];
         U[a] = rho;
-        U[nn + a] = U[2 * nn + a] = U[3 * nn + a] = 0.0;
+        U[nn + a] = rho * u[0];
+        U[2 * nn + a] = rho * u[1];
+        U[3 * nn + a] = rho * u[2];
         U[4 * nn + a] = 0.0;
         U[5 * nn + a] = rho;
     }
@@ -1493,7 +1510,8 @@ int orc_init_droplets(void *vc, double T0, int nd, const double *cen, const doub
     for (size_t a = 0; a < nn; ++a) {
         double rho = U[a];
         double g2 = q[12 * nn + a] * q[12 * nn + a] + q[13 * nn + a] * q[13 * nn + a] + q[14 * nn + a] * q[14 * nn + a];
-        U[4 * nn + a] = rho * (pr->R * pr->cv * T0 - pr->a * rho) + 0.5 * pr->gam * g2;
+        double m2 = U[nn + a] * U[nn + a] + U[2 * nn + a] * U[2 * nn + a] + U[3 * nn + a] * U[3 * nn + a];
+        U[4 * nn + a] = rho * (pr->R * pr->cv * T0 - pr->a * rho) + 0.5 * pr->gam * g2 + 0.5 * m2 / rho;
     }
     free(q);
     return 0;

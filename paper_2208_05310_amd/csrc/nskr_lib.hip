@@ -460,21 +460,24 @@ __global__ __launch_bounds__(kBlock) void k_init_rho(T *U, InitArgs a)
         for (int d = 0; d < 3; ++d) s += eg[3 + 3 * d + m] * 0.5 * (a.bas.x[idx[d]] + 1.0);
         x[m] = s;
     }
-    double rho = a.rv;
+    double rho = a.rv, u[3] = {0.0, 0.0, 0.0};
     for (int jd = 0; jd < a.ndrop; ++jd) {
+        const double *dj = a.drop + 7 * jd;
         double d2 = 0;
         for (int m = 0; m < 3; ++m) {
-            double dx = x[m] - a.drop[4 * jd + m];
+            double dx = x[m] - dj[m];
             if (a.per[m]) dx -= a.len[m] * rint(dx / a.len[m]);
             d2 += dx * dx;
         }
-        rho += 0.5 * (a.rl - a.rv) * (1.0 + tanh((a.drop[4 * jd + 3] - sqrt(d2)) / a.width));
+        const double th = 1.0 + tanh((dj[3] - sqrt(d2)) / a.width);
+        rho += 0.5 * (a.rl - a.rv) * th;
+        for (int m = 0; m < 3; ++m) u[m] += dj[4 + m] * (0.5 * th);  // v_j times the droplet indicator
     }
     if (a.noise) rho += a.noise[g];
     U[g] = T(rho);
-    U[a.NN + g] = T(0);
-    U[2 * a.NN + g] = T(0);
-    U[3 * a.NN + g] = T(0);
+    U[a.NN + g] = T(rho * u[0]);
+    U[2 * a.NN + g] = T(rho * u[1]);
+    U[3 * a.NN + g] = T(rho * u[2]);
     U[4 * a.NN + g] = T(0);
     U[5 * a.NN + g] = T(rho);
 }
@@ -487,9 +490,10 @@ __global__ __launch_bounds__(kBlock) void k_init_energy(T *U, const T *Q, int E,
     const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le;
     if (t >= G::NV || e >= E) return;
     const size_t g = (size_t)e0 * G::n3 + t;
-    const double rho = U[g];
+    const double rho = U[g], m0 = U[NN + g], m1 = U[2 * NN + g], m2 = U[3 * NN + g];
     const double q0 = Q[12 * NN + g], q1 = Q[13 * NN + g], q2 = Q[14 * NN + g];
-    U[4 * NN + g] = T(rho * (ph.R * ph.cv * T0 - ph.a * rho) + 0.5 * ph.gam * (q0 * q0 + q1 * q1 + q2 * q2));
+    U[4 * NN + g] = T(rho * (ph.R * ph.cv * T0 - ph.a * rho) + 0.5 * ph.gam * (q0 * q0 + q1 * q1 + q2 * q2) +
+                      0.5 * (m0 * m0 + m1 * m1 + m2 * m2) / rho);
 }
 
 // Zero fill (used instead of a memset so that it can sit in captured graphs).
@@ -971,16 +975,25 @@ int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, vo
         if (ic->periodic[k] && !(ic->length[k] > 0)) return fail(c, NSKR_E_ARG, "periodic axis needs a length");
     Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
     ld rv, rl;
-    if (!(ic->T0 > 0) || !maxwell_host(vdw, (ld)ic->T0, rv, rl))
-        return fail(c, NSKR_E_ARG, "T0 must be positive and subcritical");
+    if (!(ic->T0 > 0)) return fail(c, NSKR_E_ARG, "T0 must be positive");
+    if (ic->rho_v > 0 && ic->rho_l > 0) {
+        rv = ic->rho_v;
+        rl = ic->rho_l;
+        if (!(rl > rv) || (c->p.b > 0 && !(rl * c->p.b < 1)))
+            return fail(c, NSKR_E_ARG, "bulk densities must satisfy 0 < rho_v < rho_l < 1/b");
+    } else if (!maxwell_host(vdw, (ld)ic->T0, rv, rl)) {
+        return fail(c, NSKR_E_ARG, "T0 must be subcritical for the Maxwell densities");
+    }
     DeviceGuard guard(c->device);
     hipStream_t s = (hipStream_t)sv;
     if (c->d_drop) { (void)hipFree(c->d_drop); c->d_drop = nullptr; }
     if (c->d_noise) { (void)hipFree(c->d_noise); c->d_noise = nullptr; }
-    std::vector<double> drop(4 * (size_t)(ic->ndrop > 0 ? ic->ndrop : 1), 0.0);
+    // per droplet: centre (3), radius, velocity (3)
+    std::vector<double> drop(7 * (size_t)(ic->ndrop > 0 ? ic->ndrop : 1), 0.0);
     for (int j = 0; j < ic->ndrop; ++j) {
-        for (int k = 0; k < 3; ++k) drop[4 * j + k] = ic->centres[3 * j + k];
-        drop[4 * j + 3] = ic->radii[j];
+        for (int k = 0; k < 3; ++k) drop[7 * j + k] = ic->centres[3 * j + k];
+        drop[7 * j + 3] = ic->radii[j];
+        for (int k = 0; k < 3; ++k) drop[7 * j + 4 + k] = ic->velocities ? ic->velocities[3 * j + k] : 0.0;
     }
     if (hipMalloc((void **)&c->d_drop, sizeof(double) * drop.size()) != hipSuccess)
         return fail(c, NSKR_E_NOMEM, "droplet table allocation failed");

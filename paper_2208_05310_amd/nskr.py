@@ -55,7 +55,9 @@ class Mesh(ctypes.Structure):
 class Init(ctypes.Structure):
     _fields_ = [("T0", ctypes.c_double), ("ndrop", ctypes.c_int), ("centres", ctypes.POINTER(ctypes.c_double)),
                 ("radii", ctypes.POINTER(ctypes.c_double)), ("width", ctypes.c_double),
-                ("length", ctypes.c_double * 3), ("periodic", ctypes.c_int * 3)]
+                ("length", ctypes.c_double * 3), ("periodic", ctypes.c_int * 3),
+                ("velocities", ctypes.POINTER(ctypes.c_double)), ("rho_v", ctypes.c_double),
+                ("rho_l", ctypes.c_double)]
 
 
 _lib = None
@@ -237,19 +239,26 @@ class Solver:
             raise ValueError(f"expected a contiguous {self.dtype} CUDA tensor with {rows} x {self.nnodes} values")
         return ctypes.c_void_p(U.data_ptr())
 
-    def init_droplets(self, U, T0, centres, radii, width, noise=None, stream=None):
+    def init_droplets(self, U, T0, centres, radii, width, noise=None, stream=None, velocities=None, rho_v=0.0,
+                      rho_l=0.0):
         cen = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
         rad = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
-        ic = Init(float(T0), int(rad.size), cen.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                  rad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(width),
-                  (ctypes.c_double * 3)(*self.box["length"]), (ctypes.c_int * 3)(*self.box["periodic"]))
+        vel = None
+        if velocities is not None:
+            vel = np.ascontiguousarray(np.asarray(velocities, dtype=np.float64).reshape(-1, 3))
+            if vel.shape[0] != rad.size:
+                raise ValueError("one velocity per droplet")
+        dp = ctypes.POINTER(ctypes.c_double)
+        ic = Init(float(T0), int(rad.size), cen.ctypes.data_as(dp), rad.ctypes.data_as(dp), float(width),
+                  (ctypes.c_double * 3)(*self.box["length"]), (ctypes.c_int * 3)(*self.box["periodic"]),
+                  vel.ctypes.data_as(dp) if vel is not None else None, float(rho_v), float(rho_l))
         nz = None
         if noise is not None:
             nz = np.ascontiguousarray(noise, dtype=np.float64)
             if nz.size != self.nnodes:
                 raise ValueError("noise must have one value per node")
         self._check(self.L.nskr_init_droplets(self._h, ctypes.byref(ic),
-                                              nz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if nz is not None else None,
+                                              nz.ctypes.data_as(dp) if nz is not None else None,
                                               self._state_ok(U), _stream_ptr(stream)))
         return U
 
@@ -382,4 +391,5 @@ def solver_for(w, precision="fp64", device=0, kahan=True):
 def init_workload(s: Solver, w, U=None):
     if U is None:
         U = s.new_state()
-    return s.init_droplets(U, w.T0, w.centres, w.radii, w.width, w.noise())
+    return s.init_droplets(U, w.T0, w.centres, w.radii, w.width, w.noise(), velocities=w.velocities,
+                           rho_v=w.rho_v, rho_l=w.rho_l)

@@ -45,6 +45,9 @@ class Workload:
     noise_amp: float = 1e-6
     params: dict = field(default_factory=lambda: dict(TABLE1))
     curve_amp: float = 0.0
+    velocities: tuple | None = None   # one velocity per droplet, or None (at rest)
+    rho_v: float = 0.0                # bulk densities; 0 selects the Maxwell states at T0
+    rho_l: float = 0.0
 
     @property
     def nelems(self) -> int:
@@ -129,6 +132,27 @@ def c4(scale=1) -> Workload:
                     side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 90.0),
                     T0=0.85, centres=((0.5, 0.5, 0.0),), radii=(0.2,), steps=1000,
                     noise_seed=14)
+
+
+# Head-on collision regimes of Sec. 4.3 (Table 6): relative velocity and
+# viscosity; the other properties are common (Table 5).
+COLLISION = {"reflexive": (2.2, 6.944e-4), "toroidal": (4.0, 1.010e-3)}
+
+
+def c5(scale=1, regime="reflexive") -> Workload:
+    """Binary head-on droplet collision (Sec. 4.3): periodic unit cube, 50^3
+    elements at N=3 (divided by ``scale``); droplets r=0.1 at (0.3,0.5,0.5)
+    and (0.7,0.5,0.5) moving towards each other with u_rel/2 each; the
+    Young-Laplace adjusted densities 0.3537 / 1.8493 at T=0.85 and interface
+    width 0.0772 of Table 5 (tanh width 0.0772/4); gamma_K = 1/6000,
+    alpha = 200, beta = 1000, k = 1/150, c_v = 5, mu of Table 6."""
+    u_rel, mu = COLLISION[regime]
+    n = 50 // scale
+    params = dict(TABLE1, gam=1.0 / 6000.0, alpha=200.0, beta=1000.0, mu=mu)
+    return Workload(name=f"collision_{regime}_{n}x{n}x{n}_N3", N=3, n=(n, n, n), T0=0.85,
+                    centres=((0.3, 0.5, 0.5), (0.7, 0.5, 0.5)), radii=(0.1, 0.1), width=0.0772 / 4,
+                    velocities=((u_rel / 2, 0.0, 0.0), (-u_rel / 2, 0.0, 0.0)), rho_v=0.3537, rho_l=1.8493,
+                    steps=200, noise_seed=15, params=params)
 
 
 def serving_stream(seed=5, count=256, rate=50.0):

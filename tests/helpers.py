@@ -13,4 +13,4 @@ def oracle_for(w: wl.Workload, threads=None) -> oracle.Oracle:
 
 
 def oracle_init(o: oracle.Oracle, w: wl.Workload) -> np.ndarray:
-    return o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise())
+    return o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l)

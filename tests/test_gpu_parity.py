@@ -97,6 +97,7 @@ def small_cases():
         wl.c4(scale=8).with_(name="wall_6x6x3_N4_theta120", N=4,
                              side_theta=(90.0, 90.0, 90.0, 90.0, 120.0, 90.0)),
         wl.c4(scale=12).with_(name="wall_4x4x2_N2_hot", N=2, T0=0.8),
+        wl.c5(scale=10),                                                 # moving droplets, 5^3, N=3
     ]
 
 
@@ -182,10 +183,14 @@ def test_init_parity(torch_cuda, w):
     torch.cuda.synchronize()
     err = rel_err(Ug.cpu().numpy(), Uo)
     assert np.all(err[[0, 4, 5]] <= TOL), err
-    assert np.all(Ug[1:4].abs().max().item() == 0.0)
+    if w.velocities is None:
+        assert np.all(Ug[1:4].abs().max().item() == 0.0)
+    else:
+        err = rel_err(Ug.cpu().numpy(), Uo, state_floor(Uo, w.params))
+        assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[3]], ids=[IDS[0], IDS[5], IDS[3]])
+@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[3], CASES[8]], ids=[IDS[0], IDS[5], IDS[3], IDS[8]])
 def test_dt_parity(torch_cuda, w):
     torch = torch_cuda
     print(f"[case] dt {w.name}", flush=True)
@@ -197,7 +202,7 @@ def test_dt_parity(torch_cuda, w):
     assert abs(dg - do) <= 1e-14 * do, (dg, do)
 
 
-@pytest.mark.parametrize("w", [CASES[0], CASES[5]], ids=[IDS[0], IDS[5]])
+@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[8]], ids=[IDS[0], IDS[5], IDS[8]])
 def test_reduce_parity(torch_cuda, w):
     torch = torch_cuda
     print(f"[case] reduce {w.name}", flush=True)
@@ -215,7 +220,7 @@ def test_reduce_parity(torch_cuda, w):
             assert abs(rg[k] - ro[k]) <= 1e-13 * scale[k] + 1e-300, (k, rg[k], ro[k])
 
 
-@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[4]], ids=[IDS[0], IDS[5], IDS[4]])
+@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[4], CASES[8]], ids=[IDS[0], IDS[5], IDS[4], IDS[8]])
 def test_rk_steps_parity(torch_cuda, w):
     """Fixed number of RK steps with the oracle's step-0 dt on both sides."""
     torch = torch_cuda
@@ -255,17 +260,18 @@ def test_rk_split_equals_joined(torch_cuda):
     assert torch.equal(U1, U2)
 
 
-FULL = [("c2", 2), ("c3", 1), ("c4", 1)]
+FULL = [("c2", 2), ("c3", 1), ("c4", 1), ("c5", 1)]
 
 
 @pytest.mark.parametrize("which,steps", FULL, ids=[f"{w}_{n}steps" for w, n in FULL])
 def test_full_size_workload_parity(torch_cuda, which, steps):
     """The benchmark workloads at full size, same kernels and launch
     configuration as bench.py: 16^3 N=4 (512000 nodes), 32^3 N=5 (7.08M
-    nodes) and the 48x48x24 N=3 wall box (3.54M nodes).  GPU initial state,
+    nodes), the 48x48x24 N=3 wall box (3.54M nodes) and the 50^3 N=3 head-on
+    collision (8M nodes, moving droplets).  GPU initial state,
     time step and RK steps against the oracle's, on every node."""
     torch = torch_cuda
-    w = {"c2": wl.c2, "c3": wl.c3, "c4": wl.c4}[which]()
+    w = {"c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[which]()
     print(f"[case] full-size {w.name}, {steps} step(s)", flush=True)
     from paper_2208_05310_amd.nskr import init_workload
     s = gpu_solver(w)

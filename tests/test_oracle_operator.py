@@ -295,3 +295,51 @@ def test_init_recovers_temperature():
     assert np.max(np.abs(T - 0.85)) < 1e-13
     rv, rl, _ = oracle.maxwell(0.85)
     assert abs(U[0].min() - rv) < 1e-3 and abs(U[0].max() - rl) < 1e-2
+
+
+def collision_pair(o, u_rel=2.2):
+    """Two droplets approaching head-on along x (the collision set-up of
+    Sec. 4.3 with the Young-Laplace densities of Table 5)."""
+    return o.init_droplets(0.85, [(0.3, 0.5, 0.5), (0.7, 0.5, 0.5)], [0.1, 0.1], 0.0772 / 4, None,
+                           velocities=[(u_rel / 2, 0, 0), (-u_rel / 2, 0, 0)], rho_v=0.3537, rho_l=1.8493)
+
+
+def test_init_with_velocities_recovers_temperature_and_densities():
+    """With moving droplets the total energy must carry the kinetic part:
+    the recovered temperature is T0 at every node (a missing or doubled
+    kinetic term shifts T by |u|^2/(2 R c_v), ~0.05 here); the prescribed
+    bulk densities replace the Maxwell states; the droplets move with their
+    velocities and the vapour between them is at rest."""
+    o = make(3, (6, 4, 4))
+    U = collision_pair(o)
+    T = o.lift2(U)[0]
+    assert np.max(np.abs(T - 0.85)) < 1e-12
+    assert abs(U[0].min() - 0.3537) < 1e-6 and abs(U[0].max() - 1.8493) < 2e-2
+    u = U[1] / U[0]
+    X = o.coords().T
+    x = X[:, 0]
+    inside1 = np.linalg.norm(X - np.array([0.3, 0.5, 0.5]), axis=1) < 0.05
+    inside2 = np.linalg.norm(X - np.array([0.7, 0.5, 0.5]), axis=1) < 0.05
+    assert inside1.any() and inside2.any()
+    assert np.allclose(u[inside1], 1.1, rtol=1e-3) and np.allclose(u[inside2], -1.1, rtol=1e-3)
+    mid = np.abs(x - 0.5) < 0.05
+    assert np.max(np.abs(u[mid])) < 1e-3
+    assert np.all(U[2] == 0.0) and np.all(U[3] == 0.0)
+
+
+def test_collision_state_is_mirror_antisymmetric():
+    """The head-on pair is symmetric under x -> 1 - x with the x-momentum
+    changing sign: total x-momentum vanishes and the integrals of density and
+    energy equal twice those of one half (checked through the mirror image
+    node by node on a mesh symmetric about x = 1/2)."""
+    o = make(3, (6, 4, 4))
+    U = collision_pair(o)
+    X = o.coords().T
+    key = lambda P: np.round(P, 12)
+    idx = {tuple(k): n for n, k in enumerate(key(X))}
+    mirror = np.array([idx[tuple(key(np.array([1.0 - p[0], p[1], p[2]])))] for p in X])
+    assert np.allclose(U[0][mirror], U[0], rtol=0, atol=1e-14)
+    assert np.allclose(U[1][mirror], -U[1], rtol=0, atol=1e-13)
+    assert np.allclose(U[4][mirror], U[4], rtol=1e-12, atol=1e-12)
+    sums = o.reduce(U)
+    assert abs(sums[1]) < 1e-12 * abs(sums[0])

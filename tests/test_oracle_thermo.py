@@ -128,8 +128,8 @@ def test_sigma_and_interface_width_table1():
     assert round(Li, 4) == g["L_i"]
 
 
-def test_sigma_and_interface_width_table4():
-    g = GOLD["table4_droplet_collision"]
+def test_sigma_and_interface_width_table5():
+    g = GOLD["table5_droplet_collision"]
     sig = oracle.sigma(g["T0"], g["gamma_K"])
     rv, rl, _ = oracle.maxwell(g["T0"])
     Li = math.sqrt(2.0) * g["gamma_K"] * (rl - rv) ** 2 / sig
@@ -161,10 +161,10 @@ def test_sigma_printed_prefactor_is_garbled():
     assert abs(s / math.sqrt(2e-4) * math.sqrt(2 / 1e-4) - 52.3) < 0.1
 
 
-def test_young_laplace_densities_table4():
+def test_young_laplace_densities_table5():
     # Sec. 4.3: p_v = p_sat + rho_v/(rho_l-rho_v) 2 sigma/r, p_l = p_sat + rho_l/(rho_l-rho_v) 2 sigma/r,
     # densities from the inverse pressure law at T0.
-    g = GOLD["table4_droplet_collision"]
+    g = GOLD["table5_droplet_collision"]
     T = g["T0"]
     rv, rl, ps = oracle.maxwell(T)
     sig = oracle.sigma(T, g["gamma_K"])
@@ -196,7 +196,7 @@ def test_wall_energy_properties(theta):
 
 
 def test_appendix_states_consistent_with_porous_setup():
-    # Consistency with the porous-medium set-up (Sec. 4.4): rho = 1.5 lies outside the
+    # Consistency with the porous-medium set-up (Sec. 4.5): rho = 1.5 lies outside the
     # saturation dome at T = 0.95 and inside the spinodal at T = 0.75.
     rv, rl, _ = oracle.maxwell(0.95)
     assert 1.5 > rl

@@ -15,11 +15,13 @@ from paper_2208_05310_amd import workloads as wl
     (wl.c2, 16 ** 3 * 5 ** 3, 4, 0.85),
     (wl.c3, 32 ** 3 * 6 ** 3, 5, 0.9),
     (wl.c4, 48 * 48 * 24 * 4 ** 3, 3, 0.85),
+    (wl.c5, 50 ** 3 * 4 ** 3, 3, 0.85),
 ])
 def test_benchmark_workload_sizes(make, nodes, N, T0):
     w = make()
     assert w.nnodes == nodes and w.N == N and w.T0 == T0
-    assert w.params == wl.TABLE1
+    if make is not wl.c5:
+        assert w.params == wl.TABLE1
 
 
 def test_sizes_of_the_named_configurations():
@@ -83,3 +85,15 @@ def test_request_stream_distributions():
     for w in walls:
         assert 45.0 <= w.side_theta[4] <= 135.0 and w.side_twall[4] == w.T0
     assert len({w.noise_seed for w in ws}) == len(ws)
+
+
+def test_collision_workload_matches_tables_4_and_5():
+    for regime, (u_rel, mu) in (("reflexive", (2.2, 6.944e-4)), ("toroidal", (4.0, 1.010e-3))):
+        w = wl.c5(regime=regime)
+        assert w.params["mu"] == mu and w.params["alpha"] == 200.0 and w.params["beta"] == 1000.0
+        assert w.params["gam"] == 1.0 / 6000.0 and w.params["kappa"] == 1.0 / 150.0 and w.params["cv"] == 5.0
+        assert (w.rho_v, w.rho_l, w.T0, w.radii) == (0.3537, 1.8493, 0.85, (0.1, 0.1))
+        assert w.width == 0.0772 / 4
+        # relative velocity u_rel along x, droplets approaching each other
+        (v1, v2) = w.velocities
+        assert v1[0] - v2[0] == u_rel and v1[0] > 0 > v2[0] and w.centres[0][0] < w.centres[1][0]
