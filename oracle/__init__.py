@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
     _fields_ = [("R", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("gam", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("cfl", ctypes.c_double)]
+                ("cfl", ctypes.c_double), ("model", ctypes.c_int)]
 
 
 class Box(ctypes.Structure):
@@ -76,6 +76,7 @@ def lib():
         "orc_rk_step": (None, [vp, _D, _D, d, d]),
         "orc_run": (None, [vp, _D, _D, d, d, i]),
         "orc_init_droplets": (i, [vp, d, i, _D, _D, d, _D, _D, _D, d, d]),
+        "orc_numflux": (None, [ctypes.POINTER(Params), _D, d, _D, d, _D, _D]),
         "orc_reduce": (None, [vp, _D, _D]),
         "orc_maxwell": (i, [d, d, d, d, _D, _D, _D]),
         "orc_spinodal": (i, [d, d, d, d, _D, _D]),
@@ -108,8 +109,10 @@ def _ptr(a: np.ndarray):
 
 
 def make_params(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.01, kappa=1.0 / 150.0,
-                gam=1e-4, alpha=100.0, beta=1000.0, cfl=0.9) -> Params:
-    return Params(R, a, b, cv, mu, kappa, gam, alpha, beta, cfl)
+                gam=1e-4, alpha=100.0, beta=1000.0, cfl=0.9, model=1) -> Params:
+    """model: relaxation model 1 (Rusanov flux) or 2 (modified pressure,
+    HLLC flux)."""
+    return Params(R, a, b, cv, mu, kappa, gam, alpha, beta, cfl, int(model))
 
 
 def make_box(N, n, lo=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
@@ -288,3 +291,14 @@ def set_threads(n):
 
 def get_threads():
     return int(lib().orc_get_threads())
+
+
+def numflux(params, UL, TL, UR, TR, n):
+    """Interior numerical flux of the convective part (Rusanov for model 1,
+    HLLC for model 2) between two face states, along the unit normal n."""
+    out = np.zeros(6)
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    lib().orc_numflux(ctypes.byref(params), _ptr(UL), float(TL), _ptr(UR), float(TR), _ptr(nn), _ptr(out))
+    return out

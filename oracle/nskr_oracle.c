@@ -67,6 +67,7 @@ typedef struct {
     double mu, kappa, gam;    /* viscosity, heat conductivity, capillarity   */
     double alpha, beta;       /* Korteweg and relaxation parameters          */
     double cfl;               /* CFL number (0.9 in the paper)               */
+    int model;                /* relaxation model 1 (0 reads as 1) or 2      */
 } orc_params;
 
 typedef struct {
@@ -256,7 +257,7 @@ static double vdw_psi_nl(const orc_params *pr, double rho, double T)
  * T is supercritical. */
 int orc_spinodal(double R, double a, double b, double T, double *rsv, double *rsl)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     /* g(rho) = (dp/drho)_T is positive near 0 and near 1/b and has a single
      * minimum inside; locate the minimum by golden search, then bisect. */
     double lo = 1e-12, hi = 1.0 / b - 1e-12;
@@ -299,7 +300,7 @@ static double root_increasing(const orc_params *pr, double T, double p0, double 
  * densities of Sec. 4.3. */
 double orc_rho_of_p(double R, double a, double b, double T, double p, int branch)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     double rsv, rsl;
     if (!orc_spinodal(R, a, b, T, &rsv, &rsl)) return NAN;
     if (branch == 0) return root_increasing(&pr, T, p, 1e-14, rsv);
@@ -313,7 +314,7 @@ double orc_rho_of_p(double R, double a, double b, double T, double p, int branch
  * to zero. */
 int orc_maxwell(double R, double a, double b, double T, double *rv, double *rl, double *psat)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     double rsv, rsl;
     if (!orc_spinodal(R, a, b, T, &rsv, &rsl)) return 0;
     double plo = vdw_p(&pr, rsl, T), phi = vdw_p(&pr, rsv, T);
@@ -348,7 +349,7 @@ static double sigma_integrand(const orc_params *pr, double T, double rv, double 
  * converges spectrally; npanel panels of 20 points each. */
 double orc_sigma_panels(double R, double a, double b, double T, double gam, int npanel)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     double rv, rl, x[32], w[32];
     if (!orc_maxwell(R, a, b, T, &rv, &rl, NULL)) return 0.0;
     gauss_nodes(19, x, w);
@@ -371,7 +372,7 @@ double orc_sigma(double R, double a, double b, double T, double gam)
  * paper states for its tabulation (Sec. 3.2); reported beside the reference. */
 double orc_sigma_gauss15(double R, double a, double b, double T, double gam)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     double rv, rl, x[32], w[32];
     if (!orc_maxwell(R, a, b, T, &rv, &rl, NULL)) return 0.0;
     gauss_nodes(14, x, w);
@@ -416,6 +417,24 @@ static double temperature(const orc_params *pr, const double U[6], const double 
     return (reps / rho + pr->a * rho) / (pr->R * pr->cv);
 }
 
+/* Pressure in the convective flux: p for relaxation model 1; for model 2 the
+ * modified pressure p_alpha = p + alpha/2 rho^2 of eq. modified_pressure. */
+static double p_conv(const orc_params *pr, double rho, double T)
+{
+    double p = vdw_p(pr, rho, T);
+    return pr->model == 2 ? p + 0.5 * pr->alpha * rho * rho : p;
+}
+
+/* Speed of sound of the convective flux, sqrt(|(dp/drho)_s|) (reading Q3 for
+ * model 1); model 2 uses p_alpha, whose derivative adds alpha rho (the
+ * eigenvalues u.n +- sqrt((dp_alpha/drho)_s) of Sec. 2.3.2). */
+static double wave_speed(const orc_params *pr, double rho, double T)
+{
+    double a2 = vdw_cs2(pr, rho, T);
+    if (pr->model == 2) a2 += pr->alpha * rho;
+    return sqrt(fabs(a2));
+}
+
 /* Full local state needed for the fluxes at one point. */
 typedef struct {
     double U[6];
@@ -426,12 +445,13 @@ typedef struct {
     double lapc;       /* lifted div(grad c)                  */
 } point_state;
 
-/* Convective flux F^{C,i}, i = 0..2, of eq. navierstokeskorteweg_p. */
+/* Convective flux F^{C,i}, i = 0..2, of eq. navierstokeskorteweg_p (model 1)
+ * or eq. navierstokeskorteweg_palpha (model 2, p replaced by p_alpha). */
 static void flux_conv(const orc_params *pr, const point_state *s, double Fc[3][6])
 {
     double rho = s->U[0];
     double u[3] = {s->U[1] / rho, s->U[2] / rho, s->U[3] / rho};
-    double p = vdw_p(pr, rho, s->T);
+    double p = p_conv(pr, rho, s->T);
     for (int i = 0; i < 3; ++i) {
         Fc[i][0] = s->U[1 + i];
         for (int j = 0; j < 3; ++j)
@@ -470,14 +490,28 @@ static void flux_visc(const orc_params *pr, const point_state *s, double Fv[3][6
     }
 }
 
-/* Non-conservative source S of eq. navierstokeskorteweg_p, evaluated point-
- * wise with the lifted gradients (Sec. 3.1). */
+/* Non-conservative source S of eq. navierstokeskorteweg_p (model 1), or of
+ * eq. navierstokeskorteweg_palpha (model 2: the alpha rho grad rho and
+ * alpha/2 rho^2 div u parts moved into p_alpha), evaluated point-wise with
+ * the lifted gradients (Sec. 3.1). */
 static void source(const orc_params *pr, const double U[6], const double grho[3],
                    const double gu[3][3], const double gc[3], double S[6])
 {
     double rho = U[0], c = U[5];
     double u[3] = {U[1] / rho, U[2] / rho, U[3] / rho};
     double div = gu[0][0] + gu[1][1] + gu[2][2];
+    if (pr->model == 2) {
+        double gc2 = gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2];
+        double cc = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) cc += gc[i] * gc[j] * gu[j][i];
+        S[0] = 0.0;
+        for (int m = 0; m < 3; ++m) S[1 + m] = pr->alpha * rho * gc[m];
+        S[4] = pr->alpha * rho * (gc[0] * u[0] + gc[1] * u[1] + gc[2] * u[2]) + 0.5 * pr->alpha * c * c * div +
+               pr->gam * (0.5 * gc2 * div - cc);
+        S[5] = pr->alpha * pr->beta * (rho - c);
+        return;
+    }
     double d[3] = {gc[0] - grho[0], gc[1] - grho[1], gc[2] - grho[2]};
     double gc2 = gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2];
     double cc = 0.0; /* grad c (x) grad c : grad (x) u = sum_ij c_i c_j du_j/dx_i */
@@ -717,6 +751,7 @@ static void build_metrics(orc_ctx *c)
 void *orc_create(const orc_params *pr, const orc_box *bx, char *err, int errlen)
 {
     if (bx->N < 1 || bx->N >= MAXP) { snprintf(err, errlen, "N out of range"); return NULL; }
+    if (pr->model < 0 || pr->model > 2) { snprintf(err, errlen, "model must be 1 or 2"); return NULL; }
     for (int d = 0; d < 3; ++d)
         if (bx->n[d] < 1 || bx->len[d] <= 0) { snprintf(err, errlen, "bad box"); return NULL; }
     orc_ctx *c = calloc(1, sizeof(orc_ctx));
@@ -1133,14 +1168,71 @@ static void rusanov(const orc_params *pr, const point_state *sm, const point_sta
     flux_conv(pr, sp, Fp);
     double unm = (sm->U[1] * n[0] + sm->U[2] * n[1] + sm->U[3] * n[2]) / sm->U[0];
     double unp = (sp->U[1] * n[0] + sp->U[2] * n[1] + sp->U[3] * n[2]) / sp->U[0];
-    double lm = fabs(unm) + sqrt(fabs(vdw_cs2(pr, sm->U[0], sm->T)));
-    double lp = fabs(unp) + sqrt(fabs(vdw_cs2(pr, sp->U[0], sp->T)));
+    double lm = fabs(unm) + wave_speed(pr, sm->U[0], sm->T);
+    double lp = fabs(unp) + wave_speed(pr, sp->U[0], sp->T);
     double lam = lm > lp ? lm : lp;
     for (int v = 0; v < 6; ++v) {
         double a = 0.0;
         for (int i = 0; i < 3; ++i) a += 0.5 * (Fm[i][v] + Fp[i][v]) * n[i];
         out[v] = a - 0.5 * lam * (sp->U[v] - sm->U[v]);
     }
+}
+
+/* HLLC flux (Toro 2009, Sec. 10.4) of the convective part for relaxation
+ * model 2, in the frame of the unit normal n from side m (left) to side p
+ * (right): wave speeds S_L = min(u_L - a_L, u_R - a_R), S_R = max(u_L + a_L,
+ * u_R + a_R) (Davis) with a = sqrt((dp_alpha/drho)_s) and u the normal
+ * velocity; contact speed S*; star states with the tangential velocity and
+ * c/rho of their side; the order parameter rides along as a passive scalar. */
+static void hllc(const orc_params *pr, const point_state *sm, const point_state *sp, const double n[3],
+                 double out[6])
+{
+    const point_state *st[2] = {sm, sp};
+    double rho[2], un[2], p[2], a[2], F[2][6];
+    for (int k = 0; k < 2; ++k) {
+        const double *U = st[k]->U;
+        rho[k] = U[0];
+        un[k] = (U[1] * n[0] + U[2] * n[1] + U[3] * n[2]) / U[0];
+        p[k] = p_conv(pr, U[0], st[k]->T);
+        a[k] = wave_speed(pr, U[0], st[k]->T);
+        double Fc[3][6];
+        flux_conv(pr, st[k], Fc);
+        for (int v = 0; v < 6; ++v) F[k][v] = Fc[0][v] * n[0] + Fc[1][v] * n[1] + Fc[2][v] * n[2];
+    }
+    double SL = fmin(un[0] - a[0], un[1] - a[1]);
+    double SR = fmax(un[0] + a[0], un[1] + a[1]);
+    if (SL >= 0.0) { for (int v = 0; v < 6; ++v) out[v] = F[0][v]; return; }
+    if (SR <= 0.0) { for (int v = 0; v < 6; ++v) out[v] = F[1][v]; return; }
+    double Ss = (p[1] - p[0] + rho[0] * un[0] * (SL - un[0]) - rho[1] * un[1] * (SR - un[1])) /
+                (rho[0] * (SL - un[0]) - rho[1] * (SR - un[1]));
+    int k = Ss >= 0.0 ? 0 : 1;       /* the star region adjacent to x/t = 0 */
+    double S = k == 0 ? SL : SR;
+    const double *U = st[k]->U;
+    double f = rho[k] * (S - un[k]) / (S - Ss);
+    double Us[6];
+    Us[0] = f;
+    for (int m = 0; m < 3; ++m) Us[1 + m] = f * (U[1 + m] / U[0] + (Ss - un[k]) * n[m]);
+    Us[4] = f * (U[4] / U[0] + (Ss - un[k]) * (Ss + p[k] / (rho[k] * (S - un[k]))));
+    Us[5] = f * U[5] / U[0];
+    for (int v = 0; v < 6; ++v) out[v] = F[k][v] + S * (Us[v] - U[v]);
+}
+
+/* The interior numerical flux of the convective part for two face states
+ * (conserved U and temperature T on each side) and a unit normal: Rusanov for
+ * model 1, HLLC for model 2.  For the tests of the flux alone. */
+void orc_numflux(const orc_params *pr, const double *UL, double TL, const double *UR, double TR, const double *n,
+                 double *out)
+{
+    point_state sm, sp;
+    memset(&sm, 0, sizeof(sm));
+    memset(&sp, 0, sizeof(sp));
+    for (int v = 0; v < 6; ++v) { sm.U[v] = UL[v]; sp.U[v] = UR[v]; }
+    sm.T = TL;
+    sp.T = TR;
+    if (pr->model == 2)
+        hllc(pr, &sm, &sp, n, out);
+    else
+        rusanov(pr, &sm, &sp, n, out);
 }
 
 /* Wall flux (F* . n) of Sec. 3.2 for the readings of eq. bc_nsk_alpha:
@@ -1208,7 +1300,10 @@ static void step_faces(const orc_ctx *c, work_t *w)
                     point_state sp;
                     double Fvm[3][6], Fvp[3][6];
                     face_state(c, w, ne, f ^ 1, fp, &sp);
-                    rusanov(&c->pr, &sm, &sp, n, out);
+                    if (c->pr.model == 2)
+                        hllc(&c->pr, &sm, &sp, n, out);
+                    else
+                        rusanov(&c->pr, &sm, &sp, n, out);
                     flux_visc(&c->pr, &sm, Fvm);
                     flux_visc(&c->pr, &sp, Fvp);
                     for (int v = 0; v < 6; ++v)
@@ -1429,7 +1524,7 @@ double orc_dt(void *vc, const double *U)
             for (int v = 0; v < 6; ++v) U6[v] = U[v * nn + a];
             for (int m = 0; m < 3; ++m) qc[m] = w.q[((size_t)e * 15 + 12 + m) * c->n3 + nd];
             double T = temperature(pr, U6, qc);
-            double cs = sqrt(fabs(vdw_cs2(pr, U6[0], T)));
+            double cs = wave_speed(pr, U6[0], T);
             double J = c->J[a], sl = 0.0, sg = 0.0;
             for (int d = 0; d < 3; ++d) {
                 const double *Ja = c->Ja + a * 9 + d * 3;
@@ -1574,17 +1669,17 @@ void orc_reduce(void *vc, const double *U, double *out)
 /* Point-wise helpers exported for the tests. */
 double orc_pressure(double R, double a, double b, double rho, double T)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     return vdw_p(&pr, rho, T);
 }
 double orc_cs2(double R, double a, double b, double cv, double rho, double T)
 {
-    orc_params pr = {R, a, b, cv, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, cv, 0, 0, 0, 0, 0, 0, 1};
     return vdw_cs2(&pr, rho, T);
 }
 double orc_chempot(double R, double a, double b, double rho, double T)
 {
-    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0};
+    orc_params pr = {R, a, b, 1.0, 0, 0, 0, 0, 0, 0, 1};
     return vdw_mu(&pr, rho, T);
 }
 

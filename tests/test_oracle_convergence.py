@@ -165,14 +165,17 @@ def _ev(fn, x, y, z):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("N", [2, 3])
-def test_manufactured_solution_order(N):
+@pytest.mark.parametrize("N,model", [(2, 1), (3, 1), (3, 2)])
+def test_manufactured_solution_order(N, model):
+    """Model 2 writes the same PDE with alpha/2 rho^2 moved from the source into
+    the pressure, so the same forcing must give the same solution; its
+    discretisation (HLLC, p_alpha in the volume flux) differs from model 1's."""
     fn_f, fn_U = mms_forcing()
     errs, hs = [], []
     T_end = 0.02
     A_, B_, _ = oracle.rk_coeffs()
     for m in (2, 4, 8):
-        o = oracle.Oracle(oracle.make_params(**MMS_PARAMS), oracle.make_box(N, (m, m, m)))
+        o = oracle.Oracle(oracle.make_params(**MMS_PARAMS, model=model), oracle.make_box(N, (m, m, m)))
         x, y, z = o.coords()
         f = np.stack([_ev(fn, x, y, z) for fn in fn_f])
         Uex = np.stack([_ev(fn, x, y, z) for fn in fn_U])
@@ -195,5 +198,8 @@ def test_manufactured_solution_order(N):
     # Every conserved field converges at order >= N (observed 3.3-4.2 for N = 3 and
     # 2.4-2.7 for N = 2 from 4^3 to 8^3; 3.1-3.6 from 8^3 to 16^3 for N = 3): the BR1
     # viscous terms may cost up to one order below N + 1, while a wrong or missing term
-    # would stall the rate near 0.
-    assert np.all(rates[-1] >= N), (errs, rates)
+    # would stall the rate near 0.  Model 2 (HLLC, the alpha/2 rho^2 part inside
+    # the flux divergence rather than a point-wise product of lifted gradients)
+    # converges at 2.8-4.4 for N = 3 from 4^3 to 8^3: held to N - 1/2.
+    need = N if model == 1 else N - 0.5
+    assert np.all(rates[-1] >= need), (errs, rates)
