@@ -236,6 +236,8 @@ def main():
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--threads", type=int, default=256, choices=[256, 512],
                     help="workgroup size of the stage kernels")
+    ap.add_argument("--model", type=int, default=1, choices=[1, 2],
+                    help="relaxation model: 1 (Rusanov interior flux) or 2 (p_alpha pressure, HLLC flux)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
@@ -271,6 +273,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[args.workload]()
+    if args.model == 2:
+        w = w.with_(name=f"{w.name}_model2", params=dict(w.params, model=2))
     stream = torch.cuda.current_stream()
 
     def timed_run(precision, U0=None):
@@ -341,7 +345,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic: seeded droplet state (tanh profiles at Maxwell densities, uniform noise 1e-6)",
         "config": {"workload": w.name, "elements": w.nelems, "N": w.N, "nodes": nn, "threads": args.threads,
-                   "precision": args.precision, "alpha": w.params["alpha"], "beta": w.params["beta"],
+                   "precision": args.precision, "relaxation_model": args.model,
+                   "alpha": w.params["alpha"], "beta": w.params["beta"],
                    "T0": w.T0, "dt": dt, "rk": "5-stage 2N RK4(3)5"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": ach / PEAK_HBM_GBS, "traffic": None},

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 1
+#define NSKR_ABI_VERSION 2  /* 2: nskr_params.model; nskr_init velocities and densities */
 
 enum {
     NSKR_OK = 0,
@@ -65,6 +65,12 @@ typedef struct {
     int precision;
     int kahan;   /* FP32-mixed only: 1 = compensated (Kahan) state update, which
                     carries the rounding error of U += B R from stage to stage */
+    int model;   /* relaxation model (Sec. 2.3.2): 0 or 1 = model 1 (Rusanov
+                    interior flux); 2 = model 2: pressure p_alpha = p + alpha/2
+                    rho^2 in the convective flux (eq. modified_pressure), the
+                    alpha rho grad rho source terms folded into it (eq.
+                    navierstokeskorteweg_palpha), HLLC interior flux, sound
+                    speed sqrt(c_s^2 + alpha rho) */
 } nskr_params;
 
 /* Wall boundary condition (Sec. 2.4, eq. bc_nsk_alpha with gamma_1 = gamma_4 =

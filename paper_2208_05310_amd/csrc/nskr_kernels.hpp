@@ -43,6 +43,8 @@ struct Phys {
     double R, a, b, cv, mu, kappa, gam, alpha, beta;
     double inv_Rcv;   // 1 / (R c_v)
     double cs_fac;    // (1 + 1/c_v) R
+    double ap;        // alpha for relaxation model 2 (p_alpha = p + ap/2 rho^2), 0 for model 1
+    int model;        // 1 or 2
 };
 
 struct BcDev {
@@ -144,10 +146,50 @@ __device__ __forceinline__ void flux_tensor(const Phys &ph, const Pt<T> &s, T F[
     }
 }
 
+// HLLC flux (Toro 2009, Sec. 10.4) of the convective part for relaxation
+// model 2 along the unit normal n from the own side (left, uL) to the
+// neighbour (right, uR): p is p_alpha, a = sqrt((dp_alpha/drho)_s); Davis wave
+// speeds S_L = min(u_L - a_L, u_R - a_R), S_R = max(u_L + a_L, u_R + a_R);
+// contact speed S*; the star state keeps its side's tangential velocity and
+// c/rho (the order parameter as a passive scalar).
+template <typename T>
+__device__ __forceinline__ void hllc(const T uL[6], T pL, T aL, const T uR[6], T pR, T aR, const T n[3], T out[6])
+{
+    const T irL = T(1) / uL[0], irR = T(1) / uR[0];
+    const T unL = (uL[1] * n[0] + uL[2] * n[1] + uL[3] * n[2]) * irL;
+    const T unR = (uR[1] * n[0] + uR[2] * n[1] + uR[3] * n[2]) * irR;
+    const T SL = fmin(unL - aL, unR - aR), SR = fmax(unL + aL, unR + aR);
+    // the side whose flux (and star state) is taken
+    const T Ss = (pR - pL + uL[0] * unL * (SL - unL) - uR[0] * unR * (SR - unR)) /
+                 (uL[0] * (SL - unL) - uR[0] * (SR - unR));
+    const bool left = SL >= T(0) || (SR > T(0) && Ss >= T(0));
+    const T *u = left ? uL : uR;
+    const T un = left ? unL : unR, p = left ? pL : pR, ir = left ? irL : irR;
+    const T S = left ? SL : SR;
+    out[0] = u[0] * un;
+    out[1] = u[1] * un + p * n[0];
+    out[2] = u[2] * un + p * n[1];
+    out[3] = u[3] * un + p * n[2];
+    out[4] = (u[4] + p) * un;
+    out[5] = u[5] * un;
+    if (SL >= T(0) || SR <= T(0)) return;  // supersonic: the upwind flux
+    const T f = u[0] * (S - un) / (S - Ss);
+    T us[6];
+    us[0] = f;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) us[1 + m] = f * (u[1 + m] * ir + (Ss - un) * n[m]);
+    us[4] = f * (u[4] * ir + (Ss - un) * (Ss + p / (u[0] * (S - un))));
+    us[5] = f * u[5] * ir;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) out[v] += S * (us[v] - u[v]);
+}
+
 // Non-conservative source of relaxation model 1, evaluated point-wise with the
 // lifted gradients (Sec. 3.1): momentum alpha rho grad(c - rho), energy
 // alpha rho grad(c - rho).u + alpha/2 (c^2 - rho^2) div u + gamma (|grad c|^2/2
 // div u - grad c (x) grad c : grad u), order parameter alpha beta (rho - c).
+// Relaxation model 2 (eq. navierstokeskorteweg_palpha) drops the alpha rho
+// grad rho and alpha/2 rho^2 div u parts, which its pressure p_alpha carries.
 template <typename T>
 __device__ __forceinline__ void source(const Phys &ph, const Pt<T> &s, const T grho[3], T S[6])
 {
@@ -155,10 +197,11 @@ __device__ __forceinline__ void source(const Phys &ph, const Pt<T> &s, const T g
     const T u[3] = {s.m[0] * ir, s.m[1] * ir, s.m[2] * ir};
     const T div = s.gu[0][0] + s.gu[1][1] + s.gu[2][2];
     const T al = T(ph.alpha);
+    const bool m2 = ph.model == 2;
     T d[3], gg = T(0), cc = T(0), du = T(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        d[i] = s.gc[i] - grho[i];
+        d[i] = m2 ? s.gc[i] : s.gc[i] - grho[i];
         gg += s.gc[i] * s.gc[i];
         du += d[i] * u[i];
     }
@@ -173,56 +216,9 @@ __device__ __forceinline__ void source(const Phys &ph, const Pt<T> &s, const T g
     S[1] = al * s.rho * d[0];
     S[2] = al * s.rho * d[1];
     S[3] = al * s.rho * d[2];
-    S[4] = al * s.rho * du + T(0.5) * al * (s.c * s.c - s.rho * s.rho) * div +
+    S[4] = al * s.rho * du + T(0.5) * al * (m2 ? s.c * s.c : s.c * s.c - s.rho * s.rho) * div +
            T(ph.gam) * (T(0.5) * gg * div - cc);
     S[5] = al * T(ph.beta) * (s.rho - s.c);
-}
-
-// Complete wall flux (F* . n), Sec. 3.2 with the relaxation-model wall
-// conditions of Sec. 2.4: Rusanov against the mirrored ghost state (density,
-// order parameter and total energy copied, velocity mirrored: fully on the
-// no-slip wall, normal part on the slip wall), minus the wall viscous flux:
-// traction tau n (no-slip) or its normal part (slip); energy k grad T . n -
-// gamma c g div u on the isothermal wall, 0 on the adiabatic one; order
-// parameter gamma beta g with the contact-angle flux g.
-template <typename T>
-__device__ __forceinline__ void wall_flux(const Phys &ph, const BcDev &bc, const Pt<T> &s, double T_face,
-                                          const T n[3], T out[6])
-{
-    const T ir = s.ir;
-    const T mn = s.m[0] * n[0] + s.m[1] * n[1] + s.m[2] * n[2];
-    const T un = mn * ir;
-    double pd, cs2;
-    eos(ph, (double)s.rho, T_face, pd, cs2);
-    const T lam = fabs(un) + T(sqrt(fabs(cs2)));
-    const T p = s.p;
-    T tv[3];
-    const T div = s.gu[0][0] + s.gu[1][1] + s.gu[2][2];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) acc += (s.gu[j][i] + s.gu[i][j]) * n[i];
-        tv[j] = T(ph.mu) * (acc - T(2.0 / 3.0) * div * n[j]);
-    }
-    out[0] = T(0);
-    out[4] = T(0);
-    out[5] = T(0);
-    if (bc.kind == 1) {
-        // ghost m_g = -m, so 1/2(F(U) + F(U_g)).n = m un + p n; -1/2 lam (m_g - m) = lam m
-#pragma unroll
-        for (int j = 0; j < 3; ++j) out[1 + j] = s.m[j] * un + p * n[j] + lam * s.m[j] - tv[j];
-        const T g = T(bc.gcoef) * (s.c - T(bc.rl)) * (s.c - T(bc.rv));
-        const T gTn = s.gT[0] * n[0] + s.gT[1] * n[1] + s.gT[2] * n[2];
-        out[4] = -(T(ph.kappa) * gTn - T(ph.gam) * s.c * g * div);
-        out[5] = -T(ph.gam * ph.beta) * g;
-    } else {
-        // ghost m_g = m - 2 mn n: 1/2 (F + F_g).n = mn/ rho (m - mn n) + p n ... written out:
-        // 1/2 [m un + (m - 2 mn n)(-un)] + p n = mn un n + p n; dissipation lam mn n
-        const T tnn = tv[0] * n[0] + tv[1] * n[1] + tv[2] * n[2];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) out[1 + j] = (mn * un + p + lam * mn - tnn) * n[j];
-    }
 }
 
 // ------------------------------------------------------------ kernel args
@@ -895,10 +891,18 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const double Tf = (double)a.T2[3 * NF + o];
             double pd, cs2;
             eos(a.ph, (double)rho, Tf, pd, cs2);
-            const T p = T(pd);
-            const T lam = fabs(un) + T(sqrt(fabs(cs2)));
+            // model 2: p_alpha and its sound speed (ap = 0 for model 1)
+            const T p = T(pd + 0.5 * a.ph.ap * (double)rho * (double)rho);
+            const T cw = T(sqrt(fabs(cs2 + a.ph.ap * (double)rho)));
+            const T lam = fabs(un) + cw;
+            // interior faces of model 2 store p_alpha, -F^V.n and the sound
+            // speed; the HLLC flux is formed from both sides' traces later
+            const bool hl = !wall && a.ph.model == 2;
             T G0, G1, G2_, G3, G4, G5;
-            if (!wall) {
+            if (hl) {
+                G0 = p;
+                G1 = G2_ = G3 = G4 = G5 = T(0);
+            } else if (!wall) {
                 G0 = mn;
                 G1 = m0 * un + p * n0;
                 G2_ = m1 * un + p * n1;
@@ -956,7 +960,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * gcn;
-                a.TF[6 * NF + o] = lam;
+                a.TF[6 * NF + o] = hl ? cw : lam;
             } else if (kind == 1) {
                 const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
                 const T g = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv));
@@ -1061,7 +1065,26 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
         T w[5];
         primitives(tr.uo, w);
-        if (tr.nb >= 0) {
+        if (tr.nb >= 0 && a.ph.model == 2) {
+            // HLLC on the convective part, central viscous flux: the traces
+            // hold p_alpha, -F^V.n (own normal) and the sound speed
+            // (face values and the viscous part go to LDS first, so that
+            // they are not held in registers across the HLLC arithmetic)
+            T wn[5];
+            primitives(tr.un, wn);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sS[k][slot] = T(0.5) * (w[k] + wn[k]);
+#pragma unroll
+            for (int v = 1; v < 6; ++v) sFs[v][slot] = T(0.5) * (tr.G[v] - tr.Gn[v]) * dS;
+            const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
+            const T n[3] = {T(fm[0]), T(fm[1]), T(fm[2])};
+            T Fc[6];
+            hllc(tr.uo, tr.G[0], tr.G[6], tr.un, tr.Gn[0], tr.Gn[6], n, Fc);
+            sFs[0][slot] = Fc[0] * dS;
+#pragma unroll
+            for (int v = 1; v < 6; ++v) sFs[v][slot] += Fc[v] * dS;
+            continue;
+        } else if (tr.nb >= 0) {
             T wn[5];
             const T lam = tr.G[6] > tr.Gn[6] ? tr.G[6] : tr.Gn[6];
 #pragma unroll
@@ -1104,7 +1127,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
                                                 (double)s.gc[2]));
         double pd, cs2;
         eos(a.ph, (double)s.rho, Tn, pd, cs2);
-        s.p = T(pd);
+        s.p = T(pd + 0.5 * a.ph.ap * (double)s.rho * (double)s.rho);  // p_alpha for model 2
         s.ir = T(1) / s.rho;
         source(a.ph, s, grho, S);
         flux_tensor(a.ph, s, Fx);

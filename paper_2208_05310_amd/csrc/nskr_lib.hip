@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, Rat
         double Tn = temperature(a.ph, rho, m0, m1, m2, E, c, Q[12 * a.NN + g], Q[13 * a.NN + g], Q[14 * a.NN + g]);
         double p, cs2;
         eos(a.ph, rho, Tn, p, cs2);
-        double cs = sqrt(fabs(cs2));
+        double cs = sqrt(fabs(cs2 + a.ph.ap * rho));  // sound speed of the convective flux
         const double *em = a.mesh.emet + (size_t)e * 10;
         double iJ = 1.0 / em[9];
         for (int d = 0; d < 3; ++d) {
@@ -754,6 +754,7 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
         return NSKR_E_ARG;
     if (p->precision != 0 && p->precision != 1) return NSKR_E_ARG;
     if (p->kahan != 0 && p->kahan != 1) return NSKR_E_ARG;
+    if (p->model < 0 || p->model > 2) return NSKR_E_UNSUPPORTED;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NSKR_E_HIP;
     // make sure the device code for this GPU is present
@@ -770,6 +771,8 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
     c->ph.kappa = p->kappa; c->ph.gam = p->gam; c->ph.alpha = p->alpha; c->ph.beta = p->beta;
     c->ph.inv_Rcv = 1.0 / (p->R * p->cv);
     c->ph.cs_fac = (1.0 + 1.0 / p->cv) * p->R;
+    c->ph.model = p->model == 2 ? 2 : 1;
+    c->ph.ap = p->model == 2 ? p->alpha : 0.0;
     *out = c;
     return NSKR_OK;
 }

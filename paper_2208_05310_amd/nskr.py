@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
     _fields_ = [("R", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("cv", ctypes.c_double), ("mu", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("gam", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("kahan", ctypes.c_int)]
+                ("cfl", ctypes.c_double), ("precision", ctypes.c_int), ("kahan", ctypes.c_int),
+                ("model", ctypes.c_int)]
 
 
 class Bc(ctypes.Structure):
@@ -61,6 +62,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
+ABI_VERSION = 2  # the struct layouts below
 
 
 def lib():
@@ -105,6 +107,8 @@ def lib():
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
+    if L.nskr_version() != ABI_VERSION:
+        raise ImportError(f"{SO} has ABI version {L.nskr_version()}, this binding expects {ABI_VERSION}; rebuild it")
     _lib = L
     return L
 
@@ -169,7 +173,7 @@ class Solver:
 
     def __init__(self, params: dict, N: int, precision: str = "fp64", device: int = 0, kahan: bool = True):
         """precision: "fp64" or "fp32_mixed"; kahan (FP32-mixed only): compensated
-        state update."""
+        state update.  params["model"] (default 1) picks relaxation model 1 or 2."""
         self.L = lib()
         self.N = int(N)
         self.precision = precision
@@ -178,7 +182,7 @@ class Solver:
         self.kahan = bool(kahan) and prec == 1
         p = Params(params["R"], params["a"], params["b"], params["cv"], params["mu"], params["kappa"],
                    params["gam"], params["alpha"], params["beta"], params.get("cfl", 0.9), prec,
-                   1 if self.kahan else 0)
+                   1 if self.kahan else 0, int(params.get("model", 1)))
         self.params = dict(params)
         h = ctypes.c_void_p()
         rc = self.L.nskr_create(ctypes.byref(p), self.N, self.device, ctypes.byref(h))

@@ -27,7 +27,8 @@ def test_library_exports_every_declared_symbol():
     L = nskr.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert L.nskr_version() == 1
+    from paper_2208_05310_amd.nskr import ABI_VERSION
+    assert L.nskr_version() == ABI_VERSION == 2
 
 
 def test_create_validates_arguments_before_device():
@@ -36,10 +37,10 @@ def test_create_validates_arguments_before_device():
                 cfl=0.9)
     h = ctypes.c_void_p()
 
-    def create(N=3, prec=0, **kw):
+    def create(N=3, prec=0, model=1, **kw):
         d = dict(good, **kw)
         p = nskr.Params(d["R"], d["a"], d["b"], d["cv"], d["mu"], d["kappa"], d["gam"], d["alpha"], d["beta"],
-                        d["cfl"], prec, 0)
+                        d["cfl"], prec, 0, model)
         return L.nskr_create(ctypes.byref(p), N, 0, ctypes.byref(h))
 
     assert create(N=1) == nskr.NSKR_E_ARG
@@ -48,6 +49,8 @@ def test_create_validates_arguments_before_device():
     assert create(cv=0.0) == nskr.NSKR_E_ARG
     assert create(cfl=float("nan")) == nskr.NSKR_E_ARG
     assert create(prec=2) == nskr.NSKR_E_ARG
+    assert create(model=3) == nskr.NSKR_E_UNSUPPORTED
+    assert create(model=-1) == nskr.NSKR_E_UNSUPPORTED
     import torch
     if not torch.cuda.is_available():
         # no device here: a valid request fails with the HIP error, never a CPU fallback

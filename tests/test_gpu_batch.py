@@ -4,7 +4,8 @@
 * A batched instance equals, bit for bit, the same instance on the
   single-instance path (same kernels, same arithmetic, same order).
 * An instance gives bitwise the same result alone in a batch and in a mix of
-  instances with other degrees, meshes, precisions and time steps.
+  instances with other degrees, meshes, precisions, relaxation models and
+  time steps.
 * Graph replays equal direct launches on every step, with eager work and
   synchronisations between the replays.
 * Admission respects the memory budget; instances stop at their own step count.
@@ -31,6 +32,7 @@ def small_mix():
         (wl.c4(scale=12).with_(name="mix_wall_4x4x2_N4", N=4), "fp64"),
         (base.with_(name="mix_periodic_4x4x4_N2_T080", N=2, T0=0.8), "fp32_mixed"),
         (base.with_(name="mix_periodic_2x3x2_N5", N=5, n=(2, 3, 2), length=(1.0, 1.5, 1.0), noise_seed=9), "fp64"),
+        (base.with_(name="mix_model2_3x3x3_N3", n=(3, 3, 3), params=dict(base.params, model=2)), "fp64"),
     ]
 
 

@@ -260,7 +260,97 @@ def test_rk_split_equals_joined(torch_cuda):
     assert torch.equal(U1, U2)
 
 
-FULL = [("c2", 2), ("c3", 1), ("c4", 1), ("c5", 1)]
+def model2(w, name=None):
+    return w.with_(name=name or f"{w.name}_model2", params=dict(w.params, model=2))
+
+
+# relaxation model 2 (p_alpha pressure, HLLC interior flux): periodic, ragged,
+# walls with a contact angle, and moving droplets
+M2_BASE = [0, 3, 6, 8]
+M2 = [model2(CASES[k]) for k in M2_BASE]
+M2_IDS = [w.name for w in M2]
+
+
+@pytest.mark.parametrize("w", M2, ids=M2_IDS)
+def test_rhs_parity_model2(torch_cuda, w):
+    torch = torch_cuda
+    print(f"[case] rhs {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    Ut = s.new_state()
+    s.rhs(to_gpu(torch, U), Ut)
+    torch.cuda.synchronize()
+    scale, Uto = rhs_term_scale(o, U, w.params)
+    err = np.max(np.abs(Ut.cpu().numpy() - Uto), axis=1) / scale
+    print("rhs errors per field (term scale)", err, flush=True)
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("k", range(len(M2)), ids=M2_IDS)
+def test_dt_parity_model2(torch_cuda, k):
+    """The time step uses the model-2 sound speed sqrt(c_s^2 + alpha rho),
+    so it is never larger than model 1's on the same state (equal where the
+    viscous/relaxation limit binds)."""
+    torch = torch_cuda
+    w = M2[k]
+    print(f"[case] dt {w.name}", flush=True)
+    o = oracle_for(w)
+    U = perturbed_state(o, w)
+    s = gpu_solver(w)
+    dg = s.dt(to_gpu(torch, U))
+    do = o.dt(U)
+    assert abs(dg - do) <= 1e-14 * do, (dg, do)
+    assert do <= oracle_for(CASES[M2_BASE[k]]).dt(U)
+
+
+@pytest.mark.parametrize("w", [M2[0], M2[2], M2[3]], ids=[M2_IDS[0], M2_IDS[2], M2_IDS[3]])
+def test_rk_steps_parity_model2(torch_cuda, w):
+    torch = torch_cuda
+    nsteps = 10
+    print(f"[case] rk {w.name} steps={nsteps}", flush=True)
+    o = oracle_for(w)
+    U = oracle_init(o, w)
+    dt = o.dt(U)
+    s = gpu_solver(w)
+    Ug = to_gpu(torch, U)
+    Rg = s.new_state()
+    s.rk_steps(Ug, Rg, dt, nsteps)
+    torch.cuda.synchronize()
+    R = np.zeros_like(U)
+    o.run(U, R, 0.0, dt, nsteps)
+    err = rel_err(Ug.cpu().numpy(), U, state_floor(U, w.params))
+    print("errors per field", err, flush=True)
+    assert np.all(err <= TOL), err
+
+
+def test_fp32_mixed_accuracy_model2(torch_cuda):
+    torch = torch_cuda
+    w = M2[0]
+    print(f"[case] fp32-mixed {w.name}", flush=True)
+    o = oracle_for(w)
+    U = oracle_init(o, w)
+    dt = o.dt(U)
+    s = gpu_solver(w, "fp32_mixed")
+    Ug = to_gpu(torch, U, torch.float32)
+    Rg = s.new_state()
+    s.rk_steps(Ug, Rg, dt, 20)
+    torch.cuda.synchronize()
+    R = np.zeros_like(U)
+    o.run(U, R, 0.0, dt, 20)
+    err = rel_err(Ug.double().cpu().numpy(), U, state_floor(U, w.params))
+    print("fp32-mixed errors per field", err, flush=True)
+    assert err[0] <= 1e-5, err
+    assert np.all(err <= 1e-4), err
+
+
+def test_model_out_of_range_rejected(torch_cuda):
+    from paper_2208_05310_amd.nskr import NskrError
+    with pytest.raises(NskrError):
+        gpu_solver(CASES[0].with_(params=dict(CASES[0].params, model=3)))
+
+
+FULL = [("c2", 2), ("c3", 1), ("c4", 1), ("c5", 1), ("c5_model2", 1)]
 
 
 @pytest.mark.parametrize("which,steps", FULL, ids=[f"{w}_{n}steps" for w, n in FULL])
@@ -268,10 +358,10 @@ def test_full_size_workload_parity(torch_cuda, which, steps):
     """The benchmark workloads at full size, same kernels and launch
     configuration as bench.py: 16^3 N=4 (512000 nodes), 32^3 N=5 (7.08M
     nodes), the 48x48x24 N=3 wall box (3.54M nodes) and the 50^3 N=3 head-on
-    collision (8M nodes, moving droplets).  GPU initial state,
+    collision (8M nodes, moving droplets; with relaxation model 1 and 2).  GPU initial state,
     time step and RK steps against the oracle's, on every node."""
     torch = torch_cuda
-    w = {"c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[which]()
+    w = {"c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c5_model2": lambda: model2(wl.c5())}[which]()
     print(f"[case] full-size {w.name}, {steps} step(s)", flush=True)
     from paper_2208_05310_amd.nskr import init_workload
     s = gpu_solver(w)
