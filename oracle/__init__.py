@@ -47,7 +47,10 @@ class Box(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
                 ("len", ctypes.c_double * 3), ("periodic", ctypes.c_int * 3),
                 ("side_kind", ctypes.c_int * 6), ("side_twall", ctypes.c_double * 6),
-                ("side_theta", ctypes.c_double * 6), ("curve_amp", ctypes.c_double)]
+                ("side_theta", ctypes.c_double * 6), ("curve_amp", ctypes.c_double),
+                ("side_uwall", (ctypes.c_double * 3) * 6), ("side_g1", ctypes.c_double * 6),
+                ("side_g2", ctypes.c_double * 6), ("side_g4", ctypes.c_double * 6),
+                ("side_g3", ctypes.c_double * 6)]
 
 
 _lib = None
@@ -117,11 +120,18 @@ def make_params(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.01, kappa=1.0 / 15
 
 def make_box(N, n, lo=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
              side_kind=(0,) * 6, side_twall=(0.0,) * 6, side_theta=(90.0,) * 6,
-             curve_amp=0.0) -> Box:
+             curve_amp=0.0, side_uwall=((0.0, 0.0, 0.0),) * 6, side_g1=(0.0,) * 6,
+             side_g2=(0.0,) * 6, side_g3=(float("inf"),) * 6, side_g4=(0.0,) * 6) -> Box:
+    """Wall kinds per side (x-, x+, y-, y+, z-, z+): 1 no-slip isothermal with a
+    static contact angle, moving with side_uwall; 2 slip adiabatic neutral;
+    3 generalized Navier slip with gamma_1..gamma_4 (side_g3 infinite =
+    isothermal)."""
+    uw = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_uwall])
+    d6 = lambda v: (ctypes.c_double * 6)(*[float(x) for x in v])
     return Box(int(N), (ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo),
                (ctypes.c_double * 3)(*length), (ctypes.c_int * 3)(*periodic),
-               (ctypes.c_int * 6)(*side_kind), (ctypes.c_double * 6)(*side_twall),
-               (ctypes.c_double * 6)(*side_theta), float(curve_amp))
+               (ctypes.c_int * 6)(*side_kind), d6(side_twall), d6(side_theta), float(curve_amp),
+               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3))
 
 
 class Oracle:

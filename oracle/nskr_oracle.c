@@ -43,8 +43,11 @@
  *   - Lifted variables are the primitives rho, u, v, w, c, then theta.
  *   - Face primitives come from the prolonged conserved state.
  *   - Rusanov wave speed uses sqrt(|c_s^2|) where c_s^2 < 0.
- *   - Walls: no-slip isothermal wall with static contact angle, or slip
- *     adiabatic neutral wall (gamma_1 = gamma_4 = 0, so zeta_c = 0 on the wall).
+ *   - Walls: no-slip isothermal wall with static contact angle (possibly
+ *     moving tangentially), slip adiabatic neutral wall (gamma_1 = gamma_4 = 0,
+ *     so zeta_c = 0 on the wall), or the generalized Navier-slip wall of
+ *     eq. bc_nsk_alpha with gamma_1, gamma_2, gamma_4 and either a fixed
+ *     temperature or the heat-transfer condition with gamma_3.
  *   - Time integration: Carpenter-Kennedy 5-stage 2N-storage RK4(3)5.
  *   - Time step: advective limit with 1D Rusanov stability constants, and a
  *     parabolic/source limit with 1D BR1 spectral radii.
@@ -76,10 +79,14 @@ typedef struct {
     double lo[3], len[3];     /* box origin and extent                        */
     int periodic[3];          /* 1 = periodic along that axis                 */
     int side_kind[6];         /* x-,x+,y-,y+,z-,z+ : 1 no-slip isothermal with
-                                 contact angle, 2 slip adiabatic neutral      */
-    double side_twall[6];     /* wall temperature (kind 1)                    */
-    double side_theta[6];     /* static contact angle in degrees (kind 1)     */
+                                 contact angle, 2 slip adiabatic neutral,
+                                 3 generalized Navier slip (eq. bc_nsk_alpha) */
+    double side_twall[6];     /* wall temperature (kinds 1, 3)                */
+    double side_theta[6];     /* static contact angle in degrees (kinds 1, 3) */
     double curve_amp;         /* amplitude of the smooth sine perturbation    */
+    double side_uwall[6][3];  /* wall velocity (kinds 1, 3; tangential)       */
+    double side_g1[6], side_g2[6], side_g4[6]; /* gamma_1, gamma_2, gamma_4 (kind 3) */
+    double side_g3[6];        /* gamma_3 (kind 3); infinite = isothermal wall */
 } orc_box;
 
 typedef struct {
@@ -796,8 +803,13 @@ void *orc_create(const orc_params *pr, const orc_box *bx, char *err, int errlen)
                     c->side[e * 6 + f] = -1;
                 } else {
                     int k = bx->side_kind[f];
-                    if (k != 1 && k != 2) {
-                        snprintf(err, errlen, "non-periodic side %d needs a wall kind", f);
+                    int bad = (k != 1 && k != 2 && k != 3);
+                    if (k == 3)
+                        bad = !(bx->side_g1[f] >= 0 && bx->side_g2[f] >= 0 && bx->side_g3[f] >= 0 &&
+                                bx->side_g4[f] >= 0);
+                    if (bad) {
+                        snprintf(err, errlen, "non-periodic side %d needs a wall kind (1, 2, 3 with "
+                                 "non-negative coefficients)", f);
                         free(c->nbr); free(c->kind); free(c->side); free(c->Ja); free(c->J);
                         free(c->nv); free(c->xyz); free(c);
                         return NULL;
@@ -812,7 +824,7 @@ void *orc_create(const orc_params *pr, const orc_box *bx, char *err, int errlen)
     /* wall constants: Maxwell states and sigma at the wall temperature */
     for (int f = 0; f < 6; ++f) {
         c->wrv[f] = c->wrl[f] = c->wsig[f] = 0.0; c->wcos[f] = 0.0;
-        if (bx->periodic[f / 2] || bx->side_kind[f] != 1) continue;
+        if (bx->periodic[f / 2] || (bx->side_kind[f] != 1 && bx->side_kind[f] != 3)) continue;
         double rv, rl;
         if (!orc_maxwell(pr->R, pr->a, pr->b, bx->side_twall[f], &rv, &rl, NULL)) {
             snprintf(err, errlen, "wall temperature %d is not subcritical", f);
@@ -1029,8 +1041,9 @@ static void unit_normal(const orc_ctx *c, int e, int f, int fp, double n[3], dou
 }
 
 /* Step 2: BR1 pass 1 for w in (rho, u1, u2, u3, c).  Interior faces use the
- * central value w* = (w- + w+)/2.  Walls: rho* = rho-, c* = c-, and u* = 0 on
- * the no-slip wall or the tangential part of u- on the slip wall. */
+ * central value w* = (w- + w+)/2.  Walls: rho* = rho-, c* = c-, and u* = the
+ * wall velocity on the no-slip wall or the tangential part of u- on the slip
+ * and Navier-slip walls. */
 static void step_lift1(const orc_ctx *c, const double *U, work_t *w)
 {
     int n2 = c->n2, n3 = c->n3;
@@ -1058,7 +1071,7 @@ static void step_lift1(const orc_ctx *c, const double *U, work_t *w)
                     } else if (k == 0 || k == 4) {
                         val = prim(Um, k);
                     } else if (c->kind[e * 6 + f] == 1) {
-                        val = 0.0; /* no-slip, non-moving wall */
+                        val = c->box.side_uwall[c->side[e * 6 + f]][k - 1]; /* no-slip */
                     } else {
                         double n[3], dS, un;
                         unit_normal(c, e, f, fp, n, &dS);
@@ -1072,16 +1085,28 @@ static void step_lift1(const orc_ctx *c, const double *U, work_t *w)
     }
 }
 
-/* Contact-angle flux g = grad c . n on a kind-1 wall, from the constitutive
- * relation eq. bc_contactangle_alpha with gamma_1 = 0. */
-static double wall_g(const orc_ctx *c, int f_side, double cm)
+/* Contact-angle flux g = grad c . n on a wall of kind 1 or 3, from the
+ * constitutive relation eq. bc_contactangle_alpha: g = (gamma_1 div u -
+ * dpsi/dc) / gamma, with gamma_1 = 0 on the no-slip wall; div u is the trace
+ * of the lifted velocity gradient at the wall. */
+static double wall_g(const orc_ctx *c, int kind, int f_side, double cm, double div)
 {
-    return -orc_dpsiwall_dc(cm, c->wrv[f_side], c->wrl[f_side], c->wsig[f_side], c->wcos[f_side]) / c->pr.gam;
+    double g = -orc_dpsiwall_dc(cm, c->wrv[f_side], c->wrl[f_side], c->wsig[f_side], c->wcos[f_side]) / c->pr.gam;
+    if (kind == 3) g += c->box.side_g1[f_side] * div / c->pr.gam;
+    return g;
+}
+
+/* Isothermal wall: theta* = T_wall in the lifting and the conductive flux
+ * from the lifted gradient (kind 1, and kind 3 with gamma_3 infinite). */
+static int wall_isothermal(const orc_ctx *c, int kind, int f_side)
+{
+    return kind == 1 || (kind == 3 && isinf(c->box.side_g3[f_side]));
 }
 
 /* Step 3: temperature at nodes and faces, then BR1 pass 2 for theta and the
  * divergence lifting of grad c.  Walls: theta* = T_wall (isothermal) or
- * theta- (adiabatic); (grad c . n)* = g (contact angle) or 0 (slip). */
+ * theta- (adiabatic and heat-transfer walls); (grad c . n)* = g (contact
+ * angle, kinds 1 and 3) or 0 (slip). */
 static void step_lift2(const orc_ctx *c, const double *U, work_t *w)
 {
     int n2 = c->n2, n3 = c->n3;
@@ -1128,13 +1153,23 @@ static void step_lift2(const orc_ctx *c, const double *U, work_t *w)
                 } else {
                     int sd = c->side[e * 6 + f];
                     double dS = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-                    if (c->kind[e * 6 + f] == 1) {
-                        Ts[f * n2 + fp] = c->box.side_twall[sd];
-                        double cm = w->Uf[(((size_t)e * 6 + f) * 6 + 5) * n2 + fp];
-                        fs[f * n2 + fp] = wall_g(c, sd, cm) * dS;
-                    } else {
-                        Ts[f * n2 + fp] = Tm;
+                    int kd = c->kind[e * 6 + f];
+                    Ts[f * n2 + fp] = wall_isothermal(c, kd, sd) ? c->box.side_twall[sd] : Tm;
+                    if (kd == 2) {
                         fs[f * n2 + fp] = 0.0;
+                    } else {
+                        double cm = w->Uf[(((size_t)e * 6 + f) * 6 + 5) * n2 + fp];
+                        double div = 0.0;
+                        if (kd == 3) {
+                            /* trace of the lifted div u: d u/dx + d v/dy + d w/dz */
+                            const double *qe = w->q + (size_t)e * 15 * n3;
+                            double tr[MAXP * MAXP];
+                            for (int m = 0; m < 3; ++m) {
+                                prolong(c, qe + (3 + 4 * m) * n3, f, tr);
+                                div += tr[fp];
+                            }
+                        }
+                        fs[f * n2 + fp] = wall_g(c, kd, sd, cm, div) * dS;
                     }
                 }
             }
@@ -1235,20 +1270,47 @@ void orc_numflux(const orc_params *pr, const double *UL, double TL, const double
         rusanov(pr, &sm, &sp, n, out);
 }
 
-/* Wall flux (F* . n) of Sec. 3.2 for the readings of eq. bc_nsk_alpha:
- * Rusanov against the mirrored ghost state (rho, c, rho e copied; velocity
- * mirrored entirely on the no-slip wall, normal part only on the slip wall)
- * minus the wall viscous flux: traction T^V n (no-slip) or its normal part
- * (slip); energy k grad T . n - gamma c g div u on the isothermal wall and 0
- * on the adiabatic one; order parameter gamma beta g. */
+/* Wall flux (F* . n) of Sec. 3.2 for the readings of eq. bc_nsk_alpha.
+ * Convective part: Rusanov against a ghost state with the same density,
+ * order parameter and temperature, and the velocity reflected about the
+ * wall velocity (2 u_w - u, no-slip wall) or stripped of twice its normal
+ * part (slip and Navier-slip walls).  Viscous part F^V . n:
+ *   no-slip (kind 1): traction T^V n; energy (T^V n) . u_w + k grad T . n
+ *     - gamma c g div u; order parameter gamma beta g.
+ *   slip (kind 2): the normal traction only; no energy or c flux.
+ *   Navier slip (kind 3): normal traction plus the tangential traction of
+ *     eq. bc_navierstokes_alpha, t = gamma_1 div u grad_G c - gamma_2 (u_t -
+ *     u_w); energy t . u_t + q - gamma c g div u + gamma g zeta_c with the
+ *     wall value zeta_c = -gamma_1 gamma_4 div u of eq. bc_relaxation_alpha
+ *     and q = k grad T . n (gamma_3 infinite: isothermal) or -gamma_3 (1/T_w
+ *     - 1/T-) (eq. bc_energy_alpha); order parameter gamma beta g.
+ * g is the contact-angle flux of wall_g; grad_G c and u_t are the tangential
+ * parts of the lifted grad c and of u- at the face. */
 static void wall_flux(const orc_ctx *c, int e, int f, const point_state *sm, const double n[3], double out[6])
 {
     const orc_params *pr = &c->pr;
+    const orc_box *bx = &c->box;
     int kd = c->kind[e * 6 + f], sd = c->side[e * 6 + f];
+    const double *uw = bx->side_uwall[sd];
+    double rho = sm->U[0], u[3], un = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        u[m] = sm->U[1 + m] / rho;
+        un += u[m] * n[m];
+    }
     point_state sg = *sm;
-    double mn = sm->U[1] * n[0] + sm->U[2] * n[1] + sm->U[3] * n[2];
-    for (int m = 0; m < 3; ++m)
-        sg.U[1 + m] = (kd == 1) ? -sm->U[1 + m] : sm->U[1 + m] - 2.0 * mn * n[m];
+    if (kd == 1) {
+        double ke = 0.0, keg = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            double ug = 2.0 * uw[m] - u[m];
+            sg.U[1 + m] = 2.0 * rho * uw[m] - sm->U[1 + m];
+            ke += u[m] * u[m];
+            keg += ug * ug;
+        }
+        if (uw[0] != 0.0 || uw[1] != 0.0 || uw[2] != 0.0) sg.U[4] = sm->U[4] + 0.5 * rho * (keg - ke);
+    } else {
+        double mn = sm->U[1] * n[0] + sm->U[2] * n[1] + sm->U[3] * n[2];
+        for (int m = 0; m < 3; ++m) sg.U[1 + m] = sm->U[1 + m] - 2.0 * mn * n[m];
+    }
     double fc[6];
     rusanov(pr, sm, &sg, n, fc);
 
@@ -1257,15 +1319,33 @@ static void wall_flux(const orc_ctx *c, int e, int f, const point_state *sm, con
     double fv[6] = {0, 0, 0, 0, 0, 0};
     double tn[3];
     for (int i = 0; i < 3; ++i) tn[i] = Tv[i][0] * n[0] + Tv[i][1] * n[1] + Tv[i][2] * n[2];
+    double div = sm->gu[0][0] + sm->gu[1][1] + sm->gu[2][2];
+    double gTn = sm->gT[0] * n[0] + sm->gT[1] * n[1] + sm->gT[2] * n[2];
     if (kd == 1) {
-        double g = wall_g(c, sd, sm->U[5]);
-        double div = sm->gu[0][0] + sm->gu[1][1] + sm->gu[2][2];
+        double g = wall_g(c, kd, sd, sm->U[5], div);
         for (int m = 0; m < 3; ++m) fv[1 + m] = tn[m];
-        fv[4] = pr->kappa * (sm->gT[0] * n[0] + sm->gT[1] * n[1] + sm->gT[2] * n[2]) - pr->gam * sm->U[5] * g * div;
+        fv[4] = (tn[0] * uw[0] + tn[1] * uw[1] + tn[2] * uw[2]) + pr->kappa * gTn - pr->gam * sm->U[5] * g * div;
         fv[5] = pr->gam * pr->beta * g;
-    } else {
+    } else if (kd == 2) {
         double nn = tn[0] * n[0] + tn[1] * n[1] + tn[2] * n[2];
         for (int m = 0; m < 3; ++m) fv[1 + m] = nn * n[m];
+    } else {
+        double g1 = bx->side_g1[sd], g2 = bx->side_g2[sd], g3 = bx->side_g3[sd], g4 = bx->side_g4[sd];
+        double g = wall_g(c, kd, sd, sm->U[5], div);
+        double nn = tn[0] * n[0] + tn[1] * n[1] + tn[2] * n[2];
+        double gcn = sm->gc[0] * n[0] + sm->gc[1] * n[1] + sm->gc[2] * n[2];
+        double uwn = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
+        double work = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            double ut = u[m] - un * n[m];
+            double t = g1 * div * (sm->gc[m] - gcn * n[m]) - g2 * (ut - (uw[m] - uwn * n[m]));
+            fv[1 + m] = nn * n[m] + t;
+            work += t * ut;
+        }
+        double q = wall_isothermal(c, kd, sd) ? pr->kappa * gTn : -g3 * (1.0 / bx->side_twall[sd] - 1.0 / sm->T);
+        double zeta = -g1 * g4 * div;
+        fv[4] = work + q - pr->gam * sm->U[5] * g * div + pr->gam * g * zeta;
+        fv[5] = pr->gam * pr->beta * g;
     }
     for (int v = 0; v < 6; ++v) out[v] = fc[v] - fv[v];
 }
