@@ -75,6 +75,17 @@ def survey_bytes_model(N, word):
     return 24 * word, (24 + 12 + 2 * F * 35 + 38) * word
 
 
+def oracle_box(w):
+    """The oracle's box for a workload description (walls included)."""
+    import oracle
+    from paper_2208_05310_amd import workloads as wl
+    g = w.side_gamma or (wl.NO_GAMMA,) * 6
+    return oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
+                           w.side_theta, w.curve_amp, side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
+                           side_g1=[v[0] for v in g], side_g2=[v[1] for v in g], side_g3=[v[2] for v in g],
+                           side_g4=[v[3] for v in g])
+
+
 def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
     """The FP64 C oracle on the host's cores (OpenMP over elements): full RK
     steps on the whole workload mesh for about budget_s seconds, then the same
@@ -83,9 +94,7 @@ def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
 
     import oracle
     p = oracle.make_params(**w.params)
-    b = oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
-                        w.side_theta)
-    o = oracle.Oracle(p, b)
+    o = oracle.Oracle(p, oracle_box(w))
     U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l)
     dt = o.dt(U0)
 
@@ -170,7 +179,7 @@ def precision_study(which="c3", steps=None, restriction=True):
             out[f"{name}_rel_max"] = float(d.abs().max() / b[k].abs().max())
         return out
 
-    w = {"c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[which]()
+    w = {"c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c6": wl.c6}[which]()
     steps = steps or w.steps
     res = {"steps": steps}
     s = solver_for(w, "fp64")
@@ -192,7 +201,8 @@ def precision_study(which="c3", steps=None, restriction=True):
     if not restriction:
         return res
     # restriction: same set-up on a small mesh, GPU forms vs the oracle
-    wr = {"c3": lambda: wl.c3(4), "c4": lambda: wl.c4(scale=8), "c5": lambda: wl.c5(scale=10)}[which]()
+    wr = {"c3": lambda: wl.c3(4), "c4": lambda: wl.c4(scale=8), "c5": lambda: wl.c5(scale=10),
+          "c6": lambda: wl.c6(scale=10)}[which]()
     sr = solver_for(wr, "fp64")
     Ur = init_workload(sr, wr)
     dtr = sr.dt(Ur)
@@ -201,9 +211,7 @@ def precision_study(which="c3", steps=None, restriction=True):
     G32, _, _ = run(wr, "fp32_mixed", Ur, dtr)
     import oracle
     p = oracle.make_params(**wr.params)
-    b = oracle.make_box(wr.N, wr.n, (0.0, 0.0, 0.0), wr.length, wr.periodic, wr.side_kind, wr.side_twall,
-                        wr.side_theta)
-    o = oracle.Oracle(p, b)
+    o = oracle.Oracle(p, oracle_box(wr))
     Uo = Ur.double().cpu().numpy().copy()
     Ro = np.zeros_like(Uo)
     t0 = time.perf_counter()
@@ -220,18 +228,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6"],
                     help="c1 4^3 N=3 droplet; c2 16^3 N=4 two droplets (default); c3 32^3 N=5 eight "
-                         "droplets; c4 48x48x24 N=3 sessile wall box; c5 50^3 N=3 head-on collision")
+                         "droplets; c4 48x48x24 N=3 sessile wall box; c5 50^3 N=3 head-on collision; "
+                         "c6 100x50x25 N=3 droplet sliding on a Navier-slip floor under a moving lid")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serving", action="store_true", help="run only the request-stream serving measurement")
-    ap.add_argument("--precision-study", choices=["c3", "c4", "c5"], default=None,
+    ap.add_argument("--precision-study", choices=["c3", "c4", "c5", "c6"], default=None,
                     help="FP32-mixed vs FP64 errors over the workload's full step count (c3: 32^3 N=5, "
-                         "500 steps; c4: sessile wall case, 1000 steps; c5: head-on collision, 200 steps)")
+                         "500 steps; c4: sessile wall case, 1000 steps; c5: head-on collision, 200 steps; "
+                         "c6: sliding droplet, 200 steps)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--threads", type=int, default=256, choices=[256, 512],
@@ -272,7 +282,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5}[args.workload]()
+    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c6": wl.c6}[args.workload]()
     if args.model == 2:
         w = w.with_(name=f"{w.name}_model2", params=dict(w.params, model=2))
     stream = torch.cuda.current_stream()

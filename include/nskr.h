@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 2  /* 2: nskr_params.model; nskr_init velocities and densities */
+#define NSKR_ABI_VERSION 3  /* 3: nskr_bc wall velocity and gamma1..gamma4; 2: nskr_params.model */
 
 enum {
     NSKR_OK = 0,
@@ -73,15 +73,31 @@ typedef struct {
                     speed sqrt(c_s^2 + alpha rho) */
 } nskr_params;
 
-/* Wall boundary condition (Sec. 2.4, eq. bc_nsk_alpha with gamma_1 = gamma_4 =
- * 0).  kind 1: impermeable no-slip isothermal wall at twall with a static
- * contact angle theta_deg (cubic wall energy, eq. helmfreesurftot_derivative,
- * Maxwell states and sigma_vl evaluated at twall).  kind 2: slip adiabatic wall
- * with neutral wetting (zero contact-angle flux, zero tangential traction). */
+/* Wall boundary condition (Sec. 2.4, eq. bc_nsk_alpha; weak enforcement
+ * through the face flux, Sec. 3.2).  All walls are impermeable.
+ *   kind 1: no-slip isothermal wall at twall with a static contact angle
+ *     theta_deg (cubic wall energy, eq. helmfreesurftot_derivative, Maxwell
+ *     states and sigma_vl evaluated at twall), moving with the tangential
+ *     velocity uwall (a lid; zero for a fixed wall).
+ *   kind 2: slip adiabatic wall with neutral wetting (zero contact-angle flux,
+ *     zero tangential traction).
+ *   kind 3: generalized Navier-slip wall: tangential traction gamma1 div u
+ *     grad_Gamma c - gamma2 (u_t - uwall) (eq. bc_navierstokes_alpha),
+ *     contact-angle flux grad c . n = (gamma1 div u - dpsi/dc) / gamma at
+ *     twall and theta_deg (eq. bc_contactangle_alpha), wall value zeta_c =
+ *     -gamma1 gamma4 div u of the relaxation condition (eq.
+ *     bc_relaxation_alpha), and heat flux k grad T . n = -gamma3 (1/twall -
+ *     1/T) (eq. bc_energy_alpha); gamma3 = +infinity makes it isothermal at
+ *     twall.
+ * gamma1..gamma4 >= 0 and are read for kind 3 only; uwall must be tangential
+ * to every face of the wall (NSKR_E_ARG otherwise) and is read for kinds 1
+ * and 3. */
 typedef struct {
     int kind;
     double twall;
     double theta_deg;
+    double uwall[3];
+    double gamma1, gamma2, gamma3, gamma4;
 } nskr_bc;
 
 /* Hexahedral mesh (Sec. 3.1).  Every element must be a parallelepiped (affine

@@ -48,10 +48,16 @@ struct Phys {
 };
 
 struct BcDev {
-    int kind;         // 1 no-slip isothermal with contact angle, 2 slip adiabatic
+    int kind;         // 1 no-slip isothermal with contact angle (moving with uw),
+                      // 2 slip adiabatic neutral, 3 generalized Navier slip
+    int iso;          // 1: T* = twall in the lifting and k grad T . n (kind 1; kind 3 with gamma3 infinite)
     double twall;
     double rv, rl;    // Maxwell densities at twall
-    double gcoef;     // contact-angle flux g(c) = gcoef (c - rl)(c - rv)
+    double gcoef;     // static contact-angle flux g(c) = gcoef (c - rl)(c - rv)
+    double uw[3];     // tangential wall velocity (kinds 1, 3)
+    double g1, g2, g3, g4;  // gamma_1..gamma_4 (kind 3; zero otherwise)
+    double g1_gam;    // gamma_1 / gamma: the dynamic part of g, times div u
+    double inv_tw;    // 1 / twall
 };
 
 // 1D operators for one polynomial degree (host computed, FP64).
@@ -71,6 +77,7 @@ struct MeshDev {
     const double *fmet;  // [E][6][4] outward unit normal, surface element
     const double *egeo;  // [E][12] corner 0 and the three edge vectors
     const BcDev *bcs;
+    int dyn;             // some Navier-slip wall has gamma_1 != 0 (g needs div u at the wall)
 };
 
 template <int P, int BS = kBlock> struct Tile {
@@ -373,12 +380,15 @@ template <typename T> __device__ __forceinline__ void primitives(const T u6[6], 
 }
 
 // BR1 face values of the primitives on a wall face: the interior values with
-// the velocity set to zero (no-slip) or stripped of its normal part (slip).
+// the velocity set to the wall's (no-slip) or stripped of its normal part
+// (slip and Navier-slip walls).
 template <typename T> __device__ __forceinline__ void wall_primitives(const MeshDev &m, int el, int f, T w[5])
 {
-    const BcDev bc = m.bcs[m.bcid[el * 6 + f] - 1];
+    const BcDev &bc = m.bcs[m.bcid[el * 6 + f] - 1];
     if (bc.kind == 1) {
-        w[1] = w[2] = w[3] = T(0);
+        w[1] = T(bc.uw[0]);
+        w[2] = T(bc.uw[1]);
+        w[3] = T(bc.uw[2]);
     } else {
         const double *fm = m.fmet + ((size_t)el * 6 + f) * 4;
         const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
@@ -750,13 +760,14 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             Fs = acc;
         } else {
             wall_primitives(a.mesh, el, f, w);
-            const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-            if (bc.kind == 1) {
-                Ts = T(bc.twall);
+            const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+            Ts = bc.iso ? T(bc.twall) : tr.own[3];
+            if (bc.kind != 2) {
+                // static part of the contact-angle flux; the dynamic part
+                // (gamma_1 div u) is added once grad u is lifted
                 const T c = uf[5];
                 Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
             } else {
-                Ts = tr.own[3];
                 Fs = T(0);
             }
         }
@@ -791,6 +802,30 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         for (int r = 0; r < 9; ++r) sGu[r][t] = gu[r];
     }
     __syncthreads();
+    if (a.mesh.dyn) {
+        // Navier-slip walls with gamma_1 != 0: the contact-angle flux gains
+        // (gamma_1/gamma) div u, div u the trace of the lifted velocity gradient
+        for (int task = t; task < G::NF; task += BS) {
+            const FaceTask<P> ft(task);
+            const int el = e0 + ft.le, f = ft.f;
+            if (el >= E) continue;
+            if (a.mesh.nbr[el * 6 + f] >= 0) continue;  // interior: no wall-table entry
+            const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+            if (bc.kind != 3 || bc.g1 == 0.0) continue;
+            const double *Lf = sL + (f & 1) * P;
+            const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
+            T d0 = T(0), d1 = T(0), d2 = T(0);
+#pragma unroll
+            for (int l = 0; l < P; ++l) {
+                d0 += T(Lf[l]) * sGu[0][lo + l * ls];
+                d1 += T(Lf[l]) * sGu[4][lo + l * ls];
+                d2 += T(Lf[l]) * sGu[8][lo + l * ls];
+            }
+            const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+            sFs[ft.le * 6 * G::n2 + f * G::n2 + ft.fp] += T(bc.g1_gam) * ((d0 + d1) + d2) * dS;
+        }
+        __syncthreads();
+    }
     // grad T (BR1 with T*) and lap c (divergence lifting of grad c)
     T gT[3] = {T(0), T(0), T(0)}, lap = T(0);
     if (act) {
@@ -876,7 +911,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
             const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
             const bool wall = a.mesh.nbr[el * 6 + f] < 0;
-            const int kind = wall ? a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind : 0;
+            int kind = 0;  // interior faces have no wall-table entry
+            if (wall) kind = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind;
             // state and convective part
             // scheduling barriers keep each field group's LDS loads next to the
             // arithmetic that consumes them (otherwise all of them are hoisted
@@ -909,12 +945,17 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G3 = m2 * un + p * n2;
                 G4 = (E + p) * un;
                 G5 = c * un;
-            } else if (kind == 1) {  // mirrored ghost, all velocity components
+            } else if (kind == 1) {  // ghost velocity 2 u_w - u (same rho, c, T)
+                const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                const T w0 = T(bc.uw[0]), w1 = T(bc.uw[1]), w2 = T(bc.uw[2]);
+                const T r0 = m0 - rho * w0, r1 = m1 - rho * w1, r2 = m2 - rho * w2;
                 G0 = T(0);
-                G1 = m0 * un + p * n0 + lam * m0;
-                G2_ = m1 * un + p * n1 + lam * m1;
-                G3 = m2 * un + p * n2 + lam * m2;
-                G4 = T(0);
+                G1 = r0 * un + p * n0 + lam * r0;
+                G2_ = r1 * un + p * n1 + lam * r1;
+                G3 = r2 * un + p * n2 + lam * r2;
+                // energy: -(u.n + lam)/2 times the ghost's extra kinetic energy
+                // 2 rho (|u_w|^2 - u_w . u)
+                G4 = -(un + lam) * rho * (w0 * (w0 - u0) + w1 * (w1 - u1) + w2 * (w2 - u2));
                 G5 = T(0);
             } else {                 // mirrored normal velocity only
                 const T q = mn * un + p + lam * mn;
@@ -936,21 +977,50 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G2_ -= tn1;
                 G3 -= tn2;
                 G4 -= tn0 * u0 + tn1 * u1 + tn2 * u2;
-            } else if (kind == 1) {
+            } else if (kind == 1) {  // traction, and its work at the wall velocity
+                const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
                 G1 -= tn0;
                 G2_ -= tn1;
                 G3 -= tn2;
+                G4 -= tn0 * T(bc.uw[0]) + tn1 * T(bc.uw[1]) + tn2 * T(bc.uw[2]);
             } else {
                 const T tnn = tn0 * n0 + tn1 * n1 + tn2 * n2;
                 G1 -= tnn * n0;
                 G2_ -= tnn * n1;
                 G3 -= tnn * n2;
+                if (kind == 3) {
+                    // Navier slip: tangential traction gamma_1 div u grad_G c -
+                    // gamma_2 (u_t - u_w,t), and its work on u_t
+                    const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                    const T gc0 = a.T2[0 * NF + o], gc1 = a.T2[1 * NF + o], gc2 = a.T2[2 * NF + o];
+                    const T gcn = gc0 * n0 + gc1 * n1 + gc2 * n2;
+                    const T w0 = T(bc.uw[0]), w1 = T(bc.uw[1]), w2 = T(bc.uw[2]);
+                    const T wn = w0 * n0 + w1 * n1 + w2 * n2;
+                    const T a1 = T(bc.g1) * div, a2 = T(bc.g2);
+                    const T ut0 = u0 - un * n0, ut1 = u1 - un * n1, ut2 = u2 - un * n2;
+                    const T t0 = a1 * (gc0 - gcn * n0) - a2 * (ut0 - (w0 - wn * n0));
+                    const T t1 = a1 * (gc1 - gcn * n1) - a2 * (ut1 - (w1 - wn * n1));
+                    const T t2 = a1 * (gc2 - gcn * n2) - a2 * (ut2 - (w2 - wn * n2));
+                    G1 -= t0;
+                    G2_ -= t1;
+                    G3 -= t2;
+                    G4 -= t0 * ut0 + t1 * ut1 + t2 * ut2;
+                }
             }
             // heat flux
             __builtin_amdgcn_sched_barrier(0);
-            if (kind != 2) {
+            // (interior faces have no wall-table entry: bcid is 0 there)
+            if (!wall) {
                 const T gTn = sgn * pro(nf + 3 * G::NV);
                 G4 -= T(a.ph.kappa) * gTn;
+            } else if (kind != 2) {
+                const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                if (bc.iso) {
+                    const T gTn = sgn * pro(nf + 3 * G::NV);
+                    G4 -= T(a.ph.kappa) * gTn;
+                } else {  // heat transfer, eq. bc_energy_alpha
+                    G4 -= T(-bc.g3 * (bc.inv_tw - 1.0 / Tf));
+                }
             }
             // order-parameter terms of j_e and F^V_c
             __builtin_amdgcn_sched_barrier(0);
@@ -961,10 +1031,13 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * gcn;
                 a.TF[6 * NF + o] = hl ? cw : lam;
-            } else if (kind == 1) {
-                const BcDev bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                const T g = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv));
-                G4 += T(a.ph.gam) * c * g * div;
+            } else if (kind != 2) {
+                // contact-angle flux g (with gamma_1 div u on Navier-slip
+                // walls) and the wall value zeta_c = -gamma_1 gamma_4 div u
+                const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+                const T g = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) + T(bc.g1_gam) * div;
+                const T zeta = -T(bc.g1 * bc.g4) * div;
+                G4 -= -T(a.ph.gam) * c * g * div + T(a.ph.gam) * g * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * g;
             }
             a.TF[0 * NF + o] = G0;

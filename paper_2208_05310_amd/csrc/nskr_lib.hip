@@ -31,6 +31,7 @@ struct nskr_ctx {
     int *d_nbr = nullptr, *d_bcid = nullptr;
     double *d_emet = nullptr, *d_fmet = nullptr, *d_egeo = nullptr;
     BcDev *d_bcs = nullptr;
+    int dyn = 0;                 // a Navier-slip wall with gamma_1 != 0
     std::vector<double> h_emet;  // host copy of the element metrics (weights for reductions)
     // scratch (element type of the precision)
     void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
@@ -515,7 +516,7 @@ template <int P, typename T, int BS> struct Impl {
     {
         MeshDev m;
         m.E = c->E; m.nbr = c->d_nbr; m.bcid = c->d_bcid; m.emet = c->d_emet; m.fmet = c->d_fmet;
-        m.egeo = c->d_egeo; m.bcs = c->d_bcs;
+        m.egeo = c->d_egeo; m.bcs = c->d_bcs; m.dyn = c->dyn;
         return m;
     }
     static Inst<T> inst(const nskr_ctx *c, const void *U, void *R, void *Ut, double dt)
@@ -839,8 +840,12 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
                 if (bc != 0) return fail(c, NSKR_E_ARG, "interior face with a wall index");
             } else {
                 if (bc < 1 || bc > m->nbcs) return fail(c, NSKR_E_ARG, "wall face without a valid wall index");
-                const int kind = m->bcs[bc - 1].kind;
-                if (kind != 1 && kind != 2) return fail(c, NSKR_E_ARG, "wall kind must be 1 or 2");
+                const nskr_bc &w = m->bcs[bc - 1];
+                if (w.kind != 1 && w.kind != 2 && w.kind != 3) return fail(c, NSKR_E_ARG, "wall kind must be 1, 2 or 3");
+                if (w.kind == 3 && !(w.gamma1 >= 0 && w.gamma2 >= 0 && w.gamma3 >= 0 && w.gamma4 >= 0))
+                    return fail(c, NSKR_E_ARG, "Navier-slip wall coefficients must be non-negative");
+                if (w.kind != 2 && !(std::isfinite(w.uwall[0]) && std::isfinite(w.uwall[1]) && std::isfinite(w.uwall[2])))
+                    return fail(c, NSKR_E_ARG, "wall velocity must be finite");
             }
         }
     // per-element affine metrics
@@ -887,16 +892,37 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + k] = cr[k];
         for (int d = 0; d < 3; ++d)
             for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + 3 + 3 * d + k] = a[d][k];
+        // a moving wall moves within its own plane
+        for (int f = 0; f < 6; ++f) {
+            const int bc = m->bc[e * 6 + f];
+            if (m->nbr[e * 6 + f] >= 0 || m->bcs[bc - 1].kind == 2) continue;
+            const double *uw = m->bcs[bc - 1].uwall, *fm = &fmet[((size_t)e * 6 + f) * 4];
+            const double un = uw[0] * fm[0] + uw[1] * fm[1] + uw[2] * fm[2];
+            if (fabs(un) > 1e-12 * (fabs(uw[0]) + fabs(uw[1]) + fabs(uw[2])))
+                return fail(c, NSKR_E_ARG, "wall velocity must be tangential to the wall");
+        }
     }
     // wall constants
     std::vector<BcDev> bcs(m->nbcs > 0 ? m->nbcs : 1);
+    int dyn = 0;
     Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
     for (int k = 0; k < m->nbcs; ++k) {
         BcDev &b = bcs[k];
         memset(&b, 0, sizeof(b));
         b.kind = m->bcs[k].kind;
         b.twall = m->bcs[k].twall;
-        if (b.kind == 1) {
+        b.iso = b.kind == 1 || (b.kind == 3 && std::isinf(m->bcs[k].gamma3));
+        if (b.kind != 2)
+            for (int d = 0; d < 3; ++d) b.uw[d] = m->bcs[k].uwall[d];
+        if (b.kind == 3) {
+            b.g1 = m->bcs[k].gamma1;
+            b.g2 = m->bcs[k].gamma2;
+            b.g3 = b.iso ? 0.0 : m->bcs[k].gamma3;
+            b.g4 = m->bcs[k].gamma4;
+            b.g1_gam = c->p.gam > 0 ? b.g1 / c->p.gam : 0.0;
+            if (b.g1 != 0.0) dyn = 1;
+        }
+        if (b.kind != 2) {
             ld rv, rl;
             if (!(m->bcs[k].twall > 0) || !maxwell_host(vdw, (ld)m->bcs[k].twall, rv, rl))
                 return fail(c, NSKR_E_ARG, "wall temperature must be subcritical and positive");
@@ -907,12 +933,14 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
             b.rl = (double)rl;
             // g = -(1/gamma) dpsi_Gamma/dc = -6 sigma cos(theta) / (gamma (rl - rv)^3) (c - rl)(c - rv)
             b.gcoef = c->p.gam > 0 ? (double)(-6 * sig * ct / ((ld)c->p.gam * d * d * d)) : 0.0;
+            b.inv_tw = 1.0 / b.twall;
         }
     }
     DeviceGuard guard(c->device);
     hipStream_t s = (hipStream_t)sv;
     free_mesh(c);
     c->E = E;
+    c->dyn = dyn;
     const int n3 = c->P * c->P * c->P, n2 = c->P * c->P;
     c->NN = (size_t)E * n3;
     c->NF = (size_t)E * 6 * n2;

@@ -44,7 +44,9 @@ class Params(ctypes.Structure):
 
 
 class Bc(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("twall", ctypes.c_double), ("theta_deg", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("twall", ctypes.c_double), ("theta_deg", ctypes.c_double),
+                ("uwall", ctypes.c_double * 3), ("gamma1", ctypes.c_double), ("gamma2", ctypes.c_double),
+                ("gamma3", ctypes.c_double), ("gamma4", ctypes.c_double)]
 
 
 class Mesh(ctypes.Structure):
@@ -62,7 +64,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 2  # the struct layouts below
+ABI_VERSION = 3  # the struct layouts below
 
 
 def lib():
@@ -114,11 +116,14 @@ def lib():
 
 
 def box_mesh(n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6, side_twall=(0.0,) * 6,
-             side_theta=(90.0,) * 6, lo=(0.0, 0.0, 0.0)):
+             side_theta=(90.0,) * 6, lo=(0.0, 0.0, 0.0), side_uwall=None, side_gamma=None):
     """Structured box of n[0] x n[1] x n[2] parallelepiped elements as host
     arrays for nskr_mesh_upload: corners, neighbours (periodic wrap or -1 at
     walls), opposite-face neighbour faces, wall indices and the wall table (one
-    entry per non-periodic box side)."""
+    entry per non-periodic box side, a dict of the nskr_bc fields).
+    side_uwall: per side wall velocity (kinds 1, 3); side_gamma: per side
+    (gamma1, gamma2, gamma3, gamma4) of Navier-slip walls (gamma3 = inf:
+    isothermal)."""
     nx, ny, nz = (int(v) for v in n)
     E = nx * ny * nz
     h = [length[d] / n[d] for d in range(3)]
@@ -138,9 +143,12 @@ def box_mesh(n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6, 
     for f in range(6):
         d, s = f // 2, f % 2
         if not periodic[d]:
-            if side_kind[f] not in (1, 2):
+            if side_kind[f] not in (1, 2, 3):
                 raise ValueError(f"box side {f} is not periodic and has no wall kind")
-            bcs.append((int(side_kind[f]), float(side_twall[f]), float(side_theta[f])))
+            g = side_gamma[f] if side_gamma is not None else (0.0, 0.0, float("inf"), 0.0)
+            bcs.append(dict(kind=int(side_kind[f]), twall=float(side_twall[f]), theta=float(side_theta[f]),
+                            uwall=tuple(float(v) for v in (side_uwall[f] if side_uwall is not None else (0, 0, 0))),
+                            gamma=tuple(float(v) for v in g)))
             side_index[f] = len(bcs)
     idx = np.stack([ex, ey, ez])
     for f in range(6):
@@ -207,8 +215,9 @@ class Solver:
         return torch.float64 if self.precision == "fp64" else torch.float32
 
     def upload_box(self, n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6,
-                   side_twall=(0.0,) * 6, side_theta=(90.0,) * 6, stream=None):
-        corners, nbr, nbf, bc, bcs = box_mesh(n, length, periodic, side_kind, side_twall, side_theta)
+                   side_twall=(0.0,) * 6, side_theta=(90.0,) * 6, stream=None, side_uwall=None, side_gamma=None):
+        corners, nbr, nbf, bc, bcs = box_mesh(n, length, periodic, side_kind, side_twall, side_theta,
+                                              side_uwall=side_uwall, side_gamma=side_gamma)
         self.upload_mesh(corners, nbr, nbf, bc, bcs, stream)
         self.box = dict(n=tuple(n), length=tuple(length), periodic=tuple(periodic))
 
@@ -217,7 +226,8 @@ class Solver:
         nbr = np.ascontiguousarray(nbr, dtype=np.int32)
         nbf = np.ascontiguousarray(nbf, dtype=np.int32)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
-        bc_arr = (Bc * max(1, len(bcs)))(*[Bc(k, t, th) for (k, t, th) in bcs])
+        bc_arr = (Bc * max(1, len(bcs)))(*[Bc(b["kind"], b["twall"], b["theta"], (ctypes.c_double * 3)(*b["uwall"]),
+                                                 *b["gamma"]) for b in bcs])
         m = Mesh(int(nbr.shape[0]), corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                  nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), nbf.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                  bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(bcs), bc_arr)
@@ -388,7 +398,8 @@ _profile_methods()
 def solver_for(w, precision="fp64", device=0, kahan=True):
     """Solver with the mesh of a workload description (paper_2208_05310_amd.workloads)."""
     s = Solver(w.params, w.N, precision, device, kahan)
-    s.upload_box(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta)
+    s.upload_box(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta,
+                 side_uwall=w.side_uwall, side_gamma=w.side_gamma)
     return s
 
 

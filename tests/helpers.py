@@ -7,9 +7,16 @@ from paper_2208_05310_amd import workloads as wl
 
 def oracle_for(w: wl.Workload, threads=None) -> oracle.Oracle:
     p = oracle.make_params(**w.params)
-    b = oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind,
-                        w.side_twall, w.side_theta, w.curve_amp)
-    return oracle.Oracle(p, b, threads=threads)
+    return oracle.Oracle(p, box_for(w), threads=threads)
+
+
+def box_for(w: wl.Workload) -> oracle.Box:
+    g = w.side_gamma or (wl.NO_GAMMA,) * 6
+    return oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind,
+                           w.side_twall, w.side_theta, w.curve_amp,
+                           side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
+                           side_g1=[v[0] for v in g], side_g2=[v[1] for v in g],
+                           side_g3=[v[2] for v in g], side_g4=[v[3] for v in g])
 
 
 def oracle_init(o: oracle.Oracle, w: wl.Workload) -> np.ndarray:

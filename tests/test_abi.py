@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(L, name), name
     from paper_2208_05310_amd.nskr import ABI_VERSION
-    assert L.nskr_version() == ABI_VERSION == 2
+    assert L.nskr_version() == ABI_VERSION == 3
 
 
 def test_create_validates_arguments_before_device():
@@ -79,7 +79,7 @@ def test_box_mesh_connectivity(periodic):
                 assert nbf[e, f] == f ^ 1 and nbr[nb, f ^ 1] == e and bc[e, f] == 0
             else:
                 assert not periodic[f // 2] and 1 <= bc[e, f] <= len(bcs)
-                assert bcs[bc[e, f] - 1][0] == kinds[f]
+                assert bcs[bc[e, f] - 1]["kind"] == kinds[f]
     # elements are axis-aligned boxes of the right size
     h = np.array([0.5, 0.25, 0.25])
     assert np.allclose(corners[:, 7] - corners[:, 0], h)
