@@ -50,7 +50,7 @@ class Box(ctypes.Structure):
                 ("side_theta", ctypes.c_double * 6), ("curve_amp", ctypes.c_double),
                 ("side_uwall", (ctypes.c_double * 3) * 6), ("side_g1", ctypes.c_double * 6),
                 ("side_g2", ctypes.c_double * 6), ("side_g4", ctypes.c_double * 6),
-                ("side_g3", ctypes.c_double * 6)]
+                ("side_g3", ctypes.c_double * 6), ("side_tgrad", (ctypes.c_double * 3) * 6)]
 
 
 _lib = None
@@ -87,6 +87,8 @@ def lib():
         "orc_sigma": (d, [d, d, d, d, d]),
         "orc_sigma_panels": (d, [d, d, d, d, d, i]),
         "orc_sigma_gauss15": (d, [d, d, d, d, d]),
+        "orc_table_build": (None, [d, d, d, _D]),
+        "orc_table_lookup": (None, [_D, d, _D]),
         "orc_dpsiwall_dc": (d, [d, d, d, d, d]),
         "orc_psiwall": (d, [d, d, d, d, d]),
         "orc_basis": (None, [i, _D, _D, _D, _D, _D, _D]),
@@ -121,17 +123,20 @@ def make_params(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.01, kappa=1.0 / 15
 def make_box(N, n, lo=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), periodic=(1, 1, 1),
              side_kind=(0,) * 6, side_twall=(0.0,) * 6, side_theta=(90.0,) * 6,
              curve_amp=0.0, side_uwall=((0.0, 0.0, 0.0),) * 6, side_g1=(0.0,) * 6,
-             side_g2=(0.0,) * 6, side_g3=(float("inf"),) * 6, side_g4=(0.0,) * 6) -> Box:
+             side_g2=(0.0,) * 6, side_g3=(float("inf"),) * 6, side_g4=(0.0,) * 6,
+             side_tgrad=((0.0, 0.0, 0.0),) * 6) -> Box:
     """Wall kinds per side (x-, x+, y-, y+, z-, z+): 1 no-slip isothermal with a
     static contact angle, moving with side_uwall; 2 slip adiabatic neutral;
     3 generalized Navier slip with gamma_1..gamma_4 (side_g3 infinite =
-    isothermal)."""
+    isothermal).  side_tgrad: wall temperature twall + tgrad . x (kinds 1, 3),
+    through the sigma/Maxwell table."""
     uw = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_uwall])
+    tg = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_tgrad])
     d6 = lambda v: (ctypes.c_double * 6)(*[float(x) for x in v])
     return Box(int(N), (ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo),
                (ctypes.c_double * 3)(*length), (ctypes.c_int * 3)(*periodic),
                (ctypes.c_int * 6)(*side_kind), d6(side_twall), d6(side_theta), float(curve_amp),
-               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3))
+               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3), tg)
 
 
 class Oracle:
@@ -253,6 +258,22 @@ def sigma(T, gam=1e-4, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, panels=None):
 
 def sigma_gauss15(T, gam=1e-4, R=8.0 / 3.0, a=3.0, b=1.0 / 3.0):
     return lib().orc_sigma_gauss15(R, a, b, T, gam)
+
+
+NTAB = 10000  # wall-temperature table: equidistant on [0.3, 1]
+
+
+def wall_table(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0) -> np.ndarray:
+    """[NTAB][3]: sigma/sqrt(2 gamma) (15-point Gauss), rho_v, rho_l."""
+    tab = np.zeros((NTAB, 3))
+    lib().orc_table_build(R, a, b, _ptr(tab))
+    return tab
+
+
+def wall_table_lookup(tab: np.ndarray, T: float) -> np.ndarray:
+    out = np.zeros(3)
+    lib().orc_table_lookup(_ptr(np.ascontiguousarray(tab)), float(T), _ptr(out))
+    return out
 
 
 def dpsiwall_dc(c, rv, rl, sig, costh):

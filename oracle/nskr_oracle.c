@@ -48,6 +48,10 @@
  *     so zeta_c = 0 on the wall), or the generalized Navier-slip wall of
  *     eq. bc_nsk_alpha with gamma_1, gamma_2, gamma_4 and either a fixed
  *     temperature or the heat-transfer condition with gamma_3.
+ *   - A wall temperature that varies along the wall (linearly in x) takes
+ *     sigma and the Maxwell states from the table of Sec. 3.2 (15-point
+ *     Gauss rule, 10000 points on [0.3, 1], linear interpolation), the
+ *     Maxwell states tabulated alongside sigma.
  *   - Time integration: Carpenter-Kennedy 5-stage 2N-storage RK4(3)5.
  *   - Time step: advective limit with 1D Rusanov stability constants, and a
  *     parabolic/source limit with 1D BR1 spectral radii.
@@ -87,6 +91,9 @@ typedef struct {
     double side_uwall[6][3];  /* wall velocity (kinds 1, 3; tangential)       */
     double side_g1[6], side_g2[6], side_g4[6]; /* gamma_1, gamma_2, gamma_4 (kind 3) */
     double side_g3[6];        /* gamma_3 (kind 3); infinite = isothermal wall */
+    double side_tgrad[6][3];  /* wall temperature gradient (kinds 1, 3): the
+                                 wall temperature at x is twall + tgrad . x,
+                                 evaluated through the sigma/Maxwell table  */
 } orc_box;
 
 typedef struct {
@@ -109,7 +116,15 @@ typedef struct {
     double *xyz;              /* [E][n3][3]                                   */
     /* wall constants per box side: Maxwell states, sigma, cos(theta) */
     double wrv[6], wrl[6], wsig[6], wcos[6];
+    int wvar[6];              /* side with a varying wall temperature        */
+    double *stab;             /* [ORC_NTAB][3] sigma/sqrt(2 gamma), rv, rl   */
 } orc_ctx;
+
+/* Wall-temperature table of Sec. 3.2: ORC_NTAB equidistant temperatures on
+ * [0.3, 1]; sigma by the 15-point Gauss rule, linear interpolation. */
+#define ORC_NTAB 10000
+#define ORC_TAB_T0 0.3
+#define ORC_TAB_T1 1.0
 
 /* ------------------------------------------------------------------------ */
 /* 1D polynomial machinery (Sec. 3.1: Lagrange basis on Legendre-Gauss       */
@@ -389,6 +404,39 @@ double orc_sigma_gauss15(double R, double a, double b, double T, double gam)
         I += 0.5 * (rl - rv) * w[i] * sigma_integrand(&pr, T, rv, rho);
     }
     return sqrt(2.0 * gam) * I;
+}
+
+/* Entry k of the wall-temperature table at T_k = 0.3 + k (0.7/(ORC_NTAB-1)):
+ * sigma/sqrt(2 gamma) by the 15-point Gauss rule over [rv, rl] and the
+ * Maxwell states; the last entry is the critical point (sigma = 0, rv = rl =
+ * 1/(3b)). */
+static void table_entry(double R, double a, double b, int k, double out[3])
+{
+    double T = ORC_TAB_T0 + k * ((ORC_TAB_T1 - ORC_TAB_T0) / (ORC_NTAB - 1));
+    double rv, rl;
+    if (k == ORC_NTAB - 1 || !orc_maxwell(R, a, b, T, &rv, &rl, NULL)) {
+        out[0] = 0.0; out[1] = out[2] = 1.0 / (3.0 * b);
+        return;
+    }
+    out[0] = orc_sigma_gauss15(R, a, b, T, 0.5);  /* sqrt(2 gamma) = 1 */
+    out[1] = rv; out[2] = rl;
+}
+
+void orc_table_build(double R, double a, double b, double *tab)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int k = 0; k < ORC_NTAB; ++k) table_entry(R, a, b, k, tab + 3 * k);
+}
+
+/* Linear interpolation in the table at temperature T (clamped to the grid). */
+void orc_table_lookup(const double *tab, double T, double out[3])
+{
+    double sx = (T - ORC_TAB_T0) / ((ORC_TAB_T1 - ORC_TAB_T0) / (ORC_NTAB - 1));
+    int k = (int)floor(sx);
+    if (k < 0) k = 0;
+    if (k > ORC_NTAB - 2) k = ORC_NTAB - 2;
+    double w = sx - k;
+    for (int v = 0; v < 3; ++v) out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];
 }
 
 /* Derivative of the cubic wall energy, eq. helmfreesurftot_derivative. */
@@ -829,12 +877,37 @@ void *orc_create(const orc_params *pr, const orc_box *bx, char *err, int errlen)
         if (!orc_maxwell(pr->R, pr->a, pr->b, bx->side_twall[f], &rv, &rl, NULL)) {
             snprintf(err, errlen, "wall temperature %d is not subcritical", f);
             free(c->nbr); free(c->kind); free(c->side); free(c->Ja); free(c->J);
-            free(c->nv); free(c->xyz); free(c);
+            free(c->nv); free(c->xyz); free(c->stab); free(c);
             return NULL;
         }
         c->wrv[f] = rv; c->wrl[f] = rl;
         c->wsig[f] = orc_sigma(pr->R, pr->a, pr->b, bx->side_twall[f], pr->gam);
         c->wcos[f] = cos(bx->side_theta[f] * M_PI / 180.0);
+        const double *tg = bx->side_tgrad[f];
+        c->wvar[f] = tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0;
+        if (c->wvar[f]) {
+            /* the wall temperature must stay inside the table's subcritical
+             * part on the whole side (its extremes are at the side's corners) */
+            int d = f / 2;
+            for (int q = 0; q < 4; ++q) {
+                double x[3], T = bx->side_twall[f];
+                int bit = 0;
+                for (int m = 0; m < 3; ++m) {
+                    x[m] = bx->lo[m] + (m == d ? (f & 1) * bx->len[m] : ((q >> bit++) & 1) * bx->len[m]);
+                    T += tg[m] * x[m];
+                }
+                if (!(T >= 0.3 && T <= 0.99)) {
+                    snprintf(err, errlen, "wall temperature of side %d leaves [0.3, 0.99]", f);
+                    free(c->nbr); free(c->kind); free(c->side); free(c->Ja); free(c->J);
+                    free(c->nv); free(c->xyz); free(c->stab); free(c);
+                    return NULL;
+                }
+            }
+            if (!c->stab) {
+                c->stab = malloc(sizeof(double) * 3 * ORC_NTAB);
+                orc_table_build(pr->R, pr->a, pr->b, c->stab);
+            }
+        }
     }
     build_metrics(c);
     return c;
@@ -845,7 +918,7 @@ void orc_destroy(void *vc)
     orc_ctx *c = vc;
     if (!c) return;
     free(c->nbr); free(c->kind); free(c->side); free(c->Ja); free(c->J);
-    free(c->nv); free(c->xyz); free(c);
+    free(c->nv); free(c->xyz); free(c->stab); free(c);
 }
 
 long orc_nnodes(void *vc) { orc_ctx *c = vc; return (long)c->E * c->n3; }
@@ -1085,13 +1158,51 @@ static void step_lift1(const orc_ctx *c, const double *U, work_t *w)
     }
 }
 
+/* Physical position of face point fp of face f of element e (face points
+ * ordered p + P q over the two tangential directions in axis order). */
+static void face_point_x(const orc_ctx *c, int e, int f, int fp, double x[3])
+{
+    int P = c->P, d = f / 2, t[2] = {fp % P, fp / P}, it = 0;
+    int ee[3] = {e % c->box.n[0], (e / c->box.n[0]) % c->box.n[1], e / (c->box.n[0] * c->box.n[1])};
+    ldbl Xr[3], xx[3];
+    for (int m = 0; m < 3; ++m) {
+        ldbl xi = (m == d) ? ((f & 1) ? 1.0L : -1.0L) : (ldbl)c->xg[t[it++]];
+        ldbl h = (ldbl)c->box.len[m] / c->box.n[m];
+        Xr[m] = c->box.lo[m] + h * (ee[m] + 0.5L * (xi + 1.0L));
+    }
+    geom_map(&c->box, Xr, xx);
+    for (int m = 0; m < 3; ++m) x[m] = (double)xx[m];
+}
+
+/* Wall temperature and the contact-angle constants at one wall face point:
+ * the side's constants for a fixed wall temperature; for a varying one,
+ * T_w = twall + tgrad . x and sigma, rv, rl interpolated in the table. */
+typedef struct { double Tw, rv, rl, sig, cs; } wall_pt;
+static void wall_point(const orc_ctx *c, int e, int f, int fp, wall_pt *w)
+{
+    int sd = c->side[e * 6 + f];
+    w->cs = c->wcos[sd];
+    w->Tw = c->box.side_twall[sd];
+    if (!c->wvar[sd]) {
+        w->rv = c->wrv[sd]; w->rl = c->wrl[sd]; w->sig = c->wsig[sd];
+        return;
+    }
+    double x[3], v[3];
+    const double *tg = c->box.side_tgrad[sd];
+    face_point_x(c, e, f, fp, x);
+    w->Tw += tg[0] * x[0] + tg[1] * x[1] + tg[2] * x[2];
+    orc_table_lookup(c->stab, w->Tw, v);
+    w->sig = sqrt(2.0 * c->pr.gam) * v[0];
+    w->rv = v[1]; w->rl = v[2];
+}
+
 /* Contact-angle flux g = grad c . n on a wall of kind 1 or 3, from the
  * constitutive relation eq. bc_contactangle_alpha: g = (gamma_1 div u -
  * dpsi/dc) / gamma, with gamma_1 = 0 on the no-slip wall; div u is the trace
  * of the lifted velocity gradient at the wall. */
-static double wall_g(const orc_ctx *c, int kind, int f_side, double cm, double div)
+static double wall_g(const orc_ctx *c, int kind, int f_side, const wall_pt *wp, double cm, double div)
 {
-    double g = -orc_dpsiwall_dc(cm, c->wrv[f_side], c->wrl[f_side], c->wsig[f_side], c->wcos[f_side]) / c->pr.gam;
+    double g = -orc_dpsiwall_dc(cm, wp->rv, wp->rl, wp->sig, wp->cs) / c->pr.gam;
     if (kind == 3) g += c->box.side_g1[f_side] * div / c->pr.gam;
     return g;
 }
@@ -1154,7 +1265,9 @@ static void step_lift2(const orc_ctx *c, const double *U, work_t *w)
                     int sd = c->side[e * 6 + f];
                     double dS = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
                     int kd = c->kind[e * 6 + f];
-                    Ts[f * n2 + fp] = wall_isothermal(c, kd, sd) ? c->box.side_twall[sd] : Tm;
+                    wall_pt wp;
+                    wall_point(c, e, f, fp, &wp);
+                    Ts[f * n2 + fp] = wall_isothermal(c, kd, sd) ? wp.Tw : Tm;
                     if (kd == 2) {
                         fs[f * n2 + fp] = 0.0;
                     } else {
@@ -1169,7 +1282,7 @@ static void step_lift2(const orc_ctx *c, const double *U, work_t *w)
                                 div += tr[fp];
                             }
                         }
-                        fs[f * n2 + fp] = wall_g(c, kd, sd, cm, div) * dS;
+                        fs[f * n2 + fp] = wall_g(c, kd, sd, &wp, cm, div) * dS;
                     }
                 }
             }
@@ -1286,11 +1399,14 @@ void orc_numflux(const orc_params *pr, const double *UL, double TL, const double
  *     - 1/T-) (eq. bc_energy_alpha); order parameter gamma beta g.
  * g is the contact-angle flux of wall_g; grad_G c and u_t are the tangential
  * parts of the lifted grad c and of u- at the face. */
-static void wall_flux(const orc_ctx *c, int e, int f, const point_state *sm, const double n[3], double out[6])
+static void wall_flux(const orc_ctx *c, int e, int f, int fp, const point_state *sm, const double n[3],
+                      double out[6])
 {
     const orc_params *pr = &c->pr;
     const orc_box *bx = &c->box;
     int kd = c->kind[e * 6 + f], sd = c->side[e * 6 + f];
+    wall_pt wp;
+    wall_point(c, e, f, fp, &wp);
     const double *uw = bx->side_uwall[sd];
     double rho = sm->U[0], u[3], un = 0.0;
     for (int m = 0; m < 3; ++m) {
@@ -1322,7 +1438,7 @@ static void wall_flux(const orc_ctx *c, int e, int f, const point_state *sm, con
     double div = sm->gu[0][0] + sm->gu[1][1] + sm->gu[2][2];
     double gTn = sm->gT[0] * n[0] + sm->gT[1] * n[1] + sm->gT[2] * n[2];
     if (kd == 1) {
-        double g = wall_g(c, kd, sd, sm->U[5], div);
+        double g = wall_g(c, kd, sd, &wp, sm->U[5], div);
         for (int m = 0; m < 3; ++m) fv[1 + m] = tn[m];
         fv[4] = (tn[0] * uw[0] + tn[1] * uw[1] + tn[2] * uw[2]) + pr->kappa * gTn - pr->gam * sm->U[5] * g * div;
         fv[5] = pr->gam * pr->beta * g;
@@ -1331,7 +1447,7 @@ static void wall_flux(const orc_ctx *c, int e, int f, const point_state *sm, con
         for (int m = 0; m < 3; ++m) fv[1 + m] = nn * n[m];
     } else {
         double g1 = bx->side_g1[sd], g2 = bx->side_g2[sd], g3 = bx->side_g3[sd], g4 = bx->side_g4[sd];
-        double g = wall_g(c, kd, sd, sm->U[5], div);
+        double g = wall_g(c, kd, sd, &wp, sm->U[5], div);
         double nn = tn[0] * n[0] + tn[1] * n[1] + tn[2] * n[2];
         double gcn = sm->gc[0] * n[0] + sm->gc[1] * n[1] + sm->gc[2] * n[2];
         double uwn = uw[0] * n[0] + uw[1] * n[1] + uw[2] * n[2];
@@ -1342,7 +1458,7 @@ static void wall_flux(const orc_ctx *c, int e, int f, const point_state *sm, con
             fv[1 + m] = nn * n[m] + t;
             work += t * ut;
         }
-        double q = wall_isothermal(c, kd, sd) ? pr->kappa * gTn : -g3 * (1.0 / bx->side_twall[sd] - 1.0 / sm->T);
+        double q = wall_isothermal(c, kd, sd) ? pr->kappa * gTn : -g3 * (1.0 / wp.Tw - 1.0 / sm->T);
         double zeta = -g1 * g4 * div;
         fv[4] = work + q - pr->gam * sm->U[5] * g * div + pr->gam * g * zeta;
         fv[5] = pr->gam * pr->beta * g;
@@ -1389,7 +1505,7 @@ static void step_faces(const orc_ctx *c, work_t *w)
                     for (int v = 0; v < 6; ++v)
                         for (int i = 0; i < 3; ++i) out[v] -= 0.5 * (Fvm[i][v] + Fvp[i][v]) * n[i];
                 } else {
-                    wall_flux(c, e, f, &sm, n, out);
+                    wall_flux(c, e, f, fp, &sm, n, out);
                 }
                 for (int v = 0; v < 6; ++v) w->Fs[(((size_t)e * 6 + f) * 6 + v) * n2 + fp] = out[v] * dS;
             }

@@ -100,7 +100,8 @@ def test_invalid_arguments_are_rejected_and_context_survives(torch_cuda):
 
 def test_invalid_walls_are_rejected(torch_cuda):
     """A wall velocity with a normal component, a negative Navier-slip
-    coefficient and an unknown wall kind are argument errors at mesh upload."""
+    coefficient, an unknown wall kind and a wall temperature leaving the
+    table's range are argument errors at mesh upload."""
     from paper_2208_05310_amd import workloads as wl
     from paper_2208_05310_amd.nskr import NSKR_E_ARG, NskrError, Solver
     print("[case] invalid walls", flush=True)
@@ -109,12 +110,13 @@ def test_invalid_walls_are_rejected(torch_cuda):
         dict(side_uwall=((0.0, 0.0, 0.0),) * 5 + ((0.5, 0.0, 0.01),)),          # lid moving through itself
         dict(side_gamma=(wl.NO_GAMMA,) * 4 + ((20.0, -1e-4, float("inf"), 0.0), wl.NO_GAMMA)),
         dict(side_kind=(0, 0, 0, 0, 4, 1)),
+        dict(side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.2, 0.0, 0.0), (0.0, 0.0, 0.0))),  # floor reaches 1.05
     ]
     for kw in bad:
         v = w.with_(**kw)
         s = Solver(v.params, v.N, "fp64")
         with pytest.raises((NskrError, ValueError)) as ei:
             s.upload_box(v.n, v.length, v.periodic, v.side_kind, v.side_twall, v.side_theta,
-                         side_uwall=v.side_uwall, side_gamma=v.side_gamma)
+                         side_uwall=v.side_uwall, side_gamma=v.side_gamma, side_tgrad=v.side_tgrad)
         if isinstance(ei.value, NskrError):
             assert ei.value.code == NSKR_E_ARG
