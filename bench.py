@@ -83,7 +83,7 @@ def oracle_box(w):
     return oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
                            w.side_theta, w.curve_amp, side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
                            side_g1=[v[0] for v in g], side_g2=[v[1] for v in g], side_g3=[v[2] for v in g],
-                           side_g4=[v[3] for v in g])
+                           side_g4=[v[3] for v in g], side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6)
 
 
 def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
@@ -228,10 +228,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"],
                     help="c1 4^3 N=3 droplet; c2 16^3 N=4 two droplets (default); c3 32^3 N=5 eight "
                          "droplets; c4 48x48x24 N=3 sessile wall box; c5 50^3 N=3 head-on collision; "
-                         "c6 100x50x25 N=3 droplet sliding on a Navier-slip floor under a moving lid")
+                         "c6 100x50x25 N=3 droplet sliding on a Navier-slip floor under a moving lid; "
+                         "c7 the c4 wall box with a graded floor temperature")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison")
@@ -282,7 +283,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c6": wl.c6}[args.workload]()
+    w = {"c1": wl.c1, "c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c6": wl.c6,
+         "c7": wl.c7}[args.workload]()
     if args.model == 2:
         w = w.with_(name=f"{w.name}_model2", params=dict(w.params, model=2))
     stream = torch.cuda.current_stream()

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 3  /* 3: nskr_bc wall velocity and gamma1..gamma4; 2: nskr_params.model */
+#define NSKR_ABI_VERSION 4  /* 4: nskr_bc.twall_grad; 3: wall velocity, gamma1..4; 2: params.model */
 
 enum {
     NSKR_OK = 0,
@@ -91,13 +91,19 @@ typedef struct {
  *     twall.
  * gamma1..gamma4 >= 0 and are read for kind 3 only; uwall must be tangential
  * to every face of the wall (NSKR_E_ARG otherwise) and is read for kinds 1
- * and 3. */
+ * and 3.  twall_grad (kinds 1, 3): the wall temperature at a wall point x is
+ * twall + twall_grad . x; when it is non-zero, sigma_vl and the Maxwell
+ * states at that temperature come from a table of Sec. 3.2 (10000
+ * equidistant temperatures on [0.3, 1], sigma by a 15-point Gauss rule,
+ * linear interpolation) at every wall face point and stage, and the wall
+ * temperature must stay in [0.3, 0.99] on the whole wall (NSKR_E_ARG). */
 typedef struct {
     int kind;
     double twall;
     double theta_deg;
     double uwall[3];
     double gamma1, gamma2, gamma3, gamma4;
+    double twall_grad[3];
 } nskr_bc;
 
 /* Hexahedral mesh (Sec. 3.1).  Every element must be a parallelepiped (affine

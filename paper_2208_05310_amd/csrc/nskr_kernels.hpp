@@ -58,7 +58,16 @@ struct BcDev {
     double g1, g2, g3, g4;  // gamma_1..gamma_4 (kind 3; zero otherwise)
     double g1_gam;    // gamma_1 / gamma: the dynamic part of g, times div u
     double inv_tw;    // 1 / twall
+    int var;          // wall temperature twall + tg . x (table lookup per face point)
+    double tg[3];
+    double cg;        // -6 cos(theta) / gamma: gcoef = cg sigma / (rl - rv)^3
+    double s2g;       // sqrt(2 gamma): sigma = s2g * (tabulated sigma / sqrt(2 gamma))
 };
+
+// Wall-temperature table (Sec. 3.2): kTabN equidistant temperatures on
+// [kTabT0, kTabT1], entries (sigma / sqrt(2 gamma), rho_v, rho_l).
+constexpr int kTabN = 10000;
+constexpr double kTabT0 = 0.3, kTabT1 = 1.0;
 
 // 1D operators for one polynomial degree (host computed, FP64).
 struct Basis {
@@ -78,6 +87,8 @@ struct MeshDev {
     const double *egeo;  // [E][12] corner 0 and the three edge vectors
     const BcDev *bcs;
     int dyn;             // some Navier-slip wall has gamma_1 != 0 (g needs div u at the wall)
+    const double *stab;  // [kTabN][3] wall-temperature table (walls with a temperature gradient)
+    int var;             // some wall has a temperature gradient
 };
 
 template <int P, int BS = kBlock> struct Tile {
@@ -397,6 +408,51 @@ template <typename T> __device__ __forceinline__ void wall_primitives(const Mesh
         w[2] -= un * n1;
         w[3] -= un * n2;
     }
+}
+
+// Wall temperature twall + tg . x at a wall face point (x from the element's
+// corner and edge vectors at the face point's reference coordinates: +-1
+// along the face's axis, the Gauss nodes of its two tangential indices along
+// the others).
+template <int P>
+__device__ __forceinline__ double wall_temperature(const MeshDev &m, const Basis &bas, const BcDev &bc, int el, int f,
+                                                   int fp)
+{
+    const int d = f >> 1;
+    const double xn = (f & 1) ? 1.0 : -1.0, xa = bas.x[fp % P], xb = bas.x[fp / P];
+    const double r0 = d == 0 ? xn : xa, r1 = d == 1 ? xn : (d == 0 ? xa : xb), r2 = d == 2 ? xn : xb;
+    const double *g = m.egeo + (size_t)el * 12;
+    double Tw = bc.twall;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        Tw += bc.tg[k] * (g[k] + 0.5 * ((r0 + 1.0) * g[3 + k] + (r1 + 1.0) * g[6 + k] + (r2 + 1.0) * g[9 + k]));
+    return Tw;
+}
+
+// Wall temperature and contact-angle constants at one wall face point: the
+// wall's constants for a fixed temperature; for a temperature varying along
+// the wall, sigma, rho_v, rho_l interpolated linearly in the table at T_w.
+struct WallPt {
+    double Tw, rv, rl, gcoef;
+};
+template <int P>
+__device__ __forceinline__ WallPt wall_point(const MeshDev &m, const Basis &bas, const BcDev &bc, int el, int f, int fp)
+{
+    WallPt w{bc.twall, bc.rv, bc.rl, bc.gcoef};
+    if (!bc.var) return w;
+    const double Tw = wall_temperature<P>(m, bas, bc, el, f, fp);
+    const double sx = (Tw - kTabT0) / ((kTabT1 - kTabT0) / (kTabN - 1));
+    int k = (int)floor(sx);
+    k = k < 0 ? 0 : (k > kTabN - 2 ? kTabN - 2 : k);
+    const double wt = sx - k;
+    const double *t0 = m.stab + 3 * k;
+    const double sig = bc.s2g * ((1.0 - wt) * t0[0] + wt * t0[3]);
+    w.Tw = Tw;
+    w.rv = (1.0 - wt) * t0[1] + wt * t0[4];
+    w.rl = (1.0 - wt) * t0[2] + wt * t0[5];
+    const double dd = w.rl - w.rv;
+    w.gcoef = bc.cg * sig / (dd * dd * dd);
+    return w;
 }
 
 // BR1 lifted gradient of one field at element-local node (i, j, k):
@@ -763,8 +819,9 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
             Ts = bc.iso ? T(bc.twall) : tr.own[3];
             if (bc.kind != 2) {
-                // static part of the contact-angle flux; the dynamic part
-                // (gamma_1 div u) is added once grad u is lifted
+                // static part of the contact-angle flux (a varying wall
+                // temperature is applied in the pass below; the dynamic part,
+                // gamma_1 div u, once grad u is lifted)
                 const T c = uf[5];
                 Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
             } else {
@@ -776,6 +833,26 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         for (int k = 0; k < 4; ++k) sS[k][slot] = w[1 + k];
         sTs[slot] = Ts;
         sFs[slot] = Fs;
+    }
+    if (a.mesh.var) {
+        // walls whose temperature varies along them: T* and the static
+        // contact-angle flux at the local wall temperature, through the table
+        // (each thread rewrites only the face points it wrote above)
+        for (int task = t; task < G::NF; task += BS) {
+            const FaceTask<P> ft(task);
+            const int el = e0 + ft.le, f = ft.f;
+            if (el >= E) continue;
+            if (a.mesh.nbr[el * 6 + f] >= 0) continue;  // interior: no wall-table entry
+            const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
+            if (!bc.var) continue;
+            const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp);
+            const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
+            const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
+            if (bc.iso) sTs[slot] = T(wp.Tw);
+            else a.TF[6 * NF + o] = T(1.0 / wp.Tw);  // 1/T_w for the heat-transfer flux below (TF[6] is free on walls)
+            const T c = TU[5 * NF + o];
+            sFs[slot] = T(wp.gcoef) * (c - T(wp.rl)) * (c - T(wp.rv)) * T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+        }
     }
     __syncthreads();
     // lifted grad u, grad c and the nodal temperature
@@ -1019,7 +1096,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                     const T gTn = sgn * pro(nf + 3 * G::NV);
                     G4 -= T(a.ph.kappa) * gTn;
                 } else {  // heat transfer, eq. bc_energy_alpha
-                    G4 -= T(-bc.g3 * (bc.inv_tw - 1.0 / Tf));
+                    const double itw = bc.var ? (double)a.TF[6 * NF + o] : bc.inv_tw;
+                    G4 -= T(-bc.g3 * (itw - 1.0 / Tf));
                 }
             }
             // order-parameter terms of j_e and F^V_c
@@ -1033,9 +1111,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 a.TF[6 * NF + o] = hl ? cw : lam;
             } else if (kind != 2) {
                 // contact-angle flux g (with gamma_1 div u on Navier-slip
-                // walls) and the wall value zeta_c = -gamma_1 gamma_4 div u
+                // walls), as the second lifting used it: sFs holds g dS; and
+                // the wall value zeta_c = -gamma_1 gamma_4 div u
                 const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                const T g = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) + T(bc.g1_gam) * div;
+                const T g = sFs[ft.le * 6 * G::n2 + f * G::n2 + ft.fp] / T(fm[3]);
                 const T zeta = -T(bc.g1 * bc.g4) * div;
                 G4 -= -T(a.ph.gam) * c * g * div + T(a.ph.gam) * g * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * g;

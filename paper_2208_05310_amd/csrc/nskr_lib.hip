@@ -9,6 +9,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <array>
+#include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -32,6 +35,8 @@ struct nskr_ctx {
     double *d_emet = nullptr, *d_fmet = nullptr, *d_egeo = nullptr;
     BcDev *d_bcs = nullptr;
     int dyn = 0;                 // a Navier-slip wall with gamma_1 != 0
+    double *d_stab = nullptr;    // wall-temperature table (walls with a temperature gradient)
+    int var = 0;                 // some wall has a temperature gradient
     std::vector<double> h_emet;  // host copy of the element metrics (weights for reductions)
     // scratch (element type of the precision)
     void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
@@ -200,6 +205,8 @@ struct Vdw {
     ld psi_nl(ld r, ld T) const { return r * R * T * logl(b * r / (1 - b * r)) - a * r * r; }
 };
 
+static bool maxwell_newton(const Vdw &v, ld T, ld sv, ld sl, ld &rv, ld &rl);
+
 // Maxwell states: Newton on p(rv) = p(rl), mu(rv) = mu(rl), started from the
 // two spinodal densities pushed outwards, with a step-halving guard that keeps
 // both iterates on their branches.
@@ -218,6 +225,14 @@ static bool maxwell_host(const Vdw &v, ld T, ld &rv, ld &rl)
     if (sv < 0 || sl < 0) return false;
     rv = 0.5L * sv;
     rl = 0.5L * (sl + rmax);
+    return maxwell_newton(v, T, sv, sl, rv, rl);
+}
+
+// Newton for the Maxwell states from (rv, rl), each iterate kept inside (0, sv)
+// and (sl, 1/b) by step halving.
+static bool maxwell_newton(const Vdw &v, ld T, ld sv, ld sl, ld &rv, ld &rl)
+{
+    const ld rmax = 1 / v.b;
     for (int it = 0; it < 200; ++it) {
         ld f1 = v.p(rv, T) - v.p(rl, T), f2 = v.mu(rv, T) - v.mu(rl, T);
         ld a11 = v.dp(rv, T), a12 = -v.dp(rl, T), a21 = v.dmu(rv, T), a22 = -v.dmu(rl, T);
@@ -267,6 +282,72 @@ static ld sigma_host(const Vdw &v, ld T, ld gam, ld rv, ld rl)
         }
     }
     return sqrtl(2 * gam) * I;
+}
+
+// sigma_vl / sqrt(2 gamma) by the single 15-point Gauss-Legendre rule over
+// [rv, rl] that the wall-temperature table of Sec. 3.2 prescribes.
+static ld sigma15_host(const Vdw &v, ld T, ld rv, ld rl)
+{
+    const int m = 15;
+    const ld muv = v.mu(rv, T), psiv = v.psi_nl(rv, T);
+    ld I = 0;
+    for (int i = 0; i < m; ++i) {
+        ld xi = -cosl(3.14159265358979323846264338327950288L * (i + 0.75L) / (m + 0.5L));
+        for (int it = 0; it < 60; ++it) {
+            ld Pn, dP;
+            legendre_ld(m, xi, Pn, dP);
+            ld dx = Pn / dP;
+            xi -= dx;
+            if (fabsl(dx) < 1e-21L) break;
+        }
+        ld Pn, dP;
+        legendre_ld(m, xi, Pn, dP);
+        const ld wi = 2 / ((1 - xi * xi) * dP * dP);
+        const ld r = 0.5L * (rv + rl) + 0.5L * (rl - rv) * xi;
+        const ld d = v.psi_nl(r, T) - (psiv + (r - rv) * muv);
+        I += 0.5L * (rl - rv) * wi * (d > 0 ? sqrtl(d) : 0);
+    }
+    return I;
+}
+
+// The wall-temperature table: kTabN temperatures T_k = 0.3 + k (0.7/(kTabN-1))
+// with (sigma / sqrt(2 gamma), rho_v, rho_l); Maxwell states by Newton
+// continued from the previous temperature (a full solve where that fails);
+// the last entry is the critical point.  Built once per van der Waals fluid.
+static const std::vector<double> &wall_table_host(const Vdw &v)
+{
+    static std::mutex mtx;
+    static std::map<std::array<double, 3>, std::vector<double>> cache;
+    std::lock_guard<std::mutex> lock(mtx);
+    const std::array<double, 3> key{(double)v.R, (double)v.a, (double)v.b};
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    std::vector<double> tab(3 * kTabN);
+    ld rv = 0, rl = 0;
+    bool have = false;
+    const ld rc = 1 / (3 * v.b);
+    for (int k = 0; k < kTabN; ++k) {
+        const double Tk = kTabT0 + k * ((kTabT1 - kTabT0) / (kTabN - 1));
+        bool ok = false;
+        if (k < kTabN - 1) {
+            if (have) {
+                ld a = rv, b = rl;
+                ok = maxwell_newton(v, Tk, rc, rc, a, b) && a < rc && b > rc;
+                if (ok) { rv = a; rl = b; }
+            }
+            if (!ok) ok = maxwell_host(v, Tk, rv, rl);
+        }
+        if (ok) {
+            tab[3 * k] = (double)sigma15_host(v, Tk, rv, rl);
+            tab[3 * k + 1] = (double)rv;
+            tab[3 * k + 2] = (double)rl;
+        } else {
+            tab[3 * k] = 0.0;
+            tab[3 * k + 1] = tab[3 * k + 2] = (double)rc;
+        }
+        have = ok;
+    }
+    return cache.emplace(key, std::move(tab)).first->second;
 }
 
 // ------------------------------------------------- RK and time-step constants
@@ -516,7 +597,7 @@ template <int P, typename T, int BS> struct Impl {
     {
         MeshDev m;
         m.E = c->E; m.nbr = c->d_nbr; m.bcid = c->d_bcid; m.emet = c->d_emet; m.fmet = c->d_fmet;
-        m.egeo = c->d_egeo; m.bcs = c->d_bcs; m.dyn = c->dyn;
+        m.egeo = c->d_egeo; m.bcs = c->d_bcs; m.dyn = c->dyn; m.stab = c->d_stab; m.var = c->var;
         return m;
     }
     static Inst<T> inst(const nskr_ctx *c, const void *U, void *R, void *Ut, double dt)
@@ -781,12 +862,14 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
 static void free_mesh(nskr_ctx *c)
 {
     void *ptrs[] = {c->d_nbr, c->d_bcid, c->d_emet, c->d_fmet, c->d_egeo, c->d_bcs, c->d_Q, c->d_TH,
-                    c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop, c->d_Ck};
+                    c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop, c->d_Ck,
+                    c->d_stab};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_nbr = c->d_bcid = nullptr;
     c->d_emet = c->d_fmet = c->d_egeo = nullptr;
     c->d_bcs = nullptr;
+    c->d_stab = nullptr;
     c->d_Q = c->d_TH = c->d_G2 = c->d_T2 = c->d_TF = c->d_TU = c->d_Ck = nullptr;
     c->d_part = c->d_out = c->d_noise = c->d_drop = nullptr;
     c->E = 0;
@@ -892,7 +975,9 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + k] = cr[k];
         for (int d = 0; d < 3; ++d)
             for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + 3 + 3 * d + k] = a[d][k];
-        // a moving wall moves within its own plane
+        // a moving wall moves within its own plane; a varying wall
+        // temperature stays in the table's subcritical range on the face
+        // (it is linear, so its extremes are at the face's corners)
         for (int f = 0; f < 6; ++f) {
             const int bc = m->bc[e * 6 + f];
             if (m->nbr[e * 6 + f] >= 0 || m->bcs[bc - 1].kind == 2) continue;
@@ -900,11 +985,23 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
             const double un = uw[0] * fm[0] + uw[1] * fm[1] + uw[2] * fm[2];
             if (fabs(un) > 1e-12 * (fabs(uw[0]) + fabs(uw[1]) + fabs(uw[2])))
                 return fail(c, NSKR_E_ARG, "wall velocity must be tangential to the wall");
+            const double *tg = m->bcs[bc - 1].twall_grad;
+            if (!(std::isfinite(tg[0]) && std::isfinite(tg[1]) && std::isfinite(tg[2])))
+                return fail(c, NSKR_E_ARG, "wall temperature gradient must be finite");
+            if (tg[0] == 0.0 && tg[1] == 0.0 && tg[2] == 0.0) continue;
+            const int d = f >> 1, sd = f & 1;
+            for (int v = 0; v < 8; ++v) {
+                if (((v >> d) & 1) != sd) continue;
+                double T = m->bcs[bc - 1].twall;
+                for (int k = 0; k < 3; ++k) T += tg[k] * cr[3 * v + k];
+                if (!(T >= 0.3 && T <= 0.99))
+                    return fail(c, NSKR_E_ARG, "wall temperature must stay in [0.3, 0.99] along the wall");
+            }
         }
     }
     // wall constants
     std::vector<BcDev> bcs(m->nbcs > 0 ? m->nbcs : 1);
-    int dyn = 0;
+    int dyn = 0, var = 0;
     Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
     for (int k = 0; k < m->nbcs; ++k) {
         BcDev &b = bcs[k];
@@ -934,13 +1031,21 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
             // g = -(1/gamma) dpsi_Gamma/dc = -6 sigma cos(theta) / (gamma (rl - rv)^3) (c - rl)(c - rv)
             b.gcoef = c->p.gam > 0 ? (double)(-6 * sig * ct / ((ld)c->p.gam * d * d * d)) : 0.0;
             b.inv_tw = 1.0 / b.twall;
+            const double *tg = m->bcs[k].twall_grad;
+            b.var = tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0;
+            for (int q = 0; q < 3; ++q) b.tg[q] = tg[q];
+            b.cg = c->p.gam > 0 ? (double)(-6 * ct / (ld)c->p.gam) : 0.0;
+            b.s2g = (double)sqrtl(2 * (ld)c->p.gam);
+            if (b.var) var = 1;
         }
     }
     DeviceGuard guard(c->device);
     hipStream_t s = (hipStream_t)sv;
+    const std::vector<double> *tab = var ? &wall_table_host(vdw) : nullptr;
     free_mesh(c);
     c->E = E;
     c->dyn = dyn;
+    c->var = var;
     const int n3 = c->P * c->P * c->P, n2 = c->P * c->P;
     c->NN = (size_t)E * n3;
     c->NF = (size_t)E * 6 * n2;
@@ -958,7 +1063,8 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         (rc = dalloc(c, &c->d_TF, ts * 7 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 3 * 6 * c->NF)) ||
         (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
         (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS)) ||
-        (c->p.precision == 1 && c->p.kahan && (rc = dalloc(c, &c->d_Ck, ts * 6 * c->NN)))) {
+        (c->p.precision == 1 && c->p.kahan && (rc = dalloc(c, &c->d_Ck, ts * 6 * c->NN))) ||
+        (tab && (rc = dalloc(c, (void **)&c->d_stab, sizeof(double) * tab->size())))) {
         free_mesh(c);
         return rc;
     }
@@ -968,6 +1074,7 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
     HIPCHK(c, hipMemcpyAsync(c->d_fmet, fmet.data(), sizeof(double) * fmet.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->d_egeo, egeo.data(), sizeof(double) * egeo.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->d_bcs, bcs.data(), sizeof(BcDev) * bcs.size(), hipMemcpyHostToDevice, s));
+    if (tab) HIPCHK(c, hipMemcpyAsync(c->d_stab, tab->data(), sizeof(double) * tab->size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     c->h_emet.swap(emet);
     return NSKR_OK;

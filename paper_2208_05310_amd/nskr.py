@@ -46,7 +46,7 @@ class Params(ctypes.Structure):
 class Bc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("twall", ctypes.c_double), ("theta_deg", ctypes.c_double),
                 ("uwall", ctypes.c_double * 3), ("gamma1", ctypes.c_double), ("gamma2", ctypes.c_double),
-                ("gamma3", ctypes.c_double), ("gamma4", ctypes.c_double)]
+                ("gamma3", ctypes.c_double), ("gamma4", ctypes.c_double), ("twall_grad", ctypes.c_double * 3)]
 
 
 class Mesh(ctypes.Structure):
@@ -64,7 +64,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 3  # the struct layouts below
+ABI_VERSION = 4  # the struct layouts below
 
 
 def lib():
@@ -116,14 +116,15 @@ def lib():
 
 
 def box_mesh(n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6, side_twall=(0.0,) * 6,
-             side_theta=(90.0,) * 6, lo=(0.0, 0.0, 0.0), side_uwall=None, side_gamma=None):
+             side_theta=(90.0,) * 6, lo=(0.0, 0.0, 0.0), side_uwall=None, side_gamma=None, side_tgrad=None):
     """Structured box of n[0] x n[1] x n[2] parallelepiped elements as host
     arrays for nskr_mesh_upload: corners, neighbours (periodic wrap or -1 at
     walls), opposite-face neighbour faces, wall indices and the wall table (one
     entry per non-periodic box side, a dict of the nskr_bc fields).
     side_uwall: per side wall velocity (kinds 1, 3); side_gamma: per side
     (gamma1, gamma2, gamma3, gamma4) of Navier-slip walls (gamma3 = inf:
-    isothermal)."""
+    isothermal); side_tgrad: per side wall temperature gradient (kinds 1, 3:
+    T_wall(x) = twall + tgrad . x)."""
     nx, ny, nz = (int(v) for v in n)
     E = nx * ny * nz
     h = [length[d] / n[d] for d in range(3)]
@@ -148,7 +149,8 @@ def box_mesh(n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6, 
             g = side_gamma[f] if side_gamma is not None else (0.0, 0.0, float("inf"), 0.0)
             bcs.append(dict(kind=int(side_kind[f]), twall=float(side_twall[f]), theta=float(side_theta[f]),
                             uwall=tuple(float(v) for v in (side_uwall[f] if side_uwall is not None else (0, 0, 0))),
-                            gamma=tuple(float(v) for v in g)))
+                            gamma=tuple(float(v) for v in g),
+                            tgrad=tuple(float(v) for v in (side_tgrad[f] if side_tgrad is not None else (0, 0, 0)))))
             side_index[f] = len(bcs)
     idx = np.stack([ex, ey, ez])
     for f in range(6):
@@ -215,9 +217,10 @@ class Solver:
         return torch.float64 if self.precision == "fp64" else torch.float32
 
     def upload_box(self, n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6,
-                   side_twall=(0.0,) * 6, side_theta=(90.0,) * 6, stream=None, side_uwall=None, side_gamma=None):
+                   side_twall=(0.0,) * 6, side_theta=(90.0,) * 6, stream=None, side_uwall=None, side_gamma=None,
+                   side_tgrad=None):
         corners, nbr, nbf, bc, bcs = box_mesh(n, length, periodic, side_kind, side_twall, side_theta,
-                                              side_uwall=side_uwall, side_gamma=side_gamma)
+                                              side_uwall=side_uwall, side_gamma=side_gamma, side_tgrad=side_tgrad)
         self.upload_mesh(corners, nbr, nbf, bc, bcs, stream)
         self.box = dict(n=tuple(n), length=tuple(length), periodic=tuple(periodic))
 
@@ -227,7 +230,8 @@ class Solver:
         nbf = np.ascontiguousarray(nbf, dtype=np.int32)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
         bc_arr = (Bc * max(1, len(bcs)))(*[Bc(b["kind"], b["twall"], b["theta"], (ctypes.c_double * 3)(*b["uwall"]),
-                                                 *b["gamma"]) for b in bcs])
+                                                 *b["gamma"], (ctypes.c_double * 3)(*b.get("tgrad", (0, 0, 0))))
+                                              for b in bcs])
         m = Mesh(int(nbr.shape[0]), corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                  nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), nbf.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                  bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(bcs), bc_arr)
@@ -399,7 +403,7 @@ def solver_for(w, precision="fp64", device=0, kahan=True):
     """Solver with the mesh of a workload description (paper_2208_05310_amd.workloads)."""
     s = Solver(w.params, w.N, precision, device, kahan)
     s.upload_box(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta,
-                 side_uwall=w.side_uwall, side_gamma=w.side_gamma)
+                 side_uwall=w.side_uwall, side_gamma=w.side_gamma, side_tgrad=w.side_tgrad)
     return s
 
 

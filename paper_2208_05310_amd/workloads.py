@@ -52,6 +52,7 @@ class Workload:
     rho_l: float = 0.0
     side_uwall: tuple | None = None   # per side wall velocity (kinds 1, 3), or None (fixed walls)
     side_gamma: tuple | None = None   # per side (gamma_1, gamma_2, gamma_3, gamma_4) of Navier-slip walls
+    side_tgrad: tuple | None = None   # per side wall temperature gradient: T_wall(x) = twall + tgrad . x
 
     @property
     def nelems(self) -> int:
@@ -182,6 +183,17 @@ def c6(scale=1, gamma1=0.0) -> Workload:
                     side_gamma=(NO_GAMMA,) * 4 + ((float(gamma1), 8e-4, float("inf"), 0.0), NO_GAMMA),
                     T0=0.85, centres=((0.5, 0.25, 0.0),), radii=(0.1,),
                     width=0.0598 / 4 if scale == 1 else 0.05, steps=200, noise_seed=16, params=params)
+
+
+def c7(scale=1) -> Workload:
+    """The sessile-droplet wall box of c4 with a floor temperature rising
+    linearly along x, T_w = 0.85 + 0.1 x (0.85 .. 0.95), so the contact-angle
+    constants (sigma_vl and the Maxwell states) vary along the wall and come
+    from the wall-temperature table of Sec. 3.2 at every floor face point."""
+    w = c4(scale)
+    return w.with_(name=w.name.replace("sessile_wall", "graded_wall"),
+                   side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.0),
+                   side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.1, 0.0, 0.0), (0.0, 0.0, 0.0)), noise_seed=17)
 
 
 def serving_stream(seed=5, count=256, rate=50.0):
