@@ -95,7 +95,8 @@ def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
     import oracle
     p = oracle.make_params(**w.params)
     o = oracle.Oracle(p, oracle_box(w))
-    U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l)
+    U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l,
+                         w.cylinder_axis)
     dt = o.dt(U0)
 
     def timed(budget, cap):
@@ -223,6 +224,99 @@ def precision_study(which="c3", steps=None, restriction=True):
     return res
 
 
+def young_laplace(theta, t_end=15.0, precision="fp32_mixed", n=(50, 50, 10), chunk=2000, log=None):
+    """Static contact-angle validation (Sec. 4.4.1): the liquid pillar between
+    two walls with static angle theta, run to t_end; then the pressure jump
+    between the pillar's axis (0.5, 0.5, z) and the vapour column (0, 0.5, z),
+    each averaged over z with the quadrature weights, against the
+    Young-Laplace law sigma (1/r1 + 1/r2) with r1 = -H / (2 cos theta) and r2
+    the pillar's radius at mid-height (the radius of the circle with the
+    liquid fraction's area in the two node layers closest to z = H/2); the
+    same jump taken in those two layers only (away from the walls) is
+    reported beside it.
+    sigma_vl and the Maxwell states come from the oracle's thermodynamics."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2208_05310_amd import workloads as wl
+    from paper_2208_05310_amd.nskr import init_workload, solver_for
+
+    w = wl.c8(theta, n)
+    pr = w.params
+    s = solver_for(w, precision)
+    U = init_workload(s, w)
+    R = s.new_state()
+    dt = s.dt(U)
+    nsteps = int(round(t_end / dt))
+    rv, rl, _ = oracle.maxwell(w.T0)
+    sigma = oracle.sigma(w.T0, pr["gam"])
+    H = w.length[2]
+    # node coordinates and quadrature weights of the structured mesh
+    P = w.N + 1
+    xg, wg = np.polynomial.legendre.leggauss(P)
+    h = [w.length[d] / w.n[d] for d in range(3)]
+    E = w.nelems
+    e = np.arange(E)
+    ex, ey, ez = e % w.n[0], (e // w.n[0]) % w.n[1], e // (w.n[0] * w.n[1])
+    i, j, k = np.meshgrid(np.arange(P), np.arange(P), np.arange(P), indexing="ij")
+    i, j, k = i.transpose(2, 1, 0).reshape(-1), j.transpose(2, 1, 0).reshape(-1), k.transpose(2, 1, 0).reshape(-1)
+    X = (ex[:, None] + 0.5 * (xg[i][None, :] + 1)) * h[0]
+    Y = (ey[:, None] + 0.5 * (xg[j][None, :] + 1)) * h[1]
+    Z = (ez[:, None] + 0.5 * (xg[k][None, :] + 1)) * h[2]
+    Wz = np.broadcast_to(wg[k][None, :], X.shape)
+    Wxy = np.broadcast_to((wg[i] * wg[j])[None, :], X.shape) * (h[0] * h[1] / 4)
+    X, Y, Z, Wz, Wxy = (a.reshape(-1) for a in (X, Y, Z, Wz, Wxy))
+    near = lambda a, b: np.abs((a - b + 0.5) % 1.0 - 0.5) < 0.5 * h[0]
+    axis_l = near(X, 0.5) & near(Y, 0.5)
+    axis_v = near(X, 0.0) & near(Y, 0.5)
+    zs = np.unique(np.round(Z, 12))
+    mid = np.isin(np.round(Z, 12), zs[np.argsort(np.abs(zs - 0.5 * H))[:2]])
+    out = torch.empty((5, s.nnodes), dtype=s.dtype, device="cuda:0")
+
+    def measure():
+        s.lift2(U, out)
+        T = out[0].double().cpu().numpy()
+        rho = U[0].double().cpu().numpy()
+        p = rho * pr["R"] * T / (1 - pr["b"] * rho) - pr["a"] * rho * rho
+        pl = np.sum(p[axis_l] * Wz[axis_l]) / np.sum(Wz[axis_l])
+        pv = np.sum(p[axis_v] * Wz[axis_v]) / np.sum(Wz[axis_v])
+        # the same jump in the mid-height plane only, away from the walls
+        pl_mid = float(np.mean(p[axis_l & mid]))
+        pv_mid = float(np.mean(p[axis_v & mid]))
+        phi = np.clip((rho - rv) / (rl - rv), 0.0, 1.0)
+        area = np.sum(phi[mid] * Wxy[mid]) / 2.0  # two node layers
+        r2 = float(np.sqrt(area / np.pi))
+        ct = np.cos(np.radians(theta))
+        inv_r1 = -2.0 * ct / H
+        return {"dp": float(pl - pv), "dp_mid": pl_mid - pv_mid, "r2": r2,
+                "young_laplace": float(sigma * (inv_r1 + 1.0 / r2)), "p_liquid": float(pl), "p_vapour": float(pv)}
+
+    history = []
+    done = 0
+    t0 = time.perf_counter()
+    while done < nsteps:
+        k_ = min(chunk, nsteps - done)
+        s.rk_steps(U, R, dt, k_)
+        done += k_
+        torch.cuda.synchronize()
+        if done % (10 * chunk) == 0 or done == nsteps:
+            m = measure()
+            m["t"] = done * dt
+            history.append(m)
+            if log:
+                log(f"pillar theta={theta:g}: t={m['t']:.3f} dp={m['dp']:.5f} dp_mid={m['dp_mid']:.5f} "
+                    f"young-laplace={m['young_laplace']:.5f} "
+                    f"r2={m['r2']:.4f} ({time.perf_counter() - t0:.0f} s)")
+    sums = s.reduce(U)
+    final = history[-1]
+    return {"workload": w.name, "theta_deg": theta, "precision": precision, "dt": dt, "steps": nsteps,
+            "t_end": nsteps * dt, "sigma_vl": sigma, "H": H, "final": final,
+            "rel_dev": abs(final["dp"] - final["young_laplace"]) / abs(final["young_laplace"]),
+            "rel_dev_mid": abs(final["dp_mid"] - final["young_laplace"]) / abs(final["young_laplace"]),
+            "history": history[-6:], "wall_s": time.perf_counter() - t0, "mass": float(sums[0])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +341,11 @@ def main():
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
     ap.add_argument("--threads", type=int, default=256, choices=[256, 512],
                     help="workgroup size of the stage kernels")
+    ap.add_argument("--young-laplace", type=float, default=None, metavar="THETA",
+                    help="static contact-angle validation: liquid pillar with this angle (degrees) to --t-end, "
+                         "pressure jump against the Young-Laplace law")
+    ap.add_argument("--t-end", type=float, default=15.0)
+    ap.add_argument("--pillar-mesh", default="50,50,10", help="elements of the pillar box (x,y,z)")
     ap.add_argument("--model", type=int, default=1, choices=[1, 2],
                     help="relaxation model: 1 (Rusanov interior flux) or 2 (p_alpha pressure, HLLC flux)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -262,6 +361,12 @@ def main():
     from paper_2208_05310_amd import workloads as wl
     from paper_2208_05310_amd.nskr import init_workload, solver_for
 
+    if args.young_laplace is not None:
+        prec = "fp32_mixed" if args.precision == "fp64" and "--precision" not in sys.argv else args.precision
+        n = tuple(int(v) for v in args.pillar_mesh.split(","))
+        print(json.dumps({"young_laplace": young_laplace(args.young_laplace, args.t_end, prec, n=n, log=progress)}),
+              flush=True)
+        return
     if args.precision_study:
         print(json.dumps({"precision_study": precision_study(args.precision_study)}), flush=True)
         return

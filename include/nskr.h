@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 4  /* 4: nskr_bc.twall_grad; 3: wall velocity, gamma1..4; 2: params.model */
+#define NSKR_ABI_VERSION 5  /* 5: nskr_init.cylinder_axis; 4: nskr_bc.twall_grad; 3: wall velocity, gamma1..4 */
 
 enum {
     NSKR_OK = 0,
@@ -134,8 +134,10 @@ typedef struct {
  * droplet carrying its own velocity v_j (zero when velocities is NULL);
  * m = rho u; c = rho; rho e from eq. totalenergyalpha with the lifted grad c
  * and the kinetic energy, so that the recovered temperature is T0.
- * centres: ndrop x 3, radii: ndrop, velocities: ndrop x 3 or NULL; host
- * memory. */
+ * cylinder_axis in 0..2 makes every droplet a cylinder along that axis (the
+ * liquid pillar of Sec. 4.4.1; d_j measured in the normal plane), -1 keeps
+ * spheres.  centres: ndrop x 3, radii: ndrop, velocities: ndrop x 3 or NULL;
+ * host memory. */
 typedef struct {
     double T0;
     int ndrop;
@@ -146,6 +148,7 @@ typedef struct {
     int periodic[3];
     const double *velocities;
     double rho_v, rho_l;
+    int cylinder_axis;
 } nskr_init;
 
 /* Integrals returned by nskr_reduce (Gauss quadrature with the Jacobian, FP64

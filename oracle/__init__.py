@@ -78,7 +78,7 @@ def lib():
         "orc_dt": (d, [vp, _D]),
         "orc_rk_step": (None, [vp, _D, _D, d, d]),
         "orc_run": (None, [vp, _D, _D, d, d, i]),
-        "orc_init_droplets": (i, [vp, d, i, _D, _D, d, _D, _D, _D, d, d]),
+        "orc_init_droplets": (i, [vp, d, i, _D, _D, d, _D, _D, _D, d, d, i]),
         "orc_numflux": (None, [ctypes.POINTER(Params), _D, d, _D, d, _D, _D]),
         "orc_reduce": (None, [vp, _D, _D]),
         "orc_maxwell": (i, [d, d, d, d, _D, _D, _D]),
@@ -205,7 +205,7 @@ class Oracle:
         lib().orc_run(self._c, _ptr(U), _ptr(R), float(t), float(dt), int(nsteps))
 
     def init_droplets(self, T0, centres, radii, width, noise=None, velocities=None, rho_v=0.0,
-                      rho_l=0.0) -> np.ndarray:
+                      rho_l=0.0, cylinder_axis=-1) -> np.ndarray:
         U = self.state()
         cen = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
         rad = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
@@ -219,7 +219,8 @@ class Oracle:
             assert vel.shape[0] == rad.size
         rc = lib().orc_init_droplets(self._c, float(T0), int(rad.size), _ptr(cen), _ptr(rad),
                                      float(width), _ptr(nz) if nz is not None else None, _ptr(U),
-                                     _ptr(vel) if vel is not None else None, float(rho_v), float(rho_l))
+                                     _ptr(vel) if vel is not None else None, float(rho_v), float(rho_l),
+                                     int(cylinder_axis))
         if rc != 0:
             raise ValueError("init failed (supercritical temperature?)")
         return U

@@ -1759,10 +1759,12 @@ double orc_dt(void *vc, const double *U)
  * from it is at rest (the collision velocity field of Sec. 4.3 read as
  * u_rel/2 per droplet); m = rho u.  rho e from eq. totalenergyalpha with the
  * lifted grad c and the kinetic energy, so the recovered temperature is T0.
- * noise and vel may be NULL. */
+ * noise and vel may be NULL.  cyl_axis in 0..2 makes every droplet a
+ * cylinder along that axis (the liquid pillar of Sec. 4.4.1): d_j is then
+ * measured in the plane normal to it; -1 keeps spheres. */
 int orc_init_droplets(void *vc, double T0, int nd, const double *cen, const double *rad,
                       double width, const double *noise, double *U, const double *vel, double rv_in,
-                      double rl_in)
+                      double rl_in, int cyl_axis)
 {
     orc_ctx *c = vc;
     const orc_params *pr = &c->pr;
@@ -1779,6 +1781,7 @@ int orc_init_droplets(void *vc, double T0, int nd, const double *cen, const doub
         for (int j = 0; j < nd; ++j) {
             double d2 = 0.0;
             for (int m = 0; m < 3; ++m) {
+                if (m == cyl_axis) continue;
                 double dx = c->xyz[a * 3 + m] - cen[3 * j + m];
                 if (c->box.periodic[m]) dx -= c->box.len[m] * round(dx / c->box.len[m]);
                 d2 += dx * dx;

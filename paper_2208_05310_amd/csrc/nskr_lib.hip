@@ -524,6 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_integrals_final(const double *part, 
 struct InitArgs {
     MeshDev mesh; Basis bas; size_t NN; const double *drop; int ndrop; double width, rv, rl;
     double len[3]; int per[3]; const double *noise;
+    double wax[3];  // 1 for the axes the droplet distance spans, 0 for a cylinder's axis
 };
 
 template <int P, typename T>
@@ -549,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_init_rho(T *U, InitArgs a)
         for (int m = 0; m < 3; ++m) {
             double dx = x[m] - dj[m];
             if (a.per[m]) dx -= a.len[m] * rint(dx / a.len[m]);
-            d2 += dx * dx;
+            d2 += a.wax[m] * (dx * dx);
         }
         const double th = 1.0 + tanh((dj[3] - sqrt(d2)) / a.width);
         rho += 0.5 * (a.rl - a.rv) * th;
@@ -1114,6 +1115,7 @@ int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, vo
     Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
     ld rv, rl;
     if (!(ic->T0 > 0)) return fail(c, NSKR_E_ARG, "T0 must be positive");
+    if (ic->cylinder_axis < -1 || ic->cylinder_axis > 2) return fail(c, NSKR_E_ARG, "cylinder_axis must be -1, 0, 1 or 2");
     if (ic->rho_v > 0 && ic->rho_l > 0) {
         rv = ic->rho_v;
         rl = ic->rho_l;
@@ -1151,6 +1153,7 @@ int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, vo
     ia.rv = (double)rv;
     ia.rl = (double)rl;
     for (int k = 0; k < 3; ++k) { ia.len[k] = ic->length[k]; ia.per[k] = ic->periodic[k]; }
+    for (int k = 0; k < 3; ++k) ia.wax[k] = k == ic->cylinder_axis ? 0.0 : 1.0;
     ia.noise = c->d_noise;
     rc = dispatch(c, [&](auto impl) { return decltype(impl)::init(c, ia, ic->T0, U, s); });
     if (rc) return rc;

@@ -60,11 +60,11 @@ class Init(ctypes.Structure):
                 ("radii", ctypes.POINTER(ctypes.c_double)), ("width", ctypes.c_double),
                 ("length", ctypes.c_double * 3), ("periodic", ctypes.c_int * 3),
                 ("velocities", ctypes.POINTER(ctypes.c_double)), ("rho_v", ctypes.c_double),
-                ("rho_l", ctypes.c_double)]
+                ("rho_l", ctypes.c_double), ("cylinder_axis", ctypes.c_int)]
 
 
 _lib = None
-ABI_VERSION = 4  # the struct layouts below
+ABI_VERSION = 5  # the struct layouts below
 
 
 def lib():
@@ -258,7 +258,7 @@ class Solver:
         return ctypes.c_void_p(U.data_ptr())
 
     def init_droplets(self, U, T0, centres, radii, width, noise=None, stream=None, velocities=None, rho_v=0.0,
-                      rho_l=0.0):
+                      rho_l=0.0, cylinder_axis=-1):
         cen = np.ascontiguousarray(np.asarray(centres, dtype=np.float64).reshape(-1, 3))
         rad = np.ascontiguousarray(np.asarray(radii, dtype=np.float64).reshape(-1))
         vel = None
@@ -269,7 +269,8 @@ class Solver:
         dp = ctypes.POINTER(ctypes.c_double)
         ic = Init(float(T0), int(rad.size), cen.ctypes.data_as(dp), rad.ctypes.data_as(dp), float(width),
                   (ctypes.c_double * 3)(*self.box["length"]), (ctypes.c_int * 3)(*self.box["periodic"]),
-                  vel.ctypes.data_as(dp) if vel is not None else None, float(rho_v), float(rho_l))
+                  vel.ctypes.data_as(dp) if vel is not None else None, float(rho_v), float(rho_l),
+                  int(cylinder_axis))
         nz = None
         if noise is not None:
             nz = np.ascontiguousarray(noise, dtype=np.float64)
@@ -411,4 +412,4 @@ def init_workload(s: Solver, w, U=None):
     if U is None:
         U = s.new_state()
     return s.init_droplets(U, w.T0, w.centres, w.radii, w.width, w.noise(), velocities=w.velocities,
-                           rho_v=w.rho_v, rho_l=w.rho_l)
+                           rho_v=w.rho_v, rho_l=w.rho_l, cylinder_axis=w.cylinder_axis)

@@ -53,6 +53,7 @@ class Workload:
     side_uwall: tuple | None = None   # per side wall velocity (kinds 1, 3), or None (fixed walls)
     side_gamma: tuple | None = None   # per side (gamma_1, gamma_2, gamma_3, gamma_4) of Navier-slip walls
     side_tgrad: tuple | None = None   # per side wall temperature gradient: T_wall(x) = twall + tgrad . x
+    cylinder_axis: int = -1           # droplets are cylinders along this axis (-1: spheres)
 
     @property
     def nelems(self) -> int:
@@ -194,6 +195,24 @@ def c7(scale=1) -> Workload:
     return w.with_(name=w.name.replace("sessile_wall", "graded_wall"),
                    side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.0),
                    side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.1, 0.0, 0.0), (0.0, 0.0, 0.0)), noise_seed=17)
+
+
+def c8(theta=60.0, n=(50, 50, 10)) -> Workload:
+    """Liquid pillar between two walls (Sec. 4.4.1, static contact angles):
+    box (0,1)x(0,1)x(0,0.2), periodic in x and y, isothermal no-slip walls at
+    T=0.85 with the static angle ``theta`` at z=0 and z=0.2; a cylinder r=0.2
+    about (0.5, 0.5) spanning the gap at the Maxwell densities of T=0.85,
+    interface width L_i = 0.0598 of Table 1 (tanh width L_i/4); alpha = 100,
+    beta = 100, fluid at rest.  The paper refines the centre to h = 0.01 with
+    mortars (64000 elements); here a conforming mesh of n elements (h = 0.02
+    at the default)."""
+    params = dict(TABLE1, alpha=100.0, beta=100.0)
+    return Workload(name=f"pillar_theta{theta:g}_{n[0]}x{n[1]}x{n[2]}_N3", N=3, n=tuple(n), length=(1.0, 1.0, 0.2),
+                    periodic=(1, 1, 0), side_kind=(0, 0, 0, 0, NOSLIP_CA, NOSLIP_CA),
+                    side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.85),
+                    side_theta=(90.0, 90.0, 90.0, 90.0, float(theta), float(theta)),
+                    T0=0.85, centres=((0.5, 0.5, 0.1),), radii=(0.2,), width=0.0598 / 4, cylinder_axis=2,
+                    steps=1000, noise_seed=18, params=params)
 
 
 def serving_stream(seed=5, count=256, rate=50.0):

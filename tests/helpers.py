@@ -21,4 +21,5 @@ def box_for(w: wl.Workload) -> oracle.Box:
 
 
 def oracle_init(o: oracle.Oracle, w: wl.Workload) -> np.ndarray:
-    return o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l)
+    return o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l,
+                           w.cylinder_axis)

@@ -114,6 +114,7 @@ def small_cases():
             side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.9), side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 120.0),
             side_gamma=(wl.NO_GAMMA,) * 5 + ((0.0, 0.05, 0.02, 0.0),),
             side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.08, 0.04, 0.0), (-0.05, 0.0, 0.0))),
+        wl.c8(theta=60.0, n=(5, 5, 2)).with_(width=0.05),                # liquid pillar between walls
     ]
 
 
@@ -236,7 +237,8 @@ def test_reduce_parity(torch_cuda, w):
             assert abs(rg[k] - ro[k]) <= 1e-13 * scale[k] + 1e-300, (k, rg[k], ro[k])
 
 
-@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 4, 8, 9, 10, 11)], ids=[IDS[k] for k in (0, 5, 4, 8, 9, 10, 11)])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 4, 8, 9, 10, 11, 12)],
+                         ids=[IDS[k] for k in (0, 5, 4, 8, 9, 10, 11, 12)])
 def test_rk_steps_parity(torch_cuda, w):
     """Fixed number of RK steps with the oracle's step-0 dt on both sides
     (1/100 of it where the dynamic contact angle is on)."""

@@ -343,3 +343,25 @@ def test_collision_state_is_mirror_antisymmetric():
     assert np.allclose(U[4][mirror], U[4], rtol=1e-12, atol=1e-12)
     sums = o.reduce(U)
     assert abs(sums[1]) < 1e-12 * abs(sums[0])
+
+
+def test_cylinder_initial_state_is_uniform_along_its_axis():
+    """The liquid pillar of Sec. 4.4.1: with cylinder_axis = 2 the initial
+    density depends on x and y only, equals the same droplet's profile
+    through its centre plane, and the recovered temperature is T0."""
+    p = oracle.make_params(alpha=100.0, beta=100.0)
+    b = oracle.make_box(3, (4, 4, 3), (0.0, 0.0, 0.0), (1.0, 1.0, 0.2), (1, 1, 0), (0, 0, 0, 0, 1, 1),
+                        (0, 0, 0, 0, 0.85, 0.85), (90, 90, 90, 90, 60, 60))
+    o = oracle.Oracle(p, b)
+    U = o.init_droplets(0.85, [(0.5, 0.5, 0.1)], [0.2], 0.05, None, None, 0.0, 0.0, 2)
+    x, y, z = o.coords()
+    key = np.round(x, 12) * 1e3 + np.round(y, 12)
+    for k in np.unique(key)[::7]:
+        sel = key == k
+        assert np.ptp(U[0][sel]) <= 1e-15 * U[0][sel].max()
+    # a sphere with its centre at the node's height has the same profile
+    for i in range(0, o.nnodes, 97):
+        s = o.init_droplets(0.85, [(0.5, 0.5, z[i])], [0.2], 0.05)
+        assert abs(s[0][i] - U[0][i]) <= 1e-15
+    T = o.lift2(U)[0]
+    assert np.max(np.abs(T - 0.85)) <= 1e-12
