@@ -317,6 +317,26 @@ def young_laplace(theta, t_end=15.0, precision="fp32_mixed", n=(50, 50, 10), chu
             "history": history[-6:], "wall_s": time.perf_counter() - t0, "mass": float(sums[0])}
 
 
+def copy_bandwidth(mib=1024, reps=5):
+    """Device-to-device copy of mib MiB (far above the 256 MB Infinity Cache),
+    timed with events: bytes read + written per second, best of reps."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b) * 1e-3)
+    del src, dst
+    return 2 * n * 8 / best / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,6 +538,12 @@ def main():
                               "max_active_nodes": args.serving_max_nodes}
         except Exception as e:  # reported, never hides the main measurement
             out["serving"] = {"error": repr(e)}
+    # the same figures against a measured device copy (the attainable HBM rate)
+    cp = copy_bandwidth()
+    out["roofline"]["copy_GBs"] = cp
+    out["roofline"]["frac_of_copy"] = ach / cp
+    if "measured_GBs" in out["stage_model"]:
+        out["stage_model"]["measured_frac_of_copy"] = out["stage_model"]["measured_GBs"] / cp
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
         progress(f"cpu baseline: {out['cpu_baseline']['sample']}")
