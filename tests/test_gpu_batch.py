@@ -4,8 +4,8 @@
 * A batched instance equals, bit for bit, the same instance on the
   single-instance path (same kernels, same arithmetic, same order).
 * An instance gives bitwise the same result alone in a batch and in a mix of
-  instances with other degrees, meshes, precisions, relaxation models and
-  time steps.
+  instances with other degrees, meshes, precisions, relaxation models, wall
+  conditions and time steps.
 * Graph replays equal direct launches on every step, with eager work and
   synchronisations between the replays.
 * Admission respects the memory budget; instances stop at their own step count.
@@ -33,6 +33,14 @@ def small_mix():
         (base.with_(name="mix_periodic_4x4x4_N2_T080", N=2, T0=0.8), "fp32_mixed"),
         (base.with_(name="mix_periodic_2x3x2_N5", N=5, n=(2, 3, 2), length=(1.0, 1.5, 1.0), noise_seed=9), "fp64"),
         (base.with_(name="mix_model2_3x3x3_N3", n=(3, 3, 3), params=dict(base.params, model=2)), "fp64"),
+        # Navier-slip walls (gamma_1 pass), a moving heat-transfer lid and a
+        # graded wall temperature (table pass)
+        (wl.c4(scale=12).with_(
+            name="mix_navier_graded_4x4x2_N3", side_kind=(0, 0, 0, 0, wl.NAVIER, wl.NAVIER),
+            side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.9), side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 120.0),
+            side_uwall=((0.0, 0.0, 0.0),) * 5 + ((0.1, 0.0, 0.0),),
+            side_gamma=(wl.NO_GAMMA,) * 4 + ((1e-3, 0.05, float("inf"), 0.1), (0.0, 0.1, 0.02, 0.0)),
+            side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.08, 0.0, 0.0), (0.0, -0.05, 0.0))), "fp64"),
     ]
 
 
