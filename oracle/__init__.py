@@ -50,7 +50,8 @@ class Box(ctypes.Structure):
                 ("side_theta", ctypes.c_double * 6), ("curve_amp", ctypes.c_double),
                 ("side_uwall", (ctypes.c_double * 3) * 6), ("side_g1", ctypes.c_double * 6),
                 ("side_g2", ctypes.c_double * 6), ("side_g4", ctypes.c_double * 6),
-                ("side_g3", ctypes.c_double * 6), ("side_tgrad", (ctypes.c_double * 3) * 6)]
+                ("side_g3", ctypes.c_double * 6), ("side_tgrad", (ctypes.c_double * 3) * 6),
+                ("side_trate", ctypes.c_double * 6)]
 
 
 _lib = None
@@ -88,6 +89,7 @@ def lib():
         "orc_sigma_panels": (d, [d, d, d, d, d, i]),
         "orc_sigma_gauss15": (d, [d, d, d, d, d]),
         "orc_table_build": (None, [d, d, d, _D]),
+        "orc_set_time": (None, [vp, d]),
         "orc_table_lookup": (None, [_D, d, _D]),
         "orc_dpsiwall_dc": (d, [d, d, d, d, d]),
         "orc_psiwall": (d, [d, d, d, d, d]),
@@ -124,19 +126,19 @@ def make_box(N, n, lo=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), periodic=(1, 1, 1
              side_kind=(0,) * 6, side_twall=(0.0,) * 6, side_theta=(90.0,) * 6,
              curve_amp=0.0, side_uwall=((0.0, 0.0, 0.0),) * 6, side_g1=(0.0,) * 6,
              side_g2=(0.0,) * 6, side_g3=(float("inf"),) * 6, side_g4=(0.0,) * 6,
-             side_tgrad=((0.0, 0.0, 0.0),) * 6) -> Box:
+             side_tgrad=((0.0, 0.0, 0.0),) * 6, side_trate=(0.0,) * 6) -> Box:
     """Wall kinds per side (x-, x+, y-, y+, z-, z+): 1 no-slip isothermal with a
     static contact angle, moving with side_uwall; 2 slip adiabatic neutral;
     3 generalized Navier slip with gamma_1..gamma_4 (side_g3 infinite =
-    isothermal).  side_tgrad: wall temperature twall + tgrad . x (kinds 1, 3),
-    through the sigma/Maxwell table."""
+    isothermal).  side_tgrad, side_trate: wall temperature twall + tgrad . x
+    + trate t (kinds 1, 3), through the sigma/Maxwell table."""
     uw = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_uwall])
     tg = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_tgrad])
     d6 = lambda v: (ctypes.c_double * 6)(*[float(x) for x in v])
     return Box(int(N), (ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo),
                (ctypes.c_double * 3)(*length), (ctypes.c_int * 3)(*periodic),
                (ctypes.c_int * 6)(*side_kind), d6(side_twall), d6(side_theta), float(curve_amp),
-               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3), tg)
+               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3), tg, d6(side_trate))
 
 
 class Oracle:
@@ -175,6 +177,11 @@ class Oracle:
         nv = np.zeros((3, self.nelems * 6 * P * P))
         lib().orc_metrics(self._c, _ptr(Ja), _ptr(J), _ptr(nv))
         return Ja, J, nv.reshape(3, self.nelems, 6, P * P)
+
+    def set_time(self, t: float):
+        """Time at which rhs() evaluates (walls whose temperature changes in
+        time); run() and rk_step() set each stage's time themselves."""
+        lib().orc_set_time(self._c, float(t))
 
     def rhs(self, U: np.ndarray) -> np.ndarray:
         U = np.ascontiguousarray(U, dtype=np.float64)

@@ -94,6 +94,7 @@ typedef struct {
     double side_tgrad[6][3];  /* wall temperature gradient (kinds 1, 3): the
                                  wall temperature at x is twall + tgrad . x,
                                  evaluated through the sigma/Maxwell table  */
+    double side_trate[6];     /* wall temperature rate: + trate * t          */
 } orc_box;
 
 typedef struct {
@@ -117,6 +118,9 @@ typedef struct {
     /* wall constants per box side: Maxwell states, sigma, cos(theta) */
     double wrv[6], wrl[6], wsig[6], wcos[6];
     int wvar[6];              /* side with a varying wall temperature        */
+    double time;              /* time at which orc_rhs evaluates (walls whose
+                                 temperature changes in time); orc_rk_step
+                                 sets it to each stage's time               */
     double *stab;             /* [ORC_NTAB][3] sigma/sqrt(2 gamma), rv, rl   */
 } orc_ctx;
 
@@ -884,7 +888,7 @@ void *orc_create(const orc_params *pr, const orc_box *bx, char *err, int errlen)
         c->wsig[f] = orc_sigma(pr->R, pr->a, pr->b, bx->side_twall[f], pr->gam);
         c->wcos[f] = cos(bx->side_theta[f] * M_PI / 180.0);
         const double *tg = bx->side_tgrad[f];
-        c->wvar[f] = tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0;
+        c->wvar[f] = tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0 || bx->side_trate[f] != 0.0;
         if (c->wvar[f]) {
             /* the wall temperature must stay inside the table's subcritical
              * part on the whole side (its extremes are at the side's corners) */
@@ -1176,7 +1180,8 @@ static void face_point_x(const orc_ctx *c, int e, int f, int fp, double x[3])
 
 /* Wall temperature and the contact-angle constants at one wall face point:
  * the side's constants for a fixed wall temperature; for a varying one,
- * T_w = twall + tgrad . x and sigma, rv, rl interpolated in the table. */
+ * T_w = twall + tgrad . x + trate t and sigma, rv, rl interpolated in the
+ * table. */
 typedef struct { double Tw, rv, rl, sig, cs; } wall_pt;
 static void wall_point(const orc_ctx *c, int e, int f, int fp, wall_pt *w)
 {
@@ -1191,6 +1196,7 @@ static void wall_point(const orc_ctx *c, int e, int f, int fp, wall_pt *w)
     const double *tg = c->box.side_tgrad[sd];
     face_point_x(c, e, f, fp, x);
     w->Tw += tg[0] * x[0] + tg[1] * x[1] + tg[2] * x[2];
+    w->Tw += c->box.side_trate[sd] * c->time;
     orc_table_lookup(c->stab, w->Tw, v);
     w->sig = sqrt(2.0 * c->pr.gam) * v[0];
     w->rv = v[1]; w->rl = v[2];
@@ -1653,6 +1659,8 @@ static const double RK_C[5] = {0.0,
     2006345519317.0 / 3224310063776.0,
     2802321613138.0 / 2924317926251.0};
 
+void orc_set_time(void *vc, double t) { ((orc_ctx *)vc)->time = t; }
+
 void orc_rk_coeffs(double *A, double *B, double *C)
 {
     for (int s = 0; s < 5; ++s) { A[s] = RK_A[s]; B[s] = RK_B[s]; C[s] = RK_C[s]; }
@@ -1665,8 +1673,8 @@ void orc_rk_step(void *vc, double *U, double *R, double t, double dt)
     orc_ctx *c = vc;
     size_t n = (size_t)6 * c->E * c->n3;
     double *Ut = malloc(sizeof(double) * n);
-    (void)t;
     for (int s = 0; s < 5; ++s) {
+        c->time = t + RK_C[s] * dt;  /* stage time of the 2N scheme */
         orc_rhs(c, U, Ut);
         for (size_t a = 0; a < n; ++a) {
             R[a] = (s == 0) ? dt * Ut[a] : RK_A[s] * R[a] + dt * Ut[a];

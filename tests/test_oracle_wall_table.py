@@ -119,3 +119,82 @@ def test_wall_temperature_out_of_range_is_rejected():
         oracle.Oracle(p, box((0.2, 0.0, 0.0), twall=0.85))   # reaches 1.05 at x = 1
     with pytest.raises(ValueError):
         oracle.Oracle(p, box((-0.6, 0.0, 0.0), twall=0.85))  # reaches 0.25
+
+
+def box_t(twall=0.85, tgrad=(1e-9, 0.0, 0.0), trate=0.0):
+    return oracle.make_box(3, (3, 3, 2), (0.0, 0.0, 0.0), (1.0, 1.0, 0.5), (1, 1, 0), (0, 0, 0, 0, 1, 2),
+                           (0, 0, 0, 0, twall, 0), (90, 90, 90, 90, 60, 90),
+                           side_tgrad=((0, 0, 0),) * 4 + (tgrad, (0, 0, 0)),
+                           side_trate=(0.0,) * 4 + (trate, 0.0))
+
+
+def droplet_state(o):
+    U = o.init_droplets(0.85, [[0.5, 0.5, 0.0]], [0.2], 0.05)
+    x, y, z = o.coords()
+    U[5] = U[0] + 0.01 * np.sin(2 * np.pi * (x + y))
+    return U
+
+
+def test_wall_temperature_rate_is_a_shift_in_time():
+    """T_w = twall + r t evaluated at time t equals the wall at twall + r t
+    and time 0 (both through the table)."""
+    p = oracle.make_params()
+    r, t = 0.4, 0.2
+    timed = oracle.Oracle(p, box_t(trate=r))
+    shifted = oracle.Oracle(p, box_t(twall=0.85 + r * t))
+    U = droplet_state(timed)
+    timed.set_time(t)
+    a, b = timed.rhs(U), shifted.rhs(U)
+    scale = np.max(np.abs(b), axis=1)
+    assert np.all(np.max(np.abs(a - b), axis=1) <= 1e-13 * scale)
+    timed.set_time(0.0)
+    assert np.max(np.abs(timed.rhs(U)[5] - b[5])) > 1e-6 * scale[5]
+
+
+def test_rk_stages_use_their_own_times():
+    """One step of run() from t0 equals the 2N scheme evaluated stage by stage
+    at t0 + c_s dt with rhs() (and differs from evaluating every stage at t0),
+    on a wall whose temperature changes quickly in time."""
+    p = oracle.make_params()
+    o = oracle.Oracle(p, box_t(trate=50.0))
+    U0 = droplet_state(o)
+    t0, dt = 0.001, 2e-5
+    A, B, C = (np.zeros(5) for _ in range(3))
+    oracle.lib().orc_rk_coeffs(oracle._ptr(A), oracle._ptr(B), oracle._ptr(C))
+    assert np.all(np.diff(C) > 0) and C[0] == 0.0 and 0.9 < C[4] < 1.0
+
+    def manual(times):
+        U, R = U0.copy(), np.zeros_like(U0)
+        for s in range(5):
+            o.set_time(times[s])
+            Ut = o.rhs(U)
+            R = dt * Ut if s == 0 else A[s] * R + dt * Ut
+            U = U + B[s] * R
+        return U
+
+    U, R = U0.copy(), np.zeros_like(U0)
+    o.run(U, R, t0, dt, 1)
+    ref = manual([t0 + C[s] * dt for s in range(5)])
+    scale = np.max(np.abs(U0), axis=1)
+    assert np.all(np.max(np.abs(U - ref), axis=1) <= 1e-14 * scale)
+    wrong = manual([t0] * 5)
+    assert np.max(np.abs(U[5] - wrong[5])) > 1e-12 * scale[5]
+
+
+def test_isothermal_wall_heating_with_the_fluid():
+    """x-walls at T_w = 0.85 + r t, fluid at rest with uniform T = 0.85 + r t1:
+    the lifted grad T vanishes at t = t1 and not at other times."""
+    p = oracle.make_params()
+    r, t1 = 0.3, 0.1
+    b = oracle.make_box(3, (3, 3, 2), (0.0, 0.0, 0.0), (1.0, 1.0, 0.5), (0, 1, 1), (1, 1, 0, 0, 0, 0),
+                        (0.85, 0.85, 0, 0, 0, 0), (90.0,) * 6, side_trate=(r, r, 0, 0, 0, 0))
+    o = oracle.Oracle(p, b)
+    rho = 0.3
+    U = np.zeros((6, o.nnodes))
+    U[0] = rho
+    U[4] = rho * (8.0 / 3.0 * 5.0 * (0.85 + r * t1) - 3.0 * rho)
+    U[5] = rho
+    o.set_time(t1)
+    assert np.max(np.abs(o.lift2(U)[1:4])) <= 1e-12
+    o.set_time(0.0)
+    assert np.max(np.abs(o.lift2(U)[1])) > 1e-3
