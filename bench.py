@@ -83,7 +83,8 @@ def oracle_box(w):
     return oracle.make_box(w.N, w.n, (0.0, 0.0, 0.0), w.length, w.periodic, w.side_kind, w.side_twall,
                            w.side_theta, w.curve_amp, side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
                            side_g1=[v[0] for v in g], side_g2=[v[1] for v in g], side_g3=[v[2] for v in g],
-                           side_g4=[v[3] for v in g], side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6)
+                           side_g4=[v[3] for v in g], side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6,
+                           side_trate=w.side_trate or (0.0,) * 6)
 
 
 def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 5  /* 5: nskr_init.cylinder_axis; 4: nskr_bc.twall_grad; 3: wall velocity, gamma1..4 */
+#define NSKR_ABI_VERSION 6  /* 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
 
 enum {
     NSKR_OK = 0,
@@ -91,12 +91,16 @@ typedef struct {
  *     twall.
  * gamma1..gamma4 >= 0 and are read for kind 3 only; uwall must be tangential
  * to every face of the wall (NSKR_E_ARG otherwise) and is read for kinds 1
- * and 3.  twall_grad (kinds 1, 3): the wall temperature at a wall point x is
- * twall + twall_grad . x; when it is non-zero, sigma_vl and the Maxwell
- * states at that temperature come from a table of Sec. 3.2 (10000
- * equidistant temperatures on [0.3, 1], sigma by a 15-point Gauss rule,
- * linear interpolation) at every wall face point and stage, and the wall
- * temperature must stay in [0.3, 0.99] on the whole wall (NSKR_E_ARG). */
+ * and 3.  twall_grad, twall_rate (kinds 1, 3): the wall temperature at a
+ * wall point x and time t is twall + twall_grad . x + twall_rate t; when
+ * either is non-zero, sigma_vl and the Maxwell states at that temperature
+ * come from a table of Sec. 3.2 (10000 equidistant temperatures on [0.3, 1],
+ * sigma by a 15-point Gauss rule, linear interpolation) at every wall face
+ * point and stage, and the wall temperature must stay in [0.3, 0.99] on the
+ * whole wall: at mesh upload for t = 0, and over the time span of every
+ * call that evaluates the operator (NSKR_E_ARG otherwise).  Walls whose
+ * temperature changes in time are not accepted into batches
+ * (NSKR_E_UNSUPPORTED from nskr_batch_admit). */
 typedef struct {
     int kind;
     double twall;
@@ -104,6 +108,7 @@ typedef struct {
     double uwall[3];
     double gamma1, gamma2, gamma3, gamma4;
     double twall_grad[3];
+    double twall_rate;
 } nskr_bc;
 
 /* Hexahedral mesh (Sec. 3.1).  Every element must be a parallelepiped (affine
@@ -207,6 +212,14 @@ int nskr_device_bytes(const nskr_ctx *ctx, size_t *bytes);
  * width <= 0, T0 not below the critical temperature when the Maxwell
  * densities are needed, densities outside (0, 1/b) or rho_l <= rho_v). */
 int nskr_init_droplets(nskr_ctx *ctx, const nskr_init *ic, const double *noise, void *U, nskr_stream s);
+
+/* Simulation time of the context: the time at which nskr_rhs, nskr_lift1
+ * and nskr_lift2 evaluate walls whose temperature changes in time
+ * (nskr_bc.twall_rate); nskr_rk_steps evaluates stage s of step n at t + n dt
+ * + c_s dt (the stage times of the RK scheme) and advances t by nsteps dt.
+ * Starts at 0.  Errors: NSKR_E_ARG (null ctx or output, non-finite t). */
+int nskr_set_time(nskr_ctx *ctx, double t);
+int nskr_get_time(const nskr_ctx *ctx, double *t);
 
 /* U_t = L(U), the semi-discrete operator (Sec. 3.1).  Asynchronous.
  * Errors: NSKR_E_STATE, NSKR_E_ARG (null or aliasing buffers), NSKR_E_HIP. */

@@ -58,8 +58,9 @@ struct BcDev {
     double g1, g2, g3, g4;  // gamma_1..gamma_4 (kind 3; zero otherwise)
     double g1_gam;    // gamma_1 / gamma: the dynamic part of g, times div u
     double inv_tw;    // 1 / twall
-    int var;          // wall temperature twall + tg . x (table lookup per face point)
+    int var;          // wall temperature twall + tg . x + rate t (table lookup per face point)
     double tg[3];
+    double rate;
     double cg;        // -6 cos(theta) / gamma: gcoef = cg sigma / (rl - rv)^3
     double s2g;       // sqrt(2 gamma): sigma = s2g * (tabulated sigma / sqrt(2 gamma))
 };
@@ -88,7 +89,7 @@ struct MeshDev {
     const BcDev *bcs;
     int dyn;             // some Navier-slip wall has gamma_1 != 0 (g needs div u at the wall)
     const double *stab;  // [kTabN][3] wall-temperature table (walls with a temperature gradient)
-    int var;             // some wall has a temperature gradient
+    int var;             // some wall has a temperature gradient or rate
 };
 
 template <int P, int BS = kBlock> struct Tile {
@@ -268,6 +269,7 @@ template <typename T> struct Launch {
     int tb, tw;      // conserved-trace buffer read by this stage, written for the next
     int full;        // host side: launch the k_lift1 variant that also writes Q and TH
     double A, B;     // RK coefficients of this stage
+    double t;        // time of this stage (walls whose temperature changes in time)
 };
 
 // A pointer read from ordinary device memory is generic to the compiler,
@@ -410,13 +412,13 @@ template <typename T> __device__ __forceinline__ void wall_primitives(const Mesh
     }
 }
 
-// Wall temperature twall + tg . x at a wall face point (x from the element's
-// corner and edge vectors at the face point's reference coordinates: +-1
-// along the face's axis, the Gauss nodes of its two tangential indices along
-// the others).
+// Wall temperature twall + tg . x + rate t at a wall face point (x from the
+// element's corner and edge vectors at the face point's reference
+// coordinates: +-1 along the face's axis, the Gauss nodes of its two
+// tangential indices along the others).
 template <int P>
 __device__ __forceinline__ double wall_temperature(const MeshDev &m, const Basis &bas, const BcDev &bc, int el, int f,
-                                                   int fp)
+                                                   int fp, double t)
 {
     const int d = f >> 1;
     const double xn = (f & 1) ? 1.0 : -1.0, xa = bas.x[fp % P], xb = bas.x[fp / P];
@@ -426,7 +428,7 @@ __device__ __forceinline__ double wall_temperature(const MeshDev &m, const Basis
 #pragma unroll
     for (int k = 0; k < 3; ++k)
         Tw += bc.tg[k] * (g[k] + 0.5 * ((r0 + 1.0) * g[3 + k] + (r1 + 1.0) * g[6 + k] + (r2 + 1.0) * g[9 + k]));
-    return Tw;
+    return Tw + bc.rate * t;
 }
 
 // Wall temperature and contact-angle constants at one wall face point: the
@@ -436,11 +438,12 @@ struct WallPt {
     double Tw, rv, rl, gcoef;
 };
 template <int P>
-__device__ __forceinline__ WallPt wall_point(const MeshDev &m, const Basis &bas, const BcDev &bc, int el, int f, int fp)
+__device__ __forceinline__ WallPt wall_point(const MeshDev &m, const Basis &bas, const BcDev &bc, int el, int f, int fp,
+                                             double t)
 {
     WallPt w{bc.twall, bc.rv, bc.rl, bc.gcoef};
     if (!bc.var) return w;
-    const double Tw = wall_temperature<P>(m, bas, bc, el, f, fp);
+    const double Tw = wall_temperature<P>(m, bas, bc, el, f, fp, t);
     const double sx = (Tw - kTabT0) / ((kTabT1 - kTabT0) / (kTabN - 1));
     int k = (int)floor(sx);
     k = k < 0 ? 0 : (k > kTabN - 2 ? kTabN - 2 : k);
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             if (a.mesh.nbr[el * 6 + f] >= 0) continue;  // interior: no wall-table entry
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
             if (!bc.var) continue;
-            const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp);
+            const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp, L.t);
             const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
             const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
             if (bc.iso) sTs[slot] = T(wp.Tw);

@@ -36,7 +36,10 @@ struct nskr_ctx {
     BcDev *d_bcs = nullptr;
     int dyn = 0;                 // a Navier-slip wall with gamma_1 != 0
     double *d_stab = nullptr;    // wall-temperature table (walls with a temperature gradient)
-    int var = 0;                 // some wall has a temperature gradient
+    int var = 0;                 // some wall has a temperature gradient or rate
+    int trate = 0;               // some wall's temperature changes in time
+    double time = 0.0;           // simulation time (walls whose temperature changes in time)
+    std::vector<std::array<double, 3>> wall_trange;  // per wall: min, max of twall + grad . x over it; rate
     std::vector<double> h_emet;  // host copy of the element metrics (weights for reductions)
     // scratch (element type of the precision)
     void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
@@ -354,6 +357,9 @@ static const std::vector<double> &wall_table_host(const Vdw &v)
 // 5-stage 2N-storage RK4(3)5, Carpenter & Kennedy (1994).
 static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
                                -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+// stage times c_s of the same scheme (stage s is evaluated at t + c_s dt)
+static const double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                               2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                                1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
@@ -617,6 +623,7 @@ template <int P, typename T, int BS> struct Impl {
         memset(&L, 0, sizeof(L));
         L.one = I;
         L.bas = c->bas;
+        L.t = c->time;
         return L;
     }
     // every stage kernel's static LDS fits the device's per-block limit
@@ -704,6 +711,7 @@ template <int P, typename T, int BS> struct Impl {
         Launch<T> L = launch(c, inst(c, U, R, nullptr, dt));
         zero_comp(c, s);
         prolong(c, L, s);
+        const double t0 = c->time;
         for (int n = 0; n < nsteps; ++n)
             for (int st = 0; st < 5; ++st) {
                 L.mode = 1;
@@ -712,10 +720,12 @@ template <int P, typename T, int BS> struct Impl {
                 L.B = kRkB[st];
                 L.tb = kTraceBuf[st];
                 L.tw = kTraceBuf[st + 1];
+                L.t = (t0 + n * dt) + kRkC[st] * dt;
                 lift1(c, L, s);
                 lift2(c, L, s);
                 update(c, L, s);
             }
+        c->time = t0 + nsteps * dt;
         HIPCHK(c, hipGetLastError());
         return NSKR_OK;
     }
@@ -932,6 +942,9 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
                     return fail(c, NSKR_E_ARG, "wall velocity must be finite");
             }
         }
+    // per wall: extremes of twall + grad . x over its faces, and the rate
+    std::vector<std::array<double, 3>> trange(m->nbcs > 0 ? m->nbcs : 1,
+                                              std::array<double, 3>{INFINITY, -INFINITY, 0.0});
     // per-element affine metrics
     std::vector<double> emet((size_t)E * 10), fmet((size_t)E * 24), egeo((size_t)E * 12);
     for (int e = 0; e < E; ++e) {
@@ -987,22 +1000,27 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
             if (fabs(un) > 1e-12 * (fabs(uw[0]) + fabs(uw[1]) + fabs(uw[2])))
                 return fail(c, NSKR_E_ARG, "wall velocity must be tangential to the wall");
             const double *tg = m->bcs[bc - 1].twall_grad;
-            if (!(std::isfinite(tg[0]) && std::isfinite(tg[1]) && std::isfinite(tg[2])))
-                return fail(c, NSKR_E_ARG, "wall temperature gradient must be finite");
-            if (tg[0] == 0.0 && tg[1] == 0.0 && tg[2] == 0.0) continue;
+            const double rate = m->bcs[bc - 1].twall_rate;
+            if (!(std::isfinite(tg[0]) && std::isfinite(tg[1]) && std::isfinite(tg[2]) && std::isfinite(rate)))
+                return fail(c, NSKR_E_ARG, "wall temperature gradient and rate must be finite");
+            if (tg[0] == 0.0 && tg[1] == 0.0 && tg[2] == 0.0 && rate == 0.0) continue;
             const int d = f >> 1, sd = f & 1;
+            auto &tr = trange[bc - 1];
             for (int v = 0; v < 8; ++v) {
                 if (((v >> d) & 1) != sd) continue;
                 double T = m->bcs[bc - 1].twall;
                 for (int k = 0; k < 3; ++k) T += tg[k] * cr[3 * v + k];
                 if (!(T >= 0.3 && T <= 0.99))
                     return fail(c, NSKR_E_ARG, "wall temperature must stay in [0.3, 0.99] along the wall");
+                tr[0] = T < tr[0] ? T : tr[0];
+                tr[1] = T > tr[1] ? T : tr[1];
+                tr[2] = rate;
             }
         }
     }
     // wall constants
     std::vector<BcDev> bcs(m->nbcs > 0 ? m->nbcs : 1);
-    int dyn = 0, var = 0;
+    int dyn = 0, var = 0, trate = 0;
     Vdw vdw{(ld)c->p.R, (ld)c->p.a, (ld)c->p.b};
     for (int k = 0; k < m->nbcs; ++k) {
         BcDev &b = bcs[k];
@@ -1037,6 +1055,8 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
             for (int q = 0; q < 3; ++q) b.tg[q] = tg[q];
             b.cg = c->p.gam > 0 ? (double)(-6 * ct / (ld)c->p.gam) : 0.0;
             b.s2g = (double)sqrtl(2 * (ld)c->p.gam);
+            b.rate = m->bcs[k].twall_rate;
+            if (b.rate != 0.0) { b.var = 1; trate = 1; }
             if (b.var) var = 1;
         }
     }
@@ -1047,6 +1067,8 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
     c->E = E;
     c->dyn = dyn;
     c->var = var;
+    c->trate = trate;
+    c->wall_trange.swap(trange);
     const int n3 = c->P * c->P * c->P, n2 = c->P * c->P;
     c->NN = (size_t)E * n3;
     c->NF = (size_t)E * 6 * n2;
@@ -1161,11 +1183,40 @@ int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, vo
     return NSKR_OK;
 }
 
+// walls whose temperature changes in time stay inside the table's range over
+// [t0, t1] (linear in t, so the ends suffice)
+static int check_wall_time(nskr_ctx *c, double t0, double t1)
+{
+    if (!c->trate) return NSKR_OK;
+    for (const auto &r : c->wall_trange) {
+        if (r[2] == 0.0) continue;
+        for (double t : {t0, t1})
+            if (!(r[0] + r[2] * t >= 0.3 && r[1] + r[2] * t <= 0.99))
+                return fail(c, NSKR_E_ARG, "wall temperature leaves [0.3, 0.99] during this call");
+    }
+    return NSKR_OK;
+}
+
+int nskr_set_time(nskr_ctx *c, double t)
+{
+    if (!c || !isfinite(t)) return NSKR_E_ARG;
+    c->time = t;
+    return NSKR_OK;
+}
+
+int nskr_get_time(const nskr_ctx *c, double *t)
+{
+    if (!c || !t) return NSKR_E_ARG;
+    *t = c->time;
+    return NSKR_OK;
+}
+
 int nskr_rhs(nskr_ctx *c, const void *U, void *Ut, nskr_stream sv)
 {
     int rc = ready(c);
     if (rc) return rc;
     if (!U || !Ut || U == Ut) return fail(c, NSKR_E_ARG, "null or aliasing state buffers");
+    if ((rc = check_wall_time(c, c->time, c->time))) return rc;
     DeviceGuard guard(c->device);
     return dispatch(c, [&](auto impl) { return decltype(impl)::rhs(c, U, Ut, (hipStream_t)sv); });
 }
@@ -1175,6 +1226,7 @@ int nskr_lift1(nskr_ctx *c, const void *U, void *q, nskr_stream sv)
     int rc = ready(c);
     if (rc) return rc;
     if (!U || !q || U == q) return fail(c, NSKR_E_ARG, "null or aliasing buffers");
+    if ((rc = check_wall_time(c, c->time, c->time))) return rc;
     DeviceGuard guard(c->device);
     return dispatch(c, [&](auto impl) { return decltype(impl)::lift1_out(c, U, q, (hipStream_t)sv); });
 }
@@ -1184,6 +1236,7 @@ int nskr_lift2(nskr_ctx *c, const void *U, void *o, nskr_stream sv)
     int rc = ready(c);
     if (rc) return rc;
     if (!U || !o || U == o) return fail(c, NSKR_E_ARG, "null or aliasing buffers");
+    if ((rc = check_wall_time(c, c->time, c->time))) return rc;
     DeviceGuard guard(c->device);
     return dispatch(c, [&](auto impl) { return decltype(impl)::lift2_out(c, U, o, (hipStream_t)sv); });
 }
@@ -1212,6 +1265,7 @@ int nskr_rk_steps(nskr_ctx *c, void *U, void *R, double dt, int nsteps, nskr_str
     if (rc) return rc;
     if (!U || !R || U == R) return fail(c, NSKR_E_ARG, "null or aliasing state buffers");
     if (!(dt > 0) || !isfinite(dt) || nsteps < 0) return fail(c, NSKR_E_ARG, "dt must be positive and finite");
+    if ((rc = check_wall_time(c, c->time, c->time + nsteps * dt))) return rc;
     DeviceGuard guard(c->device);
     return dispatch(c, [&](auto impl) { return decltype(impl)::rk(c, U, R, dt, nsteps, (hipStream_t)sv); });
 }
@@ -1480,6 +1534,7 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     if (!(dt > 0) || !isfinite(dt) || nsteps < 1) return bfail(b, NSKR_E_ARG, "dt must be positive, nsteps >= 1");
     for (const auto &sl : b->slots)
         if (sl.state != 0 && sl.c == c) return bfail(b, NSKR_E_ARG, "instance already admitted");
+    if (c->trate) return bfail(b, NSKR_E_UNSUPPORTED, "walls whose temperature changes in time run unbatched");
     const size_t ts = c->p.precision == 0 ? sizeof(double) : sizeof(float);
     const size_t need = c->bytes + 2 * 6 * c->NN * ts;
     if (b->used + need > b->budget) return bfail(b, NSKR_E_NOMEM, "no room in the memory budget now");

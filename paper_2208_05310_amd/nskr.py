@@ -25,7 +25,7 @@ EXPORTS = ["nskr_version", "nskr_create", "nskr_destroy", "nskr_mesh_upload", "n
            "nskr_rk_steps", "nskr_reduce", "nskr_set_profiling", "nskr_profile", "nskr_set_block",
            "nskr_get_block", "nskr_last_error", "nskr_batch_create", "nskr_batch_destroy",
            "nskr_batch_set_graph", "nskr_batch_admit", "nskr_batch_step", "nskr_batch_poll",
-           "nskr_batch_retire", "nskr_batch_info", "nskr_batch_last_error"]
+           "nskr_batch_retire", "nskr_batch_info", "nskr_batch_last_error", "nskr_set_time", "nskr_get_time"]
 KERNEL_KINDS = ["prolong", "lift1", "lift2", "update", "other"]
 
 
@@ -46,7 +46,8 @@ class Params(ctypes.Structure):
 class Bc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("twall", ctypes.c_double), ("theta_deg", ctypes.c_double),
                 ("uwall", ctypes.c_double * 3), ("gamma1", ctypes.c_double), ("gamma2", ctypes.c_double),
-                ("gamma3", ctypes.c_double), ("gamma4", ctypes.c_double), ("twall_grad", ctypes.c_double * 3)]
+                ("gamma3", ctypes.c_double), ("gamma4", ctypes.c_double), ("twall_grad", ctypes.c_double * 3),
+                ("twall_rate", ctypes.c_double)]
 
 
 class Mesh(ctypes.Structure):
@@ -64,7 +65,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 5  # the struct layouts below
+ABI_VERSION = 6  # the struct layouts below
 
 
 def lib():
@@ -95,6 +96,8 @@ def lib():
         "nskr_set_block": (i, [vp, i]),
         "nskr_get_block": (i, [vp, ctypes.POINTER(i)]),
         "nskr_last_error": (ctypes.c_char_p, [vp]),
+        "nskr_set_time": (i, [vp, d]),
+        "nskr_get_time": (i, [vp, ctypes.POINTER(d)]),
         "nskr_batch_create": (i, [i, ctypes.c_size_t, ctypes.POINTER(vp)]),
         "nskr_batch_destroy": (i, [vp]),
         "nskr_batch_set_graph": (i, [vp, i]),
@@ -116,15 +119,16 @@ def lib():
 
 
 def box_mesh(n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6, side_twall=(0.0,) * 6,
-             side_theta=(90.0,) * 6, lo=(0.0, 0.0, 0.0), side_uwall=None, side_gamma=None, side_tgrad=None):
+             side_theta=(90.0,) * 6, lo=(0.0, 0.0, 0.0), side_uwall=None, side_gamma=None, side_tgrad=None,
+             side_trate=None):
     """Structured box of n[0] x n[1] x n[2] parallelepiped elements as host
     arrays for nskr_mesh_upload: corners, neighbours (periodic wrap or -1 at
     walls), opposite-face neighbour faces, wall indices and the wall table (one
     entry per non-periodic box side, a dict of the nskr_bc fields).
     side_uwall: per side wall velocity (kinds 1, 3); side_gamma: per side
     (gamma1, gamma2, gamma3, gamma4) of Navier-slip walls (gamma3 = inf:
-    isothermal); side_tgrad: per side wall temperature gradient (kinds 1, 3:
-    T_wall(x) = twall + tgrad . x)."""
+    isothermal); side_tgrad, side_trate: per side wall temperature gradient
+    and rate (kinds 1, 3: T_wall(x, t) = twall + tgrad . x + trate t)."""
     nx, ny, nz = (int(v) for v in n)
     E = nx * ny * nz
     h = [length[d] / n[d] for d in range(3)]
@@ -150,7 +154,8 @@ def box_mesh(n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6, 
             bcs.append(dict(kind=int(side_kind[f]), twall=float(side_twall[f]), theta=float(side_theta[f]),
                             uwall=tuple(float(v) for v in (side_uwall[f] if side_uwall is not None else (0, 0, 0))),
                             gamma=tuple(float(v) for v in g),
-                            tgrad=tuple(float(v) for v in (side_tgrad[f] if side_tgrad is not None else (0, 0, 0)))))
+                            tgrad=tuple(float(v) for v in (side_tgrad[f] if side_tgrad is not None else (0, 0, 0))),
+                            trate=float(side_trate[f]) if side_trate is not None else 0.0))
             side_index[f] = len(bcs)
     idx = np.stack([ex, ey, ez])
     for f in range(6):
@@ -218,9 +223,10 @@ class Solver:
 
     def upload_box(self, n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6,
                    side_twall=(0.0,) * 6, side_theta=(90.0,) * 6, stream=None, side_uwall=None, side_gamma=None,
-                   side_tgrad=None):
+                   side_tgrad=None, side_trate=None):
         corners, nbr, nbf, bc, bcs = box_mesh(n, length, periodic, side_kind, side_twall, side_theta,
-                                              side_uwall=side_uwall, side_gamma=side_gamma, side_tgrad=side_tgrad)
+                                              side_uwall=side_uwall, side_gamma=side_gamma, side_tgrad=side_tgrad,
+                                              side_trate=side_trate)
         self.upload_mesh(corners, nbr, nbf, bc, bcs, stream)
         self.box = dict(n=tuple(n), length=tuple(length), periodic=tuple(periodic))
 
@@ -230,7 +236,8 @@ class Solver:
         nbf = np.ascontiguousarray(nbf, dtype=np.int32)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
         bc_arr = (Bc * max(1, len(bcs)))(*[Bc(b["kind"], b["twall"], b["theta"], (ctypes.c_double * 3)(*b["uwall"]),
-                                                 *b["gamma"], (ctypes.c_double * 3)(*b.get("tgrad", (0, 0, 0))))
+                                                 *b["gamma"], (ctypes.c_double * 3)(*b.get("tgrad", (0, 0, 0))),
+                                                 b.get("trate", 0.0))
                                               for b in bcs])
         m = Mesh(int(nbr.shape[0]), corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                  nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), nbf.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
@@ -240,6 +247,16 @@ class Solver:
         self._check(self.L.nskr_state_size(self._h, ctypes.byref(n)))
         self.nnodes = n.value // 6
         self.nelems = int(nbr.shape[0])
+
+    def set_time(self, t):
+        """Simulation time for walls whose temperature changes in time
+        (rk_steps advances it by nsteps dt)."""
+        self._check(self.L.nskr_set_time(self._h, float(t)))
+
+    def get_time(self):
+        t = ctypes.c_double()
+        self._check(self.L.nskr_get_time(self._h, ctypes.byref(t)))
+        return t.value
 
     def device_bytes(self):
         b = ctypes.c_size_t()
@@ -404,7 +421,7 @@ def solver_for(w, precision="fp64", device=0, kahan=True):
     """Solver with the mesh of a workload description (paper_2208_05310_amd.workloads)."""
     s = Solver(w.params, w.N, precision, device, kahan)
     s.upload_box(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta,
-                 side_uwall=w.side_uwall, side_gamma=w.side_gamma, side_tgrad=w.side_tgrad)
+                 side_uwall=w.side_uwall, side_gamma=w.side_gamma, side_tgrad=w.side_tgrad, side_trate=w.side_trate)
     return s
 
 

@@ -53,6 +53,7 @@ class Workload:
     side_uwall: tuple | None = None   # per side wall velocity (kinds 1, 3), or None (fixed walls)
     side_gamma: tuple | None = None   # per side (gamma_1, gamma_2, gamma_3, gamma_4) of Navier-slip walls
     side_tgrad: tuple | None = None   # per side wall temperature gradient: T_wall(x) = twall + tgrad . x
+    side_trate: tuple | None = None   # per side wall temperature rate: + trate * t
     cylinder_axis: int = -1           # droplets are cylinders along this axis (-1: spheres)
 
     @property

@@ -17,7 +17,7 @@ def box_for(w: wl.Workload) -> oracle.Box:
                            side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
                            side_g1=[v[0] for v in g], side_g2=[v[1] for v in g],
                            side_g3=[v[2] for v in g], side_g4=[v[3] for v in g],
-                           side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6)
+                           side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6, side_trate=w.side_trate or (0.0,) * 6)
 
 
 def oracle_init(o: oracle.Oracle, w: wl.Workload) -> np.ndarray:
