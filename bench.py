@@ -68,7 +68,7 @@ def measured_traffic(workload, precision, kernel):
     return {"read": e["read_bytes"], "written": e["written_bytes"], "total": e["read_bytes"] + e["written_bytes"]}
 
 
-def survey_bytes_model(N, word):
+def three_phase_bytes_model(N, word):
     """B_floor (state and register read+write) and B_3phase of the BR1
     three-phase byte model, per node-stage."""
     F = 6.0 / (N + 1)
@@ -373,7 +373,7 @@ def main():
                     help="run one device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library drives a single GPU",
               file=sys.stderr)
         sys.exit(2)
 
@@ -467,7 +467,7 @@ def main():
     nn, value, kern, word = r["nnodes"], r["value"], r["kern"], r["word"]
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     ach = kern[dom]["achieved_GBs"]
-    floor_b, b3 = survey_bytes_model(w.N, word)
+    floor_b, b3 = three_phase_bytes_model(w.N, word)
     stage_b = (stage_words_per_node(w.N) + (12 if args.precision == "fp32_mixed" else 0)) * word
     out = {
         "metric": METRIC,

@@ -47,7 +47,7 @@ enum {
     NSKR_E_NOMEM = 3,        /* device allocation failed                    */
     NSKR_E_HIP = 4,          /* a HIP runtime call failed                   */
     NSKR_E_NONFINITE = 5,    /* non-finite or out-of-range state detected   */
-    NSKR_E_UNSUPPORTED = 6   /* valid request this build does not implement */
+    NSKR_E_UNSUPPORTED = 6   /* valid request the library does not implement */
 };
 
 typedef struct nskr_ctx nskr_ctx;
