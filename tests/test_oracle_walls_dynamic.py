@@ -187,3 +187,45 @@ def test_dynamic_angle_wall_traction():
     # the sign and the factor gamma_1 matter
     o2 = oracle.Oracle(p, box(4, (8, 1, 2), (1.0, 1.0, H), {"kind": 3, "g1": 0.0, "twall": T0}, {"kind": 2}))
     assert abs(np.dot(W, o2.rhs(U)[1])) <= 1e-3 * abs(exact)
+
+
+def test_conduction_between_isothermal_walls_is_steady():
+    """Fluid at rest, uniform density, temperature linear between two
+    isothermal no-slip walls at Ta (z = 0) and Tb (z = H): the lifted
+    gradient is exact and the walls' conductive flux k grad T . n balances
+    the bulk, so the energy equation is steady at every node."""
+    kappa, H = 1.0 / 150.0, 0.5
+    p = oracle.make_params(kappa=kappa)
+    Ta, Tb, rho = 0.9, 0.95, 0.3
+    o = oracle.Oracle(p, box(3, (2, 2, 3), (1.0, 1.0, H), {"kind": 1, "twall": Ta}, {"kind": 1, "twall": Tb}))
+    x, y, z = o.coords()
+    U = np.zeros((6, o.nnodes))
+    U[0] = rho
+    U[4] = energy(rho, 0.0, Ta + (Tb - Ta) * z / H)
+    U[5] = rho
+    h = H / 3
+    assert np.max(np.abs(o.rhs(U)[4])) <= 1e-12 * kappa * Tb / h ** 2
+    # a wall temperature off the profile leaves a boundary heat flux
+    o2 = oracle.Oracle(p, box(3, (2, 2, 3), (1.0, 1.0, H), {"kind": 1, "twall": Ta + 0.01}, {"kind": 1, "twall": Tb}))
+    assert np.max(np.abs(o2.rhs(U)[4])) > 1e-3 * kappa * (Tb - Ta) / H / h
+
+
+def test_slip_wall_normal_traction():
+    """u = (0, 0, s z (H - z)) between two slip walls, uniform density and
+    temperature: the total z-momentum changes only through the walls' normal
+    viscous traction (4/3) mu dw/dz (the pressure is uniform and cancels),
+    at the rate -(8/3) mu s H A."""
+    mu, H, s = 0.01, 0.5, 0.3
+    p = oracle.make_params(mu=mu)
+    T0, rho = 0.9, 0.3
+    o = oracle.Oracle(p, box(4, (2, 2, 3), (1.0, 1.0, H), {"kind": 2}, {"kind": 2}))
+    x, y, z = o.coords()
+    w = s * z * (H - z)
+    U = np.zeros((6, o.nnodes))
+    U[0] = rho
+    U[3] = rho * w
+    U[4] = energy(rho, w * w, T0)
+    U[5] = rho
+    rate = np.dot(weights(o), o.rhs(U)[3])
+    exact = -(8.0 / 3.0) * mu * s * H * 1.0
+    assert abs(rate - exact) <= 1e-10 * abs(exact), (rate, exact)
