@@ -229,3 +229,35 @@ def test_slip_wall_normal_traction():
     rate = np.dot(weights(o), o.rhs(U)[3])
     exact = -(8.0 / 3.0) * mu * s * H * 1.0
     assert abs(rate - exact) <= 1e-10 * abs(exact), (rate, exact)
+
+
+def test_moving_lid_over_fluid_at_rest():
+    """Fluid at rest (uniform rho = c and T) under a no-slip lid moving at U,
+    slip floor.  Only the lid exchanges momentum and energy: its ghost flux
+    lambda rho U (momentum) and lambda rho U^2 (energy), lambda the sound
+    speed, and the traction of the lifted shear, whose trace at the lid is
+    U (2/h) c_N with c_N = sum_k l_k(1)^2 / w_k of the Gauss basis (the face
+    value U enters the lifting only through the lid's own face).  So the
+    totals change at A (lambda rho U + mu U 2 c_N / h) and
+    A (lambda rho U^2 + mu U^2 2 c_N / h)."""
+    N, nz, H, U, mu = 3, 3, 0.5, 0.3, 0.01
+    p = oracle.make_params(mu=mu)
+    T0, rho = 0.95, 0.25
+    o = oracle.Oracle(p, box(N, (2, 2, nz), (1.0, 1.0, H), {"kind": 2},
+                             {"kind": 1, "uwall": (U, 0.0, 0.0), "twall": T0}))
+    x, y, z = o.coords()
+    Ust = np.zeros((6, o.nnodes))
+    Ust[0] = rho
+    Ust[4] = energy(rho, 0.0, T0)
+    Ust[5] = rho
+    rates = weights(o) @ o.rhs(Ust).T
+    xg, wg = np.polynomial.legendre.leggauss(N + 1)
+    l1 = np.array([np.prod([(1 - xg[j]) / (xg[k] - xg[j]) for j in range(N + 1) if j != k]) for k in range(N + 1)])
+    cN = np.sum(l1 ** 2 / wg)
+    h = H / nz
+    cs2 = (1 + 1 / CV) * R * T0 / (1 - B * rho) ** 2 - 2 * A * rho
+    lam = np.sqrt(abs(cs2))
+    shear = mu * U * 2 * cN / h
+    assert abs(rates[1] - (lam * rho * U + shear)) <= 1e-12 * (lam * rho * U + shear), (rates[1], lam * rho * U + shear)
+    assert abs(rates[4] - (lam * rho * U * U + shear * U)) <= 1e-12 * (lam * rho * U * U), rates[4]
+    assert abs(rates[0]) <= 1e-14 and abs(rates[2]) <= 1e-14
