@@ -414,7 +414,7 @@ def test_full_size_workload_parity(torch_cuda, which, steps):
     assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("w", [CASES[0], CASES[5]], ids=[IDS[0], IDS[5]])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 9, 11, 12)], ids=[IDS[k] for k in (0, 5, 9, 11, 12)])
 def test_fp32_mixed_accuracy(torch_cuda, w):
     """FP32-mixed form (FP32 state and bulk arithmetic, FP64 temperature/EoS,
     dt and integrals) against the FP64 oracle after 20 steps: relative density
@@ -471,6 +471,27 @@ def timed_wall_case():
         side_gamma=(wl.NO_GAMMA,) * 5 + ((0.0, 0.05, 0.02, 0.0),),
         side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.05, 0.0, 0.0), (0.0, 0.0, 0.0)),
         side_trate=(0.0,) * 4 + (0.3, -0.2))
+
+
+def test_fp32_mixed_accuracy_time_dependent_walls(torch_cuda):
+    torch = torch_cuda
+    w = timed_wall_case()
+    print(f"[case] fp32-mixed {w.name}", flush=True)
+    o = oracle_for(w)
+    U = oracle_init(o, w)
+    dt = o.dt(U)
+    s = gpu_solver(w, "fp32_mixed")
+    s.set_time(0.15)
+    Ug = to_gpu(torch, U, torch.float32)
+    Rg = s.new_state()
+    s.rk_steps(Ug, Rg, dt, 20)
+    torch.cuda.synchronize()
+    R = np.zeros_like(U)
+    o.run(U, R, 0.15, dt, 20)
+    err = rel_err(Ug.double().cpu().numpy(), U, state_floor(U, w.params))
+    print("fp32-mixed errors per field", err, flush=True)
+    assert err[0] <= 1e-5, err
+    assert np.all(err <= 1e-4), err
 
 
 def test_time_dependent_walls(torch_cuda):
