@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 6  /* 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
+#define NSKR_ABI_VERSION 7  /* 7: batches advance the context time and admit walls that change in time; 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
 
 enum {
     NSKR_OK = 0,
@@ -98,9 +98,8 @@ typedef struct {
  * sigma by a 15-point Gauss rule, linear interpolation) at every wall face
  * point and stage, and the wall temperature must stay in [0.3, 0.99] on the
  * whole wall: at mesh upload for t = 0, and over the time span of every
- * call that evaluates the operator (NSKR_E_ARG otherwise).  Walls whose
- * temperature changes in time are not accepted into batches
- * (NSKR_E_UNSUPPORTED from nskr_batch_admit). */
+ * call that evaluates the operator or admits the context into a batch
+ * (NSKR_E_ARG otherwise). */
 typedef struct {
     int kind;
     double twall;
@@ -216,7 +215,8 @@ int nskr_init_droplets(nskr_ctx *ctx, const nskr_init *ic, const double *noise, 
 /* Simulation time of the context: the time at which nskr_rhs, nskr_lift1
  * and nskr_lift2 evaluate walls whose temperature changes in time
  * (nskr_bc.twall_rate); nskr_rk_steps evaluates stage s of step n at t + n dt
- * + c_s dt (the stage times of the RK scheme) and advances t by nsteps dt.
+ * + c_s dt (the stage times of the RK scheme) and advances t by nsteps dt;
+ * a batch does the same for each of its instances (nskr_batch_admit).
  * Starts at 0.  Errors: NSKR_E_ARG (null ctx or output, non-finite t). */
 int nskr_set_time(nskr_ctx *ctx, double t);
 int nskr_get_time(const nskr_ctx *ctx, double *t);
@@ -294,9 +294,15 @@ int nskr_batch_destroy(nskr_batch *b);
 int nskr_batch_set_graph(nskr_batch *b, int on);
 
 /* Admit ctx (mesh uploaded) with caller-owned state U and register R (borrowed
- * until retired), its time step dt and the number of steps to run.  Returns
- * NSKR_E_NOMEM when the budget has no room now (not fatal: retry after a
- * retirement); NSKR_E_ARG for bad arguments or an instance already admitted. */
+ * until retired), its time step dt and the number of steps to run.  The
+ * instance starts from the context time t at admission: stage s of its step n
+ * is evaluated at t + n dt + c_s dt, as nskr_rk_steps evaluates it, through a
+ * device step counter of the context that the replayed steps advance; the
+ * context time becomes t + nsteps dt when the instance finishes, or t + k dt
+ * when it is retired after k steps.  Returns NSKR_E_NOMEM when the budget has
+ * no room now (not fatal: retry after a retirement); NSKR_E_ARG for bad
+ * arguments, an instance already admitted, or walls whose temperature would
+ * leave [0.3, 0.99] during the admitted steps. */
 int nskr_batch_admit(nskr_batch *b, nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, int *slot);
 
 /* One RK step of every active instance on stream s (asynchronous).  Instances

@@ -254,6 +254,9 @@ template <typename T> struct Inst {
     Phys ph;
     size_t NN;                 // nodes of the instance
     double dt;
+    const int *clk;            // batch: steps taken since admission, for walls whose
+                               // temperature changes in time (null otherwise)
+    double t0;                 // batch: the instance's time at admission
 };
 
 // Kernel argument: a single instance by value, or (BATCH) a device table of
@@ -270,7 +273,17 @@ template <typename T> struct Launch {
     int full;        // host side: launch the k_lift1 variant that also writes Q and TH
     double A, B;     // RK coefficients of this stage
     double t;        // time of this stage (walls whose temperature changes in time)
+    double cs;       // batch: the stage's time fraction c_s of the step
 };
+
+// Time of RK stage s of step n from t0: (t0 + n dt) + c_s dt, rounded as the
+// host rounds it for a single instance (no fused multiply-adds), so that an
+// instance sees bitwise the same stage times alone and in a batch.
+__device__ __forceinline__ double stage_time(double t0, int n, double dt, double cs)
+{
+#pragma clang fp contract(off)
+    return (t0 + (double)n * dt) + cs * dt;
+}
 
 // A pointer read from ordinary device memory is generic to the compiler,
 // which then emits flat loads and stores for everything addressed through it.
@@ -841,6 +854,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         // walls whose temperature varies along them: T* and the static
         // contact-angle flux at the local wall temperature, through the table
         // (each thread rewrites only the face points it wrote above)
+        double tb = 0.0;  // a batch instance's stage time
+        if (BATCH && a.clk) tb = stage_time(a.t0, *a.clk, a.dt, L.cs);
         for (int task = t; task < G::NF; task += BS) {
             const FaceTask<P> ft(task);
             const int el = e0 + ft.le, f = ft.f;
@@ -848,7 +863,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             if (a.mesh.nbr[el * 6 + f] >= 0) continue;  // interior: no wall-table entry
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
             if (!bc.var) continue;
-            const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp, L.t);
+            const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp, BATCH ? tb : L.t);
             const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
             const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
             if (bc.iso) sTs[slot] = T(wp.Tw);

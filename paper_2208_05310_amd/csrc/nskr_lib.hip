@@ -44,6 +44,7 @@ struct nskr_ctx {
     // scratch (element type of the precision)
     void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
     void *d_Ck = nullptr;        // Kahan compensation of the FP32 state update
+    int *d_clk = nullptr;        // batch: steps since admission (walls whose temperature changes in time)
     double *d_part = nullptr;    // reduction partials
     double *d_out = nullptr;     // final reduction values (device)
     double *d_noise = nullptr;   // init noise
@@ -591,6 +592,14 @@ template <typename T> __global__ __launch_bounds__(kBlock) void k_zero(T *p, siz
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) p[i] = T(0);
 }
 
+// One step taken by every batch instance whose walls change in time: advance
+// its step counter (read by the next step's stages for their times).
+__global__ __launch_bounds__(64) void k_tick(int *const *clk, int n)
+{
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < n) *clk[i] += 1;
+}
+
 // ------------------------------------------------------------ launch layer
 template <int P, typename T, int BS> struct Impl {
     static constexpr int kP = P, kBS = BS;
@@ -615,6 +624,7 @@ template <int P, typename T, int BS> struct Impl {
         I.Q = (T *)c->d_Q; I.TH = (T *)c->d_TH; I.G2 = (T *)c->d_G2;
         I.T2 = (T *)c->d_T2; I.TF = (T *)c->d_TF; I.TU = (T *)c->d_TU;
         I.mesh = mesh(c); I.ph = c->ph; I.NN = c->NN; I.dt = dt;
+        I.clk = nullptr; I.t0 = 0.0;
         return I;
     }
     static Launch<T> launch(const nskr_ctx *c, const Inst<T> &I)
@@ -674,6 +684,7 @@ template <int P, typename T, int BS> struct Impl {
             L.B = kRkB[st];
             L.tb = kTraceBuf[st];
             L.tw = kTraceBuf[st + 1];
+            L.cs = kRkC[st];
             hipLaunchKernelGGL((k_lift1<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
             hipLaunchKernelGGL((k_lift2<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
             hipLaunchKernelGGL((k_update<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
@@ -874,13 +885,14 @@ static void free_mesh(nskr_ctx *c)
 {
     void *ptrs[] = {c->d_nbr, c->d_bcid, c->d_emet, c->d_fmet, c->d_egeo, c->d_bcs, c->d_Q, c->d_TH,
                     c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop, c->d_Ck,
-                    c->d_stab};
+                    c->d_stab, c->d_clk};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_nbr = c->d_bcid = nullptr;
     c->d_emet = c->d_fmet = c->d_egeo = nullptr;
     c->d_bcs = nullptr;
     c->d_stab = nullptr;
+    c->d_clk = nullptr;
     c->d_Q = c->d_TH = c->d_G2 = c->d_T2 = c->d_TF = c->d_TU = c->d_Ck = nullptr;
     c->d_part = c->d_out = c->d_noise = c->d_drop = nullptr;
     c->E = 0;
@@ -1087,7 +1099,8 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
         (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS)) ||
         (c->p.precision == 1 && c->p.kahan && (rc = dalloc(c, &c->d_Ck, ts * 6 * c->NN))) ||
-        (tab && (rc = dalloc(c, (void **)&c->d_stab, sizeof(double) * tab->size())))) {
+        (tab && (rc = dalloc(c, (void **)&c->d_stab, sizeof(double) * tab->size()))) ||
+        (trate && (rc = dalloc(c, (void **)&c->d_clk, sizeof(int))))) {
         free_mesh(c);
         return rc;
     }
@@ -1350,6 +1363,7 @@ struct BatchSlot {
     int nsteps = 0, done = 0;
     int state = 0;  // 0 free, 1 active, 2 finished (awaiting retire)
     bool fresh = true;  // face traces not yet prolonged
+    double t0 = 0.0;    // instance time at admission
     size_t bytes = 0;
 };
 
@@ -1368,6 +1382,8 @@ struct nskr_batch {
     bool dirty = true, use_graph = true, poisoned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int **d_ticks = nullptr;  // step counters of the active instances whose walls change in time
+    int nticks = 0;
     long steps = 0;
     std::string err;
 };
@@ -1395,6 +1411,8 @@ static void batch_free_groups(nskr_batch *b)
         if (g.d_be) (void)hipFree(g.d_be);
     }
     b->groups.clear();
+    if (b->d_ticks) { (void)hipFree(b->d_ticks); b->d_ticks = nullptr; }
+    b->nticks = 0;
     if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
 }
@@ -1408,6 +1426,8 @@ static int build_group(nskr_batch *b, BatchGroup &g, const std::vector<int> &mem
     for (size_t k = 0; k < members.size(); ++k) {
         BatchSlot &sl = b->slots[members[k]];
         tab.push_back(Impl<P, T, BS>::inst(sl.c, sl.U, sl.R, nullptr, sl.dt));
+        tab.back().clk = sl.c->trate ? sl.c->d_clk : nullptr;
+        tab.back().t0 = sl.t0;
         const int nb = (sl.c->E + G::EPB - 1) / G::EPB;
         for (int j = 0; j < nb; ++j) {
             bi.push_back((int)k);
@@ -1484,6 +1504,14 @@ static int batch_rebuild(nskr_batch *b)
         b->groups.push_back(g);
         if (rc) return rc;
     }
+    std::vector<int *> ticks;
+    for (const auto &sl : b->slots)
+        if (sl.state == 1 && sl.c->trate) ticks.push_back(sl.c->d_clk);
+    if (!ticks.empty()) {
+        BHIPCHK(b, hipMalloc((void **)&b->d_ticks, sizeof(int *) * ticks.size()));
+        BHIPCHK(b, hipMemcpy(b->d_ticks, ticks.data(), sizeof(int *) * ticks.size(), hipMemcpyHostToDevice));
+        b->nticks = (int)ticks.size();
+    }
     b->dirty = false;
     return NSKR_OK;
 }
@@ -1534,7 +1562,8 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     if (!(dt > 0) || !isfinite(dt) || nsteps < 1) return bfail(b, NSKR_E_ARG, "dt must be positive, nsteps >= 1");
     for (const auto &sl : b->slots)
         if (sl.state != 0 && sl.c == c) return bfail(b, NSKR_E_ARG, "instance already admitted");
-    if (c->trate) return bfail(b, NSKR_E_UNSUPPORTED, "walls whose temperature changes in time run unbatched");
+    if (check_wall_time(c, c->time, c->time + nsteps * dt))
+        return bfail(b, NSKR_E_ARG, "wall temperature leaves [0.3, 0.99] during the admitted steps");
     const size_t ts = c->p.precision == 0 ? sizeof(double) : sizeof(float);
     const size_t need = c->bytes + 2 * 6 * c->NN * ts;
     if (b->used + need > b->budget) return bfail(b, NSKR_E_NOMEM, "no room in the memory budget now");
@@ -1548,6 +1577,7 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     BatchSlot &sl = b->slots[k];
     sl.c = c; sl.U = U; sl.R = R; sl.dt = dt; sl.nsteps = nsteps; sl.done = 0; sl.state = 1; sl.bytes = need;
     sl.fresh = true;
+    sl.t0 = c->time;
     if (c->d_Ck) {
         DeviceGuard guard(b->device);
         Impl<3, float, 256>::zero_comp(c, nullptr);
@@ -1563,7 +1593,10 @@ int nskr_batch_retire(nskr_batch *b, int slot)
 {
     if (!b || slot < 0 || slot >= (int)b->slots.size() || b->slots[slot].state == 0) return NSKR_E_ARG;
     BatchSlot &sl = b->slots[slot];
-    if (sl.state == 1) b->dirty = true;
+    if (sl.state == 1) {
+        b->dirty = true;
+        sl.c->time = sl.t0 + sl.done * sl.dt;
+    }
     b->used -= sl.bytes;
     sl = BatchSlot();
     return NSKR_OK;
@@ -1586,6 +1619,7 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
     for (auto &sl : b->slots)
         if (sl.state == 1 && sl.fresh) {
             dispatch(sl.c, [&](auto impl) { return decltype(impl)::prime(sl.c, sl.U, sl.R, sl.dt, s); });
+            if (sl.c->trate) hipLaunchKernelGGL((k_zero<int>), dim3(1), dim3(kBlock), 0, s, sl.c->d_clk, (size_t)1);
             sl.fresh = false;
         }
     if (b->use_graph) {
@@ -1597,6 +1631,8 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
                     launch_group<I::kP, typename I::Real, I::kBS>(g, s);
                     return 0;
                 });
+            if (b->nticks)
+                hipLaunchKernelGGL(k_tick, dim3((b->nticks + 63) / 64), dim3(64), 0, s, b->d_ticks, b->nticks);
             BHIPCHK(b, hipStreamEndCapture(s, &b->graph));
             BHIPCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         }
@@ -1608,12 +1644,15 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
                 launch_group<I::kP, typename I::Real, I::kBS>(g, s);
                 return 0;
             });
+        if (b->nticks)
+            hipLaunchKernelGGL(k_tick, dim3((b->nticks + 63) / 64), dim3(64), 0, s, b->d_ticks, b->nticks);
         BHIPCHK(b, hipGetLastError());
     }
     b->steps++;
     for (auto &sl : b->slots)
         if (sl.state == 1 && ++sl.done >= sl.nsteps) {
             sl.state = 2;
+            sl.c->time = sl.t0 + sl.nsteps * sl.dt;
             b->dirty = true;
         }
     return NSKR_OK;

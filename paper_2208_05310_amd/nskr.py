@@ -65,7 +65,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 6  # the struct layouts below
+ABI_VERSION = 7  # the struct layouts and semantics below
 
 
 def lib():

@@ -23,3 +23,14 @@ def box_for(w: wl.Workload) -> oracle.Box:
 def oracle_init(o: oracle.Oracle, w: wl.Workload) -> np.ndarray:
     return o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l,
                            w.cylinder_axis)
+
+
+def timed_wall_case():
+    # a graded no-slip floor whose temperature also rises in time, and a
+    # heat-transfer Navier-slip lid cooling in time
+    return wl.c4(scale=12).with_(
+        name="timed_walls_4x4x2_N3", side_kind=(0, 0, 0, 0, wl.NOSLIP_CA, wl.NAVIER),
+        side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.9), side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 120.0),
+        side_gamma=(wl.NO_GAMMA,) * 5 + ((0.0, 0.05, 0.02, 0.0),),
+        side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.05, 0.0, 0.0), (0.0, 0.0, 0.0)),
+        side_trate=(0.0,) * 4 + (0.3, -0.2))

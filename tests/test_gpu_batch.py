@@ -9,10 +9,15 @@
 * Graph replays equal direct launches on every step, with eager work and
   synchronisations between the replays.
 * Admission respects the memory budget; instances stop at their own step count.
+* Walls whose temperature changes in time: each batch instance runs on its
+  own clock from its time at admission (bitwise equal to the single-instance
+  path, also across a retirement and a new admission), and the context time
+  advances as nskr_rk_steps advances it.
 """
 import numpy as np
 import pytest
 
+from helpers import timed_wall_case
 from paper_2208_05310_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -195,3 +200,62 @@ def test_serving_loop_small_stream(torch_cuda):
             b.step(stream)
         stream.synchronize()
         assert np.array_equal(U.double().cpu().numpy(), r.result), r.w.name
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_time_dependent_walls_in_a_batch(torch_cuda, graph):
+    torch = torch_cuda
+    from paper_2208_05310_amd.nskr import Batch
+    timed = timed_wall_case()
+    # two timed instances with their own start times and steps, and one whose
+    # walls do not change in time (same group: degree 3, fp64)
+    cases = [(timed, 0.15, 5), (timed.with_(noise_seed=4), 0.02, 3), (small_mix()[0][0], 0.0, 4)]
+    print(f"[case] time-dependent walls in a batch, graph={graph}", flush=True)
+    single, times = [], []
+    for w, t0, n in cases:
+        s, U, R, dt = setup(w, "fp64")
+        s.set_time(t0)
+        s.rk_steps(U, R, dt, n)
+        single.append(U)
+        times.append(s.get_time())
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    b = Batch(1 << 34, graph=graph)
+    held = []
+    for w, t0, n in cases:
+        s, U, R, dt = setup(w, "fp64")
+        s.set_time(t0)
+        assert b.admit(s, U, R, dt, n) is not None
+        held.append((s, U))
+    for _ in range(max(n for _, _, n in cases)):
+        b.step(stream)
+    stream.synchronize()
+    for k, (w, t0, n) in enumerate(cases):
+        s, U = held[k]
+        print(f"[case] {w.name} t0={t0}: batched == single bitwise: {torch.equal(U, single[k])}", flush=True)
+        assert torch.equal(U, single[k])
+        assert s.get_time() == times[k]
+    # retire after 2 of 5 steps, admit again for 3 more: equals rk_steps(2)
+    # then rk_steps(3) (the second call starts from the advanced time)
+    w, t0 = timed, 0.15
+    s, U, R, dt = setup(w, "fp64")
+    s.set_time(t0)
+    s.rk_steps(U, R, dt, 2)
+    s.rk_steps(U, R, dt, 3)
+    torch.cuda.synchronize()
+    s2, U2, R2, _ = setup(w, "fp64")
+    s2.set_time(t0)
+    b = Batch(1 << 34, graph=graph)
+    k = b.admit(s2, U2, R2, dt, 5)
+    for _ in range(2):
+        b.step(stream)
+    b.retire(k)
+    assert s2.get_time() == t0 + 2 * dt
+    assert b.admit(s2, U2, R2, dt, 3) is not None
+    for _ in range(3):
+        b.step(stream)
+    stream.synchronize()
+    print("retire and admit again: bitwise", torch.equal(U2, U), flush=True)
+    assert torch.equal(U2, U)
+    assert s2.get_time() == s.get_time()
+

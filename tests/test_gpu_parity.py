@@ -12,7 +12,7 @@ import math
 import numpy as np
 import pytest
 
-from helpers import oracle_for, oracle_init
+from helpers import oracle_for, oracle_init, timed_wall_case
 from paper_2208_05310_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -462,17 +462,6 @@ def test_fp32_compensated_update_reduces_error(torch_cuda):
     assert e_comp < e_plain and e_comp <= 1e-5
 
 
-def timed_wall_case():
-    # a graded no-slip floor whose temperature also rises in time, and a
-    # heat-transfer Navier-slip lid cooling in time
-    return wl.c4(scale=12).with_(
-        name="timed_walls_4x4x2_N3", side_kind=(0, 0, 0, 0, wl.NOSLIP_CA, wl.NAVIER),
-        side_twall=(0.0, 0.0, 0.0, 0.0, 0.85, 0.9), side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 120.0),
-        side_gamma=(wl.NO_GAMMA,) * 5 + ((0.0, 0.05, 0.02, 0.0),),
-        side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.05, 0.0, 0.0), (0.0, 0.0, 0.0)),
-        side_trate=(0.0,) * 4 + (0.3, -0.2))
-
-
 def test_fp32_mixed_accuracy_time_dependent_walls(torch_cuda):
     torch = torch_cuda
     w = timed_wall_case()
@@ -497,10 +486,10 @@ def test_fp32_mixed_accuracy_time_dependent_walls(torch_cuda):
 def test_time_dependent_walls(torch_cuda):
     """Walls whose temperature changes in time: the operator at a set time,
     RK steps from that time (each stage at its own time) and the advanced
-    time, against the oracle; batches refuse such instances; a run that would
-    carry the wall temperature out of the table's range is refused."""
+    time, against the oracle; a run or a batch admission that would carry the
+    wall temperature out of the table's range is refused."""
     torch = torch_cuda
-    from paper_2208_05310_amd.nskr import NSKR_E_ARG, NSKR_E_UNSUPPORTED, Batch, NskrError
+    from paper_2208_05310_amd.nskr import NSKR_E_ARG, Batch, NskrError
     w = timed_wall_case()
     print(f"[case] time-dependent walls {w.name}", flush=True)
     o = oracle_for(w)
@@ -529,11 +518,10 @@ def test_time_dependent_walls(torch_cuda):
     print("rk errors per field", err, flush=True)
     assert np.all(err <= TOL), err
     assert abs(s.get_time() - (t0 + 10 * dt)) <= 1e-15
-    b = Batch(1 << 34)
-    with pytest.raises(NskrError) as ei:
-        b.admit(s, Ug, Rg, dt, 3)
-    assert ei.value.code == NSKR_E_UNSUPPORTED
     s.set_time(0.5)   # the floor would reach 0.85 + 0.05 + 0.3 * 0.5 = 1.05
     with pytest.raises(NskrError) as ei:
         s.rk_steps(Ug, Rg, dt, 1)
+    assert ei.value.code == NSKR_E_ARG
+    with pytest.raises(NskrError) as ei:
+        Batch(1 << 34).admit(s, Ug, Rg, dt, 1)
     assert ei.value.code == NSKR_E_ARG
