@@ -249,7 +249,8 @@ template <typename T> struct Inst {
     T *Q, *TH;                 // grad(rho,u,c) [15] and T, for the API outputs only
     T *G2;                     // grad T + lap c [4]
     T *T2, *TF, *TU;           // face traces: grad c + T [4], flux + wave speed [7],
-                               // conserved state [3 buffers][6]
+                               // conserved state [3 buffers][6]; within an array
+                               // (a buffer) face-major: [face][field][point]
     MeshDev mesh;
     Phys ph;
     size_t NN;                 // nodes of the instance
@@ -284,6 +285,19 @@ __device__ __forceinline__ double stage_time(double t0, int n, double dt, double
 #pragma clang fp contract(off)
     return (t0 + (double)n * dt) + cs * dt;
 }
+
+// Face traces are stored face by face: the K fields of one face's N2 points
+// are contiguous ([face][field][point], face = 6 e + f). A block reading a
+// neighbour's face then fetches its fields as one run of whole cache lines,
+// not K runs of N2 values each that straddle line boundaries, and the field
+// offsets are compile-time constants.
+template <int N2> struct FaceIx {
+    size_t face;
+    int fp;
+    __device__ __forceinline__ FaceIx(size_t fc, int p) : face(fc), fp(p) {}
+    // element of field k of a K-field trace array
+    __device__ __forceinline__ size_t at(int K, int k) const { return (face * K + k) * N2 + fp; }
+};
 
 // A pointer read from ordinary device memory is generic to the compiler,
 // which then emits flat loads and stores for everything addressed through it.
@@ -576,9 +590,9 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
         for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, um[v], up[v]);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const size_t o = ((size_t)e * 6 + 2 * lt.d + s) * G::n2 + lt.fp;
+            const FaceIx<G::n2> o((size_t)e * 6 + 2 * lt.d + s, lt.fp);
 #pragma unroll
-            for (int v = 0; v < 6; ++v) TU[v * NF + o] = s ? up[v] : um[v];
+            for (int v = 0; v < 6; ++v) TU[o.at(6, v)] = s ? up[v] : um[v];
         }
     }
 }
@@ -627,13 +641,13 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
         for (int s = 0; s < 2; ++s) {
             const int nb = s ? nbp : nbm;
             if (nb >= 0) {
-                const size_t o = ((size_t)nb * 6 + (2 * lt.d + 1 - s)) * G::n2 + lt.fp;
+                const FaceIx<G::n2> o((size_t)nb * 6 + (2 * lt.d + 1 - s), lt.fp);
                 if (full) {
 #pragma unroll
                     for (int v = 0; v < 6; ++v)
-                        if (v != 4) wn[s][v] = TU[v * NF + o];
+                        if (v != 4) wn[s][v] = TU[o.at(6, v)];
                 } else {
-                    wn[s][5] = TU[5 * NF + o];
+                    wn[s][5] = TU[o.at(6, 5)];
                 }
             }
         }
@@ -729,11 +743,11 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
             const double Tf = temperature(a.ph, (double)uf[s][0], (double)uf[s][1], (double)uf[s][2], (double)uf[s][3],
                                           (double)uf[s][4], (double)uf[s][5], (double)qf[s][0], (double)qf[s][1],
                                           (double)qf[s][2]);
-            const size_t o = ((size_t)el * 6 + 2 * lt.d + s) * G::n2 + lt.fp;
-            a.T2[0 * NF + o] = qf[s][0];
-            a.T2[1 * NF + o] = qf[s][1];
-            a.T2[2 * NF + o] = qf[s][2];
-            a.T2[3 * NF + o] = T(Tf);
+            const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
+            a.T2[o.at(4, 0)] = qf[s][0];
+            a.T2[o.at(4, 1)] = qf[s][1];
+            a.T2[o.at(4, 2)] = qf[s][2];
+            a.T2[o.at(4, 3)] = T(Tf);
         }
     }
 }
@@ -780,20 +794,20 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         const int el = e0 + ft.le;
         r.nb = -1;
         if (el >= E) return;
-        const size_t o = ((size_t)el * 6 + ft.f) * G::n2 + ft.fp;
+        const FaceIx<G::n2> o((size_t)el * 6 + ft.f, ft.fp);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r.own[k] = a.T2[k * NF + o];
+        for (int k = 0; k < 4; ++k) r.own[k] = a.T2[o.at(4, k)];
 #pragma unroll
         for (int v = 0; v < 6; ++v)
-            if (v != 4) r.uo[v] = TU[v * NF + o];
+            if (v != 4) r.uo[v] = TU[o.at(6, v)];
         r.nb = a.mesh.nbr[el * 6 + ft.f];
         if (r.nb >= 0) {
-            const size_t on = ((size_t)r.nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
+            const FaceIx<G::n2> on((size_t)r.nb * 6 + (ft.f ^ 1), ft.fp);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r.oth[k] = a.T2[k * NF + on];
+            for (int k = 0; k < 4; ++k) r.oth[k] = a.T2[on.at(4, k)];
 #pragma unroll
             for (int v = 0; v < 6; ++v)
-                if (v != 4) r.wn[v] = TU[v * NF + on];
+                if (v != 4) r.wn[v] = TU[on.at(6, v)];
         }
     };
     Tr tr0;
@@ -865,10 +879,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             if (!bc.var) continue;
             const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp, BATCH ? tb : L.t);
             const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
-            const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
+            const FaceIx<G::n2> o((size_t)el * 6 + f, ft.fp);
             if (bc.iso) sTs[slot] = T(wp.Tw);
-            else a.TF[6 * NF + o] = T(1.0 / wp.Tw);  // 1/T_w for the heat-transfer flux below (TF[6] is free on walls)
-            const T c = TU[5 * NF + o];
+            else a.TF[o.at(7, 6)] = T(1.0 / wp.Tw);  // 1/T_w for the heat-transfer flux below (TF[6] is free on walls)
+            const T c = TU[o.at(6, 5)];
             sFs[slot] = T(wp.gcoef) * (c - T(wp.rl)) * (c - T(wp.rv)) * T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
         }
     }
@@ -1002,7 +1016,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 for (int l = 0; l < P; ++l) acc += T(Lf[l]) * fld[lo + l * ls];
                 return acc;
             };
-            const size_t o = ((size_t)el * 6 + f) * G::n2 + ft.fp;
+            const FaceIx<G::n2> o((size_t)el * 6 + f, ft.fp);
             const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
             const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
             const bool wall = a.mesh.nbr[el * 6 + f] < 0;
@@ -1012,14 +1026,14 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // scheduling barriers keep each field group's LDS loads next to the
             // arithmetic that consumes them (otherwise all of them are hoisted
             // and the register demand limits occupancy)
-            const T rho = TU[0 * NF + o], m0 = TU[1 * NF + o], m1 = TU[2 * NF + o], m2 = TU[3 * NF + o];
-            const T E = TU[4 * NF + o], c = TU[5 * NF + o];
+            const T rho = TU[o.at(6, 0)], m0 = TU[o.at(6, 1)], m1 = TU[o.at(6, 2)], m2 = TU[o.at(6, 3)];
+            const T E = TU[o.at(6, 4)], c = TU[o.at(6, 5)];
             __builtin_amdgcn_sched_barrier(0);
             const T ir = T(1) / rho;
             const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
             const T mn = m0 * n0 + m1 * n1 + m2 * n2;
             const T un = mn * ir;
-            const double Tf = (double)a.T2[3 * NF + o];
+            const double Tf = (double)a.T2[o.at(4, 3)];
             double pd, cs2;
             eos(a.ph, (double)rho, Tf, pd, cs2);
             // model 2: p_alpha and its sound speed (ap = 0 for model 1)
@@ -1087,7 +1101,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                     // Navier slip: tangential traction gamma_1 div u grad_G c -
                     // gamma_2 (u_t - u_w,t), and its work on u_t
                     const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                    const T gc0 = a.T2[0 * NF + o], gc1 = a.T2[1 * NF + o], gc2 = a.T2[2 * NF + o];
+                    const T gc0 = a.T2[o.at(4, 0)], gc1 = a.T2[o.at(4, 1)], gc2 = a.T2[o.at(4, 2)];
                     const T gcn = gc0 * n0 + gc1 * n1 + gc2 * n2;
                     const T w0 = T(bc.uw[0]), w1 = T(bc.uw[1]), w2 = T(bc.uw[2]);
                     const T wn = w0 * n0 + w1 * n1 + w2 * n2;
@@ -1114,19 +1128,19 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                     const T gTn = sgn * pro(nf + 3 * G::NV);
                     G4 -= T(a.ph.kappa) * gTn;
                 } else {  // heat transfer, eq. bc_energy_alpha
-                    const double itw = bc.var ? (double)a.TF[6 * NF + o] : bc.inv_tw;
+                    const double itw = bc.var ? (double)a.TF[o.at(7, 6)] : bc.inv_tw;
                     G4 -= T(-bc.g3 * (itw - 1.0 / Tf));
                 }
             }
             // order-parameter terms of j_e and F^V_c
             __builtin_amdgcn_sched_barrier(0);
             if (!wall) {
-                const T gcn = a.T2[0 * NF + o] * n0 + a.T2[1 * NF + o] * n1 + a.T2[2 * NF + o] * n2;
+                const T gcn = a.T2[o.at(4, 0)] * n0 + a.T2[o.at(4, 1)] * n1 + a.T2[o.at(4, 2)] * n2;
                 const T lapc = pro(sTs);
                 const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * gcn;
-                a.TF[6 * NF + o] = hl ? cw : lam;
+                a.TF[o.at(7, 6)] = hl ? cw : lam;
             } else if (kind != 2) {
                 // contact-angle flux g (with gamma_1 div u on Navier-slip
                 // walls), as the second lifting used it: sFs holds g dS; and
@@ -1137,12 +1151,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 G4 -= -T(a.ph.gam) * c * g * div + T(a.ph.gam) * g * zeta;
                 G5 -= T(a.ph.gam * a.ph.beta) * g;
             }
-            a.TF[0 * NF + o] = G0;
-            a.TF[1 * NF + o] = G1;
-            a.TF[2 * NF + o] = G2_;
-            a.TF[3 * NF + o] = G3;
-            a.TF[4 * NF + o] = G4;
-            a.TF[5 * NF + o] = G5;
+            a.TF[o.at(7, 0)] = G0;
+            a.TF[o.at(7, 1)] = G1;
+            a.TF[o.at(7, 2)] = G2_;
+            a.TF[o.at(7, 3)] = G3;
+            a.TF[o.at(7, 4)] = G4;
+            a.TF[o.at(7, 5)] = G5;
         }
     }
 }
@@ -1187,19 +1201,19 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         const int el = e0 + ft.le;
         r.nb = -1;
         if (el >= E) return;
-        const size_t o = ((size_t)el * 6 + ft.f) * G::n2 + ft.fp;
+        const FaceIx<G::n2> o((size_t)el * 6 + ft.f, ft.fp);
         r.nb = a.mesh.nbr[el * 6 + ft.f];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) r.uo[v] = TUr[v * NF + o];
+        for (int v = 0; v < 6; ++v) r.uo[v] = TUr[o.at(6, v)];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) r.G[v] = a.TF[v * NF + o];
+        for (int v = 0; v < 6; ++v) r.G[v] = a.TF[o.at(7, v)];
         if (r.nb >= 0) {
-            const size_t on = ((size_t)r.nb * 6 + (ft.f ^ 1)) * G::n2 + ft.fp;
-            r.G[6] = a.TF[6 * NF + o];
+            const FaceIx<G::n2> on((size_t)r.nb * 6 + (ft.f ^ 1), ft.fp);
+            r.G[6] = a.TF[o.at(7, 6)];
 #pragma unroll
-            for (int v = 0; v < 7; ++v) r.Gn[v] = a.TF[v * NF + on];
+            for (int v = 0; v < 7; ++v) r.Gn[v] = a.TF[on.at(7, v)];
 #pragma unroll
-            for (int v = 0; v < 6; ++v) r.un[v] = TUr[v * NF + on];
+            for (int v = 0; v < 6; ++v) r.un[v] = TUr[on.at(6, v)];
         }
     };
     // (only where one round covers the block: holding a round's traces across
@@ -1394,9 +1408,9 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         for (int v = 0; v < 6; ++v) prolong2<P>(sF[v], b2, sL, lt, um[v], up[v]);
 #pragma unroll
         for (int sd = 0; sd < 2; ++sd) {
-            const size_t o = ((size_t)el * 6 + 2 * lt.d + sd) * G::n2 + lt.fp;
+            const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + sd, lt.fp);
 #pragma unroll
-            for (int v = 0; v < 6; ++v) TUw[v * NF + o] = sd ? up[v] : um[v];
+            for (int v = 0; v < 6; ++v) TUw[o.at(6, v)] = sd ? up[v] : um[v];
         }
     }
 }
