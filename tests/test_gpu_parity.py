@@ -115,6 +115,17 @@ def small_cases():
             side_gamma=(wl.NO_GAMMA,) * 5 + ((0.0, 0.05, 0.02, 0.0),),
             side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.08, 0.04, 0.0), (-0.05, 0.0, 0.0))),
         wl.c8(theta=60.0, n=(5, 5, 2)).with_(width=0.05),                # liquid pillar between walls
+        # degenerate meshes: one element that is its own neighbour through
+        # every face, a periodic direction one element thick, and a box
+        # closed by walls of all three kinds (corner elements have three
+        # wall faces)
+        base.with_(name="self_periodic_1x1x1_N3", N=3, n=(1, 1, 1)),
+        base.with_(name="thin_periodic_4x4x1_N4", N=4, n=(4, 4, 1)),
+        wl.c4(scale=12).with_(
+            name="closed_box_4x4x2_N3", periodic=(0, 0, 0),
+            side_kind=(wl.NOSLIP_CA, wl.SLIP, wl.NAVIER, wl.NOSLIP_CA, wl.NOSLIP_CA, wl.SLIP),
+            side_twall=(0.9, 0.0, 0.88, 0.87, 0.9, 0.0), side_theta=(60.0, 90.0, 110.0, 90.0, 60.0, 90.0),
+            side_gamma=(wl.NO_GAMMA,) * 2 + ((0.0, 0.05, 0.02, 0.0),) + (wl.NO_GAMMA,) * 3),
     ]
 
 
@@ -207,7 +218,7 @@ def test_init_parity(torch_cuda, w):
         assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 3, 8, 9)], ids=[IDS[k] for k in (0, 5, 3, 8, 9)])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 3, 8, 9, 13, 15)], ids=[IDS[k] for k in (0, 5, 3, 8, 9, 13, 15)])
 def test_dt_parity(torch_cuda, w):
     torch = torch_cuda
     print(f"[case] dt {w.name}", flush=True)
@@ -219,7 +230,7 @@ def test_dt_parity(torch_cuda, w):
     assert abs(dg - do) <= 1e-14 * do, (dg, do)
 
 
-@pytest.mark.parametrize("w", [CASES[0], CASES[5], CASES[8]], ids=[IDS[0], IDS[5], IDS[8]])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 8, 13, 15)], ids=[IDS[k] for k in (0, 5, 8, 13, 15)])
 def test_reduce_parity(torch_cuda, w):
     torch = torch_cuda
     print(f"[case] reduce {w.name}", flush=True)
@@ -237,8 +248,8 @@ def test_reduce_parity(torch_cuda, w):
             assert abs(rg[k] - ro[k]) <= 1e-13 * scale[k] + 1e-300, (k, rg[k], ro[k])
 
 
-@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 4, 8, 9, 10, 11, 12)],
-                         ids=[IDS[k] for k in (0, 5, 4, 8, 9, 10, 11, 12)])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 4, 8, 9, 10, 11, 12, 13, 14, 15)],
+                         ids=[IDS[k] for k in (0, 5, 4, 8, 9, 10, 11, 12, 13, 14, 15)])
 def test_rk_steps_parity(torch_cuda, w):
     """Fixed number of RK steps with the oracle's step-0 dt on both sides
     (1/100 of it where the dynamic contact angle is on)."""
