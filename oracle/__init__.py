@@ -12,7 +12,14 @@ Pinned by ``tests/test_oracle_*.py`` against values the paper prints
 preservation, conservation), the relaxation ODE, a convergence study on an
 isentropic vortex (ideal-gas reduction) and a manufactured solution of the
 full system, and a dense brute-force re-implementation on a tiny mesh.
-The wall fluxes beyond those invariants are "parity unpinned".
+The wall fluxes are pinned term by term by closed forms: a fluid at rest
+between walls (pressure), Couette flow under a moving lid (no-slip and
+Navier-slip tractions, the wall's work), steady conduction between
+isothermal and between heat-transfer walls, the normal traction of a slip
+wall under compression, closed-form rates of the gamma_1 and gamma_4 terms,
+the contact-angle c-flux integral, and a lid moving over fluid at rest (its
+ghost flux); the wall-temperature table by its grid values, the linear
+interpolation bound and its time and stage evaluation.
 """
 from __future__ import annotations
 
