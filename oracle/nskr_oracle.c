@@ -1,7 +1,7 @@
 /*
  * nskr_oracle.c -- plain FP64 CPU reference of the DGSEM discretisation of the
- * relaxation model 1 of the non-isothermal Navier-Stokes-Korteweg equations
- * (Keim, Munz, Rohde, arXiv 2208.05310).
+ * relaxation models 1 and 2 of the non-isothermal Navier-Stokes-Korteweg
+ * equations (Keim, Munz, Rohde, arXiv 2208.05310).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP library is
  * checked against.  It shares no code, header, table or helper with the HIP
@@ -23,16 +23,22 @@
  *   Sec. 2.3.2      relaxation energy (eq. totalenergyalpha), chemical potential
  *                   and order-parameter source, simplified energy flux j_e,
  *                   relaxation model 1 fluxes F^C, F^V and source S
- *                   (eq. navierstokeskorteweg_p).
+ *                   (eq. navierstokeskorteweg_p); relaxation model 2: the
+ *                   modified pressure p_alpha (eq. modified_pressure) and its
+ *                   fluxes and source (eq. navierstokeskorteweg_palpha).
  *   Sec. 2.4        wall boundary conditions of the relaxation model
  *                   (eq. bc_nsk_alpha), cubic wall energy and its derivative
  *                   (eq. helmfreesurftot_derivative), surface tension
  *                   (eq. surftenscoef, read with the factor sqrt(2*gamma)).
  *   Sec. 3.1        DGSEM on Legendre-Gauss nodes with collocation, Rusanov
- *                   flux, BR1 lifting, point-wise non-conservative sources,
+ *                   flux (HLLC for model 2), BR1 lifting, point-wise non-conservative sources,
  *                   explicit low-storage RK4, CFL = 0.9 (Sec. 4 preamble).
- *   Sec. 3.2        boundary conditions enforced weakly through the face flux.
+ *   Sec. 3.2        boundary conditions enforced weakly through the face flux;
+ *                   the tabulated sigma_vl for varying wall temperatures.
  *   Sec. 4.1.1      tanh droplet profile (eq. staticbubble1D).
+ *   Sec. 4.3        colliding droplets with given velocities and bulk
+ *                   densities (Tables 4, 5); Sec. 4.4.1 the liquid pillar
+ *                   (a cylinder between two walls).
  *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - rho*e is the conserved total energy of eq. totalenergyalpha, so the
@@ -48,10 +54,14 @@
  *     so zeta_c = 0 on the wall), or the generalized Navier-slip wall of
  *     eq. bc_nsk_alpha with gamma_1, gamma_2, gamma_4 and either a fixed
  *     temperature or the heat-transfer condition with gamma_3.
- *   - A wall temperature that varies along the wall (linearly in x) takes
- *     sigma and the Maxwell states from the table of Sec. 3.2 (15-point
- *     Gauss rule, 10000 points on [0.3, 1], linear interpolation), the
- *     Maxwell states tabulated alongside sigma.
+ *   - A wall temperature that varies along the wall (linearly in x) or in
+ *     time (linearly in t, evaluated at each RK stage's time t + c_s dt)
+ *     takes sigma and the Maxwell states from the table of Sec. 3.2
+ *     (15-point Gauss rule, 10000 points on [0.3, 1], linear interpolation),
+ *     the Maxwell states tabulated alongside sigma.
+ *   - Model 2 walls use the mirrored-ghost Rusanov flux with p_alpha and
+ *     the wave speed sqrt(c_s^2 + alpha rho); interior faces the HLLC flux
+ *     with Davis wave-speed estimates, c carried as a passive scalar.
  *   - Time integration: Carpenter-Kennedy 5-stage 2N-storage RK4(3)5.
  *   - Time step: advective limit with 1D Rusanov stability constants, and a
  *     parabolic/source limit with 1D BR1 spectral radii.
