@@ -1,15 +1,18 @@
 /*
  * nskr.h -- C ABI of the MI355X (gfx950) library for the DGSEM right-hand side
- * and low-storage Runge-Kutta update of relaxation model 1 of the
+ * and low-storage Runge-Kutta update of relaxation models 1 and 2 of the
  * non-isothermal Navier-Stokes-Korteweg equations with a van der Waals
  * equation of state (Keim, Munz, Rohde, arXiv 2208.05310).
  *
- * The system (Sec. 2.3.2, flux and source vectors of relaxation model 1) is
+ * The system (Sec. 2.3.2, flux and source vectors of relaxation model 1;
+ * model 2 replaces p by p_alpha = p + alpha/2 rho^2 in F^C, eq.
+ * modified_pressure, and moves the matching terms out of S) is
  *   U_t + div(F^C(U) - F^V(U, grad U, lap c)) = S(U, grad U),
  *   U = (rho, rho u, rho v, rho w, rho e, c),
  * discretised as in Sec. 3.1: nodal DGSEM on Legendre-Gauss nodes with
- * collocated quadrature, Rusanov face flux for F^C, BR1 lifting for the
- * gradients, point-wise sources, explicit low-storage RK4.  Walls follow the
+ * collocated quadrature, Rusanov (model 2: HLLC) face flux for F^C, BR1
+ * lifting for the gradients, point-wise sources, explicit low-storage RK4.
+ * Walls follow the
  * relaxation-model boundary conditions of Sec. 2.4 (eq. bc_nsk_alpha) with the
  * cubic wall energy (eq. helmfreesurftot_derivative), enforced weakly through
  * the face flux (Sec. 3.2).

@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import hashlib
 import os
+import re
 import subprocess
 import sys
 
@@ -21,13 +22,21 @@ FLAGS = [
 KERNELS = os.path.join(HERE, "csrc", "nskr_kernels.hpp")
 
 
+def _code_only(src: str) -> str:
+    """The source without comments, trailing blanks and empty lines (the
+    kernel header holds no string literal that contains a comment marker)."""
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
+
+
 def kernel_fingerprint() -> str:
-    """sha256 over the device-kernel source and the compile flags: hardware
-    counters taken for one fingerprint say nothing about kernels built from
-    another."""
+    """sha256 over the device-kernel code (comments excluded) and the compile
+    flags: hardware counters taken for one fingerprint say nothing about
+    kernels built from another."""
     h = hashlib.sha256()
-    with open(KERNELS, "rb") as f:
-        h.update(f.read())
+    with open(KERNELS, encoding="utf-8") as f:
+        h.update(_code_only(f.read()).encode())
     h.update(" ".join(FLAGS).encode())
     return h.hexdigest()
 

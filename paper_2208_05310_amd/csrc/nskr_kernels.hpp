@@ -1,15 +1,17 @@
 // nskr_kernels.hpp -- gfx950 kernels of the DGSEM right-hand side and the
-// low-storage RK update for relaxation model 1 of the non-isothermal NSK
-// equations with a van der Waals fluid (arXiv 2208.05310, Sec. 2.3.2, 2.4, 3).
+// low-storage RK update for relaxation models 1 and 2 of the non-isothermal
+// NSK equations with a van der Waals fluid (arXiv 2208.05310, Sec. 2.3.2, 2.4,
+// 3).
 //
 // Execution model
 //   One workgroup of 256 (or 512) threads owns EPB = threads / (N+1)^3
 //   elements; each thread owns one volume node.  Element tiles are staged in
 //   LDS for the 1D derivative sweeps along xi, eta, zeta; face work runs as
 //   line tasks (one thread per grid line normal to a face pair).  State is
-//   structure-of-arrays [var][element][node]; face traces are element-major
-//   [var][element][face][point] so that each element writes its own six faces
-//   contiguously and reads its neighbour's face as one contiguous run.
+//   structure-of-arrays [var][element][node]; face traces are face-major
+//   [element][face][var][point] so that each element writes its own six faces
+//   contiguously and reads all fields of a neighbour's face as one contiguous
+//   run.
 //
 // Data flow of one stage (BR1 needs three neighbour exchanges).  Only what a
 // later kernel cannot rebuild from the state goes through memory: the lifted
@@ -24,7 +26,8 @@
 //              complete wall flux on wall faces (TF).
 //   k_update : U + neighbour conserved traces -> all lifted gradients again;
 //              volume integral of the contravariant fluxes, surface integral
-//              of the Rusanov + central viscous face flux, point-wise source,
+//              of the Rusanov (model 2: HLLC) + central viscous face flux,
+//              point-wise source,
 //              Jacobian scaling, RK stage update, and the conserved face
 //              traces of the new state for the next stage.
 // The conserved traces rotate over three buffers: stage s reads buffer b(s)
