@@ -29,12 +29,14 @@ def kernel_words_per_node(N):
     """Algorithmic words per volume node for each kernel of one stage: every
     array the kernel reads or writes, each element counted once (a face trace
     that an element and its neighbour both read counts once); F = 6/(N+1)
-    face points per node."""
+    face points per node. Wall face points also carry grad c in the T2 trace
+    (3 words written by lift1, read by lift2 on Navier-slip walls), not
+    counted: under 0.1 % of a stage on the wall workloads."""
     F = 6.0 / (N + 1)
     return {
         "prolong": 6 + 6 * F,             # U in; conserved traces out
-        "lift1": 6 + 5 * F,               # U, neighbour c traces in; grad c + T traces (4) out
-        "lift2": 10 + 17 * F,             # U, conserved traces (own and neighbour: 6), grad c + T traces (4)
+        "lift1": 6 + 3 * F,               # U, neighbour c traces in; grad c . n + T traces (2) out
+        "lift2": 10 + 15 * F,             # U, conserved traces (own and neighbour: 6), grad c . n + T traces (2)
                                           # in; grad T + lap c (4), flux + wave-speed traces (7) out
         "update": 28 + 19 * F,            # U, R, grad T + lap c, neighbour conserved traces (6), flux traces (7)
                                           # in; U, R, conserved traces (6) out

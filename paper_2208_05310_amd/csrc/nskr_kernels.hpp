@@ -19,7 +19,8 @@
 // state and the neighbours' conserved face traces, which costs a few hundred
 // flops per node and saves their storage round trip.
 //   k_lift1  : U + neighbour c traces -> lifted grad c; own-face traces of
-//              grad c and of the face temperature (T2).
+//              (grad c) . n, of the face temperature and, on walls, of grad c
+//              (T2).
 //   k_lift2  : U + neighbour conserved traces -> lifted grad u, grad c, nodal
 //              T; with the T2 traces of both sides -> grad T, lap c (G2);
 //              then the own-face flux traces (normal flux, wave speed), or the
@@ -251,7 +252,8 @@ template <typename T> struct Inst {
     T *Ck;                     // compensation of the state update (FP32 Kahan), or null
     T *Q, *TH;                 // grad(rho,u,c) [15] and T, for the API outputs only
     T *G2;                     // grad T + lap c [4]
-    T *T2, *TF, *TU;           // face traces: grad c + T [4], flux + wave speed [7],
+    T *T2, *TF, *TU;           // face traces: grad c . n and T (+ grad c on walls) [kT2],
+                               // flux + wave speed [7],
                                // conserved state [3 buffers][6]; within an array
                                // (a buffer) face-major: [face][field][point]
     MeshDev mesh;
@@ -294,6 +296,13 @@ __device__ __forceinline__ double stage_time(double t0, int n, double dt, double
 // neighbour's face then fetches its fields as one run of whole cache lines,
 // not K runs of N2 values each that straddle line boundaries, and the field
 // offsets are compile-time constants.
+// Fields of the T2 face trace: (grad c) . n with the element's own outward
+// normal, the face temperature, and on wall faces only the vector grad c
+// (the tangential gradient of a Navier-slip wall). Interior faces need only
+// the first two: the divergence lifting of grad c takes the central normal
+// component, and the neighbour's outward normal is minus the own one.
+constexpr int kT2 = 5;
+
 template <int N2> struct FaceIx {
     size_t face;
     int fp;
@@ -604,8 +613,15 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 // Lifted grad c, and the own-face traces of grad c and of the face
 // temperature.  FULL: also every lifted gradient and the nodal temperature
 // (Q, TH) for the API outputs.
+// FP32 per-stage instances are latency-bound and keep at least 7 waves per
+// SIMD, which their register demand allows without spills (8 does not).
+template <typename T, bool FULL> constexpr int lift1_waves()
+{
+    return (sizeof(T) == 4 && !FULL) ? 7 : 1;
+}
+
 template <int P, typename T, int BS, bool BATCH, bool FULL = false>
-__global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
+__global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T> L)
 {
     using G = Tile<P, BS>;
     Inst<T> a;
@@ -739,6 +755,14 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
         T qf[2][3], uf[2][6];
 #pragma unroll
         for (int m = 0; m < 3; ++m) prolong2<P>(sW[m], base, sL, lt, qf[0][m], qf[1][m]);
+        // outward normal of the + face of this line (the - face's is its
+        // negative, exactly, as the mesh upload forms it)
+        T n[3];
+        {
+            const double *fm = a.mesh.fmet + ((size_t)el * 6 + 2 * lt.d + 1) * 4;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) n[m] = T(fm[m]);
+        }
 #pragma unroll
         for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
 #pragma unroll
@@ -747,11 +771,20 @@ __global__ __launch_bounds__(BS) void k_lift1(Launch<T> L)
                                           (double)uf[s][4], (double)uf[s][5], (double)qf[s][0], (double)qf[s][1],
                                           (double)qf[s][2]);
             const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
-            a.T2[o.at(4, 0)] = qf[s][0];
-            a.T2[o.at(4, 1)] = qf[s][1];
-            a.T2[o.at(4, 2)] = qf[s][2];
-            a.T2[o.at(4, 3)] = T(Tf);
+            const T gn = qf[s][0] * n[0] + qf[s][1] * n[1] + qf[s][2] * n[2];
+            a.T2[o.at(kT2, 0)] = s ? gn : -gn;
+            a.T2[o.at(kT2, 1)] = T(Tf);
         }
+        // wall faces also keep the vector grad c (Navier-slip traction), in
+        // a loop of its own: inside the one above the branch costs ~40 VGPRs
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+            if ((s ? nbp : nbm) < 0) {
+                const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
+                a.T2[o.at(kT2, 2)] = qf[s][0];
+                a.T2[o.at(kT2, 3)] = qf[s][1];
+                a.T2[o.at(kT2, 4)] = qf[s][2];
+            }
     }
 }
 
@@ -790,7 +823,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     // the previous stage) and both sides' grad c and T
     struct Tr {
         int nb;
-        T own[4], oth[4], wn[6], uo[6];
+        T own[2], oth[2], wn[6], uo[6];
     };
     auto load_tr = [&](int task, Tr &r) {
         const FaceTask<P> ft(task);
@@ -799,7 +832,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         if (el >= E) return;
         const FaceIx<G::n2> o((size_t)el * 6 + ft.f, ft.fp);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r.own[k] = a.T2[o.at(4, k)];
+        for (int k = 0; k < 2; ++k) r.own[k] = a.T2[o.at(kT2, k)];
 #pragma unroll
         for (int v = 0; v < 6; ++v)
             if (v != 4) r.uo[v] = TU[o.at(6, v)];
@@ -807,7 +840,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         if (r.nb >= 0) {
             const FaceIx<G::n2> on((size_t)r.nb * 6 + (ft.f ^ 1), ft.fp);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r.oth[k] = a.T2[on.at(4, k)];
+            for (int k = 0; k < 2; ++k) r.oth[k] = a.T2[on.at(kT2, k)];
 #pragma unroll
             for (int v = 0; v < 6; ++v)
                 if (v != 4) r.wn[v] = TU[on.at(6, v)];
@@ -842,15 +875,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             primitives(tr.wn, v5);
 #pragma unroll
             for (int k = 1; k < 5; ++k) w[k] = T(0.5) * (w[k] + v5[k]);
-            Ts = T(0.5) * (tr.own[3] + tr.oth[3]);
-            T acc = T(0);
-#pragma unroll
-            for (int m = 0; m < 3; ++m) acc += T(0.5) * (tr.own[m] + tr.oth[m]) * T(fm[m] * fm[3]);
-            Fs = acc;
+            Ts = T(0.5) * (tr.own[1] + tr.oth[1]);
+            Fs = T(0.5) * (tr.own[0] - tr.oth[0]) * T(fm[3]);
         } else {
             wall_primitives(a.mesh, el, f, w);
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-            Ts = bc.iso ? T(bc.twall) : tr.own[3];
+            Ts = bc.iso ? T(bc.twall) : tr.own[1];
             if (bc.kind != 2) {
                 // static part of the contact-angle flux (a varying wall
                 // temperature is applied in the pass below; the dynamic part,
@@ -1036,7 +1066,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
             const T mn = m0 * n0 + m1 * n1 + m2 * n2;
             const T un = mn * ir;
-            const double Tf = (double)a.T2[o.at(4, 3)];
+            const double Tf = (double)a.T2[o.at(kT2, 1)];
             double pd, cs2;
             eos(a.ph, (double)rho, Tf, pd, cs2);
             // model 2: p_alpha and its sound speed (ap = 0 for model 1)
@@ -1104,7 +1134,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                     // Navier slip: tangential traction gamma_1 div u grad_G c -
                     // gamma_2 (u_t - u_w,t), and its work on u_t
                     const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                    const T gc0 = a.T2[o.at(4, 0)], gc1 = a.T2[o.at(4, 1)], gc2 = a.T2[o.at(4, 2)];
+                    const T gc0 = a.T2[o.at(kT2, 2)], gc1 = a.T2[o.at(kT2, 3)], gc2 = a.T2[o.at(kT2, 4)];
                     const T gcn = gc0 * n0 + gc1 * n1 + gc2 * n2;
                     const T w0 = T(bc.uw[0]), w1 = T(bc.uw[1]), w2 = T(bc.uw[2]);
                     const T wn = w0 * n0 + w1 * n1 + w2 * n2;
@@ -1138,7 +1168,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // order-parameter terms of j_e and F^V_c
             __builtin_amdgcn_sched_barrier(0);
             if (!wall) {
-                const T gcn = a.T2[o.at(4, 0)] * n0 + a.T2[o.at(4, 1)] * n1 + a.T2[o.at(4, 2)] * n2;
+                const T gcn = a.T2[o.at(kT2, 0)];
                 const T lapc = pro(sTs);
                 const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;

@@ -1094,7 +1094,7 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         (rc = dalloc(c, (void **)&c->d_egeo, sizeof(double) * egeo.size())) ||
         (rc = dalloc(c, (void **)&c->d_bcs, sizeof(BcDev) * bcs.size())) ||
         (rc = dalloc(c, &c->d_Q, ts * 15 * c->NN)) || (rc = dalloc(c, &c->d_TH, ts * c->NN)) ||
-        (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * 4 * c->NF)) ||
+        (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * kT2 * c->NF)) ||
         (rc = dalloc(c, &c->d_TF, ts * 7 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 3 * 6 * c->NF)) ||
         (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
         (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS)) ||
