@@ -298,7 +298,7 @@ def model2(w, name=None):
 
 # relaxation model 2 (p_alpha pressure, HLLC interior flux): periodic, ragged,
 # walls with a contact angle, and moving droplets
-M2_BASE = [0, 3, 6, 8]
+M2_BASE = [0, 3, 6, 8, 13, 15]
 M2 = [model2(CASES[k]) for k in M2_BASE]
 M2_IDS = [w.name for w in M2]
 
@@ -336,7 +336,7 @@ def test_dt_parity_model2(torch_cuda, k):
     assert do <= oracle_for(CASES[M2_BASE[k]]).dt(U)
 
 
-@pytest.mark.parametrize("w", [M2[0], M2[2], M2[3]], ids=[M2_IDS[0], M2_IDS[2], M2_IDS[3]])
+@pytest.mark.parametrize("w", [M2[k] for k in (0, 2, 3, 4, 5)], ids=[M2_IDS[k] for k in (0, 2, 3, 4, 5)])
 def test_rk_steps_parity_model2(torch_cuda, w):
     torch = torch_cuda
     nsteps = 10
@@ -425,7 +425,7 @@ def test_full_size_workload_parity(torch_cuda, which, steps):
     assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 9, 11, 12)], ids=[IDS[k] for k in (0, 5, 9, 11, 12)])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 9, 11, 12, 13, 14, 15)], ids=[IDS[k] for k in (0, 5, 9, 11, 12, 13, 14, 15)])
 def test_fp32_mixed_accuracy(torch_cuda, w):
     """FP32-mixed form (FP32 state and bulk arithmetic, FP64 temperature/EoS,
     dt and integrals) against the FP64 oracle after 20 steps: relative density
