@@ -46,6 +46,14 @@ def small_mix():
             side_uwall=((0.0, 0.0, 0.0),) * 5 + ((0.1, 0.0, 0.0),),
             side_gamma=(wl.NO_GAMMA,) * 4 + ((1e-3, 0.05, float("inf"), 0.1), (0.0, 0.1, 0.02, 0.0)),
             side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.08, 0.0, 0.0), (0.0, -0.05, 0.0))), "fp64"),
+        # degenerate meshes: walls on every side, and one element that is
+        # its own neighbour through every face
+        (wl.c4(scale=12).with_(
+            name="mix_closed_box_4x4x2_N3", periodic=(0, 0, 0),
+            side_kind=(wl.NOSLIP_CA, wl.SLIP, wl.NAVIER, wl.NOSLIP_CA, wl.NOSLIP_CA, wl.SLIP),
+            side_twall=(0.9, 0.0, 0.88, 0.87, 0.9, 0.0), side_theta=(60.0, 90.0, 110.0, 90.0, 60.0, 90.0),
+            side_gamma=(wl.NO_GAMMA,) * 2 + ((0.0, 0.05, 0.02, 0.0),) + (wl.NO_GAMMA,) * 3), "fp64"),
+        (base.with_(name="mix_self_periodic_1x1x1_N4", N=4, n=(1, 1, 1)), "fp32_mixed"),
     ]
 
 
