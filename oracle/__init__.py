@@ -32,6 +32,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nskr_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# a prebuilt variant of the oracle (the mutation tests build deliberately
+# broken copies of the C source and check that the pins reject them)
+_SO_OVERRIDE = os.environ.get("NSKR_ORACLE_SO")
 
 
 def build() -> str:
@@ -69,9 +72,12 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        build()
-    L = ctypes.CDLL(_SO)
+    if _SO_OVERRIDE:
+        L = ctypes.CDLL(_SO_OVERRIDE)
+    else:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
     d, i, vp = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
     sig = {
         "orc_create": (vp, [ctypes.POINTER(Params), ctypes.POINTER(Box), ctypes.c_char_p, i]),

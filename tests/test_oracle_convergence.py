@@ -88,7 +88,11 @@ def mms_fields():
     s2 = lambda v: sp.sin(2 * sp.pi * v)
     c2 = lambda v: sp.cos(2 * sp.pi * v)
     rho = 1.0 + 0.1 * s2(X) * c2(Y) + 0.05 * s2(Z)
-    u = [0.1 * s2(Y) + 0.05 * c2(Z), 0.08 * c2(X) * s2(Z), 0.06 * s2(X + Y)]
+    # compressive parts (div u != 0) exercise every div u term of the fluxes
+    # and sources: the Stokes 2/3, -gamma c grad c div u in j_e, and the
+    # alpha/2 (c^2 - rho^2) and gamma |grad c|^2/2 div u sources
+    u = [0.1 * s2(Y) + 0.05 * c2(Z) + 0.04 * s2(X), 0.08 * c2(X) * s2(Z) + 0.03 * c2(Y),
+         0.06 * s2(X + Y) + 0.02 * s2(Z)]
     T = 1.15 + 0.05 * c2(X) * s2(Y) * c2(Z)
     c = rho + 0.02 * c2(X + Z) + 0.01 * s2(Y)
     return (X, Y, Z), rho, u, T, c

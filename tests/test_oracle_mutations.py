@@ -1,0 +1,132 @@
+"""Mutation test of the oracle's pins (CPU only).
+
+Each entry below plants one plausible mistake in a copy of the C oracle -- a
+flipped sign, a dropped or wrong factor, a transposed operand, a one-sided
+instead of a central face value, a perturbed coefficient -- builds the copy,
+and runs the pins named for it in a fresh interpreter against that build
+(``NSKR_ORACLE_SO``).  Those pins must fail.  A control build of the
+unmodified source passes every pin used here, so a failure is the planted
+mistake's doing.  The mistakes are planted in the oracle only, on the CPU;
+nothing here touches the HIP library.
+"""
+import concurrent.futures
+import os
+import subprocess
+import sys
+import tempfile
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "nskr_oracle.c")
+
+OPS = "tests/test_oracle_operator.py::"
+WALLS = "tests/test_oracle_walls_dynamic.py::"
+MMS = "tests/test_oracle_convergence.py::test_manufactured_solution_order"
+
+# name, text in the source, its replacement, pins that must reject it
+MUTATIONS = [
+    ("vdw pressure: +a rho^2",
+     "return rho * pr->R * T / (1.0 - pr->b * rho) - pr->a * rho * rho;",
+     "return rho * pr->R * T / (1.0 - pr->b * rho) + pr->a * rho * rho;",
+     ["tests/test_oracle_thermo.py::test_reduced_constants_give_critical_point_one",
+      "tests/test_oracle_thermo.py::test_maxwell_matches_table2"]),
+    ("Stokes stress: 1/3 div u instead of 2/3",
+     "2.0 / 3.0 * div", "1.0 / 3.0 * div",
+     [WALLS + "test_slip_wall_normal_traction"]),
+    ("Rusanov flux: anti-dissipative jump term",
+     "out[v] = a - 0.5 * lam * (sp->U[v] - sm->U[v]);",
+     "out[v] = a + 0.5 * lam * (sp->U[v] - sm->U[v]);",
+     [WALLS + "test_moving_lid_over_fluid_at_rest"]),
+    ("relaxation source: alpha beta (c - rho)",
+     "0.5 * pr->alpha * (c * c - rho * rho) * div + pr->gam * (0.5 * gc2 * div - cc);\n"
+     "    S[5] = pr->alpha * pr->beta * (rho - c);",
+     "0.5 * pr->alpha * (c * c - rho * rho) * div + pr->gam * (0.5 * gc2 * div - cc);\n"
+     "    S[5] = pr->alpha * pr->beta * (c - rho);",
+     [OPS + "test_uniform_relaxation_follows_stability_polynomial"]),
+    ("temperature: kinetic energy |m|^2 / rho without the 1/2",
+     "double kin = 0.5 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / rho;",
+     "double kin = 1.0 * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) / rho;",
+     [OPS + "test_init_with_velocities_recovers_temperature_and_densities"]),
+    ("energy flux: + gamma c grad c div u",
+     "- pr->gam * c * s->gc[i] * div", "+ pr->gam * c * s->gc[i] * div",
+     [MMS]),
+    ("weak derivative: D_ij instead of D_ji in Dhat",
+     "c->Dh[i][j] = -(c->wg[j] / c->wg[i]) * c->D[j][i];",
+     "c->Dh[i][j] = -(c->wg[j] / c->wg[i]) * c->D[i][j];",
+     [OPS + "test_lift1_exact_for_polynomial_density_and_order_parameter"]),
+    ("BR1: one-sided face value of the primitives",
+     "val = 0.5 * (prim(Um, k) + prim(Up, k));", "val = prim(Um, k);",
+     [OPS + "test_lifted_gradients_of_a_periodic_field_integrate_to_zero"]),
+    ("BR1: one-sided face temperature",
+     "Ts[f * n2 + fp] = 0.5 * (Tm + Tp);", "Ts[f * n2 + fp] = Tm;",
+     [OPS + "test_lifted_gradients_of_a_periodic_field_integrate_to_zero"]),
+    ("divergence lifting: jump instead of mean of grad c . n",
+     "s += 0.5 * (qm + qp) * nv[m];", "s += 0.5 * (qm - qp) * nv[m];",
+     [OPS + "test_divergence_lifting_exact"]),
+    ("contact angle: wall energy derivative of the wrong sign",
+     "return 6.0 * (c - rl) * (c - rv) / (d * d * d) * sigma * costheta;",
+     "return -6.0 * (c - rl) * (c - rv) / (d * d * d) * sigma * costheta;",
+     [OPS + "test_contact_angle_wall_c_flux_integral"]),
+    ("heat flux dropped from j_e",
+     "double je = pr->kappa * s->gT[i]", "double je = 0.0 * s->gT[i]",
+     [WALLS + "test_conduction_between_isothermal_walls_is_steady"]),
+    ("low-storage RK: a digit of A_2 changed",
+     "-567301805773.0 / 1357537059087.0,", "-567301805770.0 / 1357537059087.0,",
+     ["tests/test_oracle_basis.py::test_rk_order_conditions"]),
+    ("relaxation model 2: p - alpha/2 rho^2",
+     "return pr->model == 2 ? p + 0.5 * pr->alpha * rho * rho : p;",
+     "return pr->model == 2 ? p - 0.5 * pr->alpha * rho * rho : p;",
+     [MMS]),
+    ("wall table: interpolation weights swapped",
+     "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
+     "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
+     ["tests/test_oracle_wall_table.py::test_interpolation_error_bound"]),
+]
+
+
+def _build(src_text, path):
+    with open(path + ".c", "w") as f:
+        f.write(src_text)
+    cmd = ["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE", "-o", path,
+           path + ".c", "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True)
+
+
+def _run_pins(so, pins):
+    env = dict(os.environ, NSKR_ORACLE_SO=so, OMP_NUM_THREADS="2")
+    cmd = [sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "-p", "no:randomly", *pins]
+    r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-2000:]
+
+
+@pytest.fixture(scope="module")
+def outcomes():
+    with open(SRC) as f:
+        src = f.read()
+    for name, old, new, _ in MUTATIONS:
+        assert src.count(old) == 1, f"mutation site not unique or missing: {name}"
+    jobs = [("control", src, sorted({p for *_, pins in MUTATIONS for p in pins}))]
+    jobs += [(name, src.replace(old, new), pins) for name, old, new, pins in MUTATIONS]
+    with tempfile.TemporaryDirectory() as tmp:
+        def one(k):
+            name, text, pins = jobs[k]
+            so = os.path.join(tmp, f"mut{k}.so")
+            _build(text, so)
+            return name, _run_pins(so, pins)
+        with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+            return dict(ex.map(one, range(len(jobs))))
+
+
+def test_control_build_passes_every_pin(outcomes):
+    rc, out = outcomes["control"]
+    assert rc == 0, out
+
+
+@pytest.mark.parametrize("name", [m[0] for m in MUTATIONS])
+def test_pins_reject_planted_mistake(outcomes, name):
+    rc, out = outcomes[name]
+    # 1: tests ran and at least one failed (not a crash, a usage error or an
+    # empty selection)
+    assert rc == 1, f"mutation survived or did not run cleanly (exit {rc}): {name}\n{out}"

@@ -249,6 +249,28 @@ def test_reflection_equivariance_between_two_walls():
     assert np.max(np.abs(lhs - rhs) / scale) < 1e-12
 
 
+def test_lifted_gradients_of_a_periodic_field_integrate_to_zero():
+    # BR1 takes one face value for both sides of a face (the mean of the two traces), and
+    # with collocated Gauss quadrature sum_i w_i J q_i over an element is the sum of its
+    # faces' w* n dS (the weighted column sums of Dhat vanish, the lifting weights l(+-1)
+    # sum to one). On a periodic mesh the faces cancel in pairs, so every lifted gradient,
+    # and the divergence lifting lap c, integrates to zero for any state, however
+    # discontinuous between elements. A one-sided face value would leave the integral of
+    # the jumps.
+    o = make(3, (3, 3, 3))
+    rng = np.random.default_rng(5)
+    x, y, z = o.coords()
+    rho = 0.9 + 0.3 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + 0.05 * rng.uniform(-1, 1, o.nnodes)
+    u = 0.1 * rng.uniform(-1, 1, (3, o.nnodes))
+    T = 0.9 + 0.02 * rng.uniform(-1, 1, o.nnodes)
+    c = rho + 0.05 * rng.uniform(-1, 1, o.nnodes)
+    U = conserved(o, rho, u, T, c)
+    w = quad_weights(o)
+    q1, q2 = o.lift1(U), o.lift2(U)
+    for row in list(q1) + list(q2[1:5]):
+        assert abs(np.sum(w * row)) <= 1e-12 * np.sum(w * np.abs(row))
+
+
 # ------------------------------------------------------------ wall integrals
 @pytest.mark.parametrize("theta", [45.0, 60.0, 90.0, 120.0])
 def test_contact_angle_wall_c_flux_integral(theta):
