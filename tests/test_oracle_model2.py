@@ -77,6 +77,29 @@ def test_hllc_resolves_an_isolated_contact_exactly():
     assert not np.allclose(F1, euler_flux(UL, TL, n), rtol=1e-3)
 
 
+@pytest.mark.parametrize("dT", [1e-5, -2e-5])
+def test_hllc_reproduces_linear_acoustics(dT):
+    """Two states at rest with a small pressure jump (same density, slightly
+    different temperature): linear acoustics gives the interface velocity
+    u* = (p_L - p_R) / (rho_L a_L + rho_R a_R) and pressure p* = the mean
+    (equal impedances), so the flux carries mass rho u*, momentum p* n and
+    energy (E + p) u* to first order in the jump (relative error O(u*/a))."""
+    n = np.array([0.0, 0.6, 0.8])
+    rho, T = 0.35, 0.95
+    UL, UR = state(rho, [0.0, 0.0, 0.0], T + dT), state(rho, [0.0, 0.0, 0.0], T)
+    pL, pR = p_alpha(rho, T + dT), p_alpha(rho, T)
+    aL, aR = sound(rho, T + dT), sound(rho, T)
+    us = (pL - pR) / (rho * aL + rho * aR)
+    ps = 0.5 * (pL + pR)
+    F = oracle.numflux(oracle.make_params(**P2), UL, T + dT, UR, T, n)
+    rel = abs(us) / aR
+    assert abs(F[0] - rho * us) <= 10 * rel * abs(rho * us)
+    assert np.allclose(F[1:4], ps * n, rtol=10 * rel * abs(pL - pR) / ps, atol=0)
+    h = 0.5 * (UL[4] + UR[4]) + ps
+    assert abs(F[4] - h * us) <= 10 * rel * abs(h * us)
+    assert abs(F[5] - rho * us) <= 10 * rel * abs(rho * us)
+
+
 def test_hllc_upwinds_supersonic_flow():
     n = np.array([0.0, 1.0, 0.0])
     rhoL, TL, rhoR, TR = 0.5, 1.0, 1.2, 0.95

@@ -79,6 +79,42 @@ MUTATIONS = [
      "return pr->model == 2 ? p + 0.5 * pr->alpha * rho * rho : p;",
      "return pr->model == 2 ? p - 0.5 * pr->alpha * rho * rho : p;",
      [MMS]),
+    ("moving wall: ghost velocity u_w - u instead of 2 u_w - u",
+     "sg.U[1 + m] = 2.0 * rho * uw[m] - sm->U[1 + m];",
+     "sg.U[1 + m] = rho * uw[m] - sm->U[1 + m];",
+     [WALLS + "test_moving_lid_over_fluid_at_rest"]),
+    ("slip wall: ghost keeps half the normal momentum",
+     "sg.U[1 + m] = sm->U[1 + m] - 2.0 * mn * n[m];",
+     "sg.U[1 + m] = sm->U[1 + m] - 1.0 * mn * n[m];",
+     [OPS + "test_mass_conservation_walls_and_curved"]),
+    ("Navier slip: friction gamma_2 of the wrong sign",
+     "- g2 * (ut - (uw[m] - uwn * n[m]));", "+ g2 * (ut - (uw[m] - uwn * n[m]));",
+     [WALLS + "test_navier_slip_couette_under_a_moving_lid"]),
+    ("heat-transfer wall: gamma_3 flux of the wrong sign",
+     "-g3 * (1.0 / wp.Tw - 1.0 / sm->T)", "g3 * (1.0 / wp.Tw - 1.0 / sm->T)",
+     [WALLS + "test_conduction_between_heat_transfer_walls_is_steady"]),
+    ("dynamic angle: normal instead of tangential grad c in the traction",
+     "g1 * div * (sm->gc[m] - gcn * n[m])", "g1 * div * (sm->gc[m] + gcn * n[m])",
+     [WALLS + "test_dynamic_angle_traction_is_tangential"]),
+    ("HLLC: pressure difference of the wrong sign in the contact speed",
+     "double Ss = (p[1] - p[0] + ", "double Ss = (p[0] - p[1] + ",
+     ["tests/test_oracle_model2.py::test_hllc_reproduces_linear_acoustics"]),
+    ("HLLC: star energy without the pressure work",
+     "(Ss - un[k]) * (Ss + p[k] / (rho[k] * (S - un[k]))));", "(Ss - un[k]) * (Ss + 0.0 / (rho[k] * (S - un[k]))));",
+     ["tests/test_oracle_model2.py::test_hllc_reproduces_linear_acoustics"]),
+    ("surface tension: sqrt(gamma) instead of sqrt(2 gamma)",
+     "    return sqrt(2.0 * gam) * I;\n}\n\ndouble orc_sigma(", "    return sqrt(1.0 * gam) * I;\n}\n\ndouble orc_sigma(",
+     ["tests/test_oracle_thermo.py::test_sigma_and_interface_width_table1"]),
+    ("15-point sigma of the wall table: sqrt(gamma) instead of sqrt(2 gamma)",
+     "    return sqrt(2.0 * gam) * I;\n}\n\n/* ", "    return sqrt(1.0 * gam) * I;\n}\n\n/* ",
+     ["tests/test_oracle_wall_table.py::test_interpolation_error_bound"]),
+    ("time step: CFL factor dropped from the advective limit",
+     "double dt_adv = pr->cfl * tN(c->N) * 2.0 / lmax;", "double dt_adv = tN(c->N) * 2.0 / lmax;",
+     [OPS + "test_time_step_scales_with_the_cfl_number"]),
+    ("time step: CFL factor dropped from the parabolic limit",
+     "double dt_par = den > 0.0 ? pr->cfl * RK_REAL / den : INFINITY;",
+     "double dt_par = den > 0.0 ? RK_REAL / den : INFINITY;",
+     [OPS + "test_time_step_scales_with_the_cfl_number"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",

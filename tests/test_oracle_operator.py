@@ -144,6 +144,21 @@ def droplet_state(o, centre, r=0.25, T=0.85, vel=True, seed=3):
     return U
 
 
+@pytest.mark.parametrize("limit,pk", [
+    ("advective", dict(mu=1e-7, kappa=1e-7, gam=1e-7, alpha=1.0, beta=1.0)),
+    ("parabolic", dict(mu=2.0, kappa=2.0)),
+])
+def test_time_step_scales_with_the_cfl_number(limit, pk):
+    # dt = CFL x (the smaller of the advective and the parabolic/source limits, Sec. 4):
+    # halving the CFL number halves dt, with either limit binding (near-inviscid fluid
+    # with weak relaxation: advective; viscous and conductive: parabolic).
+    dts = []
+    for cfl in (0.9, 0.45):
+        o = make(3, (3, 3, 3), cfl=cfl, **pk)
+        dts.append(o.dt(droplet_state(o, (0.5, 0.5, 0.5))))
+    assert abs(dts[0] / dts[1] - 2.0) <= 1e-14
+
+
 def test_mass_conservation_periodic():
     o = make(3, (4, 4, 4))
     U = droplet_state(o, (0.4, 0.55, 0.5))

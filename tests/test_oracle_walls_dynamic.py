@@ -210,6 +210,32 @@ def test_conduction_between_isothermal_walls_is_steady():
     assert np.max(np.abs(o2.rhs(U)[4])) > 1e-3 * kappa * (Tb - Ta) / H / h
 
 
+def test_dynamic_angle_traction_is_tangential():
+    """The gamma_1 traction uses the tangential gradient grad_Gamma c = grad c -
+    (grad c . n) n: with c varying across the floor as well as along it, the
+    floor's gamma_1 term changes the x-momentum but leaves the wall-normal
+    (z) momentum of every node exactly as it is without gamma_1 (gamma_1 enters
+    nothing else that reaches the momentum)."""
+    g1, H, s, d, rho0 = 0.5, 0.5, 0.2, 0.02, 0.3
+    p = oracle.make_params()
+    T0 = 0.9
+    mk = lambda g: oracle.Oracle(p, box(3, (4, 1, 2), (1.0, 1.0, H), {"kind": 3, "g1": g, "twall": T0},
+                                        {"kind": 2}))
+    o1, o0 = mk(g1), mk(0.0)
+    x, y, z = o1.coords()
+    rho = rho0 + d * np.sin(2 * np.pi * x) + 0.5 * d * np.cos(np.pi * z / H)
+    w = s * z * (H - z) * (1 + 0.5 * np.cos(2 * np.pi * x))
+    U = np.zeros((6, o1.nnodes))
+    U[0] = rho
+    U[3] = rho * w
+    U[4] = energy(rho, w * w, T0)
+    U[5] = rho + 0.01 * np.cos(np.pi * z / H)
+    a, b = o1.rhs(U), o0.rhs(U)
+    scale = np.max(np.abs(b[3]))
+    assert np.max(np.abs(a[3] - b[3])) <= 1e-13 * scale
+    assert np.max(np.abs(a[1] - b[1])) > 1e-6 * np.max(np.abs(b[1]))
+
+
 def test_slip_wall_normal_traction():
     """u = (0, 0, s z (H - z)) between two slip walls, uniform density and
     temperature: the total z-momentum changes only through the walls' normal
