@@ -115,6 +115,30 @@ MUTATIONS = [
      "double dt_par = den > 0.0 ? pr->cfl * RK_REAL / den : INFINITY;",
      "double dt_par = den > 0.0 ? RK_REAL / den : INFINITY;",
      [OPS + "test_time_step_scales_with_the_cfl_number"]),
+    ("temperature: relaxation energy alpha (rho - c)^2 without the 1/2",
+     "double rel = 0.5 * pr->alpha * (rho - U[5]) * (rho - U[5]);",
+     "double rel = 1.0 * pr->alpha * (rho - U[5]) * (rho - U[5]);",
+     [OPS + "test_init_recovers_temperature", OPS + "test_init_with_velocities_recovers_temperature_and_densities", MMS]),
+    ("temperature: gradient energy of the wrong sign",
+     "double reps = U[4] - kin - rel - grd;", "double reps = U[4] - kin - rel + grd;",
+     [OPS + "test_init_recovers_temperature", OPS + "test_init_with_velocities_recovers_temperature_and_densities", MMS]),
+    ("sound speed: c_v factor (1 + 1/c_v) dropped",
+     "return (1.0 + 1.0 / pr->cv) * pr->R * T / (q * q) - 2.0 * pr->a * rho;",
+     "return pr->R * T / (q * q) - 2.0 * pr->a * rho;",
+     ["tests/test_oracle_thermo.py::test_speed_of_sound_matches_isentropic_derivative"]),
+    ("model 2 source: alpha rho grad c of the wrong sign",
+     "for (int m = 0; m < 3; ++m) S[1 + m] = pr->alpha * rho * gc[m];",
+     "for (int m = 0; m < 3; ++m) S[1 + m] = -pr->alpha * rho * gc[m];",
+     [MMS]),
+    ("surface lifting: l(+1) weights on the minus faces",
+     "c->lhm[j] = c->lm[j] / c->wg[j];", "c->lhm[j] = c->lp[j] / c->wg[j];",
+     [OPS + "test_lift1_exact_for_polynomial_density_and_order_parameter"]),
+    ("wall temperature: gradient subtracted",
+     "w->Tw += tg[0] * x[0] + tg[1] * x[1] + tg[2] * x[2];", "w->Tw -= tg[0] * x[0] + tg[1] * x[1] + tg[2] * x[2];",
+     ["tests/test_oracle_wall_table.py::test_isothermal_wall_following_the_fluid_temperature"]),
+    ("stage times: every stage at the step's start",
+     "c->time = t + RK_C[s] * dt;", "c->time = t;",
+     ["tests/test_oracle_wall_table.py::test_rk_stages_use_their_own_times"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
@@ -151,7 +175,7 @@ def outcomes():
             so = os.path.join(tmp, f"mut{k}.so")
             _build(text, so)
             return name, _run_pins(so, pins)
-        with concurrent.futures.ThreadPoolExecutor(max_workers=4) as ex:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=6) as ex:
             return dict(ex.map(one, range(len(jobs))))
 
 
