@@ -139,6 +139,13 @@ MUTATIONS = [
     ("stage times: every stage at the step's start",
      "c->time = t + RK_C[s] * dt;", "c->time = t;",
      ["tests/test_oracle_wall_table.py::test_rk_stages_use_their_own_times"]),
+    ("integrals: kinetic energy without the 1/2",
+     "out[6] += wJ * 0.5 * (U6[1] * U6[1] + U6[2] * U6[2] + U6[3] * U6[3]) / rho;",
+     "out[6] += wJ * 1.0 * (U6[1] * U6[1] + U6[2] * U6[2] + U6[3] * U6[3]) / rho;",
+     [OPS + "test_integrals_against_quadrature_and_thermodynamics"]),
+    ("integrals: entropy of the wrong sign",
+     "out[18] += -wJ * rho * eta;", "out[18] += wJ * rho * eta;",
+     [OPS + "test_integrals_against_quadrature_and_thermodynamics"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",

@@ -364,6 +364,35 @@ def test_init_with_velocities_recovers_temperature_and_densities():
     assert np.all(U[2] == 0.0) and np.all(U[3] == 0.0)
 
 
+def test_integrals_against_quadrature_and_thermodynamics():
+    # The reductions are Gauss-quadrature integrals with the Jacobian: each is checked
+    # against a numpy sum over the oracle's nodes with its weights (pinned against
+    # numpy's Gauss rule) and metrics, using the lifted grad c and the nodal temperature
+    # of the liftings; the entropy integral -int rho eta against d psi / dT of the
+    # Helmholtz energy of Sec. 2.1 (entropy per volume = -d psi/dT), by a numerical
+    # derivative; the volume against the box's; the health counters are zero.
+    from test_oracle_thermo import psi
+    o = make(3, (3, 3, 2), length=(1.0, 1.0, 0.6))
+    U = droplet_state(o, (0.5, 0.5, 0.3), r=0.2)
+    s = o.reduce(U)
+    w = quad_weights(o)
+    pr = o.params
+    rho, m, E, c = U[0], U[1:4], U[4], U[5]
+    gc = o.lift1(U)[12:15]
+    T = o.lift2(U)[0]
+    expect = {0: rho, 1: m[0], 2: m[1], 3: m[2], 4: E, 5: c, 6: 0.5 * np.sum(m * m, axis=0) / rho,
+              7: 0.5 * pr.gam * np.sum(gc * gc, axis=0), 8: 0.5 * pr.alpha * (rho - c) ** 2, 9: (rho - c) ** 2}
+    for k, f in expect.items():
+        assert abs(s[k] - w @ f) <= 1e-13 * (w @ np.abs(f)) + 1e-300, k
+    assert s[10] == rho.min() and s[11] == rho.max()
+    assert abs(s[12] - T.min()) <= 1e-14 and abs(s[13] - T.max()) <= 1e-14
+    assert np.all(s[14:18] == 0)
+    h = 1e-5
+    dpsi_dT = np.array([(psi(r, t + h) - psi(r, t - h)) / (2 * h) for r, t in zip(rho, T)])
+    assert abs(s[18] - w @ dpsi_dT) <= 1e-7 * (w @ np.abs(dpsi_dT))
+    assert abs(s[19] - 0.6) <= 1e-14
+
+
 def test_collision_state_is_mirror_antisymmetric():
     """The head-on pair is symmetric under x -> 1 - x with the x-momentum
     changing sign: total x-momentum vanishes and the integrals of density and
