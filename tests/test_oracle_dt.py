@@ -1,0 +1,142 @@
+"""Pins of the time-step constants (the reading of the time-step rule: an
+advective limit CFL T_N 2 / sum_d lambda^d and a parabolic/source limit
+CFL R / (alpha beta + RHO_N nu_max sum_d (|Ja^d|/(2J))^2)).
+
+The constants are derived here independently, with numpy, from the 1D
+periodic Gauss DGSEM (nodes and weights from numpy's Gauss rule, a
+barycentric differentiation matrix) and the stability polynomial of the
+low-storage RK scheme:
+
+* R: the stability interval of the scheme on the negative real axis;
+* T_N: the largest stable dt a / h of linear advection with the upwind
+  (Rusanov) flux, over the Bloch spectrum of an infinite periodic mesh;
+* RHO_N: the spectral radius of the BR1 diffusion operator (central face
+  values in both liftings) at h = 1 on a 16-element periodic mesh, the mesh
+  the tabulated values come from; the maximum over all wavenumbers is at most
+  1 % larger, a margin the CFL number 0.9 covers.
+
+Each is recovered from the oracle's time step on a uniform state at rest
+where one limit alone binds, and compared.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from test_oracle_basis import butcher_from_2n
+
+CFL = 0.9
+
+
+def gauss_dg(N):
+    P = N + 1
+    x, w = np.polynomial.legendre.leggauss(P)
+    bw = np.array([1.0 / np.prod([x[j] - x[k] for k in range(P) if k != j]) for j in range(P)])
+    D = np.zeros((P, P))
+    for i in range(P):
+        for j in range(P):
+            if i != j:
+                D[i, j] = bw[j] / bw[i] / (x[i] - x[j])
+        D[i, i] = -D[i].sum()
+
+    def lag(t):
+        return np.array([np.prod([(t - x[k]) / (x[j] - x[k]) for k in range(P) if k != j]) for j in range(P)])
+    return w, D, lag(-1.0), lag(1.0)
+
+
+def stability_poly():
+    A, B, _ = oracle.rk_coeffs()
+    a, b = butcher_from_2n(A, B)
+    g, v = [1.0], np.ones(len(b))
+    for _ in range(len(b)):
+        g.append(b @ v)
+        v = a @ v
+    return np.array(g)
+
+
+def R(z, g):
+    return sum(gk * z ** k for k, gk in enumerate(g))
+
+
+def real_interval(g):
+    lo, hi = 1.0, 10.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        ok = np.max(np.abs(R(-np.linspace(0.0, mid, 20001), g))) <= 1 + 1e-12
+        lo, hi = (mid, hi) if ok else (lo, mid)
+    return lo
+
+
+def operators(N, theta):
+    """1D element operators for Bloch wavenumber theta, h = 1 (J = 1/2):
+    upwind advection (a = 1) and BR1 diffusion (nu = 1)."""
+    w, D, lm, lp = gauss_dg(N)
+    J = 0.5
+    Dt = np.diag(1 / w) @ D.T @ np.diag(w)    # (w_j / w_i) D_ji
+    e = np.exp(1j * theta)
+    adv = (Dt - np.outer(lp / w, lp) + np.outer(lm / w, lp) / e) / J
+    usR, usL = 0.5 * (lp + e * lm), 0.5 * (lp / e + lm)
+    G = (-Dt + np.outer(lp / w, usR) - np.outer(lm / w, usL)) / J
+    return adv, G @ G
+
+
+def uniform_state(o, rho, T):
+    pr = o.params
+    U = np.zeros((6, o.nnodes))
+    U[0] = rho
+    U[4] = rho * (pr.R * pr.cv * T - pr.a * rho)
+    U[5] = rho
+    return U
+
+
+def make(N, **pk):
+    p = oracle.make_params(cfl=CFL, **pk)
+    return oracle.Oracle(p, oracle.make_box(N, (2, 2, 2)))   # unit cube, h = 1/2
+
+
+@pytest.fixture(scope="module")
+def rk_interval():
+    return real_interval(stability_poly())
+
+
+def test_real_stability_interval_from_the_relaxation_limit(rk_interval):
+    # mu = k = gamma = 0: only alpha beta is left in the parabolic/source limit, and
+    # at rest with a slow sound speed the advective limit is far away
+    al, be = 50.0, 400.0
+    o = make(3, mu=0.0, kappa=0.0, gam=0.0, alpha=al, beta=be)
+    dt = o.dt(uniform_state(o, 0.3, 0.9))
+    assert abs(dt * al * be / CFL / rk_interval - 1) <= 2e-5, (dt * al * be / CFL, rk_interval)
+    assert 4.6567 <= rk_interval < 4.6568
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_advective_constant(N, rk_interval):
+    g = stability_poly()
+    lam = np.concatenate([np.linalg.eigvals(operators(N, th)[0]) for th in np.linspace(0, 2 * np.pi, 721)])
+    lo, hi = 0.0, 2.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if np.max(np.abs(R(mid * lam, g))) <= 1 + 1e-12 else (lo, mid)
+    # oracle: at rest, no diffusion or relaxation: dt = CFL T_N 2 / sum_d (c 2 / h)
+    o = make(N, mu=0.0, kappa=0.0, gam=0.0, alpha=0.0, beta=0.0)
+    rho, T = 0.3, 0.9
+    dt = o.dt(uniform_state(o, rho, T))
+    c = np.sqrt(oracle.cs2(rho, T))
+    h = 0.5
+    tn = dt * 3 * c / (CFL * h)
+    assert abs(tn / lo - 1) <= 3e-4, (N, tn, lo)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_parabolic_constant(N, rk_interval):
+    K = 16
+    rho16 = max(np.max(np.abs(np.linalg.eigvals(operators(N, 2 * np.pi * k / K)[1]))) for k in range(K))
+    bloch = max(np.max(np.abs(np.linalg.eigvals(operators(N, th)[1]))) for th in np.linspace(0, 2 * np.pi, 721))
+    assert 1.0 <= bloch / rho16 <= 1.01
+    # oracle: at rest, viscosity only (nu_max = 4 mu / (3 rho)), large enough for the
+    # parabolic limit to bind: dt = CFL R / (RHO_N nu 3 / h^2)
+    mu, rho, T, h = 5.0, 0.3, 0.9, 0.5
+    o = make(N, mu=mu, kappa=0.0, gam=0.0, alpha=0.0, beta=0.0)
+    dt = o.dt(uniform_state(o, rho, T))
+    nu = 4 * mu / (3 * rho)
+    rhon = CFL * rk_interval * h * h / (3 * nu * dt)
+    assert abs(rhon / rho16 - 1) <= 1e-3, (N, rhon, rho16)

@@ -146,6 +146,17 @@ MUTATIONS = [
     ("integrals: entropy of the wrong sign",
      "out[18] += -wJ * rho * eta;", "out[18] += wJ * rho * eta;",
      [OPS + "test_integrals_against_quadrature_and_thermodynamics"]),
+    ("time step: a digit of T_3 swapped",
+     "static const double T[6] = {0, 0, 0.3521, 0.2200, 0.1523, 0.1126};",
+     "static const double T[6] = {0, 0, 0.3521, 0.2020, 0.1523, 0.1126};",
+     ["tests/test_oracle_dt.py::test_advective_constant"]),
+    ("time step: a digit of RHO_3 swapped",
+     "static const double R[6] = {0, 0, 64.8, 176.2, 387.0, 745.2};",
+     "static const double R[6] = {0, 0, 64.8, 167.2, 387.0, 745.2};",
+     ["tests/test_oracle_dt.py::test_parabolic_constant"]),
+    ("time step: a digit of the real stability interval swapped",
+     "#define RK_REAL 4.6567", "#define RK_REAL 4.5667",
+     ["tests/test_oracle_dt.py::test_real_stability_interval_from_the_relaxation_limit"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
