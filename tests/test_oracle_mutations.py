@@ -157,6 +157,16 @@ MUTATIONS = [
     ("time step: a digit of the real stability interval swapped",
      "#define RK_REAL 4.6567", "#define RK_REAL 4.5667",
      ["tests/test_oracle_dt.py::test_real_stability_interval_from_the_relaxation_limit"]),
+    ("droplets: inverted profile (vapour inside)",
+     "double th = tanh((rad[j] - sqrt(d2)) / width);", "double th = tanh((sqrt(d2) - rad[j]) / width);",
+     [OPS + "test_droplet_excess_mass_closed_form"]),
+    ("droplets: twice the interface width",
+     "double th = tanh((rad[j] - sqrt(d2)) / width);", "double th = tanh((rad[j] - sqrt(d2)) / (2.0 * width));",
+     [OPS + "test_droplet_excess_mass_closed_form"]),
+    ("droplets: no minimum image across periodic sides",
+     "if (c->box.periodic[m]) dx -= c->box.len[m] * round(dx / c->box.len[m]);",
+     "if (c->box.periodic[m]) dx -= 0.0 * round(dx / c->box.len[m]);",
+     [OPS + "test_droplet_excess_mass_closed_form"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",

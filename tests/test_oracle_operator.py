@@ -393,6 +393,24 @@ def test_integrals_against_quadrature_and_thermodynamics():
     assert abs(s[19] - 0.6) <= 1e-14
 
 
+def test_droplet_excess_mass_closed_form():
+    # The tanh profile of Sec. 4.1.1 is a Fermi function of the distance d:
+    # (1 + tanh((r - d)/w))/2 = 1/(1 + exp((d - r)/(w/2))), so one droplet's excess mass
+    # is (rho_l - rho_v) 4 pi/3 (r^3 + pi^2 w^2 r / 4) up to terms of order exp(-2r/w)
+    # (the Sommerfeld expansion of the Fermi integral). The w^2 part is a tenth of the
+    # total here. The same droplet centred across a periodic side or corner has the same
+    # mass (minimum-image distances).
+    o = make(4, (8, 8, 8))
+    w = quad_weights(o)
+    rv, rl, _ = oracle.maxwell(0.85)
+    r, wd = 0.25, 0.05
+    exact = (rl - rv) * 4 * math.pi / 3 * (r ** 3 + math.pi ** 2 * wd ** 2 * r / 4)
+    for centre in ((0.5, 0.5, 0.5), (0.05, 0.5, 0.93), (0.0, 1.0, 0.0)):
+        U = o.init_droplets(0.85, [centre], [r], wd)
+        assert abs(w @ (U[0] - rv) / exact - 1) <= 1e-4, centre
+        assert U[0].max() <= rl and U[0].min() >= rv
+
+
 def test_collision_state_is_mirror_antisymmetric():
     """The head-on pair is symmetric under x -> 1 - x with the x-momentum
     changing sign: total x-momentum vanishes and the integrals of density and
