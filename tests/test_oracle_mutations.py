@@ -167,6 +167,28 @@ MUTATIONS = [
      "if (c->box.periodic[m]) dx -= c->box.len[m] * round(dx / c->box.len[m]);",
      "if (c->box.periodic[m]) dx -= 0.0 * round(dx / c->box.len[m]);",
      [OPS + "test_droplet_excess_mass_closed_form"]),
+    ("energy flux: viscous work tau u dropped",
+     "Fv[i][4] = Tv[i][0] * u[0] + Tv[i][1] * u[1] + Tv[i][2] * u[2] + je;", "Fv[i][4] = je;",
+     [MMS, WALLS + "test_navier_slip_couette_under_a_moving_lid"]),
+    ("order-parameter flux: gamma beta grad c without beta",
+     "Fv[i][5] = pr->gam * pr->beta * s->gc[i];", "Fv[i][5] = pr->gam * s->gc[i];",
+     [MMS, OPS + "test_contact_angle_wall_c_flux_integral"]),
+    ("energy flux: zeta_c term of the wrong sign",
+     "+ pr->gam * s->gc[i] * zeta;", "- pr->gam * s->gc[i] * zeta;",
+     [MMS, OPS + "test_energy_flux_zeta_term_closed_form"]),
+    ("zeta_c: alpha (c - rho) instead of alpha (rho - c)",
+     "double zeta = pr->beta * (pr->gam * s->lapc + pr->alpha * (rho - c));",
+     "double zeta = pr->beta * (pr->gam * s->lapc + pr->alpha * (c - rho));",
+     [MMS, OPS + "test_energy_flux_zeta_term_closed_form"]),
+    ("HLLC: Davis estimates swapped (min for the right speed)",
+     "double SR = fmax(un[0] + a[0], un[1] + a[1]);", "double SR = fmin(un[0] + a[0], un[1] + a[1]);",
+     ["tests/test_oracle_model2.py"]),
+    ("contact angle: theta in radians taken as degrees",
+     "c->wcos[f] = cos(bx->side_theta[f] * M_PI / 180.0);", "c->wcos[f] = cos(bx->side_theta[f]);",
+     [OPS + "test_contact_angle_wall_c_flux_integral"]),
+    ("Jacobian scaling: + (volume + surface) / J",
+     "Ut[v * nn + (size_t)e * n3 + nd] = -acc[v] / J + S[v];", "Ut[v * nn + (size_t)e * n3 + nd] = acc[v] / J + S[v];",
+     [OPS + "test_mass_conservation_walls_and_curved", MMS]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
