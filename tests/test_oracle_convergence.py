@@ -79,7 +79,7 @@ def test_isentropic_vortex_order(N, min_rate):
 
 
 # ------------------------------------------------------------ manufactured
-MMS_PARAMS = dict(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.02, kappa=0.03, gam=2e-3,
+MMS_PARAMS = dict(R=8.0 / 3.0, a=3.0, b=1.0 / 3.0, cv=5.0, mu=0.02, kappa=0.03, gam=2e-2,
                   alpha=2.0, beta=3.0, cfl=0.9)
 
 

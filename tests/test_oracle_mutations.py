@@ -189,6 +189,16 @@ MUTATIONS = [
     ("Jacobian scaling: + (volume + surface) / J",
      "Ut[v * nn + (size_t)e * n3 + nd] = -acc[v] / J + S[v];", "Ut[v * nn + (size_t)e * n3 + nd] = acc[v] / J + S[v];",
      [OPS + "test_mass_conservation_walls_and_curved", MMS]),
+    ("energy source: gamma grad c (x) grad c : grad u of the wrong sign",
+     "0.5 * pr->alpha * (c * c - rho * rho) * div + pr->gam * (0.5 * gc2 * div - cc);\n    S[5]",
+     "0.5 * pr->alpha * (c * c - rho * rho) * div + pr->gam * (0.5 * gc2 * div + cc);\n    S[5]",
+     [MMS]),
+    ("energy source: alpha/2 (c^2 - rho^2) div u of the wrong sign",
+     "           0.5 * pr->alpha * (c * c - rho * rho) * div", "           0.5 * pr->alpha * (rho * rho - c * c) * div",
+     [MMS]),
+    ("model 2 energy source: alpha/2 c^2 div u dropped",
+     "+ 0.5 * pr->alpha * c * c * div +", "+ 0.0 * pr->alpha * c * c * div +",
+     [MMS]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
