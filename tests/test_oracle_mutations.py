@@ -199,6 +199,15 @@ MUTATIONS = [
     ("model 2 energy source: alpha/2 c^2 div u dropped",
      "+ 0.5 * pr->alpha * c * c * div +", "+ 0.0 * pr->alpha * c * c * div +",
      [MMS]),
+    ("relaxation wall value: zeta_c = +gamma_1 gamma_4 div u",
+     "double zeta = -g1 * g4 * div;", "double zeta = g1 * g4 * div;",
+     [WALLS + "test_dynamic_angle_and_relaxation_wall_rates"]),
+    ("no-slip wall: BR1 wall velocity taken from the fluid",
+     "val = c->box.side_uwall[c->side[e * 6 + f]][k - 1]; /* no-slip */", "val = prim(Um, k); /* no-slip */",
+     [WALLS + "test_wall_values_of_the_lifted_velocity"]),
+    ("slip wall: BR1 wall velocity keeps its normal part",
+     "val = prim(Um, k) - un * n[k - 1];", "val = prim(Um, k);",
+     [WALLS + "test_wall_values_of_the_lifted_velocity"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",

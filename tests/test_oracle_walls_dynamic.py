@@ -236,6 +236,31 @@ def test_dynamic_angle_traction_is_tangential():
     assert np.max(np.abs(a[1] - b[1])) > 1e-6 * np.max(np.abs(b[1]))
 
 
+def test_wall_values_of_the_lifted_velocity():
+    """BR1 takes the wall's own value at a wall face (no-slip: the wall
+    velocity; slip: the fluid velocity without its normal part), and the
+    lifted gradient integrates to the sum over the boundary of that value
+    times the outward normal (interior faces cancel). A uniform velocity
+    (U0, 0, W0), which satisfies neither wall condition, between a slip floor
+    and a fixed no-slip lid therefore gives int du/dz = -A U0 (floor: U0,
+    lid: 0) and int dw/dz = 0 (both walls: 0), A the wall area."""
+    U0, W0, rho, T, H = 0.2, 0.15, 0.3, 0.9, 0.6
+    p = oracle.make_params()
+    o = oracle.Oracle(p, box(3, (2, 2, 3), (1.0, 1.0, H), {"kind": 2}, {"kind": 1, "twall": T}))
+    U = np.zeros((6, o.nnodes))
+    U[0] = rho
+    U[1] = rho * U0
+    U[3] = rho * W0
+    U[4] = energy(rho, U0 * U0 + W0 * W0, T)
+    U[5] = rho
+    q = o.lift1(U)
+    W = weights(o)
+    # q rows: grad rho (0-2), grad u (3-5), grad v (6-8), grad w (9-11), grad c (12-14)
+    assert abs(W @ q[5] - (-1.0 * U0)) <= 1e-13
+    assert abs(W @ q[11]) <= 1e-13
+    assert abs(W @ q[3]) <= 1e-13 and abs(W @ q[9]) <= 1e-13
+
+
 def test_slip_wall_normal_traction():
     """u = (0, 0, s z (H - z)) between two slip walls, uniform density and
     temperature: the total z-momentum changes only through the walls' normal
