@@ -208,6 +208,17 @@ MUTATIONS = [
     ("slip wall: BR1 wall velocity keeps its normal part",
      "val = prim(Um, k) - un * n[k - 1];", "val = prim(Um, k);",
      [WALLS + "test_wall_values_of_the_lifted_velocity"]),
+    ("isothermal wall: BR1 wall temperature taken from the fluid",
+     "Ts[f * n2 + fp] = wall_isothermal(c, kd, sd) ? wp.Tw : Tm;", "Ts[f * n2 + fp] = Tm;",
+     [WALLS + "test_conduction_between_isothermal_walls_is_steady", OPS + "test_hot_isothermal_wall_heats_fluid"]),
+    ("adiabatic slip wall: BR1 wall temperature set to the wall's",
+     "Ts[f * n2 + fp] = wall_isothermal(c, kd, sd) ? wp.Tw : Tm;", "Ts[f * n2 + fp] = wp.Tw;",
+     [WALLS + "test_navier_wall_without_coefficients_is_the_slip_wall", WALLS + "test_slip_wall_normal_traction",
+      OPS + "test_free_stream_at_rest_with_walls"]),
+    ("neutral slip wall: contact-angle flux not zero",
+     "                        fs[f * n2 + fp] = 0.0;\n                    } else {",
+     "                        fs[f * n2 + fp] = 1e-3;\n                    } else {",
+     [WALLS + "test_navier_wall_without_coefficients_is_the_slip_wall", OPS + "test_free_stream_at_rest_with_walls"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
