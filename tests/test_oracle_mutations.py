@@ -219,6 +219,16 @@ MUTATIONS = [
      "                        fs[f * n2 + fp] = 0.0;\n                    } else {",
      "                        fs[f * n2 + fp] = 1e-3;\n                    } else {",
      [WALLS + "test_navier_wall_without_coefficients_is_the_slip_wall", OPS + "test_free_stream_at_rest_with_walls"]),
+    ("HLLC: star momentum with (S* + u_n)",
+     "Us[1 + m] = f * (U[1 + m] / U[0] + (Ss - un[k]) * n[m]);", "Us[1 + m] = f * (U[1 + m] / U[0] + (Ss + un[k]) * n[m]);",
+     ["tests/test_oracle_model2.py"]),
+    ("HLLC: order parameter not carried as c / rho",
+     "Us[5] = f * U[5] / U[0];", "Us[5] = f;",
+     ["tests/test_oracle_model2.py"]),
+    ("viscous stress: 2 du_i/dx_j instead of the symmetric part",
+     "Tv[i][j] = pr->mu * (gu[i][j] + gu[j][i] - (i == j ? 2.0 / 3.0 * div : 0.0));",
+     "Tv[i][j] = pr->mu * (2.0 * gu[i][j] - (i == j ? 2.0 / 3.0 * div : 0.0));",
+     [MMS, WALLS + "test_navier_slip_couette_under_a_moving_lid"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
