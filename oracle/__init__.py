@@ -20,7 +20,7 @@ wall under compression, closed-form rates of the gamma_1 and gamma_4 terms,
 the contact-angle c-flux integral, and a lid moving over fluid at rest (its
 ghost flux); the wall-temperature table by its grid values, the linear
 interpolation bound and its time and stage evaluation.  A mutation test
-(``tests/test_oracle_mutations.py``) plants 60 plausible mistakes in copies of
+(``tests/test_oracle_mutations.py``) plants 63 plausible mistakes in copies of
 the C source and checks that the pins reject each of them.
 """
 from __future__ import annotations

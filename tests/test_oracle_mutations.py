@@ -229,6 +229,15 @@ MUTATIONS = [
      "Tv[i][j] = pr->mu * (gu[i][j] + gu[j][i] - (i == j ? 2.0 / 3.0 * div : 0.0));",
      "Tv[i][j] = pr->mu * (2.0 * gu[i][j] - (i == j ? 2.0 / 3.0 * div : 0.0));",
      [MMS, WALLS + "test_navier_slip_couette_under_a_moving_lid"]),
+    ("face traces: l(+1) used on the minus faces",
+     "c->lm[j] = lagrange(P, c->xg, j, -1.0);", "c->lm[j] = lagrange(P, c->xg, j, 1.0);",
+     ["tests/test_oracle_basis.py::test_face_interpolation", OPS + "test_lift1_exact_for_polynomial_density_and_order_parameter"]),
+    ("model 2: wave speed without alpha rho",
+     "if (pr->model == 2) a2 += pr->alpha * rho;", "if (pr->model == 2) a2 += 0.0 * rho;",
+     ["tests/test_oracle_model2.py", MMS]),
+    ("curved metrics: curl form of the wrong sign",
+     "JaGL[(i * 3 + n) * sz + nd] = -(s1 - s2);", "JaGL[(i * 3 + n) * sz + nd] = (s1 - s2);",
+     [OPS + "test_metrics_satisfy_the_cofactor_identity"]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",

@@ -427,6 +427,32 @@ def test_energy_flux_zeta_term_closed_form():
     assert np.max(np.abs(Et - exact)) <= 5e-5 * np.max(np.abs(exact))
 
 
+def _cofactor_identity_error(N, amp):
+    o = make(N, (3, 3, 3), amp=amp)
+    P, E = N + 1, o.nelems
+    Ja, J, _ = o.metrics()
+    X = o.coords().reshape(3, E, P, P, P)            # node axes k, j, i (i along xi^1)
+    D = oracle.basis(N)[2]
+    dX = [np.einsum("il,cekjl->cekji", D, X), np.einsum("jl,cekli->cekji", D, X),
+          np.einsum("kl,celji->cekji", D, X)]
+    err = 0.0
+    for d in range(3):
+        for e in range(3):
+            s = sum(Ja[3 * d + m] * dX[e][m].reshape(-1) for m in range(3))
+            err = max(err, np.max(np.abs(s - (J if d == e else 0.0))) / np.max(np.abs(J)))
+    return err
+
+
+def test_metrics_satisfy_the_cofactor_identity():
+    # Ja^d_m = J d xi^d / d x_m, so sum_m Ja^d_m d x_m / d xi^e = J delta_de, with the
+    # derivatives of the node coordinates taken by the (pinned) derivative matrix:
+    # exact on affine elements; on curved elements the curl form of the metrics meets it
+    # to its interpolation error, which falls with the degree.
+    assert _cofactor_identity_error(3, 0.0) <= 1e-13
+    e3, e5 = _cofactor_identity_error(3, 0.05), _cofactor_identity_error(5, 0.05)
+    assert e5 <= 5e-3 and e5 < 0.1 * e3
+
+
 def test_collision_state_is_mirror_antisymmetric():
     """The head-on pair is symmetric under x -> 1 - x with the x-momentum
     changing sign: total x-momentum vanishes and the integrals of density and
