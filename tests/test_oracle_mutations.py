@@ -238,11 +238,32 @@ MUTATIONS = [
     ("curved metrics: curl form of the wrong sign",
      "JaGL[(i * 3 + n) * sz + nd] = -(s1 - s2);", "JaGL[(i * 3 + n) * sz + nd] = (s1 - s2);",
      [OPS + "test_metrics_satisfy_the_cofactor_identity"]),
+    ("Rusanov: the smaller of the two wave speeds",
+     "double lam = lm > lp ? lm : lp;", "double lam = lm < lp ? lm : lp;",
+     [MMS, WALLS + "test_moving_lid_over_fluid_at_rest", OPS + "test_reflection_equivariance_between_two_walls"]),
+    ("Rusanov: wave speed without |u . n|",
+     "double lm = fabs(unm) + wave_speed(pr, sm->U[0], sm->T);", "double lm = wave_speed(pr, sm->U[0], sm->T);",
+     [WALLS + "test_moving_lid_over_fluid_at_rest", MMS]),
+    ("model 2: relaxation source alpha beta (c - rho)",
+     "S[5] = pr->alpha * pr->beta * (rho - c);\n        return;", "S[5] = pr->alpha * pr->beta * (c - rho);\n        return;",
+     [MMS]),
     ("wall table: interpolation weights swapped",
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
      ["tests/test_oracle_wall_table.py::test_interpolation_error_bound"]),
 ]
+
+
+# Mistakes no pin rejects yet (the oracle's header and the design notes call
+# the function "parity unpinned"); strict: a pin that starts to reject one
+# turns its entry into an unexpected pass, to be moved to the list above.
+KNOWN_SURVIVORS = {
+    "Rusanov: the smaller of the two wave speeds":
+        "the Rusanov dissipation speed only scales jump terms, which are spectrally small on "
+        "smooth states; no closed form singles out max(|u.n| + c) of the two sides",
+    "Rusanov: wave speed without |u . n|":
+        "as above; the wall pins are at rest (u.n = 0)",
+}
 
 
 def _build(src_text, path):
@@ -283,7 +304,9 @@ def test_control_build_passes_every_pin(outcomes):
     assert rc == 0, out
 
 
-@pytest.mark.parametrize("name", [m[0] for m in MUTATIONS])
+@pytest.mark.parametrize("name", [
+    pytest.param(m[0], marks=pytest.mark.xfail(strict=True, reason=KNOWN_SURVIVORS[m[0]]))
+    if m[0] in KNOWN_SURVIVORS else m[0] for m in MUTATIONS])
 def test_pins_reject_planted_mistake(outcomes, name):
     rc, out = outcomes[name]
     # 1: tests ran and at least one failed (not a crash, a usage error or an
