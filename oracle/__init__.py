@@ -21,11 +21,10 @@ the contact-angle c-flux integral, and a lid moving over fluid at rest (its
 ghost flux); the wall-temperature table by its grid values, the linear
 interpolation bound and its time and stage evaluation.  A mutation test
 (``tests/test_oracle_mutations.py``) plants 66 plausible mistakes in copies of
-the C source and checks that the pins reject each of them but two.
-Parity unpinned: the Rusanov dissipation speed (the larger of |u . n| + c on
-the two sides, as the flux is stated in Sec. 3.1); it only scales jump terms
-that are spectrally small on smooth states, and no closed form here singles
-it out (the mutation test records the two surviving variants).
+the C source and checks that the pins reject every one of them.  The Rusanov
+dissipation speed (the larger of |u . n| + c on the two sides, as the flux is
+stated in Sec. 3.1) is pinned by the discrete energy balance of a passive
+order parameter that is constant per element (``tests/test_oracle_rusanov.py``).
 """
 from __future__ import annotations
 

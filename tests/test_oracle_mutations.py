@@ -24,6 +24,7 @@ SRC = os.path.join(ROOT, "oracle", "nskr_oracle.c")
 OPS = "tests/test_oracle_operator.py::"
 WALLS = "tests/test_oracle_walls_dynamic.py::"
 MMS = "tests/test_oracle_convergence.py::test_manufactured_solution_order"
+RUS = "tests/test_oracle_rusanov.py::"
 
 # name, text in the source, its replacement, pins that must reject it
 MUTATIONS = [
@@ -240,10 +241,10 @@ MUTATIONS = [
      [OPS + "test_metrics_satisfy_the_cofactor_identity"]),
     ("Rusanov: the smaller of the two wave speeds",
      "double lam = lm > lp ? lm : lp;", "double lam = lm < lp ? lm : lp;",
-     [MMS, WALLS + "test_moving_lid_over_fluid_at_rest", OPS + "test_reflection_equivariance_between_two_walls"]),
+     [RUS + "test_rusanov_speed_is_the_larger_of_the_two_sides"]),
     ("Rusanov: wave speed without |u . n|",
      "double lm = fabs(unm) + wave_speed(pr, sm->U[0], sm->T);", "double lm = wave_speed(pr, sm->U[0], sm->T);",
-     [WALLS + "test_moving_lid_over_fluid_at_rest", MMS]),
+     [RUS + "test_rusanov_speed_of_each_side_is_its_own"]),
     ("model 2: relaxation source alpha beta (c - rho)",
      "S[5] = pr->alpha * pr->beta * (rho - c);\n        return;", "S[5] = pr->alpha * pr->beta * (c - rho);\n        return;",
      [MMS]),
@@ -257,13 +258,7 @@ MUTATIONS = [
 # Mistakes no pin rejects yet (the oracle's header and the design notes call
 # the function "parity unpinned"); strict: a pin that starts to reject one
 # turns its entry into an unexpected pass, to be moved to the list above.
-KNOWN_SURVIVORS = {
-    "Rusanov: the smaller of the two wave speeds":
-        "the Rusanov dissipation speed only scales jump terms, which are spectrally small on "
-        "smooth states; no closed form singles out max(|u.n| + c) of the two sides",
-    "Rusanov: wave speed without |u . n|":
-        "as above; the wall pins are at rest (u.n = 0)",
-}
+KNOWN_SURVIVORS = {}
 
 
 def _build(src_text, path):
