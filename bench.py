@@ -89,20 +89,41 @@ def oracle_box(w):
                            side_trate=w.side_trate or (0.0,) * 6)
 
 
-def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
+def host_cpu():
+    """The host's CPU model, logical CPU count and the CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0, single_thread_workload=None):
     """The FP64 C oracle on the host's cores (OpenMP over elements): full RK
-    steps on the whole workload mesh for about budget_s seconds, then the same
-    on one thread for about single_thread_s seconds."""
+    steps on the whole workload mesh for about budget_s seconds (at least
+    one step), then full RK steps on one thread for about single_thread_s
+    seconds on ``single_thread_workload`` (a smaller mesh of the same case
+    where one step of the whole mesh would take far longer)."""
     import numpy as np
 
     import oracle
-    p = oracle.make_params(**w.params)
-    o = oracle.Oracle(p, oracle_box(w))
-    U0 = o.init_droplets(w.T0, w.centres, w.radii, w.width, w.noise(), w.velocities, w.rho_v, w.rho_l,
-                         w.cylinder_axis)
-    dt = o.dt(U0)
 
-    def timed(budget, cap):
+    def setup(wk):
+        o = oracle.Oracle(oracle.make_params(**wk.params), oracle_box(wk))
+        U0 = o.init_droplets(wk.T0, wk.centres, wk.radii, wk.width, wk.noise(), wk.velocities, wk.rho_v,
+                             wk.rho_l, wk.cylinder_axis)
+        return o, U0, o.dt(U0)
+
+    def timed(o, U0, dt, budget, cap):
         U = U0.copy()
         R = np.zeros_like(U)
         steps = 0
@@ -115,18 +136,26 @@ def cpu_baseline(w, budget_s=15.0, single_thread_s=6.0):
                 return steps, el
 
     cores = oracle.get_threads()
-    steps, el = timed(budget_s, 200)
+    o, U0, dt = setup(w)
+    steps, el = timed(o, U0, dt, budget_s, 200)
+    nn = o.nnodes
+    del o, U0
+    w1 = single_thread_workload or w
+    o1, U1, dt1 = setup(w1)
     oracle.set_threads(1)
     try:
-        steps1, el1 = timed(single_thread_s, 50)
+        steps1, el1 = timed(o1, U1, dt1, single_thread_s, 2000)
     finally:
         oracle.set_threads(cores)
-    return {"value": o.nnodes * 5 * steps / el, "unit": "node-stage updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{w.name}: {steps} full RK4 step(s) of the FP64 C oracle on the whole mesh "
-                      f"({o.nnodes} nodes), {el:.1f} s",
-            "single_thread": {"value": o.nnodes * 5 * steps1 / el1, "cores": 1,
-                              "sample": f"{steps1} step(s), {el1:.1f} s"}}
+    out = {"value": nn * 5 * steps / el, "unit": "node-stage updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{w.name}: {steps} full RK4 step(s) of the FP64 C oracle on the whole mesh "
+                     f"({nn} nodes, {cores} OpenMP threads), {el:.1f} s",
+           "single_thread": {"value": o1.nnodes * 5 * steps1 / el1, "cores": 1,
+                             "sample": f"{w1.name}: {steps1} step(s) on one thread ({o1.nnodes} nodes), "
+                                       f"{el1:.1f} s"}}
+    out.update(host_cpu())
+    return out
 
 
 def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_active_nodes=4_000_000):
@@ -155,12 +184,28 @@ def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_activ
     return out
 
 
-def precision_study(which="c3", steps=None, restriction=True):
-    """FP32-mixed vs FP64 on the eight-droplet N=5 case: both forms run the
-    same number of steps from the same initial state with the same dt; the
-    relative L2 and max errors of rho (and c) are reported, and on the n=4
-    restriction both GPU forms are also compared with the CPU oracle."""
-    import numpy as np
+def _errs(a, b):
+    """Relative L2 and max errors of rho and c of state a against state b."""
+    out = {}
+    for name, k in (("rho", 0), ("c", 5)):
+        d = (a[k] - b[k])
+        out[f"{name}_rel_l2"] = float(d.norm() / b[k].norm())
+        out[f"{name}_rel_max"] = float(d.abs().max() / b[k].abs().max())
+    return out
+
+
+RESTRICTIONS = {"c3": lambda wl: wl.c3(4), "c4": lambda wl: wl.c4(scale=8), "c5": lambda wl: wl.c5(scale=10),
+                "c6": lambda wl: wl.c6(scale=10)}
+
+
+def precision_runs(which="c3", steps=None, restriction=True):
+    """FP32-mixed vs FP64 on the GPU over a workload's full step count: both
+    forms run the same number of steps from the same initial state with the
+    same dt; the relative L2 and max errors of rho (and c) are reported, with
+    the plain (uncompensated) FP32 state update beside the compensated one.
+    With ``restriction`` the same is run on the small restriction of the
+    workload, whose GPU states (FP64 and FP32-mixed) are returned for the
+    comparison with the CPU oracle (``oracle_restriction``)."""
     import torch
 
     from paper_2208_05310_amd import workloads as wl
@@ -170,18 +215,14 @@ def precision_study(which="c3", steps=None, restriction=True):
         s = solver_for(w, prec, kahan=kahan)
         U = U0.to(s.dtype).clone()
         R = s.new_state()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.rk_steps(U, R, dt, steps)
         torch.cuda.synchronize()
-        return U.double(), time.perf_counter() - t0, s.reduce(U, check=False)
-
-    def errs(a, b):
-        out = {}
-        for name, k in (("rho", 0), ("c", 5)):
-            d = (a[k] - b[k])
-            out[f"{name}_rel_l2"] = float(d.norm() / b[k].norm())
-            out[f"{name}_rel_max"] = float(d.abs().max() / b[k].abs().max())
-        return out
+        t = time.perf_counter() - t0
+        sums = s.reduce(U, check=False)
+        del s, R
+        return U.double(), t, sums
 
     w = {"c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c6": wl.c6}[which]()
     steps = steps or w.steps
@@ -192,38 +233,55 @@ def precision_study(which="c3", steps=None, restriction=True):
     del s
     U64, t64, sums64 = run(w, "fp64", U0, dt)
     U32, t32, sums32 = run(w, "fp32_mixed", U0, dt)
+    e32 = _errs(U32, U64)
+    del U32
     U32p, t32p, _ = run(w, "fp32_mixed", U0, dt, kahan=False)
-    nn = U0.shape[1]
-    res["full"] = {"workload": w.name, "nodes": nn, "dt": dt, "fp64_s": t64, "fp32_mixed_s": t32,
-                   "speedup": t64 / t32, "fp32_vs_fp64": errs(U32, U64),
-                   "fp32_plain_update_s": t32p, "fp32_plain_update_vs_fp64": errs(U32p, U64),
-                   "mass_fp64": float(sums64[0]), "mass_fp32_mixed": float(sums32[0])}
-    res["full"]["fp64_sums"] = dict(zip(("mass", "energy", "min_rho", "max_rho", "min_T", "max_T"),
-                                       (float(sums64[i]) for i in (0, 4, 10, 11, 12, 13))))
-    res["full"]["fp32_mixed_sums"] = dict(zip(("mass", "energy", "min_rho", "max_rho", "min_T", "max_T"),
-                                             (float(sums32[i]) for i in (0, 4, 10, 11, 12, 13))))
+    e32p = _errs(U32p, U64)
+    del U32p, U64, U0
+    names = ("mass", "energy", "min_rho", "max_rho", "min_T", "max_T")
+    res["full"] = {"workload": w.name, "nodes": w.nnodes, "dt": dt, "fp64_s": t64, "fp32_mixed_s": t32,
+                   "speedup": t64 / t32, "fp32_vs_fp64": e32,
+                   "fp32_plain_update_s": t32p, "fp32_plain_update_vs_fp64": e32p,
+                   "fp64_sums": dict(zip(names, (float(sums64[i]) for i in (0, 4, 10, 11, 12, 13)))),
+                   "fp32_mixed_sums": dict(zip(names, (float(sums32[i]) for i in (0, 4, 10, 11, 12, 13))))}
     if not restriction:
-        return res
-    # restriction: same set-up on a small mesh, GPU forms vs the oracle
-    wr = {"c3": lambda: wl.c3(4), "c4": lambda: wl.c4(scale=8), "c5": lambda: wl.c5(scale=10),
-          "c6": lambda: wl.c6(scale=10)}[which]()
+        return res, None
+    wr = RESTRICTIONS[which](wl)
     sr = solver_for(wr, "fp64")
     Ur = init_workload(sr, wr)
     dtr = sr.dt(Ur)
     del sr
     G64, _, _ = run(wr, "fp64", Ur, dtr)
     G32, _, _ = run(wr, "fp32_mixed", Ur, dtr)
+    return res, {"workload": wr, "U0": Ur.double().cpu(), "dt": dtr, "steps": steps,
+                 "fp64": G64.cpu(), "fp32_mixed": G32.cpu()}
+
+
+def oracle_restriction(gpu):
+    """The CPU oracle over the same steps of the restriction's initial state,
+    and the GPU states (FP64, FP32-mixed) against it."""
+    import numpy as np
+    import torch
+
     import oracle
-    p = oracle.make_params(**wr.params)
-    o = oracle.Oracle(p, oracle_box(wr))
-    Uo = Ur.double().cpu().numpy().copy()
+    wr = gpu["workload"]
+    o = oracle.Oracle(oracle.make_params(**wr.params), oracle_box(wr))
+    Uo = gpu["U0"].numpy().copy()
     Ro = np.zeros_like(Uo)
     t0 = time.perf_counter()
-    o.run(Uo, Ro, 0.0, dtr, steps)
+    o.run(Uo, Ro, 0.0, gpu["dt"], gpu["steps"])
     to = time.perf_counter() - t0
-    Uo_t = torch.tensor(Uo, device=G64.device)
-    res["restriction"] = {"workload": wr.name, "nodes": int(Uo.shape[1]), "oracle_s": to,
-                          "fp64_vs_oracle": errs(G64, Uo_t), "fp32_mixed_vs_oracle": errs(G32, Uo_t)}
+    Uo_t = torch.tensor(Uo)
+    return {"workload": wr.name, "nodes": int(Uo.shape[1]), "steps": gpu["steps"], "oracle_s": to,
+            "fp64_vs_oracle": _errs(gpu["fp64"], Uo_t), "fp32_mixed_vs_oracle": _errs(gpu["fp32_mixed"], Uo_t)}
+
+
+def precision_study(which="c3", steps=None, restriction=True):
+    """GPU precision runs plus, on the restriction, the comparison with the
+    CPU oracle (the --precision-study mode)."""
+    res, gpu = precision_runs(which, steps, restriction)
+    if gpu is not None:
+        res["restriction"] = oracle_restriction(gpu)
     return res
 
 
@@ -345,15 +403,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"],
-                    help="c1 4^3 N=3 droplet; c2 16^3 N=4 two droplets (default); c3 32^3 N=5 eight "
-                         "droplets; c4 48x48x24 N=3 sessile wall box; c5 50^3 N=3 head-on collision; "
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5", "c6", "c7"],
+                    help="c1 4^3 N=3 droplet; c2 16^3 N=4 two droplets; c3 32^3 N=5 eight droplets "
+                         "(default); c4 48x48x24 N=3 sessile wall box; c5 50^3 N=3 head-on collision; "
                          "c6 100x50x25 N=3 droplet sliding on a Navier-slip floor under a moving lid; "
                          "c7 the c4 wall box with a graded floor temperature")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-mixed comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-mixed accuracy run over the workload's full step count")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 16^3 N=4 throughput line beside the headline")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--serving", action="store_true", help="run only the request-stream serving measurement")
     ap.add_argument("--precision-study", choices=["c3", "c4", "c5", "c6"], default=None,
@@ -417,21 +478,19 @@ def main():
         w = w.with_(name=f"{w.name}_model2", params=dict(w.params, model=2))
     stream = torch.cuda.current_stream()
 
-    def timed_run(precision, U0=None):
-        """Warm-up + K timed steps; returns throughput, per-kernel data, final state."""
-        s = solver_for(w, precision)
+    def timed_run(wk, precision, U0, dtk):
+        """Warm-up + K timed steps of workload wk; returns throughput,
+        per-kernel data, final state."""
+        s = solver_for(wk, precision)
         s.set_block(args.threads)
-        if U0 is None:
-            U = init_workload(s, w)
-        else:
-            U = U0.to(s.dtype).clone()
+        U = U0.to(s.dtype).clone()
         R = s.new_state()
-        s.rk_steps(U, R, dt, args.warmup, stream)
+        s.rk_steps(U, R, dtk, args.warmup, stream)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record(stream)
-        s.rk_steps(U, R, dt, args.steps, stream)
+        s.rk_steps(U, R, dtk, args.steps, stream)
         ev1.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -440,12 +499,12 @@ def main():
         # carrying its own event pair (kept out of the pass above: the events
         # cost a few per cent of step time)
         s.set_profiling(True)
-        s.rk_steps(U, R, dt, args.steps, stream)
+        s.rk_steps(U, R, dtk, args.steps, stream)
         torch.cuda.synchronize()
         prof = s.profile(stream)
         s.set_profiling(False)
         word = 8 if precision == "fp64" else 4
-        words = kernel_words_per_node(w.N)
+        words = kernel_words_per_node(wk.N)
         if precision == "fp32_mixed" and s.kahan:
             words["update"] += 12  # compensation of the state update, read and written
         kern = {}
@@ -456,15 +515,21 @@ def main():
                            "alg_bytes_per_launch": words[k] * word * s.nnodes,
                            "achieved_GBs": words[k] * word * s.nnodes / (avg * 1e-3) / 1e9}
         sums = s.reduce(U)  # health check of the final state (raises on non-finite)
-        return {"value": s.nnodes * 5 * args.steps / wall, "wall": wall, "gpu_ms": ev0.elapsed_time(ev1),
-                "kern": kern, "nnodes": s.nnodes, "U": U, "mass": sums[0], "word": word}
+        nn = s.nnodes
+        del s, R
+        return {"value": nn * 5 * args.steps / wall, "wall": wall, "gpu_ms": ev0.elapsed_time(ev1),
+                "kern": kern, "nnodes": nn, "U": U, "mass": sums[0], "word": word}
 
-    s0 = solver_for(w, args.precision)
-    U0 = init_workload(s0, w)
-    dt = s0.dt(U0)
-    if args.precision == "fp64":
-        U0 = U0.double()
-    r = timed_run(args.precision, U0)
+    def initial(wk, precision):
+        s = solver_for(wk, precision)
+        U = init_workload(s, wk)
+        dtk = s.dt(U)
+        del s
+        return U, dtk
+
+    restr_gpu = None
+    U0, dt = initial(w, args.precision)
+    r = timed_run(w, args.precision, U0, dt)
     progress(f"{w.name} {args.precision}: {r['value']:.4g} node-stage updates/s")
     nn, value, kern, word = r["nnodes"], r["value"], r["kern"], r["word"]
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
@@ -516,9 +581,9 @@ def main():
                                              "ratio_to_algorithmic": tr["total"] / alg}
     if args.precision == "fp64" and not args.no_fp32:
         # the FP32-mixed form on the same workload, initial state and dt: speed and error
-        r32 = timed_run("fp32_mixed", U0)
+        r32 = timed_run(w, "fp32_mixed", U0, dt)
         progress(f"{w.name} fp32_mixed: {r32['value']:.4g} node-stage updates/s")
-        a, b_ = r32["U"][0].double(), r["U"][0]
+        a, b_ = r32["U"][0].double(), r["U"][0].double()
         k32 = r32["kern"]
         d32 = max(k32, key=lambda k: k32[k]["avg_us"] * k32[k]["launches"])
         out["fp32_mixed"] = {
@@ -529,6 +594,42 @@ def main():
             "roofline": {"kernel": d32, "achieved": k32[d32]["achieved_GBs"], "peak": PEAK_HBM_GBS,
                          "frac": k32[d32]["achieved_GBs"] / PEAK_HBM_GBS},
             "kernels": k32}
+        del r32, a, b_
+        if not args.no_accuracy and args.workload in RESTRICTIONS and args.model == 1:
+            # the whole run of the workload (C3: 500 steps) in both forms from
+            # the same state and dt, and on the small restriction for the oracle
+            acc, restr_gpu = precision_runs(args.workload)
+            full = acc["full"]
+            out["fp32_mixed"]["accuracy"] = {
+                "steps": acc["steps"], "target_rho_rel_max": 1e-5,
+                "rho_rel_max_vs_fp64": full["fp32_vs_fp64"]["rho_rel_max"],
+                "rho_rel_l2_vs_fp64": full["fp32_vs_fp64"]["rho_rel_l2"],
+                "within_target": full["fp32_vs_fp64"]["rho_rel_max"] <= 1e-5,
+                "whole_run_speedup_vs_fp64": full["speedup"],
+                "plain_fp32_update_rho_rel_max_vs_fp64": full["fp32_plain_update_vs_fp64"]["rho_rel_max"],
+                "detail": full}
+            progress(f"{w.name} fp32_mixed over {acc['steps']} steps: rho rel max err vs FP64 "
+                     f"{full['fp32_vs_fp64']['rho_rel_max']:.2e}")
+    if not args.no_c2 and args.workload != "c2" and args.model == 1:
+        # the 16^3 N=4 throughput case beside the headline
+        w2 = wl.c2()
+        U2, dt2 = initial(w2, "fp64")
+        r2 = timed_run(w2, "fp64", U2, dt2)
+        k2 = r2["kern"]
+        d2 = max(k2, key=lambda k: k2[k]["avg_us"] * k2[k]["launches"])
+        c2 = {"workload": w2.name, "nodes": r2["nnodes"], "value": r2["value"],
+              "ms_per_step": 1e3 * r2["wall"] / args.steps,
+              "roofline": {"kernel": d2, "achieved": k2[d2]["achieved_GBs"], "peak": PEAK_HBM_GBS,
+                           "frac": k2[d2]["achieved_GBs"] / PEAK_HBM_GBS}, "kernels": k2}
+        del r2
+        if not args.no_fp32:
+            r2f = timed_run(w2, "fp32_mixed", U2, dt2)
+            c2["fp32_mixed_value"] = r2f["value"]
+            c2["fp32_mixed_speedup"] = r2f["value"] / c2["value"]
+            del r2f
+        del U2
+        out["c2"] = c2
+        progress(f"{w2.name} fp64: {c2['value']:.4g} node-stage updates/s")
     if not args.no_serving:
         try:
             res = serving_bench(args.serving_requests, max_active_nodes=args.serving_max_nodes, log=progress)
@@ -547,10 +648,28 @@ def main():
     out["roofline"]["frac_of_copy"] = ach / cp
     if "measured_GBs" in out["stage_model"]:
         out["stage_model"]["measured_frac_of_copy"] = out["stage_model"]["measured_GBs"] / cp
+    del r, U0
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        small = RESTRICTIONS[args.workload](wl) if args.workload in RESTRICTIONS else None
+        if small is not None and args.model == 2:
+            small = small.with_(name=f"{small.name}_model2", params=dict(small.params, model=2))
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, single_thread_workload=small)
         progress(f"cpu baseline: {out['cpu_baseline']['sample']}")
+        acc = out.get("fp32_mixed", {}).get("accuracy")
+        if acc is not None and restr_gpu is not None:
+            # the oracle over the same steps of the small restriction, against
+            # both GPU forms
+            rr = oracle_restriction(restr_gpu)
+            acc["restriction_vs_oracle"] = rr
+            progress(f"{rr['workload']} over {rr['steps']} steps: FP64 vs oracle rho rel max "
+                     f"{rr['fp64_vs_oracle']['rho_rel_max']:.2e}, FP32-mixed vs oracle "
+                     f"{rr['fp32_mixed_vs_oracle']['rho_rel_max']:.2e}")
     print(json.dumps(out), flush=True)
+    # leave nothing behind: every library context is released before the
+    # interpreter exits, and the device is idle
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
