@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 7  /* 7: batches advance the context time and admit walls that change in time; 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
+#define NSKR_ABI_VERSION 8  /* 8: nskr_dt_noalloc; 7: batches advance the context time and admit walls that change in time; 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
 
 enum {
     NSKR_OK = 0,
@@ -242,6 +242,21 @@ int nskr_lift2(nskr_ctx *ctx, const void *U, void *out, nskr_stream s);
  * T_N and RHO_N the 1D stability constants of the RK scheme.  Synchronises s.
  * Errors: NSKR_E_NONFINITE if a rate is not finite (dt not written). */
 int nskr_dt(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
+
+/* nskr_dt for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same time step, bit for bit, with the reduction's partial maxima and
+ * results in a static device array of 3 MiB instead of the context's
+ * memory.  It calls no allocating routine; the traces and lifted gradients
+ * it evaluates are the context's own, allocated at mesh upload.  Limit: a
+ * mesh of at most 131072 element tiles of the 256-thread reduction kernel
+ * (tiles = nelems / floor(256 / (N+1)^3), rounded up; the 32^3 N = 5 mesh
+ * has 32768), else NSKR_E_ARG with nothing enqueued.  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other host
+ * threads, other streams) race and must be serialised by the caller.
+ * Synchronises s.  Errors as nskr_dt; NSKR_E_STATE if the array's address
+ * could not be set up on the context's device. */
+int nskr_dt_noalloc(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
 
 /* nsteps steps of the 5-stage 2N-storage RK4(3)5 of Carpenter & Kennedy
  * (the low-storage fourth-order scheme family cited in Sec. 3.1): per stage

@@ -762,19 +762,20 @@ template <int P, typename T, int BS> struct Impl {
         HIPCHK(c, hipMemcpyAsync((T *)o + c->NN, c->d_G2, sizeof(T) * 4 * c->NN, hipMemcpyDeviceToDevice, s));
         return NSKR_OK;
     }
-    static int dt(nskr_ctx *c, const void *U, double *out3, hipStream_t s)
+    // the largest wave speed, mesh factor and diffusivity over the nodes;
+    // part holds 3 partial maxima per tile, dout the 3 results (device)
+    static int dt(nskr_ctx *c, const void *U, double *out3, hipStream_t s, double *part, double *dout)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
         L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
-        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
+        RateArgs a{mesh(c), c->ph, c->NN, part, nblk256(c)};
         hipLaunchKernelGGL((k_dt_rates<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a);
-        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk256(c), 3,
-                           c->d_out);
+        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nblk256(c), 3, dout);
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(out3, c->d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(out3, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         return NSKR_OK;
     }
@@ -843,6 +844,38 @@ static int elem_per_block(int N)
     return kBlock / n3;
 }
 
+// Reduction scratch of nskr_dt_noalloc, for callers that cannot allocate:
+// 3 partial maxima per element tile of the 256-thread reduction kernel, then
+// the 3 results.  Each device holds its own copy for the life of the
+// process; its address on each device is looked up once, at the first
+// nskr_create on that device, and only that address is handed to kernels.
+// Every partial is written before it is read, so nothing needs clearing.
+constexpr int kStaticTiles = 131072;
+static __device__ __align__(256) double scratch[3 * kStaticTiles + 3];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mtx;
+static double *g_scratch[kMaxDevices];
+
+// Look up the array's address on `device` (the caller has made it current).
+static bool setup_static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return false;
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    if (g_scratch[device]) return true;
+    double *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return false;
+    g_scratch[device] = ptr;
+    return true;
+}
+
+static double *static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    return g_scratch[device];
+}
+
 // ------------------------------------------------------------------ ABI
 extern "C" {
 
@@ -865,6 +898,10 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
     hipFuncAttributes attr;
     if (hipFuncGetAttributes(&attr, reinterpret_cast<const void *>(&k_update<4, double, 256, false>)) != hipSuccess)
         return NSKR_E_HIP;
+    {
+        DeviceGuard guard(device);
+        if (!setup_static_scratch(device)) return NSKR_E_HIP;
+    }
     nskr_ctx *c = new nskr_ctx();
     c->p = *p;
     c->N = N;
@@ -1254,15 +1291,9 @@ int nskr_lift2(nskr_ctx *c, const void *U, void *o, nskr_stream sv)
     return dispatch(c, [&](auto impl) { return decltype(impl)::lift2_out(c, U, o, (hipStream_t)sv); });
 }
 
-int nskr_dt(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
+// dt from the three maxima (advective rate, mesh factor, diffusivity)
+static int dt_from_rates(nskr_ctx *c, const double r[3], double *dt)
 {
-    int rc = ready(c);
-    if (rc) return rc;
-    if (!U || !dt) return fail(c, NSKR_E_ARG, "null argument");
-    DeviceGuard guard(c->device);
-    double r[3];
-    rc = dispatch(c, [&](auto impl) { return decltype(impl)::dt(c, U, r, (hipStream_t)sv); });
-    if (rc) return rc;
     if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !(r[0] > 0))
         return fail(c, NSKR_E_NONFINITE, "non-finite wave speed or diffusivity");
     const double dt_adv = c->p.cfl * kTN[c->N] * 2.0 / r[0];
@@ -1270,6 +1301,38 @@ int nskr_dt(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
     const double dt_par = den > 0 ? c->p.cfl * kRkReal / den : INFINITY;
     *dt = dt_adv < dt_par ? dt_adv : dt_par;
     return NSKR_OK;
+}
+
+int nskr_dt(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !dt) return fail(c, NSKR_E_ARG, "null argument");
+    DeviceGuard guard(c->device);
+    double r[3];
+    rc = dispatch(c, [&](auto impl) { return decltype(impl)::dt(c, U, r, (hipStream_t)sv, c->d_part, c->d_out); });
+    if (rc) return rc;
+    return dt_from_rates(c, r, dt);
+}
+
+int nskr_dt_noalloc(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
+{
+    int rc = ready(c);
+    if (rc) return rc;
+    if (!U || !dt) return fail(c, NSKR_E_ARG, "null argument");
+    const int tiles = (c->E + elem_per_block(c->N) - 1) / elem_per_block(c->N);
+    if (tiles > kStaticTiles)
+        return fail(c, NSKR_E_ARG, "mesh has " + std::to_string(tiles) + " element tiles; the static reduction "
+                    "scratch of nskr_dt_noalloc holds " + std::to_string(kStaticTiles));
+    double *ptr = static_scratch(c->device);
+    if (!ptr) return fail(c, NSKR_E_STATE, "static reduction scratch not set up on this device");
+    DeviceGuard guard(c->device);
+    double r[3];
+    rc = dispatch(c, [&](auto impl) {
+        return decltype(impl)::dt(c, U, r, (hipStream_t)sv, ptr, ptr + 3 * (size_t)kStaticTiles);
+    });
+    if (rc) return rc;
+    return dt_from_rates(c, r, dt);
 }
 
 int nskr_rk_steps(nskr_ctx *c, void *U, void *R, double dt, int nsteps, nskr_stream sv)

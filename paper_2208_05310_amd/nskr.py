@@ -25,7 +25,8 @@ EXPORTS = ["nskr_version", "nskr_create", "nskr_destroy", "nskr_mesh_upload", "n
            "nskr_rk_steps", "nskr_reduce", "nskr_set_profiling", "nskr_profile", "nskr_set_block",
            "nskr_get_block", "nskr_last_error", "nskr_batch_create", "nskr_batch_destroy",
            "nskr_batch_set_graph", "nskr_batch_admit", "nskr_batch_step", "nskr_batch_poll",
-           "nskr_batch_retire", "nskr_batch_info", "nskr_batch_last_error", "nskr_set_time", "nskr_get_time"]
+           "nskr_batch_retire", "nskr_batch_info", "nskr_batch_last_error", "nskr_set_time", "nskr_get_time",
+           "nskr_dt_noalloc"]
 KERNEL_KINDS = ["prolong", "lift1", "lift2", "update", "other"]
 
 
@@ -65,7 +66,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 7  # the struct layouts and semantics below
+ABI_VERSION = 8  # the struct layouts and semantics below
 
 
 def lib():
@@ -89,6 +90,7 @@ def lib():
         "nskr_lift1": (i, [vp, vp, vp, vp]),
         "nskr_lift2": (i, [vp, vp, vp, vp]),
         "nskr_dt": (i, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
+        "nskr_dt_noalloc": (i, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
         "nskr_rk_steps": (i, [vp, vp, vp, d, i, vp]),
         "nskr_reduce": (i, [vp, vp, ctypes.POINTER(ctypes.c_double), vp]),
         "nskr_set_profiling": (i, [vp, i]),
@@ -313,6 +315,13 @@ class Solver:
     def dt(self, U, stream=None) -> float:
         v = ctypes.c_double()
         self._check(self.L.nskr_dt(self._h, self._state_ok(U), ctypes.byref(v), _stream_ptr(stream)))
+        return v.value
+
+    def dt_noalloc(self, U, stream=None) -> float:
+        """dt() through the entry point that allocates nothing (static device
+        reduction scratch shared by every call on the device)."""
+        v = ctypes.c_double()
+        self._check(self.L.nskr_dt_noalloc(self._h, self._state_ok(U), ctypes.byref(v), _stream_ptr(stream)))
         return v.value
 
     def rk_steps(self, U, R, dt, nsteps=1, stream=None):
