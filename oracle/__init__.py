@@ -66,7 +66,7 @@ class Box(ctypes.Structure):
                 ("side_uwall", (ctypes.c_double * 3) * 6), ("side_g1", ctypes.c_double * 6),
                 ("side_g2", ctypes.c_double * 6), ("side_g4", ctypes.c_double * 6),
                 ("side_g3", ctypes.c_double * 6), ("side_tgrad", (ctypes.c_double * 3) * 6),
-                ("side_trate", ctypes.c_double * 6)]
+                ("side_trate", ctypes.c_double * 6), ("ngeo", ctypes.c_int)]
 
 
 _lib = None
@@ -144,19 +144,21 @@ def make_box(N, n, lo=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), periodic=(1, 1, 1
              side_kind=(0,) * 6, side_twall=(0.0,) * 6, side_theta=(90.0,) * 6,
              curve_amp=0.0, side_uwall=((0.0, 0.0, 0.0),) * 6, side_g1=(0.0,) * 6,
              side_g2=(0.0,) * 6, side_g3=(float("inf"),) * 6, side_g4=(0.0,) * 6,
-             side_tgrad=((0.0, 0.0, 0.0),) * 6, side_trate=(0.0,) * 6) -> Box:
+             side_tgrad=((0.0, 0.0, 0.0),) * 6, side_trate=(0.0,) * 6, ngeo=0) -> Box:
     """Wall kinds per side (x-, x+, y-, y+, z-, z+): 1 no-slip isothermal with a
     static contact angle, moving with side_uwall; 2 slip adiabatic neutral;
     3 generalized Navier slip with gamma_1..gamma_4 (side_g3 infinite =
     isothermal).  side_tgrad, side_trate: wall temperature twall + tgrad . x
-    + trate t (kinds 1, 3), through the sigma/Maxwell table."""
+    + trate t (kinds 1, 3), through the sigma/Maxwell table.  curve_amp: the
+    smooth sine perturbation of the box map; ngeo: each element's geometry is
+    the degree-ngeo Gauss-Lobatto interpolant of the map (0: degree N)."""
     uw = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_uwall])
     tg = ((ctypes.c_double * 3) * 6)(*[(ctypes.c_double * 3)(*v) for v in side_tgrad])
     d6 = lambda v: (ctypes.c_double * 6)(*[float(x) for x in v])
     return Box(int(N), (ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo),
                (ctypes.c_double * 3)(*length), (ctypes.c_int * 3)(*periodic),
                (ctypes.c_int * 6)(*side_kind), d6(side_twall), d6(side_theta), float(curve_amp),
-               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3), tg, d6(side_trate))
+               uw, d6(side_g1), d6(side_g2), d6(side_g4), d6(side_g3), tg, d6(side_trate), int(ngeo))
 
 
 class Oracle:

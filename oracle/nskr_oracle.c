@@ -105,6 +105,9 @@ typedef struct {
                                  wall temperature at x is twall + tgrad . x,
                                  evaluated through the sigma/Maxwell table  */
     double side_trate[6];     /* wall temperature rate: + trate * t          */
+    int ngeo;                 /* geometry degree: each element is the degree-ngeo
+                                 interpolant of the map through its Gauss-Lobatto
+                                 points (0 or >= N: degree N)                 */
 } orc_box;
 
 typedef struct {
@@ -662,17 +665,24 @@ static void diff_matrix_ld(int n, const ldbl *xn, ldbl D[MAXP][MAXP])
 /* Metric terms by the conservative curl form of Kopriva (2006):
  *   Ja^i_n = -( curl_xi ( I^N( X_l grad_xi X_m ) ) )_i,  (n,m,l) cyclic,
  * evaluated on Gauss-Lobatto points of degree N, then interpolated to the
- * Gauss volume nodes and evaluated at xi^d = +-1 on the faces.  All of it in
- * extended precision, rounded once to FP64 at the end. */
+ * Gauss volume nodes and evaluated at xi^d = +-1 on the faces.  The element's
+ * geometry X is the Gauss-Lobatto interpolant of the map of degree ngeo <= N
+ * (Sec. 3.1, curved elements of geometry degree N_geo), and the node
+ * coordinates are its values at the Gauss nodes.  All of it in extended
+ * precision, rounded once to FP64 at the end. */
 static void build_metrics(orc_ctx *c)
 {
     int N = c->N, P = c->P, n3 = c->n3, n2 = c->n2;
-    ldbl xgl[MAXP], Dgl[MAXP][MAXP], V[MAXP][MAXP], xgs[MAXP];
+    int ng = (c->box.ngeo >= 1 && c->box.ngeo < N) ? c->box.ngeo : N;
+    ldbl xgl[MAXP], Dgl[MAXP][MAXP], V[MAXP][MAXP], xgs[MAXP], xgg[MAXP], Vg[MAXP][MAXP];
     lobatto_nodes_ld(N, xgl);
+    lobatto_nodes_ld(ng, xgg);
     diff_matrix_ld(P, xgl, Dgl);
     for (int a = 0; a < P; ++a) xgs[a] = c->xg[a];
     for (int a = 0; a < P; ++a)
         for (int b = 0; b < P; ++b) V[a][b] = lagrange_ld(P, xgl, b, xgs[a]); /* GL -> Gauss */
+    for (int a = 0; a < P; ++a)
+        for (int b = 0; b <= ng; ++b) Vg[a][b] = lagrange_ld(ng + 1, xgg, b, xgl[a]); /* GL(ngeo) -> GL(N) */
 
     size_t sz = (size_t)n3;
     ldbl *X = malloc(sizeof(ldbl) * 3 * sz);
@@ -686,18 +696,28 @@ static void build_metrics(orc_ctx *c)
     for (int ex = 0; ex < c->box.n[0]; ++ex) {
         int e = ex + c->box.n[0] * (ey + c->box.n[1] * ez);
         int ee[3] = {ex, ey, ez};
-        /* geometry at GL points */
+        /* geometry at GL points: the map at the degree-ngeo GL points,
+         * interpolated to the degree-N GL points */
         for (int k = 0; k < P; ++k)
         for (int j = 0; j < P; ++j)
         for (int i = 0; i < P; ++i) {
             int ii[3] = {i, j, k};
-            ldbl Xr[3], x[3];
-            for (int d = 0; d < 3; ++d) {
-                ldbl h = (ldbl)c->box.len[d] / c->box.n[d];
-                Xr[d] = c->box.lo[d] + h * (ee[d] + 0.5L * (xgl[ii[d]] + 1.0L));
+            ldbl acc[3] = {0.0L, 0.0L, 0.0L};
+            for (int c3 = 0; c3 <= ng; ++c3)
+            for (int c2 = 0; c2 <= ng; ++c2)
+            for (int c1 = 0; c1 <= ng; ++c1) {
+                int cc[3] = {c1, c2, c3};
+                ldbl wgt = 1.0L, Xr[3], x[3];
+                for (int d = 0; d < 3; ++d) {
+                    ldbl h = (ldbl)c->box.len[d] / c->box.n[d];
+                    Xr[d] = c->box.lo[d] + h * (ee[d] + 0.5L * (xgg[cc[d]] + 1.0L));
+                    wgt *= ng == N ? (cc[d] == ii[d] ? 1.0L : 0.0L) : Vg[ii[d]][cc[d]];
+                }
+                if (wgt == 0.0L) continue;
+                geom_map(&c->box, Xr, x);
+                for (int m = 0; m < 3; ++m) acc[m] += wgt * x[m];
             }
-            geom_map(&c->box, Xr, x);
-            for (int m = 0; m < 3; ++m) X[m * sz + nidx(P, i, j, k)] = x[m];
+            for (int m = 0; m < 3; ++m) X[m * sz + nidx(P, i, j, k)] = acc[m];
         }
         /* dX_m / d xi^d on GL points */
         for (int m = 0; m < 3; ++m)
@@ -762,14 +782,14 @@ static void build_metrics(orc_ctx *c)
                 A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
                 A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]));
             int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
-            int ii[3] = {i, j, k};
-            ldbl Xr[3], x[3];
-            for (int d = 0; d < 3; ++d) {
-                ldbl h = (ldbl)c->box.len[d] / c->box.n[d];
-                Xr[d] = c->box.lo[d] + h * (ee[d] + 0.5L * (xgs[ii[d]] + 1.0L));
+            for (int m = 0; m < 3; ++m) {
+                ldbl x = 0.0L;
+                for (int c3 = 0; c3 < P; ++c3)
+                    for (int c2 = 0; c2 < P; ++c2)
+                        for (int c1 = 0; c1 < P; ++c1)
+                            x += V[i][c1] * V[j][c2] * V[k][c3] * X[m * sz + nidx(P, c1, c2, c3)];
+                c->xyz[((size_t)e * n3 + nd) * 3 + m] = (double)x;
             }
-            geom_map(&c->box, Xr, x);
-            for (int m = 0; m < 3; ++m) c->xyz[((size_t)e * n3 + nd) * 3 + m] = (double)x[m];
         }
         /* Face metrics: Ja^d at xi^d = +-1 (GL endpoint), interpolated along
          * the two tangential directions to the Gauss face points; outward
