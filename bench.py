@@ -86,7 +86,7 @@ def oracle_box(w):
                            w.side_theta, w.curve_amp, side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
                            side_g1=[v[0] for v in g], side_g2=[v[1] for v in g], side_g3=[v[2] for v in g],
                            side_g4=[v[3] for v in g], side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6,
-                           side_trate=w.side_trate or (0.0,) * 6)
+                           side_trate=w.side_trate or (0.0,) * 6, ngeo=w.ngeo)
 
 
 def host_cpu():

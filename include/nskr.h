@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define NSKR_ABI_VERSION 8  /* 8: nskr_dt_noalloc; 7: batches advance the context time and admit walls that change in time; 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
+#define NSKR_ABI_VERSION 9  /* 9: nskr_mesh of geometry nodes (degree ngeo) with face orientations; 8: nskr_dt_noalloc; 7: batches advance the context time and admit walls that change in time; 6: nskr_bc.twall_rate, context time; 5: nskr_init.cylinder_axis; 4: twall_grad */
 
 enum {
     NSKR_OK = 0,
@@ -113,19 +113,40 @@ typedef struct {
     double twall_rate;
 } nskr_bc;
 
-/* Hexahedral mesh (Sec. 3.1).  Every element must be a parallelepiped (affine
- * map from the reference cube); corners[e][v][3] with v = i + 2j + 4k, i along
- * the first reference direction.  Faces: 0 = xi^1 = -1, 1 = +1, 2/3 = xi^2,
- * 4/5 = xi^3.  nbr[e][f] = neighbour element or -1 on a wall; nbr_face[e][f]
- * = the neighbour's face, which must be the opposite face f^1 with identical
- * face-point ordering (structured conforming meshes, periodic wrap allowed);
- * bc[e][f] = 0 for interior faces, else a 1-based index into bcs.  All arrays
- * are host memory; the library copies them. */
+/* Hexahedral mesh (Sec. 3.1: each element mapped from the reference cube
+ * [-1,1]^3; curved elements with a geometry of degree N_geo <= N, e.g. the
+ * N_geo = 2 elements of Sec. 4.5).
+ *   ngeo: geometry degree, 1..N.
+ *   xgeo[e][(ngeo+1)^3][3]: the element's geometry nodes on the Gauss-Lobatto
+ *     points of degree ngeo, node a + (ngeo+1)(b + (ngeo+1)c) at reference
+ *     coordinates (xi_a, xi_b, xi_c), a along the first reference direction
+ *     (ngeo = 1: the 8 corners, v = i + 2j + 4k).  The element is the
+ *     polynomial interpolant of these nodes; J > 0 is required at every node.
+ *   Faces: 0 = xi^1 = -1, 1 = +1, 2/3 = xi^2, 4/5 = xi^3; face point p + (N+1) q
+ *     with (p, q) the node indices along the two remaining directions in
+ *     increasing order.
+ *   nbr[e][f]: neighbour element, or -1 on a wall.
+ *   nbr_face[e][f]: the neighbour's local face (any of 0..5).
+ *   nbr_orient[e][f] (NULL: all 0): orientation o in 0..7 taking own face
+ *     point (p, q) to the neighbour's point (a, b): (a, b) = (q, p) if o & 4,
+ *     else (p, q); then a -> N - a if o & 1 and b -> N - b if o & 2.  The
+ *     neighbour's entry for the same face must be the inverse map.
+ *   bc[e][f]: 0 for interior faces, else a 1-based index into bcs.
+ * The library checks that the connectivity is reciprocal, that each face and
+ * its neighbour's face are the same surface (matching points differ by one
+ * translation: zero, or a period of the domain) with opposite normals and
+ * equal surface elements, and forms the metric terms Ja^d_m = J d xi^d/d x_m
+ * itself in the conservative curl form (Kopriva 2006), in extended precision.
+ * Meshes whose elements are all parallelepipeds keep per-element metrics;
+ * otherwise every node carries its own (10 values) and every face point its
+ * own normal.  All arrays are host memory; the library copies them. */
 typedef struct {
     int nelems;
-    const double *corners;
+    int ngeo;
+    const double *xgeo;
     const int *nbr;
     const int *nbr_face;
+    const int *nbr_orient;
     const int *bc;
     int nbcs;
     const nskr_bc *bcs;
@@ -189,16 +210,20 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out);
  * buffers.  Safe on NULL. */
 int nskr_destroy(nskr_ctx *ctx);
 
-/* Upload the mesh: per-element metric terms (Ja^d_m = J d xi^d/d x_m and J,
- * exact for affine elements), outward face normals and surface elements,
- * connectivity and per-wall constants (Maxwell states, sigma_vl of
- * eq. surftenscoef read with the factor sqrt(2 gamma)); allocates the
- * library's scratch (lifted gradients, face traces).  May be called again to
- * replace the mesh.  Errors: NSKR_E_ARG (null arrays, element not a
- * parallelepiped or J <= 0, neighbour indices out of range or not reciprocal,
- * wall face without a bc or bc index out of range, wall kind not 1/2,
- * supercritical wall temperature); NSKR_E_UNSUPPORTED (neighbour face not the
- * opposite face); NSKR_E_NOMEM; NSKR_E_HIP.  Synchronises the stream. */
+/* Upload the mesh (see nskr_mesh): metric terms, outward face normals and
+ * surface elements, connectivity and per-wall constants (Maxwell states,
+ * sigma_vl of eq. surftenscoef read with the factor sqrt(2 gamma));
+ * allocates the library's scratch (lifted gradients, face traces).  May be
+ * called again to replace the mesh.  Errors: NSKR_E_ARG (null arrays, ngeo
+ * outside 1..N, non-finite geometry, J <= 0, neighbour indices, faces or
+ * orientations out of range, connectivity not reciprocal or orientations not
+ * inverse, a face whose neighbour's face is not the same surface under the
+ * given orientation or has a different normal or surface element, wall face
+ * without a bc or bc index out of range, wall kind not 1, 2 or 3, negative
+ * Navier-slip coefficients, a wall velocity that is not tangential at every
+ * face point, supercritical wall temperature); NSKR_E_UNSUPPORTED (walls
+ * whose temperature varies on a mesh with curved elements); NSKR_E_NOMEM;
+ * NSKR_E_HIP.  Synchronises the stream. */
 int nskr_mesh_upload(nskr_ctx *ctx, const nskr_mesh *m, nskr_stream s);
 
 /* Number of values in one state buffer: 6 nelems (N+1)^3.
@@ -281,8 +306,10 @@ int nskr_profile(nskr_ctx *ctx, double *ms, long *count, nskr_stream s);
 
 /* Threads per workgroup of the stage kernels (256 or 512; a block must hold
  * at least one element): the tile shape the autotuner chooses.  Results do not
- * depend on it (every element's arithmetic is the same in any tile).
- * Errors: NSKR_E_ARG for other values. */
+ * depend on it (every element's arithmetic is the same in any tile).  A mesh
+ * with curved elements runs 256 threads (its upload sets 256).
+ * Errors: NSKR_E_ARG for other values; NSKR_E_UNSUPPORTED for 512 on a mesh
+ * with curved elements or where the kernels exceed the LDS per workgroup. */
 int nskr_set_block(nskr_ctx *ctx, int threads);
 int nskr_get_block(const nskr_ctx *ctx, int *threads);
 

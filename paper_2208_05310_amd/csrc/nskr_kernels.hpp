@@ -85,11 +85,16 @@ struct Basis {
 
 struct MeshDev {
     int E;
-    const int *nbr;      // [E][6] neighbour element, -1 on a wall
+    const int *nbr;      // [E][6] neighbour face and orientation, (6 nb + nf) 8 + o, or -1 on a wall
     const int *bcid;     // [E][6] 0 interior, else 1-based wall index
+    // affine elements (the kernels' CV = false instances)
     const double *emet;  // [E][10] Ja[d*3+m], J
     const double *fmet;  // [E][6][4] outward unit normal, surface element
     const double *egeo;  // [E][12] corner 0 and the three edge vectors
+    // curved elements (CV = true), in the element type of the precision
+    const void *nmet;    // [10][nodes] Ja[d*3+m] and J at every node
+    const void *fnrm;    // [E][6][P^2][4] outward unit normal and surface element at every face point
+    const double *xnode; // [3][nodes] node coordinates (initial state)
     const BcDev *bcs;
     int dyn;             // some Navier-slip wall has gamma_1 != 0 (g needs div u at the wall)
     const double *stab;  // [kTabN][3] wall-temperature table (walls with a temperature gradient)
@@ -106,6 +111,54 @@ template <int P, int BS = kBlock> struct Tile {
 template <int P> __device__ __forceinline__ int line_node(int d, int l, int p, int q)
 {
     return d == 0 ? l + P * (p + P * q) : (d == 1 ? p + P * (l + P * q) : p + P * (q + P * l));
+}
+
+// Face point of the neighbour that matches face point fp = p + P q of the
+// own face (p, q: the two remaining node indices in increasing axis order)
+// under orientation o: (a, b) = (q, p) if o & 4 else (p, q); a -> P-1-a if
+// o & 1; b -> P-1-b if o & 2; the neighbour's point is a + P b.
+template <int P> __device__ __forceinline__ int orient_fp(int fp, int o)
+{
+    int a = fp % P, b = fp / P;
+    if (o & 4) {
+        const int t = a;
+        a = b;
+        b = t;
+    }
+    if (o & 1) a = P - 1 - a;
+    if (o & 2) b = P - 1 - b;
+    return a + P * b;
+}
+
+// Face index (6 element + local face) of the neighbour across a face with
+// connectivity code `code` >= 0, and the neighbour's matching point.
+template <int P> __device__ __forceinline__ size_t nbr_face(int code) { return (size_t)(code >> 3); }
+template <int P> __device__ __forceinline__ int nbr_point(int code, int fp) { return orient_fp<P>(fp, code & 7); }
+
+// Outward unit normal and surface element at face point fp of face
+// `face` (= 6 element + local face): per face on affine elements, per face
+// point on curved ones.
+template <int P, typename T, bool CV>
+__device__ __forceinline__ void face_normal(const MeshDev &m, size_t face, int fp, T n[3], T &dS)
+{
+    if (CV) {
+        const T *q = (const T *)m.fnrm + (face * (P * P) + fp) * 4;
+        n[0] = q[0];
+        n[1] = q[1];
+        n[2] = q[2];
+        dS = q[3];
+    } else {
+        const double *q = m.fmet + face * 4;
+        n[0] = T(q[0]);
+        n[1] = T(q[1]);
+        n[2] = T(q[2]);
+        dS = T(q[3]);
+    }
+}
+template <int P, typename T, bool CV> __device__ __forceinline__ T face_dS(const MeshDev &m, size_t face, int fp)
+{
+    if (CV) return ((const T *)m.fnrm)[(face * (P * P) + fp) * 4 + 3];
+    return T(m.fmet[face * 4 + 3]);
 }
 
 // ---------------------------------------------------------------- physics
@@ -434,7 +487,8 @@ template <typename T> __device__ __forceinline__ void primitives(const T u6[6], 
 // BR1 face values of the primitives on a wall face: the interior values with
 // the velocity set to the wall's (no-slip) or stripped of its normal part
 // (slip and Navier-slip walls).
-template <typename T> __device__ __forceinline__ void wall_primitives(const MeshDev &m, int el, int f, T w[5])
+template <typename T>
+__device__ __forceinline__ void wall_primitives(const MeshDev &m, int el, int f, const T n[3], T w[5])
 {
     const BcDev &bc = m.bcs[m.bcid[el * 6 + f] - 1];
     if (bc.kind == 1) {
@@ -442,12 +496,10 @@ template <typename T> __device__ __forceinline__ void wall_primitives(const Mesh
         w[2] = T(bc.uw[1]);
         w[3] = T(bc.uw[2]);
     } else {
-        const double *fm = m.fmet + ((size_t)el * 6 + f) * 4;
-        const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
-        const T un = w[1] * n0 + w[2] * n1 + w[3] * n2;
-        w[1] -= un * n0;
-        w[2] -= un * n1;
-        w[3] -= un * n2;
+        const T un = w[1] * n[0] + w[2] * n[1] + w[3] * n[2];
+        w[1] -= un * n[0];
+        w[2] -= un * n[1];
+        w[3] -= un * n[2];
     }
 }
 
@@ -556,6 +608,65 @@ __device__ __forceinline__ void lifted_grads(const T (*fw)[NVS], const T (*fs)[N
     }
 }
 
+// Curved elements: the same BR1 lifting in the conservative form with the
+// metrics inside the derivative, J q_m = sum_d sum_l Dhat (Ja^d_m w)_l +
+// sum_faces lhat w* (n dS)_m, for NFLD consecutive LDS fields; sJa holds
+// Ja^d_m (row 3d+m) at every node of the tile, sN the outward n dS at every
+// face point.  Returns the physical gradients times 1/J (iJ of this node).
+template <int P, int NFLD, int NVS, int NFS, typename T>
+__device__ __forceinline__ void lifted_grads_curved(const T (*fw)[NVS], const T (*fs)[NFS], const T (*sJa)[NVS],
+                                                    const T (*sN)[NFS], int base, int fbase, int i, int j, int k,
+                                                    const double *sDh, const double *sLh, T iJ, T q[NFLD][3])
+{
+    constexpr int n2 = P * P;
+    const int idx[3] = {i, j, k};
+    const int fpd[3] = {j + P * k, i + P * k, i + P * j};
+#pragma unroll
+    for (int f = 0; f < NFLD; ++f) q[f][0] = q[f][1] = q[f][2] = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int id = idx[d];
+        const int p = d == 0 ? j : i, r = d == 2 ? j : k;
+#pragma unroll
+        for (int l = 0; l < P; ++l) {
+            const int n = base + line_node<P>(d, l, p, r);
+            const T D = T(sDh[id * P + l]);
+            const T a0 = D * sJa[3 * d][n], a1 = D * sJa[3 * d + 1][n], a2 = D * sJa[3 * d + 2][n];
+#pragma unroll
+            for (int f = 0; f < NFLD; ++f) {
+                const T v = fw[f][n];
+                q[f][0] += a0 * v;
+                q[f][1] += a1 * v;
+                q[f][2] += a2 * v;
+            }
+        }
+        const int pp = fbase + (2 * d + 1) * n2 + fpd[d], pm = fbase + (2 * d) * n2 + fpd[d];
+        const T lp = T(sLh[P + id]), lm = T(sLh[id]);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T np_ = lp * sN[m][pp], nm_ = lm * sN[m][pm];
+#pragma unroll
+            for (int f = 0; f < NFLD; ++f) q[f][m] += np_ * fs[f][pp] + nm_ * fs[f][pm];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int f = 0; f < NFLD; ++f)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) q[f][m] *= iJ;
+}
+
+// Per-node metrics of a curved element tile into LDS (nine Ja rows) and
+// this node's 1/J; t is the node's thread, g its global node index.
+template <typename T, int NVS>
+__device__ __forceinline__ T stage_node_metrics(const MeshDev &m, size_t NN, size_t g, int t, T (*sJa)[NVS])
+{
+    const T *nm = (const T *)m.nmet;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) sJa[r][t] = nm[r * NN + g];
+    return T(1) / nm[9 * NN + g];
+}
+
 template <typename T> __device__ __forceinline__ void to_physical(const T Ja[9], T iJ, const T gd[3], T q[3])
 {
 #pragma unroll
@@ -613,15 +724,16 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 // Lifted grad c, and the own-face traces of grad c and of the face
 // temperature.  FULL: also every lifted gradient and the nodal temperature
 // (Q, TH) for the API outputs.
-// FP32 per-stage instances are latency-bound and keep at least 7 waves per
-// SIMD, which their register demand allows without spills (8 does not).
-template <typename T, bool FULL> constexpr int lift1_waves()
+// FP32 per-stage instances on affine elements are latency-bound and keep at
+// least 7 waves per SIMD, which their register demand allows without spills
+// (8 does not).
+template <typename T, bool FULL, bool CV> constexpr int lift1_waves()
 {
-    return (sizeof(T) == 4 && !FULL) ? 7 : 1;
+    return (sizeof(T) == 4 && !FULL && !CV) ? 7 : 1;
 }
 
-template <int P, typename T, int BS, bool BATCH, bool FULL = false>
-__global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T> L)
+template <int P, typename T, int BS, bool BATCH, bool FULL = false, bool CV = false>
+__global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Launch<T> L)
 {
     using G = Tile<P, BS>;
     Inst<T> a;
@@ -631,9 +743,13 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
     // node values of the lifted primitives (c last; slots 0..2 later hold
     // grad c) and their BR1 face values: all five with FULL, else c only
     constexpr int NW = FULL ? 5 : 4, NS = FULL ? 5 : 1;
+    // curved elements: the metrics of every node and n dS of every face point
+    constexpr int NJ = CV ? 9 : 1, NQ = CV ? 3 : 1, NJV = CV ? G::NV : 1, NQF = CV ? G::NF : 1;
     __shared__ T sU[6][G::NV];
     __shared__ T sW[NW][G::NV];
     __shared__ T sS[NS][G::NF];
+    __shared__ T sJa[NJ][NJV];
+    __shared__ T sN[NQ][NQF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
@@ -660,7 +776,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
         for (int s = 0; s < 2; ++s) {
             const int nb = s ? nbp : nbm;
             if (nb >= 0) {
-                const FaceIx<G::n2> o((size_t)nb * 6 + (2 * lt.d + 1 - s), lt.fp);
+                const FaceIx<G::n2> o(nbr_face<P>(nb), nbr_point<P>(nb, lt.fp));
                 if (full) {
 #pragma unroll
                     for (int v = 0; v < 6; ++v)
@@ -671,6 +787,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
             }
         }
     }
+    T iJn = T(0);
     if (act) {
         T u6[6], w[5];
 #pragma unroll
@@ -681,6 +798,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
             for (int k = 0; k < 4; ++k) sW[k][t] = w[k];
         }
         sW[NW - 1][t] = w[4];
+        if constexpr (CV) iJn = stage_node_metrics<T, NJV>(a.mesh, a.NN, g, t, sJa);
     }
     __syncthreads();
     // BR1 face values w* on both faces of the line
@@ -698,6 +816,12 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
             const int f = 2 * lt.d + s;
             const int nb = s ? nbp : nbm;
             const int slot = lt.le * 6 * G::n2 + f * G::n2 + lt.fp;
+            if constexpr (CV) {
+                T n[3], dS;
+                face_normal<P, T, true>(a.mesh, (size_t)el * 6 + f, lt.fp, n, dS);
+#pragma unroll
+                for (int m = 0; m < 3; ++m) sN[m][slot] = n[m] * dS;
+            }
             if (full) {
                 T w[5];
                 primitives(uf[s], w);
@@ -707,7 +831,9 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
 #pragma unroll
                     for (int k = 0; k < 5; ++k) w[k] = T(0.5) * (w[k] + v5[k]);
                 } else {
-                    wall_primitives(a.mesh, el, f, w);
+                    T n[3], dS;
+                    face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, lt.fp, n, dS);
+                    wall_primitives(a.mesh, el, f, n, w);
                 }
 #pragma unroll
                 for (int k = 0; k < NS; ++k) sS[k][slot] = w[k];
@@ -720,19 +846,40 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
     T qc[3] = {T(0), T(0), T(0)};
     if (act) {
         const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
-        T Ja[9], iJ;
-        element_metrics(a.mesh, e, Ja, iJ);
         const int base = le * G::n3, fbase = le * 6 * G::n2;
-        if (full) {
+        if constexpr (CV) {
+            if (full) {
+                T q[5][3];
+                lifted_grads_curved<P, 5, G::NV, G::NF>(sW, sS, sJa, sN, base, fbase, i, j, k, sDh, sLh, iJn, q);
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                T q[3];
-                lifted_grad<P>(sW[w], sS[w], base, fbase, i, j, k, sDh, sLh, Ja, iJ, q);
+                for (int w = 0; w < 4; ++w)
 #pragma unroll
-                for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[m];
+                    for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[w][m];
+                qc[0] = q[4][0];
+                qc[1] = q[4][1];
+                qc[2] = q[4][2];
+            } else {
+                T q[1][3];
+                lifted_grads_curved<P, 1, G::NV, G::NF>(sW + (NW - 1), sS + (NS - 1), sJa, sN, base, fbase, i, j, k,
+                                                        sDh, sLh, iJn, q);
+                qc[0] = q[0][0];
+                qc[1] = q[0][1];
+                qc[2] = q[0][2];
             }
+        } else {
+            T Ja[9], iJ;
+            element_metrics(a.mesh, e, Ja, iJ);
+            if (full) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    T q[3];
+                    lifted_grad<P>(sW[w], sS[w], base, fbase, i, j, k, sDh, sLh, Ja, iJ, q);
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[m];
+                }
+            }
+            lifted_grad<P>(sW[NW - 1], sS[NS - 1], base, fbase, i, j, k, sDh, sLh, Ja, iJ, qc);
         }
-        lifted_grad<P>(sW[NW - 1], sS[NS - 1], base, fbase, i, j, k, sDh, sLh, Ja, iJ, qc);
         if (full) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) a.Q[(12 + m) * a.NN + g] = qc[m];
@@ -755,13 +902,23 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
         T qf[2][3], uf[2][6];
 #pragma unroll
         for (int m = 0; m < 3; ++m) prolong2<P>(sW[m], base, sL, lt, qf[0][m], qf[1][m]);
-        // outward normal of the + face of this line (the - face's is its
-        // negative, exactly, as the mesh upload forms it)
-        T n[3];
-        {
+        // outward normal of each face of this line: on affine elements the -
+        // face's is the exact negative of the + face's, as the mesh upload
+        // forms them
+        T nf[2][3];
+        if constexpr (CV) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                T dS;
+                face_normal<P, T, true>(a.mesh, (size_t)el * 6 + 2 * lt.d + s, lt.fp, nf[s], dS);
+            }
+        } else {
             const double *fm = a.mesh.fmet + ((size_t)el * 6 + 2 * lt.d + 1) * 4;
 #pragma unroll
-            for (int m = 0; m < 3; ++m) n[m] = T(fm[m]);
+            for (int m = 0; m < 3; ++m) {
+                nf[1][m] = T(fm[m]);
+                nf[0][m] = -nf[1][m];
+            }
         }
 #pragma unroll
         for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
@@ -771,8 +928,8 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
                                           (double)uf[s][4], (double)uf[s][5], (double)qf[s][0], (double)qf[s][1],
                                           (double)qf[s][2]);
             const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
-            const T gn = qf[s][0] * n[0] + qf[s][1] * n[1] + qf[s][2] * n[2];
-            a.T2[o.at(kT2, 0)] = s ? gn : -gn;
+            const T gn = qf[s][0] * nf[s][0] + qf[s][1] * nf[s][1] + qf[s][2] * nf[s][2];
+            a.T2[o.at(kT2, 0)] = gn;
             a.T2[o.at(kT2, 1)] = T(Tf);
         }
         // wall faces also keep the vector grad c (Navier-slip traction), in
@@ -789,7 +946,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL>())) void k_lift1(Launch<T
 }
 
 // ------------------------------------------------------------ k_lift2
-template <int P, typename T, int BS, bool BATCH>
+template <int P, typename T, int BS, bool BATCH, bool CV = false>
 __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 {
     using G = Tile<P, BS>;
@@ -799,9 +956,13 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     // sX holds the primitives u, v, w, c [4][NV] and their BR1 face values
     // [4][NF] while grad u and grad c are lifted, then grad u [9][NV]
     constexpr int kX = 9 * G::NV > 4 * G::NV + 4 * G::NF ? 9 * G::NV : 4 * G::NV + 4 * G::NF;
-    __shared__ T sA[4][G::NV];     // T, grad c; then grad T, lap c
+    // curved elements: the metrics of every node and n dS of every face point
+    constexpr int NJ = CV ? 9 : 1, NQ = CV ? 3 : 1, NJV = CV ? G::NV : 1, NQF = CV ? G::NF : 1;
+    __shared__ T sA[4][G::NV];     // T, grad c (curved: its contravariant components); then grad T, lap c
     __shared__ T sX[kX];
     __shared__ T sTs[G::NF], sFs[G::NF];
+    __shared__ T sJa[NJ][NJV];
+    __shared__ T sN[NQ][NQF];
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
     T(*sW)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sX);
     T(*sS)[G::NF] = reinterpret_cast<T(*)[G::NF]>(sX + 4 * G::NV);
@@ -838,7 +999,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             if (v != 4) r.uo[v] = TU[o.at(6, v)];
         r.nb = a.mesh.nbr[el * 6 + ft.f];
         if (r.nb >= 0) {
-            const FaceIx<G::n2> on((size_t)r.nb * 6 + (ft.f ^ 1), ft.fp);
+            const FaceIx<G::n2> on(nbr_face<P>(r.nb), nbr_point<P>(r.nb, ft.fp));
 #pragma unroll
             for (int k = 0; k < 2; ++k) r.oth[k] = a.T2[on.at(kT2, k)];
 #pragma unroll
@@ -849,6 +1010,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     Tr tr0;
     if (t < G::NF) load_tr(t, tr0);
     T un[6];
+    T iJn = T(0);
     if (act) {
         T w[5];
 #pragma unroll
@@ -856,6 +1018,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         primitives(un, w);
 #pragma unroll
         for (int k = 0; k < 4; ++k) sW[k][t] = w[1 + k];
+        if constexpr (CV) iJn = stage_node_metrics<T, NJV>(a.mesh, a.NN, g, t, sJa);
     }
     __syncthreads();
     // face values: BR1 w* of u, v, w, c; T* and (grad c)* . n dS of the second lifting
@@ -865,7 +1028,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         if (el >= E) continue;
         Tr tr;
         if (task == t) tr = tr0; else load_tr(task, tr);
-        const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
+        T n[3], dS;
+        face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
         const T *uf = tr.uo;
         T w[5];
         primitives(uf, w);
@@ -876,9 +1040,9 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 #pragma unroll
             for (int k = 1; k < 5; ++k) w[k] = T(0.5) * (w[k] + v5[k]);
             Ts = T(0.5) * (tr.own[1] + tr.oth[1]);
-            Fs = T(0.5) * (tr.own[0] - tr.oth[0]) * T(fm[3]);
+            Fs = T(0.5) * (tr.own[0] - tr.oth[0]) * dS;
         } else {
-            wall_primitives(a.mesh, el, f, w);
+            wall_primitives(a.mesh, el, f, n, w);
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
             Ts = bc.iso ? T(bc.twall) : tr.own[1];
             if (bc.kind != 2) {
@@ -886,7 +1050,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 // temperature is applied in the pass below; the dynamic part,
                 // gamma_1 div u, once grad u is lifted)
                 const T c = uf[5];
-                Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * T(fm[3]);
+                Fs = T(bc.gcoef) * (c - T(bc.rl)) * (c - T(bc.rv)) * dS;
             } else {
                 Fs = T(0);
             }
@@ -896,6 +1060,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         for (int k = 0; k < 4; ++k) sS[k][slot] = w[1 + k];
         sTs[slot] = Ts;
         sFs[slot] = Fs;
+        if constexpr (CV) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sN[m][slot] = n[m] * dS;
+        }
     }
     if (a.mesh.var) {
         // walls whose temperature varies along them: T* and the static
@@ -916,7 +1084,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             if (bc.iso) sTs[slot] = T(wp.Tw);
             else a.TF[o.at(7, 6)] = T(1.0 / wp.Tw);  // 1/T_w for the heat-transfer flux below (TF[6] is free on walls)
             const T c = TU[o.at(6, 5)];
-            sFs[slot] = T(wp.gcoef) * (c - T(wp.rl)) * (c - T(wp.rv)) * T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+            sFs[slot] = T(wp.gcoef) * (c - T(wp.rl)) * (c - T(wp.rv)) * face_dS<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp);
         }
     }
     __syncthreads();
@@ -926,20 +1094,40 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
     T Ja[9], iJ = T(0);
     if (act) {
-        T gd[4][3];
-        lifted_grads<P, 4>(sW, sS, le * G::n3, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
-        element_metrics(a.mesh, e, Ja, iJ);
+        if constexpr (CV) {
+            T q[4][3];
+            lifted_grads_curved<P, 4, G::NV, G::NF>(sW, sS, sJa, sN, le * G::n3, le * 6 * G::n2, i, j, k, sDh, sLh,
+                                                    iJn, q);
 #pragma unroll
-        for (int w = 0; w < 3; ++w) to_physical(Ja, iJ, gd[w], gu + 3 * w);
-        to_physical(Ja, iJ, gd[3], gc);
+            for (int w = 0; w < 3; ++w)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) gu[3 * w + m] = q[w][m];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) gc[m] = q[3][m];
+            iJ = iJn;
+        } else {
+            T gd[4][3];
+            lifted_grads<P, 4>(sW, sS, le * G::n3, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
+            element_metrics(a.mesh, e, Ja, iJ);
+#pragma unroll
+            for (int w = 0; w < 3; ++w) to_physical(Ja, iJ, gd[w], gu + 3 * w);
+            to_physical(Ja, iJ, gd[3], gc);
+        }
         Tn = temperature(a.ph, (double)un[0], (double)un[1], (double)un[2], (double)un[3], (double)un[4],
                          (double)un[5], (double)gc[0], (double)gc[1], (double)gc[2]);
     }
     __syncthreads();
     if (act) {
         sA[0][t] = T(Tn);
+        if constexpr (CV) {
+            // contravariant components Ja^d . grad c for the divergence lifting
 #pragma unroll
-        for (int m = 0; m < 3; ++m) sA[1 + m][t] = gc[m];
+            for (int d = 0; d < 3; ++d)
+                sA[1 + d][t] = sJa[3 * d][t] * gc[0] + sJa[3 * d + 1][t] * gc[1] + sJa[3 * d + 2][t] * gc[2];
+        } else {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sA[1 + m][t] = gc[m];
+        }
 #pragma unroll
         for (int r = 0; r < 9; ++r) sGu[r][t] = gu[r];
     }
@@ -963,7 +1151,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 d1 += T(Lf[l]) * sGu[4][lo + l * ls];
                 d2 += T(Lf[l]) * sGu[8][lo + l * ls];
             }
-            const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+            const T dS = face_dS<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp);
             sFs[ft.le * 6 * G::n2 + f * G::n2 + ft.fp] += T(bc.g1_gam) * ((d0 + d1) + d2) * dS;
         }
         __syncthreads();
@@ -975,61 +1163,96 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         const int fpd[3] = {j + P * k, i + P * k, i + P * j};
         const int base = le * G::n3;
         const int fbase = le * 6 * G::n2;
-        T gd[3], dl = T(0);
+        if constexpr (CV) {
+            // lap c: Dhat sweeps of the contravariant components; grad T: the
+            // conservative lifting with the node metrics
+            T dl = T(0);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int id = idx[d];
-            const int p = d == 0 ? j : i, q = d == 2 ? j : k;
-            T accT = T(0), a0 = T(0), a1 = T(0), a2 = T(0);
+            for (int d = 0; d < 3; ++d) {
+                const int id = idx[d];
+                const int p = d == 0 ? j : i, q = d == 2 ? j : k;
+                T ad = T(0);
 #pragma unroll
-            for (int l = 0; l < P; ++l) {
-                const int n = base + line_node<P>(d, l, p, q);
-                const T D = T(sDh[id * P + l]);
-                accT += D * sA[0][n];
-                a0 += D * sA[1][n];
-                a1 += D * sA[2][n];
-                a2 += D * sA[3][n];
+                for (int l = 0; l < P; ++l) ad += T(sDh[id * P + l]) * sA[1 + d][base + line_node<P>(d, l, p, q)];
+                const int fp = fbase + (2 * d + 1) * G::n2 + fpd[d], fm_ = fbase + (2 * d) * G::n2 + fpd[d];
+                dl += ad + T(sLh[P + id]) * sFs[fp] + T(sLh[id]) * sFs[fm_];
             }
-            const int fp = fbase + (2 * d + 1) * G::n2 + fpd[d], fm_ = fbase + (2 * d) * G::n2 + fpd[d];
-            accT += T(sLh[P + id]) * sTs[fp] - T(sLh[id]) * sTs[fm_];
-            gd[d] = accT;
-            dl += Ja[3 * d + 0] * a0 + Ja[3 * d + 1] * a1 + Ja[3 * d + 2] * a2 +
-                  T(sLh[P + id]) * sFs[fp] + T(sLh[id]) * sFs[fm_];
-        }
+            T qT[1][3];
+            lifted_grads_curved<P, 1, G::NV, G::NF>(sA, &sTs, sJa, sN, base, fbase, i, j, k, sDh, sLh, iJ, qT);
+            gT[0] = qT[0][0];
+            gT[1] = qT[0][1];
+            gT[2] = qT[0][2];
+            lap = iJ * dl;
+        } else {
+            T gd[3], dl = T(0);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) gT[m] = iJ * (Ja[m] * gd[0] + Ja[3 + m] * gd[1] + Ja[6 + m] * gd[2]);
-        lap = iJ * dl;
+            for (int d = 0; d < 3; ++d) {
+                const int id = idx[d];
+                const int p = d == 0 ? j : i, q = d == 2 ? j : k;
+                T accT = T(0), a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+                for (int l = 0; l < P; ++l) {
+                    const int n = base + line_node<P>(d, l, p, q);
+                    const T D = T(sDh[id * P + l]);
+                    accT += D * sA[0][n];
+                    a0 += D * sA[1][n];
+                    a1 += D * sA[2][n];
+                    a2 += D * sA[3][n];
+                }
+                const int fp = fbase + (2 * d + 1) * G::n2 + fpd[d], fm_ = fbase + (2 * d) * G::n2 + fpd[d];
+                accT += T(sLh[P + id]) * sTs[fp] - T(sLh[id]) * sTs[fm_];
+                gd[d] = accT;
+                dl += Ja[3 * d + 0] * a0 + Ja[3 * d + 1] * a1 + Ja[3 * d + 2] * a2 +
+                      T(sLh[P + id]) * sFs[fp] + T(sLh[id]) * sFs[fm_];
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) gT[m] = iJ * (Ja[m] * gd[0] + Ja[3 + m] * gd[1] + Ja[6 + m] * gd[2]);
+            lap = iJ * dl;
+        }
         a.G2[0 * a.NN + g] = gT[0];
         a.G2[1 * a.NN + g] = gT[1];
         a.G2[2 * a.NN + g] = gT[2];
         a.G2[3 * a.NN + g] = lap;
     }
     __syncthreads();
-    // per direction d, at the nodes: tau . n_d (3) and grad T . n_d with n_d
-    // the outward normal of face 2d+1 (face 2d has exactly -n_d on these
-    // affine elements), plus div u and lap c.  Their face values are the
-    // prolongations of these nodal values (n_d is constant on the face), so
-    // a face task prolongs 12 fields instead of 19.  Layout: direction 0 in
-    // sA, directions 1 and 2 and div u in sX (each thread overwrites only its
-    // own node's grad u, which it has read), lap c in sTs.
-    if (act) {
-        T g[9];
-#pragma unroll
-        for (int r = 0; r < 9; ++r) g[r] = sGu[r][t];
-        const T div = g[0] + g[4] + g[8];
-        const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double *fm = a.mesh.fmet + ((size_t)e * 6 + 2 * d + 1) * 4;
-            const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
-            T *out = d == 0 ? &sA[0][0] : sX + (d - 1) * 4 * G::NV;
-            out[0 * G::NV + t] = mu * ((g[0] + g[0]) * n0 + (g[1] + g[3]) * n1 + (g[2] + g[6]) * n2 - td * n0);
-            out[1 * G::NV + t] = mu * ((g[3] + g[1]) * n0 + (g[4] + g[4]) * n1 + (g[5] + g[7]) * n2 - td * n1);
-            out[2 * G::NV + t] = mu * ((g[6] + g[2]) * n0 + (g[7] + g[5]) * n1 + (g[8] + g[8]) * n2 - td * n2);
-            out[3 * G::NV + t] = gT[0] * n0 + gT[1] * n1 + gT[2] * n2;
+    if constexpr (CV) {
+        // curved elements: the normal varies along the face, so the face
+        // tasks prolong grad u (already in sX), grad T and lap c and take
+        // their normal components at each face point: grad T in sA[1..3],
+        // lap c in sTs
+        if (act) {
+            sA[1][t] = gT[0];
+            sA[2][t] = gT[1];
+            sA[3][t] = gT[2];
+            sTs[t] = lap;
         }
-        sX[8 * G::NV + t] = div;
-        sTs[t] = lap;
+    } else {
+        // per direction d, at the nodes: tau . n_d (3) and grad T . n_d with n_d
+        // the outward normal of face 2d+1 (face 2d has exactly -n_d on these
+        // affine elements), plus div u and lap c.  Their face values are the
+        // prolongations of these nodal values (n_d is constant on the face), so
+        // a face task prolongs 12 fields instead of 19.  Layout: direction 0 in
+        // sA, directions 1 and 2 and div u in sX (each thread overwrites only its
+        // own node's grad u, which it has read), lap c in sTs.
+        if (act) {
+            T gg[9];
+#pragma unroll
+            for (int r = 0; r < 9; ++r) gg[r] = sGu[r][t];
+            const T div = gg[0] + gg[4] + gg[8];
+            const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double *fm = a.mesh.fmet + ((size_t)e * 6 + 2 * d + 1) * 4;
+                const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+                T *out = d == 0 ? &sA[0][0] : sX + (d - 1) * 4 * G::NV;
+                out[0 * G::NV + t] = mu * ((gg[0] + gg[0]) * n0 + (gg[1] + gg[3]) * n1 + (gg[2] + gg[6]) * n2 - td * n0);
+                out[1 * G::NV + t] = mu * ((gg[3] + gg[1]) * n0 + (gg[4] + gg[4]) * n1 + (gg[5] + gg[7]) * n2 - td * n1);
+                out[2 * G::NV + t] = mu * ((gg[6] + gg[2]) * n0 + (gg[7] + gg[5]) * n1 + (gg[8] + gg[8]) * n2 - td * n2);
+                out[3 * G::NV + t] = gT[0] * n0 + gT[1] * n1 + gT[2] * n2;
+            }
+            sX[8 * G::NV + t] = div;
+            sTs[t] = lap;
+        }
     }
     __syncthreads();
     // own-face flux traces, one face point per task: G = (F^C - F^V).n and
@@ -1050,8 +1273,9 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 return acc;
             };
             const FaceIx<G::n2> o((size_t)el * 6 + f, ft.fp);
-            const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
-            const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+            T nrm[3], dSf;
+            face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, nrm, dSf);
+            const T n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
             const bool wall = a.mesh.nbr[el * 6 + f] < 0;
             int kind = 0;  // interior faces have no wall-table entry
             if (wall) kind = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind;
@@ -1110,10 +1334,31 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             }
             // viscous traction tau n = mu ((grad u + grad u^T) n - 2/3 div u n)
             __builtin_amdgcn_sched_barrier(0);
+            // affine elements: the nodal normal components of direction f/2,
+            // with the face's sign; curved: the normal components are taken
+            // of the prolonged gradients at this face point
             const T sgn = (f & 1) ? T(1) : T(-1);
             const T *nf = (f >> 1) == 0 ? &sA[0][0] : sX + ((f >> 1) - 1) * 4 * G::NV;
-            const T div = pro(sX + 8 * G::NV);
-            const T tn0 = sgn * pro(nf), tn1 = sgn * pro(nf + G::NV), tn2 = sgn * pro(nf + 2 * G::NV);
+            auto grad_T_n = [&]() {
+                if constexpr (CV) return pro(sA[1]) * n0 + pro(sA[2]) * n1 + pro(sA[3]) * n2;
+                else return sgn * pro(nf + 3 * G::NV);
+            };
+            T div, tn0, tn1, tn2;
+            if constexpr (CV) {
+                T gf[9];
+#pragma unroll
+                for (int r = 0; r < 9; ++r) gf[r] = pro(sGu[r]);  // gf[3 j + i] = d u_j / d x_i
+                div = gf[0] + gf[4] + gf[8];
+                const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
+                tn0 = mu * ((gf[0] + gf[0]) * n0 + (gf[1] + gf[3]) * n1 + (gf[2] + gf[6]) * n2 - td * n0);
+                tn1 = mu * ((gf[3] + gf[1]) * n0 + (gf[4] + gf[4]) * n1 + (gf[5] + gf[7]) * n2 - td * n1);
+                tn2 = mu * ((gf[6] + gf[2]) * n0 + (gf[7] + gf[5]) * n1 + (gf[8] + gf[8]) * n2 - td * n2);
+            } else {
+                div = pro(sX + 8 * G::NV);
+                tn0 = sgn * pro(nf);
+                tn1 = sgn * pro(nf + G::NV);
+                tn2 = sgn * pro(nf + 2 * G::NV);
+            }
             if (!wall) {
                 G1 -= tn0;
                 G2_ -= tn1;
@@ -1153,12 +1398,12 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             __builtin_amdgcn_sched_barrier(0);
             // (interior faces have no wall-table entry: bcid is 0 there)
             if (!wall) {
-                const T gTn = sgn * pro(nf + 3 * G::NV);
+                const T gTn = grad_T_n();
                 G4 -= T(a.ph.kappa) * gTn;
             } else if (kind != 2) {
                 const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
                 if (bc.iso) {
-                    const T gTn = sgn * pro(nf + 3 * G::NV);
+                    const T gTn = grad_T_n();
                     G4 -= T(a.ph.kappa) * gTn;
                 } else {  // heat transfer, eq. bc_energy_alpha
                     const double itw = bc.var ? (double)a.TF[o.at(7, 6)] : bc.inv_tw;
@@ -1179,10 +1424,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                 // walls), as the second lifting used it: sFs holds g dS; and
                 // the wall value zeta_c = -gamma_1 gamma_4 div u
                 const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                const T g = sFs[ft.le * 6 * G::n2 + f * G::n2 + ft.fp] / T(fm[3]);
+                const T gw = sFs[ft.le * 6 * G::n2 + f * G::n2 + ft.fp] / dSf;
                 const T zeta = -T(bc.g1 * bc.g4) * div;
-                G4 -= -T(a.ph.gam) * c * g * div + T(a.ph.gam) * g * zeta;
-                G5 -= T(a.ph.gam * a.ph.beta) * g;
+                G4 -= -T(a.ph.gam) * c * gw * div + T(a.ph.gam) * gw * zeta;
+                G5 -= T(a.ph.gam * a.ph.beta) * gw;
             }
             a.TF[o.at(7, 0)] = G0;
             a.TF[o.at(7, 1)] = G1;
@@ -1195,7 +1440,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 }
 
 // ------------------------------------------------------------ k_update
-template <int P, typename T, int BS, bool BATCH>
+template <int P, typename T, int BS, bool BATCH, bool CV = false>
 __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 {
     using G = Tile<P, BS>;
@@ -1209,6 +1454,10 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     __shared__ T sF[6][G::NV];
     __shared__ T sB[kB];
     __shared__ T sFs[6][G::NF];    // surface flux (F* . n) dS
+    // curved elements: the metrics of every node and n dS of every face point
+    constexpr int NJ = CV ? 9 : 1, NQ = CV ? 3 : 1, NJV = CV ? G::NV : 1, NQF = CV ? G::NF : 1;
+    __shared__ T sJa[NJ][NJV];
+    __shared__ T sN[NQ][NQF];
     T(*sS)[G::NF] = reinterpret_cast<T(*)[G::NF]>(sB);
     T(*sF2)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sB);
     __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
@@ -1241,7 +1490,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 #pragma unroll
         for (int v = 0; v < 6; ++v) r.G[v] = a.TF[o.at(7, v)];
         if (r.nb >= 0) {
-            const FaceIx<G::n2> on((size_t)r.nb * 6 + (ft.f ^ 1), ft.fp);
+            const FaceIx<G::n2> on(nbr_face<P>(r.nb), nbr_point<P>(r.nb, ft.fp));
             r.G[6] = a.TF[o.at(7, 6)];
 #pragma unroll
             for (int v = 0; v < 7; ++v) r.Gn[v] = a.TF[on.at(7, v)];
@@ -1255,7 +1504,9 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     Tr tr0;
     if (kEarly && t < G::NF) load_tr(t, tr0);
     Pt<T> s;
+    T iJn = T(0);
     if (act) {
+        if constexpr (CV) iJn = stage_node_metrics<T, NJV>(a.mesh, a.NN, g, t, sJa);
         s.rho = a.U[0 * a.NN + g];
         s.m[0] = a.U[1 * a.NN + g];
         s.m[1] = a.U[2 * a.NN + g];
@@ -1278,8 +1529,13 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         if (el >= E) continue;
         Tr tr;
         if (kEarly) tr = tr0; else load_tr(task, tr);
-        const T dS = T(a.mesh.fmet[((size_t)el * 6 + f) * 4 + 3]);
+        T n[3], dS;
+        face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
         const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
+        if constexpr (CV) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sN[m][slot] = n[m] * dS;
+        }
         T w[5];
         primitives(tr.uo, w);
         if (tr.nb >= 0 && a.ph.model == 2) {
@@ -1293,8 +1549,6 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
             for (int k = 0; k < 5; ++k) sS[k][slot] = T(0.5) * (w[k] + wn[k]);
 #pragma unroll
             for (int v = 1; v < 6; ++v) sFs[v][slot] = T(0.5) * (tr.G[v] - tr.Gn[v]) * dS;
-            const double *fm = a.mesh.fmet + ((size_t)el * 6 + f) * 4;
-            const T n[3] = {T(fm[0]), T(fm[1]), T(fm[2])};
             T Fc[6];
             hllc(tr.uo, tr.G[0], tr.G[6], tr.un, tr.Gn[0], tr.Gn[6], n, Fc);
             sFs[0][slot] = Fc[0] * dS;
@@ -1315,7 +1569,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         } else {
 #pragma unroll
             for (int v = 0; v < 6; ++v) sFs[v][slot] = tr.G[v] * dS;
-            wall_primitives(a.mesh, el, f, w);
+            wall_primitives(a.mesh, el, f, n, w);
         }
 #pragma unroll
         for (int k = 0; k < 5; ++k) sS[k][slot] = w[k];
@@ -1330,14 +1584,29 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 #pragma unroll
         for (int m = 0; m < 3; ++m) s.gT[m] = a.G2[m * a.NN + g];
         s.lapc = a.G2[3 * a.NN + g];
-        T gd[5][3];
-        lifted_grads<P, 5>(sF, sS, base, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
-        T Ja[9], grho[3];
-        element_metrics(a.mesh, e, Ja, iJ);
-        to_physical(Ja, iJ, gd[0], grho);
+        T grho[3];
+        if constexpr (CV) {
+            T q[5][3];
+            lifted_grads_curved<P, 5, G::NV, G::NF>(sF, sS, sJa, sN, base, le * 6 * G::n2, i, j, k, sDh, sLh, iJn, q);
+            iJ = iJn;
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj) to_physical(Ja, iJ, gd[1 + jj], s.gu[jj]);
-        to_physical(Ja, iJ, gd[4], s.gc);
+            for (int m = 0; m < 3; ++m) {
+                grho[m] = q[0][m];
+                s.gu[0][m] = q[1][m];
+                s.gu[1][m] = q[2][m];
+                s.gu[2][m] = q[3][m];
+                s.gc[m] = q[4][m];
+            }
+        } else {
+            T gd[5][3];
+            lifted_grads<P, 5>(sF, sS, base, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
+            T Ja[9];
+            element_metrics(a.mesh, e, Ja, iJ);
+            to_physical(Ja, iJ, gd[0], grho);
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) to_physical(Ja, iJ, gd[1 + jj], s.gu[jj]);
+            to_physical(Ja, iJ, gd[4], s.gc);
+        }
         // the temperature is held in the element type, as every stored field
         const double Tn = (double)T(temperature(a.ph, (double)s.rho, (double)s.m[0], (double)s.m[1], (double)s.m[2],
                                                 (double)s.E, (double)s.c, (double)s.gc[0], (double)s.gc[1],
@@ -1354,8 +1623,17 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     // direction d is read, one barrier per direction
     T acc[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
     auto put_flux = [&](int d, T (*buf)[G::NV]) {
-        const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
-        const T Jd[3] = {T(em[0]), T(em[1]), T(em[2])};
+        T Jd[3];
+        if constexpr (CV) {
+            Jd[0] = sJa[3 * d][t];
+            Jd[1] = sJa[3 * d + 1][t];
+            Jd[2] = sJa[3 * d + 2][t];
+        } else {
+            const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
+            Jd[0] = T(em[0]);
+            Jd[1] = T(em[1]);
+            Jd[2] = T(em[2]);
+        }
 #pragma unroll
         for (int v = 0; v < 6; ++v) buf[v][t] = Jd[0] * Fx[v][0] + Jd[1] * Fx[v][1] + Jd[2] * Fx[v][2];
     };

@@ -33,6 +33,9 @@ struct nskr_ctx {
     size_t NN = 0, NF = 0;
     int *d_nbr = nullptr, *d_bcid = nullptr;
     double *d_emet = nullptr, *d_fmet = nullptr, *d_egeo = nullptr;
+    bool curved = false;         // some element is not affine: per-node metrics
+    void *d_nmet = nullptr, *d_fnrm = nullptr;  // curved: node metrics, face-point normals (element type)
+    double *d_xnode = nullptr;   // curved: node coordinates
     BcDev *d_bcs = nullptr;
     int dyn = 0;                 // a Navier-slip wall with gamma_1 != 0
     double *d_stab = nullptr;    // wall-temperature table (walls with a temperature gradient)
@@ -40,7 +43,6 @@ struct nskr_ctx {
     int trate = 0;               // some wall's temperature changes in time
     double time = 0.0;           // simulation time (walls whose temperature changes in time)
     std::vector<std::array<double, 3>> wall_trange;  // per wall: min, max of twall + grad . x over it; rate
-    std::vector<double> h_emet;  // host copy of the element metrics (weights for reductions)
     // scratch (element type of the precision)
     void *d_Q = nullptr, *d_TH = nullptr, *d_G2 = nullptr, *d_T2 = nullptr, *d_TF = nullptr, *d_TU = nullptr;
     void *d_Ck = nullptr;        // Kahan compensation of the FP32 state update
@@ -380,7 +382,7 @@ struct RateArgs {
     MeshDev mesh; Phys ph; size_t NN; double *part; int nblk;
 };
 
-template <int P, typename T>
+template <int P, typename T, bool CV>
 __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, RateArgs a)
 {
     using G = Tile<P>;
@@ -396,7 +398,13 @@ __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, Rat
         double p, cs2;
         eos(a.ph, rho, Tn, p, cs2);
         double cs = sqrt(fabs(cs2 + a.ph.ap * rho));  // sound speed of the convective flux
-        const double *em = a.mesh.emet + (size_t)e * 10;
+        double em[10];
+        if (CV) {
+            const T *nm = (const T *)a.mesh.nmet;
+            for (int r = 0; r < 10; ++r) em[r] = (double)nm[r * a.NN + g];
+        } else {
+            for (int r = 0; r < 10; ++r) em[r] = a.mesh.emet[(size_t)e * 10 + r];
+        }
         double iJ = 1.0 / em[9];
         for (int d = 0; d < 3; ++d) {
             const double *Ja = em + 3 * d;
@@ -439,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_max_final(const double *part, int nb
 // Integrals: kinds 0 = sum, 1 = min, 2 = max for the NSKR_SUM_* slots.
 __device__ __forceinline__ int sum_kind(int k) { return k == 10 || k == 12 ? 1 : (k == 11 || k == 13 ? 2 : 0); }
 
-template <int P, typename T>
+template <int P, typename T, bool CV>
 __global__ __launch_bounds__(kBlock) void k_integrals(const T *U, const T *Q, RateArgs a, Basis bas)
 {
     using G = Tile<P>;
@@ -453,7 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_integrals(const T *U, const T *Q, Ra
     v[11] = v[13] = -INFINITY;
     if (t < G::NV && e < a.mesh.E) {
         const int i = nd % P, j = (nd / P) % P, k = nd / (P * P);
-        const double wJ = bas.w[i] * bas.w[j] * bas.w[k] * a.mesh.emet[(size_t)e * 10 + 9];
+        const double Jn = CV ? (double)((const T *)a.mesh.nmet)[9 * a.NN + g] : a.mesh.emet[(size_t)e * 10 + 9];
+        const double wJ = bas.w[i] * bas.w[j] * bas.w[k] * Jn;
         double u[6];
         bool bad = false;
         for (int q = 0; q < 6; ++q) {
@@ -534,7 +543,7 @@ struct InitArgs {
     double wax[3];  // 1 for the axes the droplet distance spans, 0 for a cylinder's axis
 };
 
-template <int P, typename T>
+template <int P, typename T, bool CV>
 __global__ __launch_bounds__(kBlock) void k_init_rho(T *U, InitArgs a)
 {
     using G = Tile<P>;
@@ -543,12 +552,16 @@ __global__ __launch_bounds__(kBlock) void k_init_rho(T *U, InitArgs a)
     if (t >= G::NV || e >= a.mesh.E) return;
     const size_t g = (size_t)e0 * G::n3 + t;
     const int idx[3] = {nd % P, (nd / P) % P, nd / (P * P)};
-    const double *eg = a.mesh.egeo + (size_t)e * 12;
     double x[3];
-    for (int m = 0; m < 3; ++m) {
-        double s = eg[m];
-        for (int d = 0; d < 3; ++d) s += eg[3 + 3 * d + m] * 0.5 * (a.bas.x[idx[d]] + 1.0);
-        x[m] = s;
+    if (CV) {
+        for (int m = 0; m < 3; ++m) x[m] = a.mesh.xnode[m * a.NN + g];
+    } else {
+        const double *eg = a.mesh.egeo + (size_t)e * 12;
+        for (int m = 0; m < 3; ++m) {
+            double s = eg[m];
+            for (int d = 0; d < 3; ++d) s += eg[3 + 3 * d + m] * 0.5 * (a.bas.x[idx[d]] + 1.0);
+            x[m] = s;
+        }
     }
     double rho = a.rv, u[3] = {0.0, 0.0, 0.0};
     for (int jd = 0; jd < a.ndrop; ++jd) {
@@ -601,8 +614,9 @@ __global__ __launch_bounds__(64) void k_tick(int *const *clk, int n)
 }
 
 // ------------------------------------------------------------ launch layer
-template <int P, typename T, int BS> struct Impl {
+template <int P, typename T, int BS, bool CV> struct Impl {
     static constexpr int kP = P, kBS = BS;
+    static constexpr bool kCV = CV;
     using Real = T;
     using G = Tile<P, BS>;
     using G256 = Tile<P, kBlock>;
@@ -614,6 +628,7 @@ template <int P, typename T, int BS> struct Impl {
         MeshDev m;
         m.E = c->E; m.nbr = c->d_nbr; m.bcid = c->d_bcid; m.emet = c->d_emet; m.fmet = c->d_fmet;
         m.egeo = c->d_egeo; m.bcs = c->d_bcs; m.dyn = c->dyn; m.stab = c->d_stab; m.var = c->var;
+        m.nmet = c->d_nmet; m.fnrm = c->d_fnrm; m.xnode = c->d_xnode;
         return m;
     }
     static Inst<T> inst(const nskr_ctx *c, const void *U, void *R, void *Ut, double dt)
@@ -640,10 +655,10 @@ template <int P, typename T, int BS> struct Impl {
     static int fits(int maxlds)
     {
         const void *fns[] = {reinterpret_cast<const void *>(&k_prolong<P, T, BS, false>),
-                             reinterpret_cast<const void *>(&k_lift1<P, T, BS, false>),
-                             reinterpret_cast<const void *>(&k_lift1<P, T, BS, false, true>),
-                             reinterpret_cast<const void *>(&k_lift2<P, T, BS, false>),
-                             reinterpret_cast<const void *>(&k_update<P, T, BS, false>)};
+                             reinterpret_cast<const void *>(&k_lift1<P, T, BS, false, false, CV>),
+                             reinterpret_cast<const void *>(&k_lift1<P, T, BS, false, true, CV>),
+                             reinterpret_cast<const void *>(&k_lift2<P, T, BS, false, CV>),
+                             reinterpret_cast<const void *>(&k_update<P, T, BS, false, CV>)};
         for (const void *f : fns) {
             hipFuncAttributes at;
             if (hipFuncGetAttributes(&at, f) != hipSuccess) return 0;
@@ -659,17 +674,17 @@ template <int P, typename T, int BS> struct Impl {
     static void lift1(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
         if (L.full)
-            stage_launch<T>(c, 1, &k_lift1<P, T, BS, false, true>, nblk(c), BS, s, L);
+            stage_launch<T>(c, 1, &k_lift1<P, T, BS, false, true, CV>, nblk(c), BS, s, L);
         else
-            stage_launch<T>(c, 1, &k_lift1<P, T, BS, false>, nblk(c), BS, s, L);
+            stage_launch<T>(c, 1, &k_lift1<P, T, BS, false, false, CV>, nblk(c), BS, s, L);
     }
     static void lift2(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        stage_launch<T>(c, 2, &k_lift2<P, T, BS, false>, nblk(c), BS, s, L);
+        stage_launch<T>(c, 2, &k_lift2<P, T, BS, false, CV>, nblk(c), BS, s, L);
     }
     static void update(nskr_ctx *c, const Launch<T> &L, hipStream_t s)
     {
-        stage_launch<T>(c, 3, &k_update<P, T, BS, false>, nblk(c), BS, s, L);
+        stage_launch<T>(c, 3, &k_update<P, T, BS, false, CV>, nblk(c), BS, s, L);
     }
     // batched launches over a group table
     // one RK step of every instance of a group; the face traces of the first
@@ -685,9 +700,9 @@ template <int P, typename T, int BS> struct Impl {
             L.tb = kTraceBuf[st];
             L.tw = kTraceBuf[st + 1];
             L.cs = kRkC[st];
-            hipLaunchKernelGGL((k_lift1<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
-            hipLaunchKernelGGL((k_lift2<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
-            hipLaunchKernelGGL((k_update<P, T, BS, true>), dim3(nblocks), dim3(BS), 0, s, L);
+            hipLaunchKernelGGL((k_lift1<P, T, BS, true, false, CV>), dim3(nblocks), dim3(BS), 0, s, L);
+            hipLaunchKernelGGL((k_lift2<P, T, BS, true, CV>), dim3(nblocks), dim3(BS), 0, s, L);
+            hipLaunchKernelGGL((k_update<P, T, BS, true, CV>), dim3(nblocks), dim3(BS), 0, s, L);
         }
     }
 
@@ -771,7 +786,7 @@ template <int P, typename T, int BS> struct Impl {
         prolong(c, L, s);
         lift1(c, L, s);
         RateArgs a{mesh(c), c->ph, c->NN, part, nblk256(c)};
-        hipLaunchKernelGGL((k_dt_rates<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
+        hipLaunchKernelGGL((k_dt_rates<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a);
         hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nblk256(c), 3, dout);
         HIPCHK(c, hipGetLastError());
@@ -786,7 +801,7 @@ template <int P, typename T, int BS> struct Impl {
         prolong(c, L, s);
         lift1(c, L, s);
         RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
-        hipLaunchKernelGGL((k_integrals<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
+        hipLaunchKernelGGL((k_integrals<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a, c->bas);
         hipLaunchKernelGGL(k_integrals_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk256(c),
                            c->d_out);
@@ -798,7 +813,7 @@ template <int P, typename T, int BS> struct Impl {
     static int init(nskr_ctx *c, const InitArgs &ia, double T0, void *Uv, hipStream_t s)
     {
         T *U = (T *)Uv;
-        hipLaunchKernelGGL((k_init_rho<P, T>), dim3(nblk256(c)), dim3(kBlock), 0, s, U, ia);
+        hipLaunchKernelGGL((k_init_rho<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, U, ia);
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
         L.full = 1;
         prolong(c, L, s);
@@ -820,15 +835,22 @@ static bool block_ok(int N, int bs)
     return epb >= 1 && epb * 3 * P * P <= bs;
 }
 
-template <typename F> static int dispatch(const nskr_ctx *c, F &&f)
+// The kernel instance set of a (degree, precision, block size, curved) choice.
+// Curved meshes run 256-thread workgroups only (their per-node metrics do
+// not fit the LDS of 512-thread tiles at every degree).
+template <typename F> static int impl_dispatch(int N, int prec, int bs, bool curved, F &&f)
 {
-    const bool dbl = c->p.precision == 0;
-    const bool big = c->bs == 512;
-#define NSKR_CASE(NN, PP)                                                                  \
-    case NN:                                                                               \
-        if (dbl) return big ? f(Impl<PP, double, 512>()) : f(Impl<PP, double, 256>());     \
-        return big ? f(Impl<PP, float, 512>()) : f(Impl<PP, float, 256>());
-    switch (c->N) {
+    const bool dbl = prec == 0;
+    const bool big = bs == 512;
+#define NSKR_CASE(NN, PP)                                                                               \
+    case NN:                                                                                            \
+        if (curved) {                                                                                   \
+            if (big) return NSKR_E_UNSUPPORTED;                                                         \
+            return dbl ? f(Impl<PP, double, 256, true>()) : f(Impl<PP, float, 256, true>());            \
+        }                                                                                               \
+        if (dbl) return big ? f(Impl<PP, double, 512, false>()) : f(Impl<PP, double, 256, false>());     \
+        return big ? f(Impl<PP, float, 512, false>()) : f(Impl<PP, float, 256, false>());
+    switch (N) {
         NSKR_CASE(2, 3)
         NSKR_CASE(3, 4)
         NSKR_CASE(4, 5)
@@ -836,6 +858,11 @@ template <typename F> static int dispatch(const nskr_ctx *c, F &&f)
     }
 #undef NSKR_CASE
     return NSKR_E_ARG;
+}
+
+template <typename F> static int dispatch(const nskr_ctx *c, F &&f)
+{
+    return impl_dispatch(c->N, c->p.precision, c->bs, c->curved, f);
 }
 
 static int elem_per_block(int N)
@@ -874,6 +901,161 @@ static double *static_scratch(int device)
     if (device < 0 || device >= kMaxDevices) return nullptr;
     std::lock_guard<std::mutex> lock(g_scratch_mtx);
     return g_scratch[device];
+}
+
+// ------------------------------------------------------------ mesh geometry
+// Elements are given by their geometry nodes on the Gauss-Lobatto points of
+// degree ngeo <= N (Sec. 3.1: curved elements of geometry degree N_geo); the
+// library interpolates them to the degree-N Gauss-Lobatto points and forms
+// the metric terms Ja^d_m = J d xi^d / d x_m in the conservative curl form
+// (Kopriva 2006): Ja^i_n = -(curl_xi (X_l grad_xi X_m))_i, (n, m, l)
+// cyclic, evaluated at the Gauss-Lobatto points, then interpolated to the
+// Gauss nodes (volume) and to the Gauss points of each face (xi^d = +-1 is a
+// Gauss-Lobatto layer).  Extended precision, rounded once.
+
+// Gauss-Lobatto points of degree n: the ends and the roots of P_{n+1} -
+// P_{n-1}, which vanish exactly where P_n' does, by Newton from the
+// Chebyshev-Lobatto points.
+static void lobatto_host(int n, ld *x)
+{
+    x[0] = -1;
+    x[n] = 1;
+    for (int i = 1; i < n; ++i) {
+        ld xi = -cosl(3.14159265358979323846264338327950288L * i / n);
+        for (int it = 0; it < 100; ++it) {
+            ld pm, dpm, pp, dpp;
+            legendre_ld(n - 1, xi, pm, dpm);
+            legendre_ld(n + 1, xi, pp, dpp);
+            const ld dx = (pp - pm) / (dpp - dpm);
+            xi -= dx;
+            if (fabsl(dx) < 1e-21L) break;
+        }
+        x[i] = xi;
+    }
+}
+
+// M[a][b] = l_b(y_a), the Lagrange basis of the nodes xs[0..nx) at ys[0..ny).
+static std::vector<ld> interp_matrix(int nx, const ld *xs, int ny, const ld *ys)
+{
+    std::vector<ld> M((size_t)ny * nx, 1.0L);
+    for (int a = 0; a < ny; ++a)
+        for (int b = 0; b < nx; ++b)
+            for (int k = 0; k < nx; ++k)
+                if (k != b) M[(size_t)a * nx + b] *= (ys[a] - xs[k]) / (xs[b] - xs[k]);
+    return M;
+}
+
+// Apply the (nout x nin) matrix M along direction d of a tensor array with
+// extents n[3] (index a + n0 (b + n1 c)); the result has n[d] = nout.
+static std::vector<ld> tensor_apply(const std::vector<ld> &in, const int n[3], int d, const ld *M, int nout)
+{
+    int m[3] = {n[0], n[1], n[2]};
+    m[d] = nout;
+    std::vector<ld> out((size_t)m[0] * m[1] * m[2], 0.0L);
+    for (int c = 0; c < m[2]; ++c)
+        for (int b = 0; b < m[1]; ++b)
+            for (int a = 0; a < m[0]; ++a) {
+                const int o[3] = {a, b, c};
+                ld acc = 0;
+                for (int l = 0; l < n[d]; ++l) {
+                    int ii[3] = {a, b, c};
+                    ii[d] = l;
+                    acc += M[(size_t)o[d] * n[d] + l] * in[ii[0] + (size_t)n[0] * (ii[1] + (size_t)n[1] * ii[2])];
+                }
+                out[a + (size_t)m[0] * (b + (size_t)m[1] * c)] = acc;
+            }
+    return out;
+}
+
+struct GeomOps {
+    int N, P, ng;
+    ld xs[8];                     // Gauss nodes
+    std::vector<ld> Vg, Dl, Vs;   // GL(ngeo) -> GL(N), derivative on GL(N), GL(N) -> Gauss
+    GeomOps(int N_, int ng_, const Basis &b) : N(N_), P(N_ + 1), ng(ng_)
+    {
+        ld xg[8], xl[8];
+        lobatto_host(ng, xg);
+        lobatto_host(N, xl);
+        Vg = interp_matrix(ng + 1, xg, P, xl);
+        for (int i = 0; i < P; ++i) xs[i] = (ld)b.x[i];
+        Vs = interp_matrix(P, xl, P, xs);
+        // barycentric derivative matrix on the Gauss-Lobatto points
+        ld lam[8];
+        for (int j = 0; j < P; ++j) {
+            ld pr = 1;
+            for (int k = 0; k < P; ++k)
+                if (k != j) pr *= xl[j] - xl[k];
+            lam[j] = 1 / pr;
+        }
+        Dl.assign((size_t)P * P, 0.0L);
+        for (int i = 0; i < P; ++i) {
+            ld sum = 0;
+            for (int j = 0; j < P; ++j)
+                if (j != i) {
+                    Dl[(size_t)i * P + j] = lam[j] / (lam[i] * (xl[i] - xl[j]));
+                    sum += Dl[(size_t)i * P + j];
+                }
+            Dl[(size_t)i * P + i] = -sum;
+        }
+    }
+    // the element's coordinates (3 arrays) at the degree-N Gauss-Lobatto points
+    void geometry(const double *xg, std::vector<ld> X[3]) const
+    {
+        const int g1 = ng + 1;
+        for (int m = 0; m < 3; ++m) {
+            std::vector<ld> v((size_t)g1 * g1 * g1);
+            for (size_t q = 0; q < v.size(); ++q) v[q] = xg[3 * q + m];
+            int n[3] = {g1, g1, g1};
+            for (int d = 0; d < 3; ++d) {
+                v = tensor_apply(v, n, d, Vg.data(), P);
+                n[d] = P;
+            }
+            X[m].swap(v);
+        }
+    }
+    std::vector<ld> to_gauss(const std::vector<ld> &v) const
+    {
+        int n[3] = {P, P, P};
+        std::vector<ld> w = v;
+        for (int d = 0; d < 3; ++d) w = tensor_apply(w, n, d, Vs.data(), P);
+        return w;
+    }
+    std::vector<ld> deriv(const std::vector<ld> &v, int d) const
+    {
+        int n[3] = {P, P, P};
+        return tensor_apply(v, n, d, Dl.data(), P);
+    }
+    // the Gauss-Lobatto layer xi^d = -1 (s = 0) or +1 (s = 1) of v, interpolated
+    // to the face's Gauss points: out[p + P q], (p, q) the two remaining axes
+    // in increasing order
+    void face(const std::vector<ld> &v, int d, int s, ld *out) const
+    {
+        const int lay = s ? N : 0;
+        const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+        for (int q = 0; q < P; ++q)
+            for (int p = 0; p < P; ++p) {
+                ld acc = 0;
+                for (int b2 = 0; b2 < P; ++b2)
+                    for (int b1 = 0; b1 < P; ++b1) {
+                        int ii[3];
+                        ii[d] = lay;
+                        ii[d1] = b1;
+                        ii[d2] = b2;
+                        acc += Vs[(size_t)p * P + b1] * Vs[(size_t)q * P + b2] * v[ii[0] + P * (ii[1] + P * ii[2])];
+                    }
+                out[p + P * q] = acc;
+            }
+    }
+};
+
+// Orientation map of face points (see nskr.h): own point fp -> neighbour's.
+static int orient_host(int P, int fp, int o)
+{
+    int a = fp % P, b = fp / P;
+    if (o & 4) std::swap(a, b);
+    if (o & 1) a = P - 1 - a;
+    if (o & 2) b = P - 1 - b;
+    return a + P * b;
 }
 
 // ------------------------------------------------------------------ ABI
@@ -922,11 +1104,14 @@ static void free_mesh(nskr_ctx *c)
 {
     void *ptrs[] = {c->d_nbr, c->d_bcid, c->d_emet, c->d_fmet, c->d_egeo, c->d_bcs, c->d_Q, c->d_TH,
                     c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop, c->d_Ck,
-                    c->d_stab, c->d_clk};
+                    c->d_stab, c->d_clk, c->d_nmet, c->d_fnrm, c->d_xnode};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_nbr = c->d_bcid = nullptr;
     c->d_emet = c->d_fmet = c->d_egeo = nullptr;
+    c->d_nmet = c->d_fnrm = nullptr;
+    c->d_xnode = nullptr;
+    c->curved = false;
     c->d_bcs = nullptr;
     c->d_stab = nullptr;
     c->d_clk = nullptr;
@@ -967,19 +1152,29 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
 {
     if (!c) return NSKR_E_ARG;
     if (c->poisoned) return fail(c, NSKR_E_STATE, "context poisoned by an earlier HIP error");
-    if (!m || m->nelems <= 0 || !m->corners || !m->nbr || !m->nbr_face || !m->bc)
+    if (!m || m->nelems <= 0 || !m->xgeo || !m->nbr || !m->nbr_face || !m->bc)
         return fail(c, NSKR_E_ARG, "mesh arrays missing or nelems <= 0");
+    if (m->ngeo < 1 || m->ngeo > c->N) return fail(c, NSKR_E_ARG, "geometry degree ngeo must be in 1..N");
     if (m->nbcs < 0 || (m->nbcs > 0 && !m->bcs)) return fail(c, NSKR_E_ARG, "bad wall table");
     const int E = m->nelems;
-    // validate connectivity
+    if ((long long)E * 48 > 2147483647LL) return fail(c, NSKR_E_ARG, "too many elements for the connectivity codes");
+    const int P = c->P, n2 = P * P, n3 = n2 * P, ng = m->ngeo, g3 = (ng + 1) * (ng + 1) * (ng + 1);
+    auto orient = [&](int e, int f) { return m->nbr_orient ? m->nbr_orient[e * 6 + f] : 0; };
+    // connectivity: reciprocal neighbours, inverse orientations, wall indices
     for (int e = 0; e < E; ++e)
         for (int f = 0; f < 6; ++f) {
             const int nb = m->nbr[e * 6 + f], bc = m->bc[e * 6 + f];
             if (nb >= E || nb < -1) return fail(c, NSKR_E_ARG, "neighbour index out of range");
             if (nb >= 0) {
-                if (m->nbr_face[e * 6 + f] != (f ^ 1))
-                    return fail(c, NSKR_E_UNSUPPORTED, "only opposite-face connectivity with identical ordering");
-                if (m->nbr[nb * 6 + (f ^ 1)] != e) return fail(c, NSKR_E_ARG, "connectivity not reciprocal");
+                const int nf = m->nbr_face[e * 6 + f], o = orient(e, f);
+                if (nf < 0 || nf > 5 || o < 0 || o > 7) return fail(c, NSKR_E_ARG, "neighbour face or orientation out of range");
+                if (nb == e && nf == f) return fail(c, NSKR_E_ARG, "a face cannot be its own neighbour");
+                if (m->nbr[nb * 6 + nf] != e || m->nbr_face[nb * 6 + nf] != f)
+                    return fail(c, NSKR_E_ARG, "connectivity not reciprocal");
+                const int ob = orient(nb, nf);
+                for (int fp = 0; fp < n2; ++fp)
+                    if (orient_host(P, orient_host(P, fp, o), ob) != fp)
+                        return fail(c, NSKR_E_ARG, "the two orientations of a face are not inverse to each other");
                 if (bc != 0) return fail(c, NSKR_E_ARG, "interior face with a wall index");
             } else {
                 if (bc < 1 || bc > m->nbcs) return fail(c, NSKR_E_ARG, "wall face without a valid wall index");
@@ -991,74 +1186,240 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
                     return fail(c, NSKR_E_ARG, "wall velocity must be finite");
             }
         }
-    // per wall: extremes of twall + grad . x over its faces, and the rate
+    // pass 1: every element's geometry at the degree-N Gauss-Lobatto points;
+    // is it affine (a parallelepiped)? its corner and edge vectors, its size,
+    // and the coordinates of its face points
+    GeomOps ops(c->N, ng, c->bas);
+    ld xl[8];
+    lobatto_host(c->N, xl);
+    std::vector<double> egeo((size_t)E * 12), fpos((size_t)E * 6 * n2 * 3), escale(E);
+    bool curved = false;
+    for (int e = 0; e < E; ++e) {
+        const double *xe = m->xgeo + (size_t)e * g3 * 3;
+        for (int q = 0; q < 3 * g3; ++q)
+            if (!std::isfinite(xe[q])) return fail(c, NSKR_E_ARG, "non-finite geometry node");
+        std::vector<ld> X[3];
+        ops.geometry(xe, X);
+        auto at = [&](int mm, int i, int j, int k) { return X[mm][i + P * (j + P * k)]; };
+        ld x0[3], a[3][3];
+        double scale = 0;
+        for (int mm = 0; mm < 3; ++mm) {
+            x0[mm] = at(mm, 0, 0, 0);
+            a[0][mm] = at(mm, c->N, 0, 0) - x0[mm];
+            a[1][mm] = at(mm, 0, c->N, 0) - x0[mm];
+            a[2][mm] = at(mm, 0, 0, c->N) - x0[mm];
+        }
+        for (int d = 0; d < 3; ++d)
+            for (int mm = 0; mm < 3; ++mm) scale = fmax(scale, (double)fabsl(a[d][mm]));
+        if (!(scale > 0)) return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " is degenerate");
+        escale[e] = scale;
+        for (int k = 0; k < P && !curved; ++k)
+            for (int j = 0; j < P && !curved; ++j)
+                for (int i = 0; i < P && !curved; ++i)
+                    for (int mm = 0; mm < 3; ++mm) {
+                        const ld lin = x0[mm] + 0.5L * ((xl[i] + 1) * a[0][mm] + (xl[j] + 1) * a[1][mm] +
+                                                        (xl[k] + 1) * a[2][mm]);
+                        if (fabsl(lin - at(mm, i, j, k)) > 1e-12L * scale) curved = true;
+                    }
+        for (int mm = 0; mm < 3; ++mm) egeo[(size_t)e * 12 + mm] = (double)x0[mm];
+        for (int d = 0; d < 3; ++d)
+            for (int mm = 0; mm < 3; ++mm) egeo[(size_t)e * 12 + 3 + 3 * d + mm] = (double)a[d][mm];
+        for (int f = 0; f < 6; ++f) {
+            ld fv[64];
+            for (int mm = 0; mm < 3; ++mm) {
+                ops.face(X[mm], f >> 1, f & 1, fv);
+                for (int fp = 0; fp < n2; ++fp) fpos[(((size_t)e * 6 + f) * n2 + fp) * 3 + mm] = (double)fv[fp];
+            }
+        }
+    }
+    // the two sides of every interior face are the same surface: the
+    // neighbour's matching points (through the orientation) differ from the
+    // own ones by one translation (zero, or a period of the domain)
+    for (int e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int nb = m->nbr[e * 6 + f];
+            if (nb < 0) continue;
+            const int nf = m->nbr_face[e * 6 + f], o = orient(e, f);
+            const double tol = 1e-10 * fmax(escale[e], escale[nb]);
+            double t0[3];
+            for (int fp = 0; fp < n2; ++fp) {
+                const double *xo = &fpos[(((size_t)e * 6 + f) * n2 + fp) * 3];
+                const double *xn = &fpos[(((size_t)nb * 6 + nf) * n2 + orient_host(P, fp, o)) * 3];
+                for (int mm = 0; mm < 3; ++mm) {
+                    const double dv = xn[mm] - xo[mm];
+                    if (fp == 0) t0[mm] = dv;
+                    else if (fabs(dv - t0[mm]) > tol)
+                        return fail(c, NSKR_E_ARG, "face " + std::to_string(f) + " of element " + std::to_string(e) +
+                                                       " does not match its neighbour's face under the given orientation");
+                }
+            }
+        }
+    std::vector<double>().swap(fpos);
+    if (curved) {
+        for (int k = 0; k < m->nbcs; ++k) {
+            const double *tg = m->bcs[k].twall_grad;
+            if (m->bcs[k].kind != 2 && (tg[0] != 0.0 || tg[1] != 0.0 || tg[2] != 0.0 || m->bcs[k].twall_rate != 0.0))
+                return fail(c, NSKR_E_UNSUPPORTED, "walls whose temperature varies need affine elements");
+        }
+    }
+    // metric terms: per element on affine meshes; per node and face point
+    // (curl form) on curved ones.  Face vectors: outward unit normal and
+    // surface element.
+    std::vector<double> emet, fmet, nmet, fnrm, xnode;
+    const size_t NN = (size_t)E * n3;
+    if (!curved) {
+        emet.resize((size_t)E * 10);
+        fmet.resize((size_t)E * 24);
+        for (int e = 0; e < E; ++e) {
+            double a[3][3];
+            for (int d = 0; d < 3; ++d)
+                for (int k = 0; k < 3; ++k) a[d][k] = egeo[(size_t)e * 12 + 3 + 3 * d + k];
+            // dx/dxi^d = a_d / 2; Ja^1 = (a_2 x a_3)/4, Ja^2 = (a_3 x a_1)/4, Ja^3 = (a_1 x a_2)/4
+            for (int d = 0; d < 3; ++d) {
+                const double *u = a[(d + 1) % 3], *w = a[(d + 2) % 3];
+                emet[(size_t)e * 10 + 3 * d + 0] = 0.25 * (u[1] * w[2] - u[2] * w[1]);
+                emet[(size_t)e * 10 + 3 * d + 1] = 0.25 * (u[2] * w[0] - u[0] * w[2]);
+                emet[(size_t)e * 10 + 3 * d + 2] = 0.25 * (u[0] * w[1] - u[1] * w[0]);
+            }
+            const double J = 0.125 * (a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                                      a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                                      a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]));
+            if (!(J > 0)) return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " has J <= 0");
+            emet[(size_t)e * 10 + 9] = J;
+            for (int d = 0; d < 3; ++d) {
+                const double *Ja = &emet[(size_t)e * 10 + 3 * d];
+                const double nrm = sqrt(Ja[0] * Ja[0] + Ja[1] * Ja[1] + Ja[2] * Ja[2]);
+                for (int s = 0; s < 2; ++s) {
+                    double *fm = &fmet[((size_t)e * 6 + 2 * d + s) * 4];
+                    const double sg = s ? 1.0 : -1.0;
+                    for (int k = 0; k < 3; ++k) fm[k] = sg * Ja[k] / nrm;
+                    fm[3] = nrm;
+                }
+            }
+        }
+    } else {
+        nmet.resize(10 * NN);
+        fnrm.resize((size_t)E * 6 * n2 * 4);
+        xnode.resize(3 * NN);
+        for (int e = 0; e < E; ++e) {
+            std::vector<ld> X[3], dX[3][3], Ja[3][3];
+            ops.geometry(m->xgeo + (size_t)e * g3 * 3, X);
+            for (int mm = 0; mm < 3; ++mm)
+                for (int d = 0; d < 3; ++d) dX[mm][d] = ops.deriv(X[mm], d);
+            for (int n = 0; n < 3; ++n) {
+                const int mm = (n + 1) % 3, l = (n + 2) % 3;
+                // R_j = X_l d X_m / d xi^j, X_l relative to the element's first
+                // point (a constant shift leaves the curl unchanged)
+                std::vector<ld> Rv[3];
+                for (int j = 0; j < 3; ++j) {
+                    Rv[j].resize(n3);
+                    for (int q = 0; q < n3; ++q) Rv[j][q] = (X[l][q] - X[l][0]) * dX[mm][j][q];
+                }
+                for (int i = 0; i < 3; ++i) {
+                    const int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+                    std::vector<ld> c1 = ops.deriv(Rv[i2], i1), c2 = ops.deriv(Rv[i1], i2);
+                    Ja[i][n].resize(n3);
+                    for (int q = 0; q < n3; ++q) Ja[i][n][q] = -(c1[q] - c2[q]);
+                }
+            }
+            // volume: Ja and J at the Gauss nodes
+            std::vector<ld> JaG[3][3], dXG[3][3], XG[3];
+            for (int i = 0; i < 3; ++i)
+                for (int n = 0; n < 3; ++n) {
+                    JaG[i][n] = ops.to_gauss(Ja[i][n]);
+                    dXG[i][n] = ops.to_gauss(dX[i][n]);
+                }
+            for (int mm = 0; mm < 3; ++mm) XG[mm] = ops.to_gauss(X[mm]);
+            for (int q = 0; q < n3; ++q) {
+                const size_t gq = (size_t)e * n3 + q;
+                for (int i = 0; i < 3; ++i)
+                    for (int n = 0; n < 3; ++n) nmet[(size_t)(3 * i + n) * NN + gq] = (double)JaG[i][n][q];
+                const ld J = dXG[0][0][q] * (dXG[1][1][q] * dXG[2][2][q] - dXG[1][2][q] * dXG[2][1][q]) -
+                             dXG[0][1][q] * (dXG[1][0][q] * dXG[2][2][q] - dXG[1][2][q] * dXG[2][0][q]) +
+                             dXG[0][2][q] * (dXG[1][0][q] * dXG[2][1][q] - dXG[1][1][q] * dXG[2][0][q]);
+                if (!(J > 0)) return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " has J <= 0");
+                nmet[9 * NN + gq] = (double)J;
+                for (int mm = 0; mm < 3; ++mm) xnode[mm * NN + gq] = (double)XG[mm][q];
+            }
+            // faces: outward n dS = +-Ja^d on the layer xi^d = +-1
+            for (int f = 0; f < 6; ++f) {
+                const int d = f >> 1;
+                ld v[3][64];
+                for (int mm = 0; mm < 3; ++mm) ops.face(Ja[d][mm], d, f & 1, v[mm]);
+                for (int fp = 0; fp < n2; ++fp) {
+                    const ld sg = (f & 1) ? 1.0L : -1.0L;
+                    const ld nx = sg * v[0][fp], ny = sg * v[1][fp], nz = sg * v[2][fp];
+                    const ld dS = sqrtl(nx * nx + ny * ny + nz * nz);
+                    double *fo = &fnrm[(((size_t)e * 6 + f) * n2 + fp) * 4];
+                    fo[0] = (double)(nx / dS);
+                    fo[1] = (double)(ny / dS);
+                    fo[2] = (double)(nz / dS);
+                    fo[3] = (double)dS;
+                }
+            }
+        }
+    }
+    // the two sides of an interior face use exactly opposite normals and the
+    // same surface element (conservation): one side (the master: the face on
+    // the element's + side, else the lower element and face) keeps its own,
+    // the other takes the master's negated, after checking that they agree
+    auto master = [&](int e, int f, int nb, int nf) {
+        if ((f & 1) != (nf & 1)) return (f & 1) == 1;
+        return e < nb || (e == nb && f < nf);
+    };
+    for (int e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int nb = m->nbr[e * 6 + f];
+            if (nb < 0) continue;
+            const int nf = m->nbr_face[e * 6 + f], o = orient(e, f);
+            if (!master(e, f, nb, nf)) continue;
+            const int npts = curved ? n2 : 1;
+            for (int fp = 0; fp < npts; ++fp) {
+                double *mo = curved ? &fnrm[(((size_t)e * 6 + f) * n2 + fp) * 4] : &fmet[((size_t)e * 6 + f) * 4];
+                double *sl = curved ? &fnrm[(((size_t)nb * 6 + nf) * n2 + orient_host(P, fp, o)) * 4]
+                                    : &fmet[((size_t)nb * 6 + nf) * 4];
+                double dn = 0;
+                for (int k = 0; k < 3; ++k) dn = fmax(dn, fabs(sl[k] + mo[k]));
+                if (dn > 1e-8 || fabs(sl[3] - mo[3]) > 1e-8 * mo[3])
+                    return fail(c, NSKR_E_ARG, "face " + std::to_string(f) + " of element " + std::to_string(e) +
+                                                   ": the neighbour's normal or surface element does not match");
+                for (int k = 0; k < 3; ++k) sl[k] = -mo[k];
+                sl[3] = mo[3];
+            }
+        }
+    // per wall: extremes of twall + grad . x over its faces, and the rate; a
+    // moving wall moves within its own plane at every face point
     std::vector<std::array<double, 3>> trange(m->nbcs > 0 ? m->nbcs : 1,
                                               std::array<double, 3>{INFINITY, -INFINITY, 0.0});
-    // per-element affine metrics
-    std::vector<double> emet((size_t)E * 10), fmet((size_t)E * 24), egeo((size_t)E * 12);
-    for (int e = 0; e < E; ++e) {
-        const double *cr = m->corners + (size_t)e * 24;
-        double a[3][3];  // edge vectors a_d = x(v_d) - x(0), v_d = 1, 2, 4
-        const int vd[3] = {1, 2, 4};
-        for (int d = 0; d < 3; ++d)
-            for (int k = 0; k < 3; ++k) a[d][k] = cr[3 * vd[d] + k] - cr[k];
-        double scale = 0;
-        for (int d = 0; d < 3; ++d)
-            for (int k = 0; k < 3; ++k) scale = fmax(scale, fabs(a[d][k]));
-        for (int v = 0; v < 8; ++v) {
-            const int ii = v & 1, jj = (v >> 1) & 1, kk = (v >> 2) & 1;
-            for (int k = 0; k < 3; ++k) {
-                double x = cr[k] + ii * a[0][k] + jj * a[1][k] + kk * a[2][k];
-                if (fabs(x - cr[3 * v + k]) > 1e-12 * scale)
-                    return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " is not a parallelepiped");
-            }
-        }
-        // dx/dxi^d = a_d / 2; Ja^1 = (a_2 x a_3)/4, Ja^2 = (a_3 x a_1)/4, Ja^3 = (a_1 x a_2)/4
-        for (int d = 0; d < 3; ++d) {
-            const double *u = a[(d + 1) % 3], *w = a[(d + 2) % 3];
-            emet[(size_t)e * 10 + 3 * d + 0] = 0.25 * (u[1] * w[2] - u[2] * w[1]);
-            emet[(size_t)e * 10 + 3 * d + 1] = 0.25 * (u[2] * w[0] - u[0] * w[2]);
-            emet[(size_t)e * 10 + 3 * d + 2] = 0.25 * (u[0] * w[1] - u[1] * w[0]);
-        }
-        const double J = 0.125 * (a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
-                                  a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
-                                  a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]));
-        if (!(J > 0)) return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " has J <= 0");
-        emet[(size_t)e * 10 + 9] = J;
-        for (int d = 0; d < 3; ++d) {
-            const double *Ja = &emet[(size_t)e * 10 + 3 * d];
-            const double nrm = sqrt(Ja[0] * Ja[0] + Ja[1] * Ja[1] + Ja[2] * Ja[2]);
-            for (int s = 0; s < 2; ++s) {
-                double *fm = &fmet[((size_t)e * 6 + 2 * d + s) * 4];
-                const double sg = s ? 1.0 : -1.0;
-                for (int k = 0; k < 3; ++k) fm[k] = sg * Ja[k] / nrm;
-                fm[3] = nrm;
-            }
-        }
-        for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + k] = cr[k];
-        for (int d = 0; d < 3; ++d)
-            for (int k = 0; k < 3; ++k) egeo[(size_t)e * 12 + 3 + 3 * d + k] = a[d][k];
-        // a moving wall moves within its own plane; a varying wall
-        // temperature stays in the table's subcritical range on the face
-        // (it is linear, so its extremes are at the face's corners)
+    for (int e = 0; e < E; ++e)
         for (int f = 0; f < 6; ++f) {
             const int bc = m->bc[e * 6 + f];
             if (m->nbr[e * 6 + f] >= 0 || m->bcs[bc - 1].kind == 2) continue;
-            const double *uw = m->bcs[bc - 1].uwall, *fm = &fmet[((size_t)e * 6 + f) * 4];
-            const double un = uw[0] * fm[0] + uw[1] * fm[1] + uw[2] * fm[2];
-            if (fabs(un) > 1e-12 * (fabs(uw[0]) + fabs(uw[1]) + fabs(uw[2])))
-                return fail(c, NSKR_E_ARG, "wall velocity must be tangential to the wall");
+            const double *uw = m->bcs[bc - 1].uwall;
+            const int npts = curved ? n2 : 1;
+            for (int fp = 0; fp < npts; ++fp) {
+                const double *fm = curved ? &fnrm[(((size_t)e * 6 + f) * n2 + fp) * 4] : &fmet[((size_t)e * 6 + f) * 4];
+                const double un = uw[0] * fm[0] + uw[1] * fm[1] + uw[2] * fm[2];
+                if (fabs(un) > 1e-12 * (fabs(uw[0]) + fabs(uw[1]) + fabs(uw[2])))
+                    return fail(c, NSKR_E_ARG, "wall velocity must be tangential to the wall");
+            }
             const double *tg = m->bcs[bc - 1].twall_grad;
             const double rate = m->bcs[bc - 1].twall_rate;
             if (!(std::isfinite(tg[0]) && std::isfinite(tg[1]) && std::isfinite(tg[2]) && std::isfinite(rate)))
                 return fail(c, NSKR_E_ARG, "wall temperature gradient and rate must be finite");
             if (tg[0] == 0.0 && tg[1] == 0.0 && tg[2] == 0.0 && rate == 0.0) continue;
+            // affine here: the temperature is linear on the face, so its
+            // extremes are at the face's corners
             const int d = f >> 1, sd = f & 1;
             auto &tr = trange[bc - 1];
             for (int v = 0; v < 8; ++v) {
                 if (((v >> d) & 1) != sd) continue;
                 double T = m->bcs[bc - 1].twall;
-                for (int k = 0; k < 3; ++k) T += tg[k] * cr[3 * v + k];
+                for (int k = 0; k < 3; ++k) {
+                    double x = egeo[(size_t)e * 12 + k];
+                    for (int dd = 0; dd < 3; ++dd) x += ((v >> dd) & 1) * egeo[(size_t)e * 12 + 3 + 3 * dd + k];
+                    T += tg[k] * x;
+                }
                 if (!(T >= 0.3 && T <= 0.99))
                     return fail(c, NSKR_E_ARG, "wall temperature must stay in [0.3, 0.99] along the wall");
                 tr[0] = T < tr[0] ? T : tr[0];
@@ -1066,7 +1427,13 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
                 tr[2] = rate;
             }
         }
-    }
+    // connectivity codes: (6 nb + nf) 8 + orientation, -1 on walls
+    std::vector<int> code((size_t)E * 6);
+    for (int e = 0; e < E; ++e)
+        for (int f = 0; f < 6; ++f) {
+            const int nb = m->nbr[e * 6 + f];
+            code[(size_t)e * 6 + f] = nb < 0 ? -1 : ((nb * 6 + m->nbr_face[e * 6 + f]) << 3) | orient(e, f);
+        }
     // wall constants
     std::vector<BcDev> bcs(m->nbcs > 0 ? m->nbcs : 1);
     int dyn = 0, var = 0, trate = 0;
@@ -1118,17 +1485,23 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
     c->var = var;
     c->trate = trate;
     c->wall_trange.swap(trange);
-    const int n3 = c->P * c->P * c->P, n2 = c->P * c->P;
+    // (n3, n2: nodes and face points per element, as above)
     c->NN = (size_t)E * n3;
     c->NF = (size_t)E * 6 * n2;
     const size_t ts = c->p.precision == 0 ? sizeof(double) : sizeof(float);
     const int nblk = (E + elem_per_block(c->N) - 1) / elem_per_block(c->N);
+    c->curved = curved;
+    if (curved) c->bs = 256;  // the only workgroup size built for curved elements
     int rc = NSKR_OK;
+    const size_t n_emet = curved ? 0 : emet.size(), n_fmet = curved ? 0 : fmet.size();
     if ((rc = dalloc(c, (void **)&c->d_nbr, sizeof(int) * E * 6)) ||
         (rc = dalloc(c, (void **)&c->d_bcid, sizeof(int) * E * 6)) ||
-        (rc = dalloc(c, (void **)&c->d_emet, sizeof(double) * emet.size())) ||
-        (rc = dalloc(c, (void **)&c->d_fmet, sizeof(double) * fmet.size())) ||
+        (!curved && (rc = dalloc(c, (void **)&c->d_emet, sizeof(double) * n_emet))) ||
+        (!curved && (rc = dalloc(c, (void **)&c->d_fmet, sizeof(double) * n_fmet))) ||
         (rc = dalloc(c, (void **)&c->d_egeo, sizeof(double) * egeo.size())) ||
+        (curved && (rc = dalloc(c, &c->d_nmet, ts * nmet.size()))) ||
+        (curved && (rc = dalloc(c, &c->d_fnrm, ts * fnrm.size()))) ||
+        (curved && (rc = dalloc(c, (void **)&c->d_xnode, sizeof(double) * xnode.size()))) ||
         (rc = dalloc(c, (void **)&c->d_bcs, sizeof(BcDev) * bcs.size())) ||
         (rc = dalloc(c, &c->d_Q, ts * 15 * c->NN)) || (rc = dalloc(c, &c->d_TH, ts * c->NN)) ||
         (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * kT2 * c->NF)) ||
@@ -1141,15 +1514,27 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         free_mesh(c);
         return rc;
     }
-    HIPCHK(c, hipMemcpyAsync(c->d_nbr, m->nbr, sizeof(int) * E * 6, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->d_bcid, m->bc, sizeof(int) * E * 6, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->d_emet, emet.data(), sizeof(double) * emet.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->d_fmet, fmet.data(), sizeof(double) * fmet.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->d_egeo, egeo.data(), sizeof(double) * egeo.size(), hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->d_bcs, bcs.data(), sizeof(BcDev) * bcs.size(), hipMemcpyHostToDevice, s));
-    if (tab) HIPCHK(c, hipMemcpyAsync(c->d_stab, tab->data(), sizeof(double) * tab->size(), hipMemcpyHostToDevice, s));
+    // curved metrics in the element type of the precision
+    auto upload_real = [&](void *dst, const std::vector<double> &v) -> hipError_t {
+        if (c->p.precision == 0) return hipMemcpy(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice);
+        std::vector<float> f(v.size());
+        for (size_t q = 0; q < v.size(); ++q) f[q] = (float)v[q];
+        return hipMemcpy(dst, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice);
+    };
     HIPCHK(c, hipStreamSynchronize(s));
-    c->h_emet.swap(emet);
+    HIPCHK(c, hipMemcpy(c->d_nbr, code.data(), sizeof(int) * E * 6, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_bcid, m->bc, sizeof(int) * E * 6, hipMemcpyHostToDevice));
+    if (!curved) {
+        HIPCHK(c, hipMemcpy(c->d_emet, emet.data(), sizeof(double) * emet.size(), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->d_fmet, fmet.data(), sizeof(double) * fmet.size(), hipMemcpyHostToDevice));
+    } else {
+        HIPCHK(c, upload_real(c->d_nmet, nmet));
+        HIPCHK(c, upload_real(c->d_fnrm, fnrm));
+        HIPCHK(c, hipMemcpy(c->d_xnode, xnode.data(), sizeof(double) * xnode.size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(c, hipMemcpy(c->d_egeo, egeo.data(), sizeof(double) * egeo.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_bcs, bcs.data(), sizeof(BcDev) * bcs.size(), hipMemcpyHostToDevice));
+    if (tab) HIPCHK(c, hipMemcpy(c->d_stab, tab->data(), sizeof(double) * tab->size(), hipMemcpyHostToDevice));
     return NSKR_OK;
 }
 
@@ -1216,7 +1601,7 @@ int nskr_init_droplets(nskr_ctx *c, const nskr_init *ic, const double *noise, vo
         HIPCHK(c, hipMemcpyAsync(c->d_noise, noise, sizeof(double) * c->NN, hipMemcpyHostToDevice, s));
     }
     InitArgs ia;
-    ia.mesh = Impl<4, double, 256>::mesh(c);
+    ia.mesh = Impl<4, double, 256, false>::mesh(c);
     ia.bas = c->bas;
     ia.NN = c->NN;
     ia.drop = c->d_drop;
@@ -1363,6 +1748,7 @@ int nskr_set_block(nskr_ctx *c, int threads)
 {
     if (!c) return NSKR_E_ARG;
     if (!block_ok(c->N, threads)) return fail(c, NSKR_E_ARG, "block size must be 256 or 512 and hold an element");
+    if (c->curved && threads != 256) return fail(c, NSKR_E_UNSUPPORTED, "meshes with curved elements run 256 threads");
     DeviceGuard guard(c->device);
     int maxlds = 0;
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
@@ -1432,6 +1818,7 @@ struct BatchSlot {
 
 struct BatchGroup {
     int N = 0, prec = 0, bs = 0, nblocks = 0;
+    bool curved = false;
     void *d_tab = nullptr;
     int *d_bi = nullptr, *d_be = nullptr;
     Basis bas;
@@ -1480,7 +1867,7 @@ static void batch_free_groups(nskr_batch *b)
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
 }
 
-template <int P, typename T, int BS>
+template <int P, typename T, int BS, bool CV>
 static int build_group(nskr_batch *b, BatchGroup &g, const std::vector<int> &members)
 {
     using G = Tile<P, BS>;
@@ -1488,7 +1875,7 @@ static int build_group(nskr_batch *b, BatchGroup &g, const std::vector<int> &mem
     std::vector<int> bi, be;
     for (size_t k = 0; k < members.size(); ++k) {
         BatchSlot &sl = b->slots[members[k]];
-        tab.push_back(Impl<P, T, BS>::inst(sl.c, sl.U, sl.R, nullptr, sl.dt));
+        tab.push_back(Impl<P, T, BS, CV>::inst(sl.c, sl.U, sl.R, nullptr, sl.dt));
         tab.back().clk = sl.c->trate ? sl.c->d_clk : nullptr;
         tab.back().t0 = sl.t0;
         const int nb = (sl.c->E + G::EPB - 1) / G::EPB;
@@ -1508,7 +1895,7 @@ static int build_group(nskr_batch *b, BatchGroup &g, const std::vector<int> &mem
     return NSKR_OK;
 }
 
-template <int P, typename T, int BS> static void launch_group(const BatchGroup &g, hipStream_t s)
+template <int P, typename T, int BS, bool CV> static void launch_group(const BatchGroup &g, hipStream_t s)
 {
     Launch<T> L;
     memset(&L, 0, sizeof(L));
@@ -1516,23 +1903,12 @@ template <int P, typename T, int BS> static void launch_group(const BatchGroup &
     L.blk_inst = g.d_bi;
     L.blk_e0 = g.d_be;
     L.bas = g.bas;
-    Impl<P, T, BS>::step_batched(L, g.nblocks, s);
+    Impl<P, T, BS, CV>::step_batched(L, g.nblocks, s);
 }
 
-template <typename F> static int group_dispatch(int N, int prec, int bs, F &&f)
+template <typename F> static int group_dispatch(const BatchGroup &g, F &&f)
 {
-#define NSKR_GCASE(NN, PP)                                                                         \
-    case NN:                                                                                       \
-        if (prec == 0) return bs == 512 ? f(Impl<PP, double, 512>()) : f(Impl<PP, double, 256>()); \
-        return bs == 512 ? f(Impl<PP, float, 512>()) : f(Impl<PP, float, 256>());
-    switch (N) {
-        NSKR_GCASE(2, 3)
-        NSKR_GCASE(3, 4)
-        NSKR_GCASE(4, 5)
-        NSKR_GCASE(5, 6)
-    }
-#undef NSKR_GCASE
-    return NSKR_E_ARG;
+    return impl_dispatch(g.N, g.prec, g.bs, g.curved, f);
 }
 
 static int batch_rebuild(nskr_batch *b)
@@ -1546,12 +1922,15 @@ static int batch_rebuild(nskr_batch *b)
         if (sl.state != 1) continue;
         int gi = -1;
         for (int k = 0; k < (int)groups.size(); ++k)
-            if (groups[k].N == sl.c->N && groups[k].prec == sl.c->p.precision && groups[k].bs == sl.c->bs) gi = k;
+            if (groups[k].N == sl.c->N && groups[k].prec == sl.c->p.precision && groups[k].bs == sl.c->bs &&
+                groups[k].curved == sl.c->curved)
+                gi = k;
         if (gi < 0) {
             BatchGroup g;
             g.N = sl.c->N;
             g.prec = sl.c->p.precision;
             g.bs = sl.c->bs;
+            g.curved = sl.c->curved;
             groups.push_back(g);
             members.emplace_back();
             gi = (int)groups.size() - 1;
@@ -1560,9 +1939,9 @@ static int batch_rebuild(nskr_batch *b)
     }
     for (size_t k = 0; k < groups.size(); ++k) {
         BatchGroup &g = groups[k];
-        int rc = group_dispatch(g.N, g.prec, g.bs, [&](auto impl) {
+        int rc = group_dispatch(g, [&](auto impl) {
             using I = decltype(impl);
-            return build_group<I::kP, typename I::Real, I::kBS>(b, g, members[k]);
+            return build_group<I::kP, typename I::Real, I::kBS, I::kCV>(b, g, members[k]);
         });
         b->groups.push_back(g);
         if (rc) return rc;
@@ -1643,7 +2022,7 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     sl.t0 = c->time;
     if (c->d_Ck) {
         DeviceGuard guard(b->device);
-        Impl<3, float, 256>::zero_comp(c, nullptr);
+        Impl<3, float, 256, false>::zero_comp(c, nullptr);
         BHIPCHK(b, hipDeviceSynchronize());
     }
     b->used += need;
@@ -1689,9 +2068,9 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
         if (!b->exec) {
             BHIPCHK(b, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             for (const auto &g : b->groups)
-                group_dispatch(g.N, g.prec, g.bs, [&](auto impl) {
+                group_dispatch(g, [&](auto impl) {
                     using I = decltype(impl);
-                    launch_group<I::kP, typename I::Real, I::kBS>(g, s);
+                    launch_group<I::kP, typename I::Real, I::kBS, I::kCV>(g, s);
                     return 0;
                 });
             if (b->nticks)
@@ -1702,9 +2081,9 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
         BHIPCHK(b, hipGraphLaunch(b->exec, s));
     } else {
         for (const auto &g : b->groups)
-            group_dispatch(g.N, g.prec, g.bs, [&](auto impl) {
+            group_dispatch(g, [&](auto impl) {
                 using I = decltype(impl);
-                launch_group<I::kP, typename I::Real, I::kBS>(g, s);
+                launch_group<I::kP, typename I::Real, I::kBS, I::kCV>(g, s);
                 return 0;
             });
         if (b->nticks)

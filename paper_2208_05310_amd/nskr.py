@@ -52,9 +52,10 @@ class Bc(ctypes.Structure):
 
 
 class Mesh(ctypes.Structure):
-    _fields_ = [("nelems", ctypes.c_int), ("corners", ctypes.POINTER(ctypes.c_double)),
+    _fields_ = [("nelems", ctypes.c_int), ("ngeo", ctypes.c_int), ("xgeo", ctypes.POINTER(ctypes.c_double)),
                 ("nbr", ctypes.POINTER(ctypes.c_int)), ("nbr_face", ctypes.POINTER(ctypes.c_int)),
-                ("bc", ctypes.POINTER(ctypes.c_int)), ("nbcs", ctypes.c_int), ("bcs", ctypes.POINTER(Bc))]
+                ("nbr_orient", ctypes.POINTER(ctypes.c_int)), ("bc", ctypes.POINTER(ctypes.c_int)),
+                ("nbcs", ctypes.c_int), ("bcs", ctypes.POINTER(Bc))]
 
 
 class Init(ctypes.Structure):
@@ -66,7 +67,7 @@ class Init(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 8  # the struct layouts and semantics below
+ABI_VERSION = 9  # the struct layouts and semantics below
 
 
 def lib():
@@ -225,25 +226,41 @@ class Solver:
 
     def upload_box(self, n, length=(1.0, 1.0, 1.0), periodic=(1, 1, 1), side_kind=(0,) * 6,
                    side_twall=(0.0,) * 6, side_theta=(90.0,) * 6, stream=None, side_uwall=None, side_gamma=None,
-                   side_tgrad=None, side_trate=None):
+                   side_tgrad=None, side_trate=None, curve_amp=0.0, ngeo=1):
+        """Structured box of parallelepipeds; with curve_amp != 0 (or ngeo >
+        1) each element's geometry is given on the Gauss-Lobatto points of
+        degree ngeo under the curved box map of workloads.box_map."""
         corners, nbr, nbf, bc, bcs = box_mesh(n, length, periodic, side_kind, side_twall, side_theta,
                                               side_uwall=side_uwall, side_gamma=side_gamma, side_tgrad=side_tgrad,
                                               side_trate=side_trate)
-        self.upload_mesh(corners, nbr, nbf, bc, bcs, stream)
+        if curve_amp != 0.0 or ngeo > 1:
+            from . import workloads as wl
+            xgeo = wl.box_geometry(n, length, ngeo, curve_amp)
+            self.upload_mesh(xgeo, nbr, nbf, bc, bcs, stream, ngeo=ngeo)
+        else:
+            self.upload_mesh(corners, nbr, nbf, bc, bcs, stream)
         self.box = dict(n=tuple(n), length=tuple(length), periodic=tuple(periodic))
 
-    def upload_mesh(self, corners, nbr, nbf, bc, bcs, stream=None):
-        corners = np.ascontiguousarray(corners, dtype=np.float64)
+    def upload_mesh(self, xgeo, nbr, nbf, bc, bcs, stream=None, ngeo=1, nbo=None):
+        """xgeo: [nelems][(ngeo+1)^3][3] geometry nodes on the Gauss-Lobatto
+        points of degree ngeo (ngeo = 1: the 8 corners); nbr, nbf, nbo:
+        [nelems][6] neighbour element (-1 on walls), its face, the face
+        orientation (None: all 0); bc: [nelems][6] wall index (1-based) or 0."""
+        xgeo = np.ascontiguousarray(xgeo, dtype=np.float64)
         nbr = np.ascontiguousarray(nbr, dtype=np.int32)
         nbf = np.ascontiguousarray(nbf, dtype=np.int32)
+        nbo = None if nbo is None else np.ascontiguousarray(nbo, dtype=np.int32)
         bc = np.ascontiguousarray(bc, dtype=np.int32)
+        if xgeo.size != nbr.shape[0] * (ngeo + 1) ** 3 * 3:
+            raise ValueError("xgeo must hold (ngeo+1)^3 nodes of 3 coordinates per element")
         bc_arr = (Bc * max(1, len(bcs)))(*[Bc(b["kind"], b["twall"], b["theta"], (ctypes.c_double * 3)(*b["uwall"]),
                                                  *b["gamma"], (ctypes.c_double * 3)(*b.get("tgrad", (0, 0, 0))),
                                                  b.get("trate", 0.0))
                                               for b in bcs])
-        m = Mesh(int(nbr.shape[0]), corners.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                 nbr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), nbf.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                 bc.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(bcs), bc_arr)
+        ip = ctypes.POINTER(ctypes.c_int)
+        m = Mesh(int(nbr.shape[0]), int(ngeo), xgeo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                 nbr.ctypes.data_as(ip), nbf.ctypes.data_as(ip), None if nbo is None else nbo.ctypes.data_as(ip),
+                 bc.ctypes.data_as(ip), len(bcs), bc_arr)
         self._check(self.L.nskr_mesh_upload(self._h, ctypes.byref(m), _stream_ptr(stream)))
         n = ctypes.c_size_t()
         self._check(self.L.nskr_state_size(self._h, ctypes.byref(n)))
@@ -429,8 +446,10 @@ _profile_methods()
 def solver_for(w, precision="fp64", device=0, kahan=True):
     """Solver with the mesh of a workload description (paper_2208_05310_amd.workloads)."""
     s = Solver(w.params, w.N, precision, device, kahan)
+    ngeo = (w.ngeo or w.N) if w.curve_amp != 0.0 else max(w.ngeo, 1)
     s.upload_box(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta,
-                 side_uwall=w.side_uwall, side_gamma=w.side_gamma, side_tgrad=w.side_tgrad, side_trate=w.side_trate)
+                 side_uwall=w.side_uwall, side_gamma=w.side_gamma, side_tgrad=w.side_tgrad, side_trate=w.side_trate,
+                 curve_amp=w.curve_amp, ngeo=ngeo)
     return s
 
 

@@ -55,6 +55,7 @@ class Workload:
     side_tgrad: tuple | None = None   # per side wall temperature gradient: T_wall(x) = twall + tgrad . x
     side_trate: tuple | None = None   # per side wall temperature rate: + trate * t
     cylinder_axis: int = -1           # droplets are cylinders along this axis (-1: spheres)
+    ngeo: int = 0                     # geometry degree of curved elements (0: N when curve_amp != 0)
 
     @property
     def nelems(self) -> int:
@@ -74,6 +75,43 @@ class Workload:
 
     def with_(self, **kw) -> "Workload":
         return replace(self, **kw)
+
+
+def lobatto_points(n: int) -> np.ndarray:
+    """Gauss-Lobatto points of degree n on [-1, 1]: the ends and the roots of
+    the derivative of the Legendre polynomial P_n."""
+    from numpy.polynomial import legendre as npleg
+    inner = npleg.legroots(npleg.legder(np.eye(n + 1)[n])) if n > 1 else np.array([])
+    return np.concatenate([[-1.0], np.sort(inner), [1.0]])
+
+
+def box_map(X, length, lo=(0.0, 0.0, 0.0), curve_amp=0.0):
+    """The mesh map of a box: the identity, perturbed by curve_amp * prod_d
+    sin(2 pi (X_d - lo_d) / L_d) added to every component (a smooth curved
+    mesh with the box's periodicity, flat on the box's sides)."""
+    X = np.asarray(X, dtype=np.float64)
+    if curve_amp == 0.0:
+        return X.copy()
+    s = np.prod([np.sin(2 * np.pi * (X[d] - lo[d]) / length[d]) for d in range(3)], axis=0)
+    return X + curve_amp * s[None]
+
+
+def box_geometry(n, length=(1.0, 1.0, 1.0), ngeo=1, curve_amp=0.0, lo=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Geometry nodes of the n[0] x n[1] x n[2] elements of a box (element
+    ex + nx (ey + ny ez)) on the Gauss-Lobatto points of degree ngeo:
+    [nelems][(ngeo+1)^3][3], node a + (ngeo+1)(b + (ngeo+1) c), the box map
+    (see box_map) at the points lo + h (e + (xi + 1)/2)."""
+    nx, ny, nz = (int(v) for v in n)
+    h = [length[d] / n[d] for d in range(3)]
+    xl = lobatto_points(ngeo)
+    g = ngeo + 1
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ee = [ex.reshape(-1), ey.reshape(-1), ez.reshape(-1)]
+    c, b, a = np.meshgrid(np.arange(g), np.arange(g), np.arange(g), indexing="ij")
+    ii = [a.reshape(-1), b.reshape(-1), c.reshape(-1)]
+    X = np.stack([lo[d] + h[d] * (ee[d][:, None] + 0.5 * (xl[ii[d]][None, :] + 1.0)) for d in range(3)])
+    x = box_map(X.reshape(3, -1), length, lo, curve_amp).reshape(3, nx * ny * nz, g ** 3)
+    return np.ascontiguousarray(np.transpose(x, (1, 2, 0)))
 
 
 def _periodic_dist(a, b, length, periodic):

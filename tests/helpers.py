@@ -17,7 +17,8 @@ def box_for(w: wl.Workload) -> oracle.Box:
                            side_uwall=w.side_uwall or ((0.0, 0.0, 0.0),) * 6,
                            side_g1=[v[0] for v in g], side_g2=[v[1] for v in g],
                            side_g3=[v[2] for v in g], side_g4=[v[3] for v in g],
-                           side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6, side_trate=w.side_trate or (0.0,) * 6)
+                           side_tgrad=w.side_tgrad or ((0.0, 0.0, 0.0),) * 6, side_trate=w.side_trate or (0.0,) * 6,
+                           ngeo=w.ngeo)
 
 
 def oracle_init(o: oracle.Oracle, w: wl.Workload) -> np.ndarray:
@@ -34,3 +35,106 @@ def timed_wall_case():
         side_gamma=(wl.NO_GAMMA,) * 5 + ((0.0, 0.05, 0.02, 0.0),),
         side_tgrad=((0.0, 0.0, 0.0),) * 4 + ((0.05, 0.0, 0.0), (0.0, 0.0, 0.0)),
         side_trate=(0.0,) * 4 + (0.3, -0.2))
+
+
+# ------------------------------------------------------------------ relabelled meshes
+def cube_rotations():
+    """The 24 proper rotations of the reference cube as signed permutation
+    matrices S (old reference coordinates = S new ones)."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            S = np.zeros((3, 3), dtype=int)
+            for d in range(3):
+                S[d, perm[d]] = signs[d]
+            if round(np.linalg.det(S)) == 1:
+                out.append(S)
+    return out
+
+
+def _old_index(S, new, P):
+    old = [0, 0, 0]
+    for d in range(3):
+        k = int(np.nonzero(S[d])[0][0])
+        old[d] = new[k] if S[d, k] > 0 else P - 1 - new[k]
+    return old
+
+
+def _orient(P, fp, o):
+    a, b = fp % P, fp // P
+    if o & 4:
+        a, b = b, a
+    if o & 1:
+        a = P - 1 - a
+    if o & 2:
+        b = P - 1 - b
+    return a + P * b
+
+
+def rotated_box_mesh(w, seed=11):
+    """The workload's structured box with every element's reference frame
+    rotated by a random proper rotation of the cube: its geometry nodes in
+    the new node order, the connectivity with the faces and orientations this
+    produces, and perm (new global node -> old global node) to carry states
+    between the two labellings."""
+    from paper_2208_05310_amd import nskr
+    corners, nbr, nbf, bc, bcs = nskr.box_mesh(w.n, w.length, w.periodic, w.side_kind, w.side_twall, w.side_theta,
+                                               side_uwall=w.side_uwall, side_gamma=w.side_gamma,
+                                               side_tgrad=w.side_tgrad, side_trate=w.side_trate)
+    curved = w.curve_amp != 0.0
+    ngeo = (w.ngeo or w.N) if curved else 1
+    xg = wl.box_geometry(w.n, w.length, ngeo, w.curve_amp) if curved else corners
+    E, P, g = w.nelems, w.N + 1, ngeo + 1
+    rots = cube_rotations()
+    rng = np.random.default_rng(seed)
+    S_e = [rots[int(k)] for k in rng.integers(0, len(rots), E)]
+
+    def face_map(S, fnew):
+        k, s = fnew // 2, fnew % 2
+        d = int(np.nonzero(S[:, k])[0][0])
+        return 2 * d + (s if S[d, k] > 0 else 1 - s)
+
+    def point_to_old(S, fnew, fp):
+        k = fnew // 2
+        rest = [a for a in range(3) if a != k]
+        new = [0, 0, 0]
+        new[rest[0]], new[rest[1]] = fp % P, fp // P
+        old = _old_index(S, new, P)
+        dold = face_map(S, fnew) // 2
+        orest = [a for a in range(3) if a != dold]
+        return old[orest[0]] + P * old[orest[1]]
+
+    xgn = np.empty_like(xg)
+    perm = np.empty(E * P ** 3, dtype=np.int64)
+    for e in range(E):
+        S = S_e[e]
+        for c in range(g):
+            for b in range(g):
+                for a in range(g):
+                    o = _old_index(S, [a, b, c], g)
+                    xgn[e, a + g * (b + g * c)] = xg[e, o[0] + g * (o[1] + g * o[2])]
+        for k in range(P):
+            for j in range(P):
+                for i in range(P):
+                    o = _old_index(S, [i, j, k], P)
+                    perm[e * P ** 3 + i + P * (j + P * k)] = e * P ** 3 + o[0] + P * (o[1] + P * o[2])
+    nbr_n = np.full((E, 6), -1, dtype=np.int32)
+    nbf_n = np.zeros((E, 6), dtype=np.int32)
+    nbo_n = np.zeros((E, 6), dtype=np.int32)
+    bc_n = np.zeros((E, 6), dtype=np.int32)
+    for e in range(E):
+        for f in range(6):
+            fo = face_map(S_e[e], f)
+            bc_n[e, f] = bc[e, fo]
+            nb = int(nbr[e, fo])
+            if nb < 0:
+                continue
+            nfo = int(nbf[e, fo])
+            nf = next(x for x in range(6) if face_map(S_e[nb], x) == nfo)
+            # own new point -> own old point = neighbour old point -> neighbour new point
+            inv = {point_to_old(S_e[nb], nf, q): q for q in range(P * P)}
+            target = [inv[point_to_old(S_e[e], f, fp)] for fp in range(P * P)]
+            o = next(x for x in range(8) if all(_orient(P, fp, x) == target[fp] for fp in range(P * P)))
+            nbr_n[e, f], nbf_n[e, f], nbo_n[e, f] = nb, nf, o
+    return dict(xgeo=xgn, ngeo=ngeo, nbr=nbr_n, nbf=nbf_n, nbo=nbo_n, bc=bc_n, bcs=bcs, perm=perm)

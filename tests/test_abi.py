@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(L, name), name
     from paper_2208_05310_amd.nskr import ABI_VERSION
-    assert L.nskr_version() == ABI_VERSION == 8
+    assert L.nskr_version() == ABI_VERSION == 9
 
 
 def test_create_validates_arguments_before_device():
