@@ -260,11 +260,17 @@ int nskr_rhs(nskr_ctx *ctx, const void *U, void *Ut, nskr_stream s);
 int nskr_lift1(nskr_ctx *ctx, const void *U, void *q, nskr_stream s);
 int nskr_lift2(nskr_ctx *ctx, const void *U, void *out, nskr_stream s);
 
-/* Stable time step (FP64): min of the advective limit CFL T_N 2 / max_nodes
- * sum_d (|u . Ja^d| + c~ |Ja^d|)/J and the parabolic/source limit
- * CFL 4.6567 / (alpha beta + RHO_N nu_max max_nodes sum_d (|Ja^d|/(2J))^2),
- * nu_max = max(4 mu/(3 rho), kappa/(rho R cv), gam beta), c~ = sqrt(|c_s^2|),
- * T_N and RHO_N the 1D stability constants of the RK scheme.  Synchronises s.
+/* Stable time step (FP64) of the explicit scheme.  The paper fixes only the
+ * CFL number 0.9 (Sec. 4, preamble) for its low-storage RK4 (Sec. 3.1); the
+ * rule is the reading of that statement: the min of the advective limit
+ * CFL T_N 2 / max_nodes sum_d (|u . Ja^d| + c~ |Ja^d|)/J (the Rusanov wave
+ * speed of Sec. 3.1 with c~ = sqrt(|c_s^2|), eq. speedofsound) and the
+ * parabolic/source limit CFL 4.6567 / (alpha beta + RHO_N nu_max max_nodes
+ * sum_d (|Ja^d|/(2J))^2) (the relaxation source rate alpha beta and the
+ * diffusivities of F^V, Sec. 2.3.2), nu_max = max(4 mu/(3 rho), kappa/(rho R
+ * cv), gam beta); T_N and RHO_N are the 1D upwind-advection and BR1-diffusion
+ * stability constants of the Gauss DGSEM under the RK scheme's stability
+ * polynomial, 4.6567 its real stability interval.  Synchronises s.
  * Errors: NSKR_E_NONFINITE if a rate is not finite (dt not written). */
 int nskr_dt(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
 
@@ -290,7 +296,14 @@ int nskr_dt_noalloc(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
  * finite, nsteps < 0, null or aliasing buffers), NSKR_E_STATE, NSKR_E_HIP. */
 int nskr_rk_steps(nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, nskr_stream s);
 
-/* Integrals and counters (the NSKR_SUM_* indices) into out[NSKR_NSUMS].
+/* Integrals and counters (the NSKR_SUM_* indices) into out[NSKR_NSUMS]:
+ * the quantities the paper follows over time (Sec. 4.1.1: the relaxation
+ * and gradient energies and L2(rho - c); Sec. 4.2-4.3: kinetic energy,
+ * total energy, the mathematical entropy from the Helmholtz energy of
+ * Sec. 2.1), plus mass, momentum, volume, extrema of rho and T and health
+ * counters (non-finite values, rho outside (0, 1/b) where the van der Waals
+ * pressure is defined, T <= 0, c_s^2 < 0 inside the spinodal, Sec. 2.3.1).
+ * Gauss quadrature with the Jacobian, FP64 accumulation in a fixed order.
  * Synchronises s.  Returns NSKR_E_NONFINITE (out still filled) when a
  * non-finite value, rho outside (0, 1/b) or T <= 0 is found. */
 int nskr_reduce(nskr_ctx *ctx, const void *U, double *out, nskr_stream s);
@@ -351,16 +364,22 @@ int nskr_batch_set_graph(nskr_batch *b, int on);
 int nskr_batch_admit(nskr_batch *b, nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, int *slot);
 
 /* One RK step of every active instance on stream s (asynchronous).  Instances
- * that reach their step count become finished and stop advancing.  The first
- * step after an instance is admitted also prolongs its state to its faces
- * (one direct launch before the graph); later steps take the face traces the
+ * that reach their step count stop advancing (nskr_batch_poll reports them
+ * once that step has run).  The first step after an instance is admitted also
+ * clears its FP32 compensation and prolongs its state to its faces (direct
+ * launches on s before the graph); later steps take the face traces the
  * previous step's last stage wrote, exactly as nskr_rk_steps does. */
 int nskr_batch_step(nskr_batch *b, nskr_stream s);
 
-/* Finished slots (up to cap written to slots, total count in *n). */
+/* Finished slots (up to cap written to slots, total count in *n): instances
+ * whose last step has completed on the GPU (an event recorded after that
+ * step), so their state can be read once the caller's stream is ordered
+ * after it.  Does not block. */
 int nskr_batch_poll(nskr_batch *b, int *slots, int cap, int *n);
 
-/* Release a slot (finished or not); its buffers are the caller's again. */
+/* Release a slot (finished or not).  Waits until every step queued so far
+ * has completed, so that on return the slot's buffers are the caller's
+ * again and its context may be admitted anew. */
 int nskr_batch_retire(nskr_batch *b, int slot);
 
 /* Budget in use, active instances, steps taken. */

@@ -257,8 +257,6 @@ static bool maxwell_newton(const Vdw &v, ld T, ld sv, ld sl, ld &rv, ld &rl)
 // composite 16-point Gauss-Legendre over 48 panels of [rv, rl].
 static ld sigma_host(const Vdw &v, ld T, ld gam, ld rv, ld rl)
 {
-    Basis b16;
-    (void)b16;
     const int m = 16;
     ld x[16], w[16];
     for (int i = 0; i < m; ++i) {
@@ -378,6 +376,21 @@ static const double kRhoN[6] = {0, 0, 64.8, 176.2, 387.0, 745.2};
 static const double kRkReal = 4.6567;
 
 // ------------------------------------------------------------ extra kernels
+// Reduction operations: 0 sum, 1 min, 2 max.
+__device__ __forceinline__ double combine(int kd, double x, double y)
+{
+    return kd == 0 ? x + y : (kd == 1 ? fmin(x, y) : fmax(x, y));
+}
+
+// Reduce over the 64 lanes of a wave by xor shuffles (every lane ends with
+// the result; the pairing is fixed, so sums do not depend on timing).
+__device__ __forceinline__ double wave_reduce(int kd, double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = combine(kd, v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 struct RateArgs {
     MeshDev mesh; Phys ph; size_t NN; double *part; int nblk;
 };
@@ -386,7 +399,7 @@ template <int P, typename T, bool CV>
 __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, RateArgs a)
 {
     using G = Tile<P>;
-    __shared__ double sr[3][kBlock];
+    __shared__ double sr[3][kBlock / 64];
     const int t = threadIdx.x;
     const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le;
     const size_t g = (size_t)e0 * G::n3 + t;
@@ -416,32 +429,46 @@ __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, Rat
         r2 = fmax(fmax(4.0 * a.ph.mu / (3.0 * rho), a.ph.kappa / (rho * a.ph.R * a.ph.cv)), a.ph.gam * a.ph.beta);
         if (!isfinite(r0) || !isfinite(r2)) r0 = r2 = INFINITY;
     }
-    sr[0][t] = r0; sr[1][t] = r1; sr[2][t] = r2;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (t < s)
-            for (int k = 0; k < 3; ++k) sr[k][t] = fmax(sr[k][t], sr[k][t + s]);
-        __syncthreads();
+    const double rv[3] = {r0, r1, r2};
+    const int w = t >> 6, lane = t & 63;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double m = wave_reduce(2, rv[k]);
+        if (lane == 0) sr[k][w] = m;
     }
-    if (t == 0)
-        for (int k = 0; k < 3; ++k) a.part[(size_t)k * a.nblk + blockIdx.x] = sr[k][0];
+    __syncthreads();
+    if (t < 3) {
+        double m = sr[t][0];
+        for (int q = 1; q < kBlock / 64; ++q) m = fmax(m, sr[t][q]);
+        a.part[(size_t)t * a.nblk + blockIdx.x] = m;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_max_final(const double *part, int nblk, int nval, double *out)
+// Final pass of a two-level reduction: workgroup k reduces partials
+// part[k][0..nblk) with the operation of kind(k) (0 sum, 1 min, 2 max): each
+// thread over a fixed stride, then the wave shuffles and the waves in order,
+// so that the result does not depend on timing.
+template <typename KindF>
+__device__ __forceinline__ void reduce_final(const double *part, int nblk, double *out, KindF kind)
 {
-    __shared__ double s[kBlock];
-    for (int k = 0; k < nval; ++k) {
-        double m = 0;
-        for (int b = threadIdx.x; b < nblk; b += kBlock) m = fmax(m, part[(size_t)k * nblk + b]);
-        s[threadIdx.x] = m;
-        __syncthreads();
-        for (int st = kBlock / 2; st > 0; st >>= 1) {
-            if (threadIdx.x < st) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + st]);
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = s[0];
-        __syncthreads();
+    __shared__ double s[kBlock / 64];
+    const int k = blockIdx.x, kd = kind(k);
+    double m = kd == 0 ? 0.0 : (kd == 1 ? INFINITY : -INFINITY);
+    for (int b = threadIdx.x; b < nblk; b += kBlock) m = combine(kd, m, part[(size_t)k * nblk + b]);
+    m = wave_reduce(kd, m);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = s[0];
+        for (int q = 1; q < kBlock / 64; ++q) r = combine(kd, r, s[q]);
+        out[k] = r;
     }
+}
+
+// maxima of the time-step rates: one workgroup per value
+__global__ __launch_bounds__(kBlock) void k_max_final(const double *part, int nblk, double *out)
+{
+    reduce_final(part, nblk, out, [](int) { return 2; });
 }
 
 // Integrals: kinds 0 = sum, 1 = min, 2 = max for the NSKR_SUM_* slots.
@@ -451,7 +478,7 @@ template <int P, typename T, bool CV>
 __global__ __launch_bounds__(kBlock) void k_integrals(const T *U, const T *Q, RateArgs a, Basis bas)
 {
     using G = Tile<P>;
-    __shared__ double sr[NSKR_NSUMS][kBlock];
+    __shared__ double sr[NSKR_NSUMS][kBlock / 64];
     const int t = threadIdx.x;
     const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le, nd = t - le * G::n3;
     const size_t g = (size_t)e0 * G::n3 + t;
@@ -498,43 +525,25 @@ __global__ __launch_bounds__(kBlock) void k_integrals(const T *U, const T *Q, Ra
             v[19] = wJ;
         }
     }
-    for (int k = 0; k < NSKR_NSUMS; ++k) sr[k][t] = v[k];
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (t < s)
-            for (int k = 0; k < NSKR_NSUMS; ++k) {
-                const int kd = sum_kind(k);
-                const double x = sr[k][t], y = sr[k][t + s];
-                sr[k][t] = kd == 0 ? x + y : (kd == 1 ? fmin(x, y) : fmax(x, y));
-            }
-        __syncthreads();
+    const int w = t >> 6, lane = t & 63;
+#pragma unroll
+    for (int k = 0; k < NSKR_NSUMS; ++k) {
+        const double m = wave_reduce(sum_kind(k), v[k]);
+        if (lane == 0) sr[k][w] = m;
     }
-    if (t == 0)
-        for (int k = 0; k < NSKR_NSUMS; ++k) a.part[(size_t)k * a.nblk + blockIdx.x] = sr[k][0];
+    __syncthreads();
+    if (t < NSKR_NSUMS) {
+        const int kd = sum_kind(t);
+        double m = sr[t][0];
+        for (int q = 1; q < kBlock / 64; ++q) m = combine(kd, m, sr[t][q]);
+        a.part[(size_t)t * a.nblk + blockIdx.x] = m;
+    }
 }
 
+// integrals: one workgroup per NSKR_SUM_* slot
 __global__ __launch_bounds__(kBlock) void k_integrals_final(const double *part, int nblk, double *out)
 {
-    __shared__ double s[kBlock];
-    for (int k = 0; k < NSKR_NSUMS; ++k) {
-        const int kd = sum_kind(k);
-        double m = kd == 0 ? 0.0 : (kd == 1 ? INFINITY : -INFINITY);
-        for (int b = threadIdx.x; b < nblk; b += kBlock) {
-            const double x = part[(size_t)k * nblk + b];
-            m = kd == 0 ? m + x : (kd == 1 ? fmin(m, x) : fmax(m, x));
-        }
-        s[threadIdx.x] = m;
-        __syncthreads();
-        for (int st = kBlock / 2; st > 0; st >>= 1) {
-            if (threadIdx.x < st) {
-                const double x = s[threadIdx.x], y = s[threadIdx.x + st];
-                s[threadIdx.x] = kd == 0 ? x + y : (kd == 1 ? fmin(x, y) : fmax(x, y));
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[k] = s[0];
-        __syncthreads();
-    }
+    reduce_final(part, nblk, out, [](int k) { return sum_kind(k); });
 }
 
 struct InitArgs {
@@ -788,7 +797,7 @@ template <int P, typename T, int BS, bool CV> struct Impl {
         RateArgs a{mesh(c), c->ph, c->NN, part, nblk256(c)};
         hipLaunchKernelGGL((k_dt_rates<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a);
-        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, nblk256(c), 3, dout);
+        hipLaunchKernelGGL(k_max_final, dim3(3), dim3(kBlock), 0, s, (const double *)part, nblk256(c), dout);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(out3, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
@@ -803,8 +812,8 @@ template <int P, typename T, int BS, bool CV> struct Impl {
         RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
         hipLaunchKernelGGL((k_integrals<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a, c->bas);
-        hipLaunchKernelGGL(k_integrals_final, dim3(1), dim3(kBlock), 0, s, (const double *)c->d_part, nblk256(c),
-                           c->d_out);
+        hipLaunchKernelGGL(k_integrals_final, dim3(NSKR_NSUMS), dim3(kBlock), 0, s, (const double *)c->d_part,
+                           nblk256(c), c->d_out);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(out, c->d_out, NSKR_NSUMS * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
@@ -1810,10 +1819,11 @@ struct BatchSlot {
     void *U = nullptr, *R = nullptr;
     double dt = 0.0;
     int nsteps = 0, done = 0;
-    int state = 0;  // 0 free, 1 active, 2 finished (awaiting retire)
-    bool fresh = true;  // face traces not yet prolonged
+    int state = 0;  // 0 free, 1 active, 2 last step queued (finished once `last` has completed)
+    bool fresh = true;  // face traces not yet prolonged (and compensation not yet cleared)
     double t0 = 0.0;    // instance time at admission
     size_t bytes = 0;
+    hipEvent_t last = nullptr;  // recorded after the step that completes the instance
 };
 
 struct BatchGroup {
@@ -1835,8 +1845,22 @@ struct nskr_batch {
     int **d_ticks = nullptr;  // step counters of the active instances whose walls change in time
     int nticks = 0;
     long steps = 0;
+    hipEvent_t queued = nullptr;  // recorded after every step: all work queued so far
+    std::vector<hipEvent_t> event_pool;
     std::string err;
 };
+
+static hipEvent_t batch_event(nskr_batch *b)
+{
+    if (!b->event_pool.empty()) {
+        hipEvent_t e = b->event_pool.back();
+        b->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
 
 static int bfail(nskr_batch *b, int code, const std::string &msg)
 {
@@ -1978,7 +2002,12 @@ int nskr_batch_destroy(nskr_batch *b)
     if (!b) return NSKR_OK;
     {
         DeviceGuard g(b->device);
+        if (b->queued) (void)hipEventSynchronize(b->queued);
         batch_free_groups(b);
+        for (auto &sl : b->slots)
+            if (sl.last) (void)hipEventDestroy(sl.last);
+        for (hipEvent_t e : b->event_pool) (void)hipEventDestroy(e);
+        if (b->queued) (void)hipEventDestroy(b->queued);
     }
     delete b;
     return NSKR_OK;
@@ -2020,11 +2049,6 @@ int nskr_batch_admit(nskr_batch *b, nskr_ctx *c, void *U, void *R, double dt, in
     sl.c = c; sl.U = U; sl.R = R; sl.dt = dt; sl.nsteps = nsteps; sl.done = 0; sl.state = 1; sl.bytes = need;
     sl.fresh = true;
     sl.t0 = c->time;
-    if (c->d_Ck) {
-        DeviceGuard guard(b->device);
-        Impl<3, float, 256, false>::zero_comp(c, nullptr);
-        BHIPCHK(b, hipDeviceSynchronize());
-    }
     b->used += need;
     b->dirty = true;
     *slot = k;
@@ -2035,10 +2059,17 @@ int nskr_batch_retire(nskr_batch *b, int slot)
 {
     if (!b || slot < 0 || slot >= (int)b->slots.size() || b->slots[slot].state == 0) return NSKR_E_ARG;
     BatchSlot &sl = b->slots[slot];
+    {
+        // the buffers go back to the caller: wait until no queued step of the
+        // batch can still touch them
+        DeviceGuard guard(b->device);
+        if (b->queued) BHIPCHK(b, hipEventSynchronize(b->queued));
+    }
     if (sl.state == 1) {
         b->dirty = true;
         sl.c->time = sl.t0 + sl.done * sl.dt;
     }
+    if (sl.last) b->event_pool.push_back(sl.last);
     b->used -= sl.bytes;
     sl = BatchSlot();
     return NSKR_OK;
@@ -2060,7 +2091,12 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
     }
     for (auto &sl : b->slots)
         if (sl.state == 1 && sl.fresh) {
-            dispatch(sl.c, [&](auto impl) { return decltype(impl)::prime(sl.c, sl.U, sl.R, sl.dt, s); });
+            // on the step stream, ahead of the instance's first step: its
+            // compensation cleared and its face traces prolonged
+            dispatch(sl.c, [&](auto impl) {
+                decltype(impl)::zero_comp(sl.c, s);
+                return decltype(impl)::prime(sl.c, sl.U, sl.R, sl.dt, s);
+            });
             if (sl.c->trate) hipLaunchKernelGGL((k_zero<int>), dim3(1), dim3(kBlock), 0, s, sl.c->d_clk, (size_t)1);
             sl.fresh = false;
         }
@@ -2091,11 +2127,19 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
         BHIPCHK(b, hipGetLastError());
     }
     b->steps++;
+    if (!b->queued) {
+        b->queued = batch_event(b);
+        if (!b->queued) return bfail(b, NSKR_E_HIP, "event creation failed");
+    }
+    BHIPCHK(b, hipEventRecord(b->queued, s));
     for (auto &sl : b->slots)
         if (sl.state == 1 && ++sl.done >= sl.nsteps) {
             sl.state = 2;
             sl.c->time = sl.t0 + sl.nsteps * sl.dt;
             b->dirty = true;
+            if (!sl.last) sl.last = batch_event(b);
+            if (!sl.last) return bfail(b, NSKR_E_HIP, "event creation failed");
+            BHIPCHK(b, hipEventRecord(sl.last, s));
         }
     return NSKR_OK;
 }
@@ -2103,12 +2147,22 @@ int nskr_batch_step(nskr_batch *b, nskr_stream sv)
 int nskr_batch_poll(nskr_batch *b, int *slots, int cap, int *n)
 {
     if (!b || !n || (cap > 0 && !slots)) return NSKR_E_ARG;
+    DeviceGuard guard(b->device);
     int k = 0;
-    for (int i = 0; i < (int)b->slots.size(); ++i)
-        if (b->slots[i].state == 2) {
-            if (k < cap) slots[k] = i;
-            ++k;
+    for (int i = 0; i < (int)b->slots.size(); ++i) {
+        const BatchSlot &sl = b->slots[i];
+        if (sl.state != 2) continue;
+        if (sl.last) {
+            const hipError_t q = hipEventQuery(sl.last);
+            if (q == hipErrorNotReady) continue;  // its last step has not run yet
+            if (q != hipSuccess) {
+                b->poisoned = true;
+                return bfail(b, NSKR_E_HIP, std::string("hipEventQuery: ") + hipGetErrorString(q));
+            }
         }
+        if (k < cap) slots[k] = i;
+        ++k;
+    }
     *n = k;
     return NSKR_OK;
 }

@@ -30,6 +30,7 @@ class Request:
         self.t_admit = None
         self.t_done = None
         self.result = None
+        self.dt = None
 
 
 def _setup(req, precision, table, setup_stream):
@@ -76,6 +77,7 @@ def serve(requests, budget_bytes, precision="fp32_mixed", table=None, keep_resul
                     sum(r.w.nnodes for r in active.values()) + req.w.nnodes > max_active_nodes:
                 break
             s, U, R, dt = _setup(req, precision, table, setup_stream)
+            req.dt = dt
             slot = batch.admit(s, U, R, dt, req.w.steps)
             if slot is None:
                 del s, U, R

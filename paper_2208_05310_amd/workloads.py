@@ -158,8 +158,9 @@ def c2() -> Workload:
 
 def c3(n=32) -> Workload:
     """Periodic unit cube, n^3 elements (32 for the full case), N=5, eight
-    droplets with radii in [0.05, 0.12] at T=0.9."""
-    cen, rad = random_droplets(3, 8, 0.05, 0.12, 0.10)
+    droplets with radii in [0.05, 0.12] at T=0.9, at least 0.2 apart (surface to
+    surface)."""
+    cen, rad = random_droplets(3, 8, 0.05, 0.12, 0.20)
     return Workload(name=f"eight_droplets_periodic_{n}x{n}x{n}_N5", N=5, n=(n, n, n),
                     centres=cen, radii=rad, T0=0.9, steps=500, noise_seed=13)
 

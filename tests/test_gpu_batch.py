@@ -172,6 +172,7 @@ def test_budget_admission_and_step_counts(torch_cuda):
     assert b.admit(s2, U2, R2, dt2, 5) is None          # no room now
     for _ in range(3):
         b.step(stream)
+    stream.synchronize()  # poll reports a slot once its last step has run
     assert b.poll() == [0]
     b.retire(0)
     assert b.admit(s2, U2, R2, dt2, 5) is not None      # room after retirement
@@ -208,6 +209,17 @@ def test_serving_loop_small_stream(torch_cuda):
             b.step(stream)
         stream.synchronize()
         assert np.array_equal(U.double().cpu().numpy(), r.result), r.w.name
+    # and the served (FP32-mixed) results against the CPU oracle over the same
+    # steps and dt from its own initial state: density within 1e-5
+    from helpers import oracle_for, oracle_init
+    for r in done:
+        o = oracle_for(r.w)
+        Uo = oracle_init(o, r.w)
+        Ro = np.zeros_like(Uo)
+        o.run(Uo, Ro, 0.0, r.dt, r.w.steps)
+        err = np.max(np.abs(r.result[0] - Uo[0])) / np.max(np.abs(Uo[0]))
+        print(f"[case] served {r.w.name} rho vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-5
 
 
 @pytest.mark.parametrize("graph", [True, False])
@@ -267,3 +279,80 @@ def test_time_dependent_walls_in_a_batch(torch_cuda, graph):
     assert torch.equal(U2, U)
     assert s2.get_time() == s.get_time()
 
+
+
+def test_batched_mix_matches_the_oracle(torch_cuda):
+    """Every instance of the mixed batch, advanced together, against the CPU
+    oracle over the same steps from the same initial state and dt: FP64
+    instances within 1e-12 per conserved field (momenta floored at |rho|
+    |c~|), FP32-mixed ones within 1e-5 in density."""
+    torch = torch_cuda
+    from helpers import oracle_for, oracle_init
+    from paper_2208_05310_amd.nskr import Batch, solver_for
+    nsteps = 4
+    b = Batch(1 << 34)
+    stream = torch.cuda.Stream()
+    runs = []
+    for w, prec in small_mix():
+        o = oracle_for(w)
+        U0 = oracle_init(o, w)
+        dt = o.dt(U0)
+        s = solver_for(w, prec)
+        U = torch.tensor(U0, dtype=s.dtype, device="cuda:0")
+        R = s.new_state()
+        assert b.admit(s, U, R, dt, nsteps) is not None
+        runs.append((w, prec, o, U0, dt, s, U))
+    for _ in range(nsteps):
+        b.step(stream)
+    stream.synchronize()
+    for w, prec, o, U0, dt, s, U in runs:
+        Uo = U0.copy()
+        Ro = np.zeros_like(Uo)
+        o.run(Uo, Ro, 0.0, dt, nsteps)
+        Ug = U.double().cpu().numpy()
+        if prec == "fp64":
+            pr = w.params
+            cs = np.sqrt(abs((1 + 1 / pr["cv"]) * pr["R"] * w.T0 / (1 - pr["b"] * Uo[0].max()) ** 2))
+            floor = [0.0] + [np.max(np.abs(Uo[0])) * cs] * 3 + [0.0, 0.0]
+            err = np.array([np.max(np.abs(Ug[f] - Uo[f])) / max(np.max(np.abs(Uo[f])), floor[f])
+                            for f in range(6)])
+            print(f"[case] batched {w.name} vs oracle: {err}", flush=True)
+            assert np.all(err <= 1e-12), err
+        else:
+            err = np.max(np.abs(Ug[0] - Uo[0])) / np.max(np.abs(Uo[0]))
+            print(f"[case] batched {w.name} (fp32-mixed) rho vs oracle: {err:.2e}", flush=True)
+            assert err <= 1e-5
+
+
+def test_poll_reports_completed_steps_and_retire_waits_for_queued_ones(torch_cuda):
+    """A finished slot is reported once its last step has run; retiring a
+    slot whose steps are still queued returns after they ran, so the state
+    equals the single-instance path after the same steps; the context can be
+    admitted again at once (its compensation is cleared on the step stream)."""
+    torch = torch_cuda
+    from paper_2208_05310_amd.nskr import Batch
+    w = wl.c2()
+    stream = torch.cuda.Stream()
+    s, U, R, dt = setup(w, "fp32_mixed")
+    ref = U.clone()
+    Rr = s.new_state()
+    s.rk_steps(ref, Rr, dt, 3)
+    torch.cuda.synchronize()
+    b = Batch(1 << 34)
+    slot = b.admit(s, U, R, dt, 10)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            b.step(stream)
+    b.retire(slot)              # waits for the three queued steps
+    assert torch.equal(U, ref)
+    # admitted again right away: the next 2 steps equal 2 more single steps
+    slot = b.admit(s, U, R, dt, 2)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            b.step(stream)
+    stream.synchronize()
+    assert b.poll() == [slot]
+    s.rk_steps(ref, Rr, dt, 2)
+    torch.cuda.synchronize()
+    b.retire(slot)
+    assert torch.equal(U, ref)

@@ -30,7 +30,7 @@ def test_sizes_of_the_named_configurations():
     assert wl.c4().nnodes == 3538944
 
 
-@pytest.mark.parametrize("make,count,rmin,rmax,gap", [(wl.c2, 2, 0.15, 0.15, 0.20), (wl.c3, 8, 0.05, 0.12, 0.10)])
+@pytest.mark.parametrize("make,count,rmin,rmax,gap", [(wl.c2, 2, 0.15, 0.15, 0.20), (wl.c3, 8, 0.05, 0.12, 0.20)])
 def test_droplets_respect_the_separation_rule(make, count, rmin, rmax, gap):
     w = make()
     assert len(w.centres) == count and len(w.radii) == count
