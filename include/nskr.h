@@ -222,8 +222,10 @@ int nskr_destroy(nskr_ctx *ctx);
  * without a bc or bc index out of range, wall kind not 1, 2 or 3, negative
  * Navier-slip coefficients, a wall velocity that is not tangential at every
  * face point, supercritical wall temperature); NSKR_E_UNSUPPORTED (walls
- * whose temperature varies on a mesh with curved elements); NSKR_E_NOMEM;
- * NSKR_E_HIP.  Synchronises the stream. */
+ * whose temperature varies on a mesh with curved elements, or a mesh whose
+ * node arrays (8 (N+1)^3 nelems bytes per field) or face-point arrays reach
+ * 4 GiB, i.e. beyond about 500M nodes); NSKR_E_NOMEM; NSKR_E_HIP.
+ * Synchronises the stream. */
 int nskr_mesh_upload(nskr_ctx *ctx, const nskr_mesh *m, nskr_stream s);
 
 /* Number of values in one state buffer: 6 nelems (N+1)^3.

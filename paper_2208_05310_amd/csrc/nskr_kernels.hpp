@@ -43,6 +43,32 @@ namespace nskr {
 
 constexpr int kBlock = 256;
 
+// Global accesses of node- and element-indexed arrays through a wave-uniform
+// base pointer and a 32-bit element index: the base stays in scalar
+// registers (read-first-lane keeps the compiler from folding it into per-lane
+// 64-bit address arithmetic) and the byte offset is one 32-bit vector
+// register shared by every field at the same node, so a load or store costs
+// no vector address instruction.  Every array addressed this way is below
+// 4 GiB (the mesh upload checks it).  Face traces keep 64-bit addresses: one
+// per face point, with the field offsets as immediates.
+template <typename P> __device__ __forceinline__ P *uniform_ptr(P *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P *)(((uint64_t)hi << 32) | lo);
+}
+template <typename T> __device__ __forceinline__ T gld(const T *base, uint32_t i)
+{
+    typedef __attribute__((address_space(1))) const char gc;
+    return *(__attribute__((address_space(1))) const T *)((gc *)uniform_ptr(base) + i * (uint32_t)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ void gst(T *base, uint32_t i, T v)
+{
+    typedef __attribute__((address_space(1))) char gc;
+    *(__attribute__((address_space(1))) T *)((gc *)uniform_ptr(base) + i * (uint32_t)sizeof(T)) = v;
+}
+
 struct Phys {
     double R, a, b, cv, mu, kappa, gam, alpha, beta;
     double inv_Rcv;   // 1 / (R c_v)
@@ -142,32 +168,47 @@ template <int P, typename T, bool CV>
 __device__ __forceinline__ void face_normal(const MeshDev &m, size_t face, int fp, T n[3], T &dS)
 {
     if (CV) {
-        const T *q = (const T *)m.fnrm + (face * (P * P) + fp) * 4;
-        n[0] = q[0];
-        n[1] = q[1];
-        n[2] = q[2];
-        dS = q[3];
+        const uint32_t q = ((uint32_t)face * (P * P) + fp) * 4;
+        const T *fn = (const T *)m.fnrm;
+        n[0] = gld(fn, q);
+        n[1] = gld(fn, q + 1);
+        n[2] = gld(fn, q + 2);
+        dS = gld(fn, q + 3);
     } else {
-        const double *q = m.fmet + face * 4;
-        n[0] = T(q[0]);
-        n[1] = T(q[1]);
-        n[2] = T(q[2]);
-        dS = T(q[3]);
+        const uint32_t q = (uint32_t)face * 4;
+        n[0] = T(gld(m.fmet, q));
+        n[1] = T(gld(m.fmet, q + 1));
+        n[2] = T(gld(m.fmet, q + 2));
+        dS = T(gld(m.fmet, q + 3));
     }
 }
 template <int P, typename T, bool CV> __device__ __forceinline__ T face_dS(const MeshDev &m, size_t face, int fp)
 {
-    if (CV) return ((const T *)m.fnrm)[(face * (P * P) + fp) * 4 + 3];
-    return T(m.fmet[face * 4 + 3]);
+    if (CV) return gld((const T *)m.fnrm, ((uint32_t)face * (P * P) + fp) * 4 + 3);
+    return T(gld(m.fmet, (uint32_t)face * 4 + 3));
 }
 
 // ---------------------------------------------------------------- physics
+// 1/x in FP64.  FAST (the FP32-mixed instances, whose inputs carry FP32
+// precision): the hardware FP32 reciprocal refined by one Newton step in FP64,
+// r + r (1 - x r), relative error about 1e-14 (the square of the FP32
+// estimate's); else the correctly rounded division.
+template <bool FAST> __device__ __forceinline__ double recip(double x)
+{
+    if (FAST) {
+        const double r = (double)__builtin_amdgcn_rcpf((float)x);
+        return fma(r, fma(-x, r, 1.0), r);
+    }
+    return 1.0 / x;
+}
+
 // Temperature recovery of eq. totalenergyalpha with eps = R c_v T - a rho
-// (always FP64: it cancels large terms near the spinodal).
+// (always FP64 arithmetic: it cancels large terms near the spinodal).
+template <bool FAST = false>
 __device__ __forceinline__ double temperature(const Phys &ph, double rho, double m0, double m1, double m2,
                                               double E, double c, double q0, double q1, double q2)
 {
-    const double ir = 1.0 / rho;
+    const double ir = recip<FAST>(rho);
     double kin = 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * ir;
     double rel = 0.5 * ph.alpha * (rho - c) * (rho - c);
     double grd = 0.5 * ph.gam * (q0 * q0 + q1 * q1 + q2 * q2);
@@ -176,11 +217,23 @@ __device__ __forceinline__ double temperature(const Phys &ph, double rho, double
 
 // van der Waals pressure (eq. pressure) and isentropic sound speed squared
 // (eq. speedofsound for the Helmholtz energy of Sec. 2.1), FP64.
+template <bool FAST = false>
 __device__ __forceinline__ void eos(const Phys &ph, double rho, double T, double &p, double &cs2)
 {
-    double q = 1.0 / (1.0 - ph.b * rho);
+    double q = recip<FAST>(1.0 - ph.b * rho);
     p = rho * ph.R * T * q - ph.a * rho * rho;
     cs2 = ph.cs_fac * T * q * q - 2.0 * ph.a * rho;
+}
+
+// The FP32-mixed instances take the refined reciprocals above.
+template <typename T> constexpr bool fast_fp64() { return sizeof(T) == 4; }
+
+// sqrt of a non-negative FP64 value into the element type: FP32 instances
+// round the argument and take the FP32 square root.
+template <typename T> __device__ __forceinline__ T sqrt_to(double x)
+{
+    if (sizeof(T) == 4) return T(sqrtf((float)x));
+    return T(sqrt(x));
 }
 
 // Local state at a point for the flux evaluation.
@@ -360,9 +413,11 @@ template <int N2> struct FaceIx {
     size_t face;
     int fp;
     __device__ __forceinline__ FaceIx(size_t fc, int p) : face(fc), fp(p) {}
-    // element of field k of a K-field trace array
+    // element of field k of a K-field trace array (64-bit: one address per
+    // face point, the field offsets folded into the instructions' immediates)
     __device__ __forceinline__ size_t at(int K, int k) const { return (face * K + k) * N2 + fp; }
 };
+
 
 // A pointer read from ordinary device memory is generic to the compiler,
 // which then emits flat loads and stores for everything addressed through it.
@@ -392,15 +447,18 @@ __device__ __forceinline__ void instance_of(const Launch<T> &L, Inst<T> &a, int 
     }
 }
 
-// Copy the basis into LDS (the rows each thread needs differ per lane).
-template <int P>
-__device__ __forceinline__ void load_basis(const Basis &b, double *sDh, double *sL, double *sLh)
+// Copy the basis into LDS (the rows each thread needs differ per lane), in
+// the element type of the kernel: FP32 instances then read and multiply
+// floats (the values are the FP64 host basis rounded once, as a conversion
+// at every use would round them).
+template <int P, typename B_>
+__device__ __forceinline__ void load_basis(const Basis &b, B_ *sDh, B_ *sL, B_ *sLh)
 {
     const int t = threadIdx.x;
-    if (t < P * P) sDh[t] = b.Dh[t];
+    if (t < P * P) sDh[t] = B_(b.Dh[t]);
     if (t < 2 * P) {
-        sL[t] = b.L[t / P][t % P];
-        sLh[t] = b.Lh[t / P][t % P];
+        sL[t] = B_(b.L[t / P][t % P]);
+        sLh[t] = B_(b.Lh[t / P][t % P]);
     }
 }
 
@@ -425,8 +483,8 @@ template <int P> struct LineTask {
 };
 
 // Prolongation of one LDS field of an element to both faces of a line.
-template <int P, typename T>
-__device__ __forceinline__ void prolong2(const T *s, int base, const double *sL, const LineTask<P> &lt, T &vm,
+template <int P, typename T, typename B_>
+__device__ __forceinline__ void prolong2(const T *s, int base, const B_ *sL, const LineTask<P> &lt, T &vm,
                                          T &vp)
 {
     T am = T(0), ap = T(0);
@@ -553,9 +611,9 @@ __device__ __forceinline__ WallPt wall_point(const MeshDev &m, const Basis &bas,
 // J q_m = sum_d Ja^d_m (Dhat w + lhat(+1) w*_+ - lhat(-1) w*_-), from the node
 // values fw (element starting at base) and face values fs (element's face
 // points starting at fbase) in LDS.
-template <int P, typename T>
+template <int P, typename T, typename B_>
 __device__ __forceinline__ void lifted_grad(const T *fw, const T *fs, int base, int fbase, int i, int j, int k,
-                                            const double *sDh, const double *sLh, const T Ja[9], T iJ, T q[3])
+                                            const B_ *sDh, const B_ *sLh, const T Ja[9], T iJ, T q[3])
 {
     constexpr int n2 = P * P;
     const int idx[3] = {i, j, k};
@@ -580,9 +638,9 @@ __device__ __forceinline__ void lifted_grad(const T *fw, const T *fs, int base, 
 // direction by direction so that only one row of Dhat is live: the reference
 // derivatives gd[f][d] first, then the metric transform.  Each (field,
 // direction) sum is formed exactly as in lifted_grad.
-template <int P, int NFLD, int NVS, int NFS, typename T>
+template <int P, int NFLD, int NVS, int NFS, typename T, typename B_>
 __device__ __forceinline__ void lifted_grads(const T (*fw)[NVS], const T (*fs)[NFS], int base, int fbase, int i, int j,
-                                             int k, const double *sDh, const double *sLh, T gd[NFLD][3])
+                                             int k, const B_ *sDh, const B_ *sLh, T gd[NFLD][3])
 {
     constexpr int n2 = P * P;
     const int idx[3] = {i, j, k};
@@ -613,10 +671,10 @@ __device__ __forceinline__ void lifted_grads(const T (*fw)[NVS], const T (*fs)[N
 // sum_faces lhat w* (n dS)_m, for NFLD consecutive LDS fields; sJa holds
 // Ja^d_m (row 3d+m) at every node of the tile, sN the outward n dS at every
 // face point.  Returns the physical gradients times 1/J (iJ of this node).
-template <int P, int NFLD, int NVS, int NFS, typename T>
+template <int P, int NFLD, int NVS, int NFS, typename T, typename B_>
 __device__ __forceinline__ void lifted_grads_curved(const T (*fw)[NVS], const T (*fs)[NFS], const T (*sJa)[NVS],
                                                     const T (*sN)[NFS], int base, int fbase, int i, int j, int k,
-                                                    const double *sDh, const double *sLh, T iJ, T q[NFLD][3])
+                                                    const B_ *sDh, const B_ *sLh, T iJ, T q[NFLD][3])
 {
     constexpr int n2 = P * P;
     const int idx[3] = {i, j, k};
@@ -663,8 +721,8 @@ __device__ __forceinline__ T stage_node_metrics(const MeshDev &m, size_t NN, siz
 {
     const T *nm = (const T *)m.nmet;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) sJa[r][t] = nm[r * NN + g];
-    return T(1) / nm[9 * NN + g];
+    for (int r = 0; r < 9; ++r) sJa[r][t] = gld(nm + r * NN, (uint32_t)g);
+    return T(1) / gld(nm + 9 * NN, (uint32_t)g);
 }
 
 template <typename T> __device__ __forceinline__ void to_physical(const T Ja[9], T iJ, const T gd[3], T q[3])
@@ -675,10 +733,9 @@ template <typename T> __device__ __forceinline__ void to_physical(const T Ja[9],
 
 template <typename T> __device__ __forceinline__ void element_metrics(const MeshDev &m, int e, T Ja[9], T &iJ)
 {
-    const double *em = m.emet + (size_t)e * 10;
 #pragma unroll
-    for (int r = 0; r < 9; ++r) Ja[r] = T(em[r]);
-    iJ = T(1.0 / em[9]);
+    for (int r = 0; r < 9; ++r) Ja[r] = T(gld(m.emet, (uint32_t)e * 10 + r));
+    iJ = T(1.0 / gld(m.emet, (uint32_t)e * 10 + 9));
 }
 
 // ------------------------------------------------------------ k_prolong
@@ -691,14 +748,15 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
     int e0;
     instance_of<T, BATCH>(L, a, e0, G::EPB);
     __shared__ T sU[6][G::NV];
-    __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
+    __shared__ T sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
     const int t = threadIdx.x;
     if (t < G::NV && e0 + t / G::n3 < E) {
         const size_t g = (size_t)e0 * G::n3 + t;
+    const uint32_t g32 = (uint32_t)g;
 #pragma unroll
-        for (int v = 0; v < 6; ++v) sU[v][t] = a.U[v * a.NN + g];
+        for (int v = 0; v < 6; ++v) sU[v][t] = gld(a.U + (v) * a.NN, g32);
     }
     __syncthreads();
     const size_t NF = (size_t)E * 6 * G::n2;
@@ -750,7 +808,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
     __shared__ T sS[NS][G::NF];
     __shared__ T sJa[NJ][NJV];
     __shared__ T sN[NQ][NQF];
-    __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
+    __shared__ T sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
     const int t = threadIdx.x;
@@ -758,6 +816,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
     const int e = e0 + le;
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
+    const uint32_t g32 = (uint32_t)g;
     const size_t NF = (size_t)E * 6 * G::n2;
     constexpr bool full = FULL;
     const T *TU = a.TU + (size_t)L.tb * 6 * NF;
@@ -770,8 +829,8 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
     int nbm = -1, nbp = -1;
     T wn[2][6];
     if (lact) {
-        nbm = a.mesh.nbr[el * 6 + 2 * lt.d];
-        nbp = a.mesh.nbr[el * 6 + 2 * lt.d + 1];
+        nbm = gld(a.mesh.nbr, el * 6 + 2 * lt.d);
+        nbp = gld(a.mesh.nbr, el * 6 + 2 * lt.d + 1);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int nb = s ? nbp : nbm;
@@ -791,7 +850,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
     if (act) {
         T u6[6], w[5];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) { u6[v] = a.U[v * a.NN + g]; sU[v][t] = u6[v]; }
+        for (int v = 0; v < 6; ++v) { u6[v] = gld(a.U + (v) * a.NN, g32); sU[v][t] = u6[v]; }
         primitives(u6, w);
         if (full) {
 #pragma unroll
@@ -854,7 +913,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
 #pragma unroll
                 for (int w = 0; w < 4; ++w)
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[w][m];
+                    for (int m = 0; m < 3; ++m) gst(a.Q + ((3 * w + m)) * a.NN, g32, T(q[w][m]));
                 qc[0] = q[4][0];
                 qc[1] = q[4][1];
                 qc[2] = q[4][2];
@@ -875,18 +934,18 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
                     T q[3];
                     lifted_grad<P>(sW[w], sS[w], base, fbase, i, j, k, sDh, sLh, Ja, iJ, q);
 #pragma unroll
-                    for (int m = 0; m < 3; ++m) a.Q[(3 * w + m) * a.NN + g] = q[m];
+                    for (int m = 0; m < 3; ++m) gst(a.Q + ((3 * w + m)) * a.NN, g32, T(q[m]));
                 }
             }
             lifted_grad<P>(sW[NW - 1], sS[NS - 1], base, fbase, i, j, k, sDh, sLh, Ja, iJ, qc);
         }
         if (full) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) a.Q[(12 + m) * a.NN + g] = qc[m];
-            const double Tn = temperature(a.ph, (double)sU[0][t], (double)sU[1][t], (double)sU[2][t], (double)sU[3][t],
+            for (int m = 0; m < 3; ++m) gst(a.Q + ((12 + m)) * a.NN, g32, T(qc[m]));
+            const double Tn = temperature<fast_fp64<T>()>(a.ph, (double)sU[0][t], (double)sU[1][t], (double)sU[2][t], (double)sU[3][t],
                                           (double)sU[4][t], (double)sU[5][t], (double)qc[0], (double)qc[1],
                                           (double)qc[2]);
-            a.TH[g] = T(Tn);
+            gst(a.TH, g32, T(Tn));
         }
     }
     __syncthreads();
@@ -913,10 +972,10 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
                 face_normal<P, T, true>(a.mesh, (size_t)el * 6 + 2 * lt.d + s, lt.fp, nf[s], dS);
             }
         } else {
-            const double *fm = a.mesh.fmet + ((size_t)el * 6 + 2 * lt.d + 1) * 4;
+            const uint32_t fq = ((uint32_t)el * 6 + 2 * lt.d + 1) * 4;
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                nf[1][m] = T(fm[m]);
+                nf[1][m] = T(gld(a.mesh.fmet, fq + m));
                 nf[0][m] = -nf[1][m];
             }
         }
@@ -924,13 +983,13 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
         for (int v = 0; v < 6; ++v) prolong2<P>(sU[v], base, sL, lt, uf[0][v], uf[1][v]);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const double Tf = temperature(a.ph, (double)uf[s][0], (double)uf[s][1], (double)uf[s][2], (double)uf[s][3],
+            const double Tf = temperature<fast_fp64<T>()>(a.ph, (double)uf[s][0], (double)uf[s][1], (double)uf[s][2], (double)uf[s][3],
                                           (double)uf[s][4], (double)uf[s][5], (double)qf[s][0], (double)qf[s][1],
                                           (double)qf[s][2]);
             const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
             const T gn = qf[s][0] * nf[s][0] + qf[s][1] * nf[s][1] + qf[s][2] * nf[s][2];
             a.T2[o.at(kT2, 0)] = gn;
-            a.T2[o.at(kT2, 1)] = T(Tf);
+            a.T2[o.at(kT2, 1)] = Tf;
         }
         // wall faces also keep the vector grad c (Navier-slip traction), in
         // a loop of its own: inside the one above the branch costs ~40 VGPRs
@@ -963,7 +1022,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     __shared__ T sTs[G::NF], sFs[G::NF];
     __shared__ T sJa[NJ][NJV];
     __shared__ T sN[NQ][NQF];
-    __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
+    __shared__ T sDh[P * P], sL[2 * P], sLh[2 * P];
     T(*sW)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sX);
     T(*sS)[G::NF] = reinterpret_cast<T(*)[G::NF]>(sX + 4 * G::NV);
     T(*sGu)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sX);
@@ -974,6 +1033,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     const int e = e0 + le;
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
+    const uint32_t g32 = (uint32_t)g;
     const size_t NF = (size_t)E * 6 * G::n2;
     const T *TU = a.TU + (size_t)L.tb * 6 * NF;
 
@@ -997,7 +1057,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 #pragma unroll
         for (int v = 0; v < 6; ++v)
             if (v != 4) r.uo[v] = TU[o.at(6, v)];
-        r.nb = a.mesh.nbr[el * 6 + ft.f];
+        r.nb = gld(a.mesh.nbr, el * 6 + ft.f);
         if (r.nb >= 0) {
             const FaceIx<G::n2> on(nbr_face<P>(r.nb), nbr_point<P>(r.nb, ft.fp));
 #pragma unroll
@@ -1014,7 +1074,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     if (act) {
         T w[5];
 #pragma unroll
-        for (int v = 0; v < 6; ++v) un[v] = a.U[v * a.NN + g];
+        for (int v = 0; v < 6; ++v) un[v] = gld(a.U + (v) * a.NN, g32);
         primitives(un, w);
 #pragma unroll
         for (int k = 0; k < 4; ++k) sW[k][t] = w[1 + k];
@@ -1028,8 +1088,13 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         if (el >= E) continue;
         Tr tr;
         if (task == t) tr = tr0; else load_tr(task, tr);
-        T n[3], dS;
-        face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
+        // the surface element always; the normal where it is used (walls,
+        // and the lifting's n dS on curved elements)
+        T n[3] = {T(0), T(0), T(0)}, dS;
+        if (CV || tr.nb < 0)
+            face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
+        else
+            dS = face_dS<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp);
         const T *uf = tr.uo;
         T w[5];
         primitives(uf, w);
@@ -1075,14 +1140,14 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const FaceTask<P> ft(task);
             const int el = e0 + ft.le, f = ft.f;
             if (el >= E) continue;
-            if (a.mesh.nbr[el * 6 + f] >= 0) continue;  // interior: no wall-table entry
+            if (gld(a.mesh.nbr, el * 6 + f) >= 0) continue;  // interior: no wall-table entry
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
             if (!bc.var) continue;
             const WallPt wp = wall_point<P>(a.mesh, L.bas, bc, el, f, ft.fp, BATCH ? tb : L.t);
             const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
             const FaceIx<G::n2> o((size_t)el * 6 + f, ft.fp);
             if (bc.iso) sTs[slot] = T(wp.Tw);
-            else a.TF[o.at(7, 6)] = T(1.0 / wp.Tw);  // 1/T_w for the heat-transfer flux below (TF[6] is free on walls)
+            else a.TF[o.at(7, 6)] = 1.0 / wp.Tw;  // 1/T_w for the heat-transfer flux below (TF[6] is free on walls)
             const T c = TU[o.at(6, 5)];
             sFs[slot] = T(wp.gcoef) * (c - T(wp.rl)) * (c - T(wp.rv)) * face_dS<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp);
         }
@@ -1113,7 +1178,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             for (int w = 0; w < 3; ++w) to_physical(Ja, iJ, gd[w], gu + 3 * w);
             to_physical(Ja, iJ, gd[3], gc);
         }
-        Tn = temperature(a.ph, (double)un[0], (double)un[1], (double)un[2], (double)un[3], (double)un[4],
+        Tn = temperature<fast_fp64<T>()>(a.ph, (double)un[0], (double)un[1], (double)un[2], (double)un[3], (double)un[4],
                          (double)un[5], (double)gc[0], (double)gc[1], (double)gc[2]);
     }
     __syncthreads();
@@ -1139,10 +1204,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const FaceTask<P> ft(task);
             const int el = e0 + ft.le, f = ft.f;
             if (el >= E) continue;
-            if (a.mesh.nbr[el * 6 + f] >= 0) continue;  // interior: no wall-table entry
+            if (gld(a.mesh.nbr, el * 6 + f) >= 0) continue;  // interior: no wall-table entry
             const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
             if (bc.kind != 3 || bc.g1 == 0.0) continue;
-            const double *Lf = sL + (f & 1) * P;
+            const T *Lf = sL + (f & 1) * P;
             const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
             T d0 = T(0), d1 = T(0), d2 = T(0);
 #pragma unroll
@@ -1209,10 +1274,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             for (int m = 0; m < 3; ++m) gT[m] = iJ * (Ja[m] * gd[0] + Ja[3 + m] * gd[1] + Ja[6 + m] * gd[2]);
             lap = iJ * dl;
         }
-        a.G2[0 * a.NN + g] = gT[0];
-        a.G2[1 * a.NN + g] = gT[1];
-        a.G2[2 * a.NN + g] = gT[2];
-        a.G2[3 * a.NN + g] = lap;
+        gst(a.G2 + (0) * a.NN, g32, T(gT[0]));
+        gst(a.G2 + (1) * a.NN, g32, T(gT[1]));
+        gst(a.G2 + (2) * a.NN, g32, T(gT[2]));
+        gst(a.G2 + (3) * a.NN, g32, T(lap));
     }
     __syncthreads();
     if constexpr (CV) {
@@ -1242,8 +1307,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const double *fm = a.mesh.fmet + ((size_t)e * 6 + 2 * d + 1) * 4;
-                const T n0 = T(fm[0]), n1 = T(fm[1]), n2 = T(fm[2]);
+                const uint32_t fq = ((uint32_t)e * 6 + 2 * d + 1) * 4;
+                const T n0 = T(gld(a.mesh.fmet, fq)), n1 = T(gld(a.mesh.fmet, fq + 1)), n2 = T(gld(a.mesh.fmet, fq + 2));
                 T *out = d == 0 ? &sA[0][0] : sX + (d - 1) * 4 * G::NV;
                 out[0 * G::NV + t] = mu * ((gg[0] + gg[0]) * n0 + (gg[1] + gg[3]) * n1 + (gg[2] + gg[6]) * n2 - td * n0);
                 out[1 * G::NV + t] = mu * ((gg[3] + gg[1]) * n0 + (gg[4] + gg[4]) * n1 + (gg[5] + gg[7]) * n2 - td * n1);
@@ -1264,7 +1329,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const FaceTask<P> ft(task);
             const int el = e0 + ft.le, f = ft.f;
             if (el >= E) continue;
-            const double *Lf = sL + (f & 1) * P;
+            const T *Lf = sL + (f & 1) * P;
             const int lo = ft.le * G::n3 + ft.off, ls = ft.str;
             auto pro = [&](const T *fld) {
                 T acc = T(0);
@@ -1276,7 +1341,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             T nrm[3], dSf;
             face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, nrm, dSf);
             const T n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
-            const bool wall = a.mesh.nbr[el * 6 + f] < 0;
+            const bool wall = gld(a.mesh.nbr, el * 6 + f) < 0;
             int kind = 0;  // interior faces have no wall-table entry
             if (wall) kind = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind;
             // state and convective part
@@ -1292,10 +1357,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const T un = mn * ir;
             const double Tf = (double)a.T2[o.at(kT2, 1)];
             double pd, cs2;
-            eos(a.ph, (double)rho, Tf, pd, cs2);
+            eos<fast_fp64<T>()>(a.ph, (double)rho, Tf, pd, cs2);
             // model 2: p_alpha and its sound speed (ap = 0 for model 1)
             const T p = T(pd + 0.5 * a.ph.ap * (double)rho * (double)rho);
-            const T cw = T(sqrt(fabs(cs2 + a.ph.ap * (double)rho)));
+            const T cw = sqrt_to<T>(fabs(cs2 + a.ph.ap * (double)rho));
             const T lam = fabs(un) + cw;
             // interior faces of model 2 store p_alpha, -F^V.n and the sound
             // speed; the HLLC flux is formed from both sides' traces later
@@ -1460,7 +1525,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     __shared__ T sN[NQ][NQF];
     T(*sS)[G::NF] = reinterpret_cast<T(*)[G::NF]>(sB);
     T(*sF2)[G::NV] = reinterpret_cast<T(*)[G::NV]>(sB);
-    __shared__ double sDh[P * P], sL[2 * P], sLh[2 * P];
+    __shared__ T sDh[P * P], sL[2 * P], sLh[2 * P];
     load_basis<P>(L.bas, sDh, sL, sLh);
     const int E = a.mesh.E;
     const int t = threadIdx.x;
@@ -1468,6 +1533,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     const int e = e0 + le;
     const bool act = t < G::NV && e < E;
     const size_t g = (size_t)e0 * G::n3 + t;
+    const uint32_t g32 = (uint32_t)g;
     const size_t NF = (size_t)E * 6 * G::n2;
     const T *TUr = a.TU + (size_t)L.tb * 6 * NF;
 
@@ -1484,7 +1550,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         r.nb = -1;
         if (el >= E) return;
         const FaceIx<G::n2> o((size_t)el * 6 + ft.f, ft.fp);
-        r.nb = a.mesh.nbr[el * 6 + ft.f];
+        r.nb = gld(a.mesh.nbr, el * 6 + ft.f);
 #pragma unroll
         for (int v = 0; v < 6; ++v) r.uo[v] = TUr[o.at(6, v)];
 #pragma unroll
@@ -1507,12 +1573,12 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     T iJn = T(0);
     if (act) {
         if constexpr (CV) iJn = stage_node_metrics<T, NJV>(a.mesh, a.NN, g, t, sJa);
-        s.rho = a.U[0 * a.NN + g];
-        s.m[0] = a.U[1 * a.NN + g];
-        s.m[1] = a.U[2 * a.NN + g];
-        s.m[2] = a.U[3 * a.NN + g];
-        s.E = a.U[4 * a.NN + g];
-        s.c = a.U[5 * a.NN + g];
+        s.rho = gld(a.U + (0) * a.NN, g32);
+        s.m[0] = gld(a.U + (1) * a.NN, g32);
+        s.m[1] = gld(a.U + (2) * a.NN, g32);
+        s.m[2] = gld(a.U + (3) * a.NN, g32);
+        s.E = gld(a.U + (4) * a.NN, g32);
+        s.c = gld(a.U + (5) * a.NN, g32);
         const T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
         T w[5];
         primitives(u6, w);
@@ -1529,8 +1595,13 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         if (el >= E) continue;
         Tr tr;
         if (kEarly) tr = tr0; else load_tr(task, tr);
-        T n[3], dS;
-        face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
+        // the surface element always; the normal where it is used (walls,
+        // model 2's HLLC, the lifting's n dS on curved elements)
+        T n[3] = {T(0), T(0), T(0)}, dS;
+        if (CV || tr.nb < 0 || a.ph.model == 2)
+            face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
+        else
+            dS = face_dS<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp);
         const int slot = ft.le * 6 * G::n2 + f * G::n2 + ft.fp;
         if constexpr (CV) {
 #pragma unroll
@@ -1582,8 +1653,8 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     const int base = le * G::n3;
     if (act) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) s.gT[m] = a.G2[m * a.NN + g];
-        s.lapc = a.G2[3 * a.NN + g];
+        for (int m = 0; m < 3; ++m) s.gT[m] = gld(a.G2 + (m) * a.NN, g32);
+        s.lapc = gld(a.G2 + (3) * a.NN, g32);
         T grho[3];
         if constexpr (CV) {
             T q[5][3];
@@ -1607,12 +1678,12 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
             for (int jj = 0; jj < 3; ++jj) to_physical(Ja, iJ, gd[1 + jj], s.gu[jj]);
             to_physical(Ja, iJ, gd[4], s.gc);
         }
-        // the temperature is held in the element type, as every stored field
-        const double Tn = (double)T(temperature(a.ph, (double)s.rho, (double)s.m[0], (double)s.m[1], (double)s.m[2],
-                                                (double)s.E, (double)s.c, (double)s.gc[0], (double)s.gc[1],
-                                                (double)s.gc[2]));
+        // the temperature stays FP64 through the pressure in both precisions
+        const double Tn = temperature<fast_fp64<T>()>(a.ph, (double)s.rho, (double)s.m[0], (double)s.m[1],
+                                                      (double)s.m[2], (double)s.E, (double)s.c, (double)s.gc[0],
+                                                      (double)s.gc[1], (double)s.gc[2]);
         double pd, cs2;
-        eos(a.ph, (double)s.rho, Tn, pd, cs2);
+        eos<fast_fp64<T>()>(a.ph, (double)s.rho, Tn, pd, cs2);
         s.p = T(pd + 0.5 * a.ph.ap * (double)s.rho * (double)s.rho);  // p_alpha for model 2
         s.ir = T(1) / s.rho;
         source(a.ph, s, grho, S);
@@ -1629,10 +1700,10 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
             Jd[1] = sJa[3 * d + 1][t];
             Jd[2] = sJa[3 * d + 2][t];
         } else {
-            const double *em = a.mesh.emet + (size_t)e * 10 + 3 * d;
-            Jd[0] = T(em[0]);
-            Jd[1] = T(em[1]);
-            Jd[2] = T(em[2]);
+            const uint32_t eq = (uint32_t)e * 10 + 3 * d;
+            Jd[0] = T(gld(a.mesh.emet, eq));
+            Jd[1] = T(gld(a.mesh.emet, eq + 1));
+            Jd[2] = T(gld(a.mesh.emet, eq + 2));
         }
 #pragma unroll
         for (int v = 0; v < 6; ++v) buf[v][t] = Jd[0] * Fx[v][0] + Jd[1] * Fx[v][1] + Jd[2] * Fx[v][2];
@@ -1679,7 +1750,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     if (L.mode == 0) {
         if (act) {
 #pragma unroll
-            for (int v = 0; v < 6; ++v) a.Ut[v * a.NN + g] = Ut[v];
+            for (int v = 0; v < 6; ++v) gst(a.Ut + (v) * a.NN, g32, T(Ut[v]));
         }
         return;
     }
@@ -1690,19 +1761,19 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            const T r = L.first ? dt * Ut[v] : A * a.R[v * a.NN + g] + dt * Ut[v];
-            a.R[v * a.NN + g] = r;
+            const T r = L.first ? dt * Ut[v] : A * gld(a.R + (v) * a.NN, g32) + dt * Ut[v];
+            gst(a.R + (v) * a.NN, g32, T(r));
             T u;
             if (a.Ck) {
                 // compensated summation: the low-order part lost by u6 + B r is
                 // kept in Ck and fed into the next stage's increment
-                const T y = B * r - a.Ck[v * a.NN + g];
+                const T y = B * r - gld(a.Ck + (v) * a.NN, g32);
                 u = u6[v] + y;
-                a.Ck[v * a.NN + g] = (u - u6[v]) - y;
+                gst(a.Ck + (v) * a.NN, g32, T((u - u6[v]) - y));
             } else {
                 u = u6[v] + B * r;
             }
-            a.U[v * a.NN + g] = u;
+            gst(a.U + (v) * a.NN, g32, T(u));
             sF[v][t] = u;
         }
     }

@@ -1195,6 +1195,15 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
                     return fail(c, NSKR_E_ARG, "wall velocity must be finite");
             }
         }
+    // the kernels address node- and element-indexed arrays with 32-bit byte
+    // offsets from a per-field base: every such array stays below 4 GiB
+    {
+        const double tsz = c->p.precision == 0 ? 8.0 : 4.0, nn = (double)E * n3;
+        const double worst = fmax(fmax(nn * 8.0, (double)E * 24 * 8), (double)E * 6 * n2 * 4 * tsz);
+        if (worst >= 4294967296.0)
+            return fail(c, NSKR_E_UNSUPPORTED, "mesh too large for one context (a node or face-point array exceeds "
+                                               "4 GiB); split it into several instances");
+    }
     // pass 1: every element's geometry at the degree-N Gauss-Lobatto points;
     // is it affine (a parallelepiped)? its corner and edge vectors, its size,
     // and the coordinates of its face points
