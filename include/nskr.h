@@ -272,14 +272,24 @@ int nskr_lift2(nskr_ctx *ctx, const void *U, void *out, nskr_stream s);
  * diffusivities of F^V, Sec. 2.3.2), nu_max = max(4 mu/(3 rho), kappa/(rho R
  * cv), gam beta); T_N and RHO_N are the 1D upwind-advection and BR1-diffusion
  * stability constants of the Gauss DGSEM under the RK scheme's stability
- * polynomial, 4.6567 its real stability interval.  Synchronises s.
+ * polynomial, 4.6567 its real stability interval.  A mesh with generalized
+ * Navier-slip walls of gamma_1 > 0 (eq. bc_navierstokes_alpha,
+ * eq. bc_contactangle_alpha) adds the wall limit CFL 3.3407 / max_nodes W
+ * over the nodes of elements with such a face: per face of direction n,
+ * W = SIGMA_N (Lambda a gamma_1 sum_d |grad c . Ja^d|/(J rho)
+ * + sqrt(alpha beta gamma_1 Lambda a sum_d (|Ja^d|/J)^2)), d the two other
+ * directions, a = |Ja^n|/J, Lambda = (N+1)^2/2, grad c the lifted gradient
+ * and SIGMA_N the spectral radius of the lifted first derivative; the
+ * traction gamma_1 div u grad_G c and the c-flux beta gamma_1 div u give
+ * eigenvalues near the imaginary axis, whose stability interval under the
+ * RK scheme is 3.3407.  Synchronises s.
  * Errors: NSKR_E_NONFINITE if a rate is not finite (dt not written). */
 int nskr_dt(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
 
 /* nskr_dt for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same time step, bit for bit, with the reduction's partial maxima and
- * results in a static device array of 3 MiB instead of the context's
+ * results in a static device array of 4 MiB instead of the context's
  * memory.  It calls no allocating routine; the traces and lifted gradients
  * it evaluates are the context's own, allocated at mesh upload.  Limit: a
  * mesh of at most 131072 element tiles of the 256-thread reduction kernel

@@ -1735,12 +1735,60 @@ static double rhoN(int N)
     return (N >= 2 && N <= 5) ? R[N] : 0.0;
 }
 #define RK_REAL 4.6567
+/* Wall limit (generalized Navier-slip walls with gamma_1 > 0): SIGMA_N is the
+ * spectral radius of the BR1 lifted first derivative on the reference element
+ * over the Bloch spectrum of the periodic Gauss DGSEM, RK_IMAG the stability
+ * interval of the scheme on the imaginary axis. */
+static double sigmaN(int N)
+{
+    static const double S[6] = {0, 0, 4.0406, 6.6385, 9.8386, 13.6629};
+    return (N >= 2 && N <= 5) ? S[N] : 0.0;
+}
+#define RK_IMAG 3.3407
+
+/* Stiffness of the gamma_1 terms of eq. bc_navierstokes_alpha and
+ * eq. bc_contactangle_alpha at one node of an element with Navier-slip wall
+ * faces.  Both enter through the surface lifting of the wall face (weight
+ * Lambda_N = sum_j l_j(-1)^2 / w_j = (N+1)^2/2 on Gauss nodes, times
+ * |Ja^n|/J of the face direction n) and act on the tangential derivatives
+ * of u (SIGMA_N |Ja^d|/J per tangential direction d):
+ *   traction gamma_1 div u grad_G c: a wall viscosity gamma_1 |grad_G c|/rho,
+ *     lambda_t = SIGMA_N Lambda_N (|Ja^n|/J) gamma_1 sum_d |grad c . Ja^d|/(J rho);
+ *   c-flux beta gamma_1 div u, closed through alpha grad c in the momentum
+ *     source: lambda_c = SIGMA_N sqrt(alpha beta gamma_1 Lambda_N (|Ja^n|/J)
+ *     sum_d (|Ja^d|/J)^2).
+ * Both eigenvalues lie near the imaginary axis.  Returns the sum over the
+ * element's Navier-slip faces of lambda_t + lambda_c. */
+static double wall_rate(const orc_ctx *c, int e, const double *Ja, double J, double rho, const double gc[3])
+{
+    const orc_params *pr = &c->pr;
+    double lam = 0.5 * (c->N + 1) * (c->N + 1), r = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        if (c->kind[e * 6 + f] != 3) continue;
+        double g1 = c->box.side_g1[c->side[e * 6 + f]];
+        if (!(g1 > 0.0)) continue;
+        int dn = f / 2;
+        const double *An = Ja + dn * 3;
+        double an = sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]) / J, st = 0.0, gt = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            if (d == dn) continue;
+            const double *A = Ja + d * 3;
+            double nd = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]) / J;
+            st += nd * nd;
+            gt += fabs(gc[0] * A[0] + gc[1] * A[1] + gc[2] * A[2]) / J;
+        }
+        r += sigmaN(c->N) * (lam * an * g1 * gt / rho + sqrt(pr->alpha * pr->beta * g1 * lam * an * st));
+    }
+    return r;
+}
 
 /* Time step: min of an advective limit CFL T_N 2 / max sum_d lambda^d with
- * lambda^d = (|u . Ja^d| + c~ |Ja^d|)/J, and a parabolic/source limit
+ * lambda^d = (|u . Ja^d| + c~ |Ja^d|)/J, a parabolic/source limit
  * CFL RK_REAL / (alpha beta + RHO_N nu_max max sum_d (|Ja^d|/(2J))^2), with
- * nu_max = max(4 mu/(3 rho), k/(rho R c_v), gamma beta).  Needs the
- * temperature, hence one lifting pass. */
+ * nu_max = max(4 mu/(3 rho), k/(rho R c_v), gamma beta), and a wall limit
+ * CFL RK_IMAG / max wall_rate on elements with Navier-slip walls of
+ * gamma_1 > 0.  Needs the temperature and the lifted grad c, hence one
+ * lifting pass. */
 double orc_dt(void *vc, const double *U)
 {
     orc_ctx *c = vc;
@@ -1750,7 +1798,7 @@ double orc_dt(void *vc, const double *U)
     step_prolong(c, U, &w);
     step_lift1(c, U, &w);
     size_t nn = (size_t)c->E * c->n3;
-    double lmax = 0.0, gmax = 0.0, nmax = 0.0;
+    double lmax = 0.0, gmax = 0.0, nmax = 0.0, wmax = 0.0;
     for (int e = 0; e < c->E; ++e)
         for (int nd = 0; nd < c->n3; ++nd) {
             size_t a = (size_t)e * c->n3 + nd;
@@ -1774,12 +1822,16 @@ double orc_dt(void *vc, const double *U)
             if (sl > lmax) lmax = sl;
             if (sg > gmax) gmax = sg;
             if (nu > nmax) nmax = nu;
+            double wr = wall_rate(c, e, c->Ja + a * 9, J, U6[0], qc);
+            if (wr > wmax) wmax = wr;
         }
     work_free(&w);
     double dt_adv = pr->cfl * tN(c->N) * 2.0 / lmax;
     double den = pr->alpha * pr->beta + rhoN(c->N) * nmax * gmax;
     double dt_par = den > 0.0 ? pr->cfl * RK_REAL / den : INFINITY;
-    return dt_adv < dt_par ? dt_adv : dt_par;
+    double dt_wall = wmax > 0.0 ? pr->cfl * RK_IMAG / wmax : INFINITY;
+    double dt = dt_adv < dt_par ? dt_adv : dt_par;
+    return dt < dt_wall ? dt : dt_wall;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -374,6 +374,11 @@ static const int kTraceBuf[6] = {0, 1, 0, 1, 2, 0};
 static const double kTN[6] = {0, 0, 0.3521, 0.2200, 0.1523, 0.1126};
 static const double kRhoN[6] = {0, 0, 64.8, 176.2, 387.0, 745.2};
 static const double kRkReal = 4.6567;
+// Wall limit of Navier-slip walls with gamma_1 > 0: spectral radius of the
+// BR1 lifted first derivative on the reference element (Bloch spectrum of
+// the periodic Gauss DGSEM), index N; stability interval on the imaginary axis.
+static const double kSigN[6] = {0, 0, 4.0406, 6.6385, 9.8386, 13.6629};
+static const double kRkImag = 3.3407;
 
 // ------------------------------------------------------------ extra kernels
 // Reduction operations: 0 sum, 1 min, 2 max.
@@ -393,17 +398,56 @@ __device__ __forceinline__ double wave_reduce(int kd, double v)
 
 struct RateArgs {
     MeshDev mesh; Phys ph; size_t NN; double *part; int nblk;
+    double sig;  // spectral radius of the lifted first derivative (wall limit)
 };
+
+// Number of time-step rates reduced by k_dt_rates: the advective rate, the
+// mesh factor, the diffusivity and the wall rate.
+constexpr int kNRates = 4;
+
+// Wall rate of one node of element e (gamma_1 terms of the generalized
+// Navier-slip condition, Sec. 2.4): for each Navier-slip face with gamma_1 > 0
+// and face direction n, with Lambda = (N+1)^2/2 the Gauss surface-lifting
+// weight, a = |Ja^n|/J and the tangential directions d,
+//   sig (Lambda a gamma_1 sum_d |grad c . Ja^d|/(J rho)
+//        + sqrt(alpha beta gamma_1 Lambda a sum_d (|Ja^d|/J)^2)),
+// the traction gamma_1 div u grad_G c acting as a wall viscosity, and the
+// c-flux beta gamma_1 div u closed through the alpha grad c source.
+template <int P>
+__device__ double wall_rate(const RateArgs &a, int e, const double *em, double rho, const double gc[3])
+{
+    const double lam = 0.5 * P * P, iJ = 1.0 / em[9];
+    double r = 0.0;
+    for (int f = 0; f < 6; ++f) {
+        const int b = a.mesh.bcid[(size_t)e * 6 + f];
+        if (!b) continue;
+        const BcDev &bc = a.mesh.bcs[b - 1];
+        if (bc.kind != 3 || !(bc.g1 > 0.0)) continue;
+        const int dn = f >> 1;
+        const double *An = em + 3 * dn;
+        const double an = sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]) * iJ;
+        double st = 0.0, gt = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            if (d == dn) continue;
+            const double *Ad = em + 3 * d;
+            const double nd = sqrt(Ad[0] * Ad[0] + Ad[1] * Ad[1] + Ad[2] * Ad[2]) * iJ;
+            st += nd * nd;
+            gt += fabs(gc[0] * Ad[0] + gc[1] * Ad[1] + gc[2] * Ad[2]) * iJ;
+        }
+        r += a.sig * (lam * an * bc.g1 * gt / rho + sqrt(a.ph.alpha * a.ph.beta * bc.g1 * lam * an * st));
+    }
+    return r;
+}
 
 template <int P, typename T, bool CV>
 __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, RateArgs a)
 {
     using G = Tile<P>;
-    __shared__ double sr[3][kBlock / 64];
+    __shared__ double sr[kNRates][kBlock / 64];
     const int t = threadIdx.x;
     const int e0 = blockIdx.x * G::EPB, le = t / G::n3, e = e0 + le;
     const size_t g = (size_t)e0 * G::n3 + t;
-    double r0 = 0, r1 = 0, r2 = 0;
+    double r0 = 0, r1 = 0, r2 = 0, r3 = 0;
     if (t < G::NV && e < a.mesh.E) {
         double rho = U[g], m0 = U[a.NN + g], m1 = U[2 * a.NN + g], m2 = U[3 * a.NN + g];
         double E = U[4 * a.NN + g], c = U[5 * a.NN + g];
@@ -427,17 +471,21 @@ __global__ __launch_bounds__(kBlock) void k_dt_rates(const T *U, const T *Q, Rat
             r1 += h * h;
         }
         r2 = fmax(fmax(4.0 * a.ph.mu / (3.0 * rho), a.ph.kappa / (rho * a.ph.R * a.ph.cv)), a.ph.gam * a.ph.beta);
-        if (!isfinite(r0) || !isfinite(r2)) r0 = r2 = INFINITY;
+        if (a.mesh.dyn) {
+            const double gc[3] = {(double)Q[12 * a.NN + g], (double)Q[13 * a.NN + g], (double)Q[14 * a.NN + g]};
+            r3 = wall_rate<P>(a, e, em, rho, gc);
+        }
+        if (!isfinite(r0) || !isfinite(r2) || !isfinite(r3)) r0 = r2 = INFINITY;
     }
-    const double rv[3] = {r0, r1, r2};
+    const double rv[kNRates] = {r0, r1, r2, r3};
     const int w = t >> 6, lane = t & 63;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kNRates; ++k) {
         const double m = wave_reduce(2, rv[k]);
         if (lane == 0) sr[k][w] = m;
     }
     __syncthreads();
-    if (t < 3) {
+    if (t < kNRates) {
         double m = sr[t][0];
         for (int q = 1; q < kBlock / 64; ++q) m = fmax(m, sr[t][q]);
         a.part[(size_t)t * a.nblk + blockIdx.x] = m;
@@ -786,20 +834,20 @@ template <int P, typename T, int BS, bool CV> struct Impl {
         HIPCHK(c, hipMemcpyAsync((T *)o + c->NN, c->d_G2, sizeof(T) * 4 * c->NN, hipMemcpyDeviceToDevice, s));
         return NSKR_OK;
     }
-    // the largest wave speed, mesh factor and diffusivity over the nodes;
-    // part holds 3 partial maxima per tile, dout the 3 results (device)
-    static int dt(nskr_ctx *c, const void *U, double *out3, hipStream_t s, double *part, double *dout)
+    // the largest wave speed, mesh factor, diffusivity and wall rate over the
+    // nodes; part holds kNRates partial maxima per tile, dout the results (device)
+    static int dt(nskr_ctx *c, const void *U, double *rates, hipStream_t s, double *part, double *dout)
     {
         Launch<T> L = launch(c, inst(c, U, nullptr, nullptr, 0.0));
         L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
-        RateArgs a{mesh(c), c->ph, c->NN, part, nblk256(c)};
+        RateArgs a{mesh(c), c->ph, c->NN, part, nblk256(c), kSigN[P - 1]};
         hipLaunchKernelGGL((k_dt_rates<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a);
-        hipLaunchKernelGGL(k_max_final, dim3(3), dim3(kBlock), 0, s, (const double *)part, nblk256(c), dout);
+        hipLaunchKernelGGL(k_max_final, dim3(kNRates), dim3(kBlock), 0, s, (const double *)part, nblk256(c), dout);
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipMemcpyAsync(out3, dout, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(rates, dout, kNRates * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         return NSKR_OK;
     }
@@ -809,7 +857,7 @@ template <int P, typename T, int BS, bool CV> struct Impl {
         L.full = 1;  // every lifted gradient and the nodal temperature
         prolong(c, L, s);
         lift1(c, L, s);
-        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c)};
+        RateArgs a{mesh(c), c->ph, c->NN, c->d_part, nblk256(c), 0.0};
         hipLaunchKernelGGL((k_integrals<P, T, CV>), dim3(nblk256(c)), dim3(kBlock), 0, s, (const T *)U,
                            (const T *)c->d_Q, a, c->bas);
         hipLaunchKernelGGL(k_integrals_final, dim3(NSKR_NSUMS), dim3(kBlock), 0, s, (const double *)c->d_part,
@@ -881,13 +929,13 @@ static int elem_per_block(int N)
 }
 
 // Reduction scratch of nskr_dt_noalloc, for callers that cannot allocate:
-// 3 partial maxima per element tile of the 256-thread reduction kernel, then
-// the 3 results.  Each device holds its own copy for the life of the
+// kNRates partial maxima per element tile of the 256-thread reduction kernel,
+// then the kNRates results.  Each device holds its own copy for the life of the
 // process; its address on each device is looked up once, at the first
 // nskr_create on that device, and only that address is handed to kernels.
 // Every partial is written before it is read, so nothing needs clearing.
 constexpr int kStaticTiles = 131072;
-static __device__ __align__(256) double scratch[3 * kStaticTiles + 3];
+static __device__ __align__(256) double scratch[kNRates * (kStaticTiles + 1)];
 
 constexpr int kMaxDevices = 64;
 static std::mutex g_scratch_mtx;
@@ -1694,15 +1742,16 @@ int nskr_lift2(nskr_ctx *c, const void *U, void *o, nskr_stream sv)
     return dispatch(c, [&](auto impl) { return decltype(impl)::lift2_out(c, U, o, (hipStream_t)sv); });
 }
 
-// dt from the three maxima (advective rate, mesh factor, diffusivity)
-static int dt_from_rates(nskr_ctx *c, const double r[3], double *dt)
+// dt from the maxima (advective rate, mesh factor, diffusivity, wall rate)
+static int dt_from_rates(nskr_ctx *c, const double r[kNRates], double *dt)
 {
-    if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !(r[0] > 0))
+    if (!isfinite(r[0]) || !isfinite(r[1]) || !isfinite(r[2]) || !isfinite(r[3]) || !(r[0] > 0))
         return fail(c, NSKR_E_NONFINITE, "non-finite wave speed or diffusivity");
     const double dt_adv = c->p.cfl * kTN[c->N] * 2.0 / r[0];
     const double den = c->p.alpha * c->p.beta + kRhoN[c->N] * r[2] * r[1];
     const double dt_par = den > 0 ? c->p.cfl * kRkReal / den : INFINITY;
-    *dt = dt_adv < dt_par ? dt_adv : dt_par;
+    const double dt_wall = r[3] > 0 ? c->p.cfl * kRkImag / r[3] : INFINITY;
+    *dt = fmin(fmin(dt_adv, dt_par), dt_wall);
     return NSKR_OK;
 }
 
@@ -1712,7 +1761,7 @@ int nskr_dt(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
     if (rc) return rc;
     if (!U || !dt) return fail(c, NSKR_E_ARG, "null argument");
     DeviceGuard guard(c->device);
-    double r[3];
+    double r[kNRates];
     rc = dispatch(c, [&](auto impl) { return decltype(impl)::dt(c, U, r, (hipStream_t)sv, c->d_part, c->d_out); });
     if (rc) return rc;
     return dt_from_rates(c, r, dt);
@@ -1730,9 +1779,9 @@ int nskr_dt_noalloc(nskr_ctx *c, const void *U, double *dt, nskr_stream sv)
     double *ptr = static_scratch(c->device);
     if (!ptr) return fail(c, NSKR_E_STATE, "static reduction scratch not set up on this device");
     DeviceGuard guard(c->device);
-    double r[3];
+    double r[kNRates];
     rc = dispatch(c, [&](auto impl) {
-        return decltype(impl)::dt(c, U, r, (hipStream_t)sv, ptr, ptr + 3 * (size_t)kStaticTiles);
+        return decltype(impl)::dt(c, U, r, (hipStream_t)sv, ptr, ptr + kNRates * (size_t)kStaticTiles);
     });
     if (rc) return rc;
     return dt_from_rates(c, r, dt);

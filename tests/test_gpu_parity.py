@@ -100,8 +100,8 @@ def small_cases():
         wl.c5(scale=10),                                                 # moving droplets, 5^3, N=3
         wl.c6(scale=10),                                                 # Navier-slip floor, moving lid
         # Navier-slip walls with every coefficient and a heat-transfer
-        # condition on both sides, the top one moving (gamma_1 = 0.5 is
-        # stiff: RK runs of this case take 1/100 of the time step)
+        # condition on both sides, the top one moving (gamma_1 = 0.5: the
+        # wall limit of the time-step rule binds)
         wl.c4(scale=12).with_(
             name="navier_heat_4x4x2_N4", N=4, side_kind=(0, 0, 0, 0, wl.NAVIER, wl.NAVIER),
             side_twall=(0.0, 0.0, 0.0, 0.0, 0.9, 0.88), side_theta=(90.0, 90.0, 90.0, 90.0, 60.0, 120.0),
@@ -126,6 +126,7 @@ def small_cases():
             side_kind=(wl.NOSLIP_CA, wl.SLIP, wl.NAVIER, wl.NOSLIP_CA, wl.NOSLIP_CA, wl.SLIP),
             side_twall=(0.9, 0.0, 0.88, 0.87, 0.9, 0.0), side_theta=(60.0, 90.0, 110.0, 90.0, 60.0, 90.0),
             side_gamma=(wl.NO_GAMMA,) * 2 + ((0.0, 0.05, 0.02, 0.0),) + (wl.NO_GAMMA,) * 3),
+        wl.c6(scale=10, gamma1=20.0),                                    # the printed gamma_1 = 20
     ]
 
 
@@ -218,7 +219,8 @@ def test_init_parity(torch_cuda, w):
         assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 3, 8, 9, 13, 15)], ids=[IDS[k] for k in (0, 5, 3, 8, 9, 13, 15)])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 3, 8, 9, 10, 13, 15, 16)],
+                         ids=[IDS[k] for k in (0, 5, 3, 8, 9, 10, 13, 15, 16)])
 def test_dt_parity(torch_cuda, w):
     torch = torch_cuda
     print(f"[case] dt {w.name}", flush=True)
@@ -248,19 +250,16 @@ def test_reduce_parity(torch_cuda, w):
             assert abs(rg[k] - ro[k]) <= 1e-13 * scale[k] + 1e-300, (k, rg[k], ro[k])
 
 
-@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 4, 8, 9, 10, 11, 12, 13, 14, 15)],
-                         ids=[IDS[k] for k in (0, 5, 4, 8, 9, 10, 11, 12, 13, 14, 15)])
+@pytest.mark.parametrize("w", [CASES[k] for k in (0, 5, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16)],
+                         ids=[IDS[k] for k in (0, 5, 4, 8, 9, 10, 11, 12, 13, 14, 15, 16)])
 def test_rk_steps_parity(torch_cuda, w):
-    """Fixed number of RK steps with the oracle's step-0 dt on both sides
-    (1/100 of it where the dynamic contact angle is on)."""
+    """Fixed number of RK steps with the oracle's step-0 dt on both sides."""
     torch = torch_cuda
     nsteps = 20 if w.name.startswith("droplet") else 10
     print(f"[case] rk {w.name} steps={nsteps}", flush=True)
     o = oracle_for(w)
     U = oracle_init(o, w)
     dt = o.dt(U)
-    if w.side_gamma and any(g[0] > 0 for g in w.side_gamma):
-        dt /= 100
     s = gpu_solver(w)
     Ug = to_gpu(torch, U)
     Rg = s.new_state()
@@ -382,7 +381,7 @@ def test_model_out_of_range_rejected(torch_cuda):
         gpu_solver(CASES[0].with_(params=dict(CASES[0].params, model=3)))
 
 
-FULL = [("c2", 2), ("c3", 1), ("c4", 1), ("c5", 1), ("c5_model2", 1), ("c6", 1), ("c7", 1)]
+FULL = [("c2", 2), ("c3", 1), ("c4", 1), ("c5", 1), ("c5_model2", 1), ("c6", 1), ("c6_gamma1_20", 1), ("c7", 1)]
 
 
 @pytest.mark.parametrize("which,steps", FULL, ids=[f"{w}_{n}steps" for w, n in FULL])
@@ -392,12 +391,13 @@ def test_full_size_workload_parity(torch_cuda, which, steps):
     nodes), the 48x48x24 N=3 wall box (3.54M nodes) and the 50^3 N=3 head-on
     collision (8M nodes, moving droplets; with relaxation model 1 and 2) and
     the 100x50x25 N=3 sliding droplet (8M nodes, Navier-slip floor and a
-    moving lid) and the wall box with a graded floor temperature (table
+    moving lid; also with the printed gamma_1 = 20, where the wall limit
+    sets the step) and the wall box with a graded floor temperature (table
     lookups on the floor).  GPU initial state,
     time step and RK steps against the oracle's, on every node."""
     torch = torch_cuda
     w = {"c2": wl.c2, "c3": wl.c3, "c4": wl.c4, "c5": wl.c5, "c5_model2": lambda: model2(wl.c5()),
-         "c6": wl.c6, "c7": wl.c7}[which]()
+         "c6": wl.c6, "c6_gamma1_20": lambda: wl.c6(gamma1=20.0), "c7": wl.c7}[which]()
     print(f"[case] full-size {w.name}, {steps} step(s)", flush=True)
     from paper_2208_05310_amd.nskr import init_workload
     s = gpu_solver(w)

@@ -17,6 +17,20 @@ low-storage RK scheme:
 
 Each is recovered from the oracle's time step on a uniform state at rest
 where one limit alone binds, and compared.
+
+The wall limit of generalized Navier-slip walls with gamma_1 > 0 (the
+traction gamma_1 div u grad_G c and the c-flux beta gamma_1 div u of the
+wall conditions, Sec. 2.4) is pinned the same way:
+
+* I: the stability interval of the scheme on the imaginary axis;
+* SIGMA_N: the spectral radius of the BR1 lifted first derivative (central
+  face values) on the reference element over the Bloch spectrum;
+* Lambda_N = sum_j l_j(-1)^2 / w_j, the weight of the wall face's lifting;
+* with alpha = 0 and c linear along the wall only the traction path acts:
+  SIGMA_N Lambda_N / I is recovered; with c = rho only the c-flux path acts:
+  SIGMA_N sqrt(Lambda_N) / I is recovered;
+* end to end: the sliding droplet with the printed gamma_1 = 20 on a coarse
+  mesh stays bounded at the rule's step and blows up at 2.5 times it.
 """
 import numpy as np
 import pytest
@@ -140,3 +154,102 @@ def test_parabolic_constant(N, rk_interval):
     nu = 4 * mu / (3 * rho)
     rhon = CFL * rk_interval * h * h / (3 * nu * dt)
     assert abs(rhon / rho16 - 1) <= 1e-3, (N, rhon, rho16)
+
+
+def imaginary_interval(g):
+    lo, hi = 1.0, 6.0
+    for _ in range(50):
+        mid = 0.5 * (lo + hi)
+        ok = np.max(np.abs(R(1j * np.linspace(0.0, mid, 20001), g))) <= 1 + 1e-12
+        lo, hi = (mid, hi) if ok else (lo, mid)
+    return lo
+
+
+def lifted_derivative_radius(N):
+    """Spectral radius over Bloch wavenumbers of the BR1 lifted first
+    derivative on the reference element [-1, 1]."""
+    w, D, lm, lp = gauss_dg(N)
+    Dt = np.diag(1 / w) @ D.T @ np.diag(w)
+    best = 0.0
+    for th in np.linspace(0, 2 * np.pi, 1441):
+        e = np.exp(1j * th)
+        usR, usL = 0.5 * (lp + e * lm), 0.5 * (lp / e + lm)
+        G = -Dt + np.outer(lp / w, usR) - np.outer(lm / w, usL)
+        best = max(best, np.max(np.abs(np.linalg.eigvals(G))))
+    return best
+
+
+def wall_box(N, G, **pk):
+    """Unit cube of 2^3 elements (h = 1/2), periodic in y, slip walls at x,
+    isothermal Navier-slip walls with gamma_1 = G at z."""
+    p = oracle.make_params(cfl=CFL, mu=0.0, kappa=0.0, **pk)
+    b = oracle.make_box(N, (2, 2, 2), periodic=(0, 1, 0), side_kind=(2, 2, 0, 0, 3, 3),
+                        side_twall=(0, 0, 0, 0, 0.9, 0.9), side_g1=(0, 0, 0, 0, G, G))
+    return oracle.Oracle(p, b)
+
+
+def test_imaginary_stability_interval():
+    i = imaginary_interval(stability_poly())
+    assert 3.3407 <= i < 3.3408, i
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_wall_constant_of_the_traction_path(N):
+    # alpha = 0 removes the c-flux path; c = rho + s x is linear, so its lifted
+    # gradient is (s, 0, 0) exactly (slip walls at x take c* = c-): per wall
+    # node W = SIGMA_N Lambda_N (2/h) gamma_1 s (2/h) / rho
+    G, s, rho, h = 10.0, 0.2, 0.3, 0.5
+    o = wall_box(N, G, alpha=0.0, beta=1.0)
+    U = uniform_state(o, rho, 0.9)
+    x = o.coords()[0]
+    U[5] = rho + s * x
+    dt = o.dt(U)
+    w, _, lm, _ = gauss_dg(N)
+    lam = np.sum(lm ** 2 / w)
+    assert abs(lam - (N + 1) ** 2 / 2) <= 1e-12
+    want = lifted_derivative_radius(N) * lam / imaginary_interval(stability_poly())
+    got = CFL * rho / (dt * (2 / h) ** 2 * G * s)
+    assert abs(got / want - 1) <= 2e-4, (N, got, want)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_wall_constant_of_the_c_flux_path(N):
+    # c = rho: no tangential grad c, so only the c-flux path is left:
+    # W = SIGMA_N sqrt(alpha beta gamma_1 Lambda_N (2/h) 2 (2/h)^2)
+    G, al, be, h = 50.0, 2.0, 3.0, 0.5
+    o = wall_box(N, G, alpha=al, beta=be)
+    dt = o.dt(uniform_state(o, 0.3, 0.9))
+    w, _, lm, _ = gauss_dg(N)
+    lam = np.sum(lm ** 2 / w)
+    want = lifted_derivative_radius(N) * np.sqrt(lam) / imaginary_interval(stability_poly())
+    got = CFL / (dt * np.sqrt(al * be * G * (2 / h) * 2 * (2 / h) ** 2))
+    assert abs(got / want - 1) <= 2e-4, (N, got, want)
+
+
+def test_wall_limit_off_without_gamma_1():
+    # gamma_1 = 0 on the Navier-slip walls: the same step as slip walls
+    p = oracle.make_params(cfl=CFL, mu=0.0, kappa=0.0, alpha=1.0, beta=1.0)
+    slip = oracle.Oracle(p, oracle.make_box(3, (2, 2, 2), periodic=(0, 1, 0), side_kind=(2,) * 6))
+    o = wall_box(3, 0.0, alpha=1.0, beta=1.0)
+    U = uniform_state(o, 0.3, 0.9)
+    U[5] += 0.2 * o.coords()[0]
+    assert o.dt(U) == slip.dt(U)
+    assert wall_box(3, 1.0, alpha=1.0, beta=1.0).dt(U) < o.dt(U)
+
+
+def test_sliding_droplet_at_the_printed_gamma_1_is_stable_at_the_rule_step():
+    from helpers import oracle_for, oracle_init
+    from paper_2208_05310_amd import workloads as wl
+    w = wl.c6(scale=10, gamma1=20.0)
+    o = oracle_for(w)
+    U0 = oracle_init(o, w)
+    dt = o.dt(U0)
+    U, Rg = U0.copy(), np.zeros_like(U0)
+    for _ in range(4):
+        o.run(U, Rg, 0.0, dt, 50)
+        assert np.all(np.isfinite(U))
+        assert np.max(np.abs(U[1:4] / U[0])) < 0.05
+    U, Rg = U0.copy(), np.zeros_like(U0)
+    with np.errstate(all="ignore"):
+        o.run(U, Rg, 0.0, 2.5 * dt, 50)
+        assert not np.all(np.isfinite(U)) or np.max(np.abs(U[1:4] / U[0])) > 1.0

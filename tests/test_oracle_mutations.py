@@ -252,6 +252,24 @@ MUTATIONS = [
      "out[v] = (1.0 - w) * tab[3 * k + v] + w * tab[3 * (k + 1) + v];",
      "out[v] = w * tab[3 * k + v] + (1.0 - w) * tab[3 * (k + 1) + v];",
      ["tests/test_oracle_wall_table.py::test_interpolation_error_bound"]),
+    ("wall time-step limit: traction path divided by the wrong direction's |Ja|",
+     "r += sigmaN(c->N) * (lam * an * g1 * gt / rho",
+     "r += sigmaN(c->N) * (lam * sqrt(st) * g1 * gt / rho",
+     ["tests/test_oracle_dt.py::test_wall_constant_of_the_traction_path"]),
+    ("wall time-step limit: c-flux path without beta",
+     "sqrt(pr->alpha * pr->beta * g1 * lam * an * st)", "sqrt(pr->alpha * g1 * lam * an * st)",
+     ["tests/test_oracle_dt.py::test_wall_constant_of_the_c_flux_path"]),
+    ("wall time-step limit: normal direction counted as tangential",
+     "            if (d == dn) continue;\n            const double *A = Ja + d * 3;",
+     "            const double *A = Ja + d * 3;",
+     ["tests/test_oracle_dt.py::test_wall_constant_of_the_c_flux_path"]),
+    ("wall time-step limit: the real instead of the imaginary interval",
+     "double dt_wall = wmax > 0.0 ? pr->cfl * RK_IMAG / wmax : INFINITY;",
+     "double dt_wall = wmax > 0.0 ? pr->cfl * RK_REAL / wmax : INFINITY;",
+     ["tests/test_oracle_dt.py::test_wall_constant_of_the_traction_path"]),
+    ("wall time-step limit: left out of the minimum",
+     "return dt < dt_wall ? dt : dt_wall;", "return dt;",
+     ["tests/test_oracle_dt.py::test_sliding_droplet_at_the_printed_gamma_1_is_stable_at_the_rule_step"]),
 ]
 
 
