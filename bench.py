@@ -26,15 +26,19 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_words_per_node(N):
+def kernel_words_per_node(N, curved=False, fp32=False):
     """Algorithmic words per volume node for each kernel of one stage: every
     array the kernel reads or writes, each element counted once (a face trace
     that an element and its neighbour both read counts once); F = 6/(N+1)
     face points per node. Wall face points also carry grad c in the T2 trace
     (3 words written by lift1, read by lift2 on Navier-slip walls), not
-    counted: under 0.1 % of a stage on the wall workloads."""
+    counted: under 0.1 % of a stage on the wall workloads.  Curved meshes:
+    each stage kernel also reads the node metrics (9 Ja + J) and the face
+    points' normal and surface element (4 per face point).  FP32 instances
+    carry the face temperature's rounding error as a third T2 field (written
+    by lift1, read by lift2 on the own face)."""
     F = 6.0 / (N + 1)
-    return {
+    k = {
         "prolong": 6 + 6 * F,             # U in; conserved traces out
         "lift1": 6 + 3 * F,               # U, neighbour c traces in; grad c . n + T traces (2) out
         "lift2": 10 + 15 * F,             # U, conserved traces (own and neighbour: 6), grad c . n + T traces (2)
@@ -42,10 +46,17 @@ def kernel_words_per_node(N):
         "update": 28 + 19 * F,            # U, R, grad T + lap c, neighbour conserved traces (6), flux traces (7)
                                           # in; U, R, conserved traces (6) out
     }
+    if fp32:
+        k["lift1"] += F
+        k["lift2"] += F
+    if curved:
+        for name in ("lift1", "lift2", "update"):
+            k[name] += 10 + 4 * F
+    return k
 
 
-def stage_words_per_node(N):
-    k = kernel_words_per_node(N)
+def stage_words_per_node(N, curved=False, fp32=False):
+    k = kernel_words_per_node(N, curved, fp32)
     return k["lift1"] + k["lift2"] + k["update"]
 
 
@@ -175,6 +186,8 @@ def serving_bench(nreq=256, budget_gb=32.0, sequential=True, log=None, max_activ
     if log:
         log(f"serving batched: p50 {stats['p50_s']:.2f} s, p99 {stats['p99_s']:.2f} s")
     out = {"batched_fp32_mixed": stats, "tiles": {k: v["threads"] for k, v in table.items()},
+           "tile_ms_per_step": {k: v["ms_per_step"] for k, v in table.items()},
+           "tiles_bitwise_equal": all(v.get("bitwise_equal", False) for v in table.values()),
            "autotune_s": t_tune, "budget_GiB": budget_gb}
     if sequential:
         seq, _ = serving.serve_sequential(reqs, "fp64")
@@ -484,8 +497,9 @@ def main():
                          "c6: sliding droplet, 200 steps)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
-    ap.add_argument("--threads", type=int, default=256, choices=[256, 512],
-                    help="workgroup size of the stage kernels")
+    ap.add_argument("--threads", type=int, default=256, choices=[128, 192, 256, 448, 512],
+                    help="workgroup size of the stage kernels: 256, 512 or the degree's tight size "
+                         "(N=2: 192, N=3 and 4: 128, N=5: 448)")
     ap.add_argument("--young-laplace", type=float, default=None, metavar="THETA",
                     help="static contact-angle validation: liquid pillar with this angle (degrees) to --t-end, "
                          "pressure jump against the Young-Laplace law")
@@ -495,6 +509,9 @@ def main():
     ap.add_argument("--sliding-scale", type=int, default=4, help="mesh coarsening of the sliding droplet")
     ap.add_argument("--sliding-t-end", type=float, default=0.1)
     ap.add_argument("--pillar-mesh", default="50,50,10", help="elements of the pillar box (x,y,z)")
+    ap.add_argument("--curve-amp", type=float, default=0.0,
+                    help="curve the workload's mesh by this amplitude of the sine map (per-node metrics)")
+    ap.add_argument("--ngeo", type=int, default=0, help="geometry degree of a curved mesh (0: N)")
     ap.add_argument("--model", type=int, default=1, choices=[1, 2],
                     help="relaxation model: 1 (Rusanov interior flux) or 2 (p_alpha pressure, HLLC flux)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -546,6 +563,9 @@ def main():
          "c7": wl.c7}[args.workload]()
     if args.model == 2:
         w = w.with_(name=f"{w.name}_model2", params=dict(w.params, model=2))
+    if args.curve_amp != 0.0:
+        w = w.with_(name=f"{w.name}_curved{args.curve_amp:g}_ngeo{args.ngeo or w.N}", curve_amp=args.curve_amp,
+                    ngeo=args.ngeo)
     stream = torch.cuda.current_stream()
 
     def timed_run(wk, precision, U0, dtk):
@@ -574,7 +594,7 @@ def main():
         prof = s.profile(stream)
         s.set_profiling(False)
         word = 8 if precision == "fp64" else 4
-        words = kernel_words_per_node(wk.N)
+        words = kernel_words_per_node(wk.N, wk.curve_amp != 0.0, precision == "fp32_mixed")
         if precision == "fp32_mixed" and s.kahan:
             words["update"] += 12  # compensation of the state update, read and written
         kern = {}
@@ -605,7 +625,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
     ach = kern[dom]["achieved_GBs"]
     floor_b, b3 = three_phase_bytes_model(w.N, word)
-    stage_b = (stage_words_per_node(w.N) + (12 if args.precision == "fp32_mixed" else 0)) * word
+    stage_b = (stage_words_per_node(w.N, w.curve_amp != 0.0, args.precision == "fp32_mixed") +
+               (12 if args.precision == "fp32_mixed" else 0)) * word
     out = {
         "metric": METRIC,
         "value": value,
@@ -665,7 +686,7 @@ def main():
                          "frac": k32[d32]["achieved_GBs"] / PEAK_HBM_GBS},
             "kernels": k32}
         del r32, a, b_
-        if not args.no_accuracy and args.workload in RESTRICTIONS and args.model == 1:
+        if not args.no_accuracy and args.workload in RESTRICTIONS and args.model == 1 and args.curve_amp == 0.0:
             # the whole run of the workload (C3: 500 steps) in both forms from
             # the same state and dt, and on the small restriction for the oracle
             acc, restr_gpu = precision_runs(args.workload)
@@ -680,7 +701,7 @@ def main():
                 "detail": full}
             progress(f"{w.name} fp32_mixed over {acc['steps']} steps: rho rel max err vs FP64 "
                      f"{full['fp32_vs_fp64']['rho_rel_max']:.2e}")
-    if not args.no_c2 and args.workload != "c2" and args.model == 1:
+    if not args.no_c2 and args.workload != "c2" and args.model == 1 and args.curve_amp == 0.0:
         # the 16^3 N=4 throughput case beside the headline
         w2 = wl.c2()
         U2, dt2 = initial(w2, "fp64")
@@ -709,6 +730,8 @@ def main():
                               "one_at_a_time_fp64": {k: sq.get(k) for k in ("p50_s", "p99_s",
                                                                              "node_stage_updates_per_s")},
                               "throughput_speedup": res.get("speedup_throughput"), "tiles": res["tiles"],
+                              "tile_ms_per_step": res["tile_ms_per_step"],
+                              "tiles_bitwise_equal": res["tiles_bitwise_equal"],
                               "max_active_nodes": args.serving_max_nodes}
         except Exception as e:  # reported, never hides the main measurement
             out["serving"] = {"error": repr(e)}

@@ -329,12 +329,15 @@ int nskr_reduce(nskr_ctx *ctx, const void *U, double *out, nskr_stream s);
 int nskr_set_profiling(nskr_ctx *ctx, int on);
 int nskr_profile(nskr_ctx *ctx, double *ms, long *count, nskr_stream s);
 
-/* Threads per workgroup of the stage kernels (256 or 512; a block must hold
- * at least one element): the tile shape the autotuner chooses.  Results do not
+/* Threads per workgroup of the stage kernels: 256, 512, or the degree's
+ * tight size that packs whole elements into waves (N = 2: 192, N = 3 and 4:
+ * 128, N = 5: 448); a block must hold at least one element.  This is the tile
+ * shape (elements per workgroup) the autotuner chooses.  Results do not
  * depend on it (every element's arithmetic is the same in any tile).  A mesh
  * with curved elements runs 256 threads (its upload sets 256).
- * Errors: NSKR_E_ARG for other values; NSKR_E_UNSUPPORTED for 512 on a mesh
- * with curved elements or where the kernels exceed the LDS per workgroup. */
+ * Errors: NSKR_E_ARG for other values; NSKR_E_UNSUPPORTED for another size on
+ * a mesh with curved elements or where the kernels exceed the LDS per
+ * workgroup. */
 int nskr_set_block(nskr_ctx *ctx, int threads);
 int nskr_get_block(const nskr_ctx *ctx, int *threads);
 

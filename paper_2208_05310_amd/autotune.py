@@ -1,7 +1,12 @@
-"""Tile-shape autotuner: picks the stage kernels' workgroup size (256 or 512
-threads, i.e. how many elements share a workgroup) per (degree, precision) by
-timing a few RK steps of a droplet workload on the device.  Results do not
-depend on the choice; only speed does.  The table is kept in a JSON file."""
+"""Tile-shape autotuner: picks the stage kernels' workgroup size per (degree,
+precision), i.e. how many elements share a workgroup and how tightly they fill
+its waves, among the sizes the library builds for that degree (256, 512 and a
+tight size: N = 2 192, N = 3 and 4 128, N = 5 448).  Each candidate runs a few
+RK steps of a droplet workload at the mesh sizes the request stream draws,
+from the same initial state; the fastest total wins.  The tuner also records
+whether every candidate ended in bitwise the same state (an element's
+arithmetic does not depend on its tile).  The table can be kept in a JSON
+file."""
 from __future__ import annotations
 
 import json
@@ -12,34 +17,55 @@ from .nskr import NskrError, init_workload, solver_for
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "nskr_tiles.json")
 
+# the serving stream's smallest-but-one and largest element grids
+DEFAULT_SIZES = ((8, 8, 8), (16, 16, 16))
+
+
+def block_sizes(N):
+    """Workgroup sizes the library builds for degree N."""
+    tight = {2: 192, 3: 128, 4: 128, 5: 448}[N]
+    return tuple(sorted({256, 512, tight}))
+
 
 def _key(N, precision):
     return f"N{N}_{precision}"
 
 
-def tune_one(N, precision, n=(8, 8, 8), steps=3, candidates=(256, 512)):
+def tune_one(N, precision, sizes=DEFAULT_SIZES, steps=3, candidates=None):
+    """Time `steps` RK steps per candidate workgroup size on each mesh size;
+    returns (best, {size: total ms per step}, bitwise_equal)."""
     import torch
-    w = wl.Workload(name=f"tune_N{N}", N=N, n=n, steps=steps)
-    s = solver_for(w, precision)
-    U = init_workload(s, w)
-    R = s.new_state()
-    dt = s.dt(U)
-    stream = torch.cuda.current_stream()
+    candidates = candidates or block_sizes(N)
     times = {}
-    for bs in candidates:
-        try:
-            s.set_block(bs)
-        except NskrError:
-            continue
-        s.rk_steps(U, R, dt, 1, stream)  # warm-up
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        s.rk_steps(U, R, dt, steps, stream)
-        b.record(stream)
-        torch.cuda.synchronize()
-        times[bs] = a.elapsed_time(b) / steps
+    equal = True
+    stream = torch.cuda.current_stream()
+    for n in sizes:
+        w = wl.Workload(name=f"tune_N{N}_{n[0]}x{n[1]}x{n[2]}", N=N, n=n, steps=steps)
+        s = solver_for(w, precision)
+        U0 = init_workload(s, w)
+        dt = s.dt(U0)
+        ref = None
+        for bs in candidates:
+            try:
+                s.set_block(bs)
+            except NskrError:
+                continue
+            U = U0.clone()
+            R = s.new_state()
+            s.rk_steps(U, R, dt, 1, stream)  # warm-up
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            s.rk_steps(U, R, dt, steps, stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times[bs] = times.get(bs, 0.0) + a.elapsed_time(b) / steps
+            if ref is None:
+                ref = U
+            elif not torch.equal(ref, U):
+                equal = False
+        del s
     best = min(times, key=times.get)
-    return best, times
+    return best, times, equal
 
 
 def load(path=DEFAULT_CACHE):
@@ -52,15 +78,16 @@ def load(path=DEFAULT_CACHE):
         return {}
 
 
-def tune(pairs, path=DEFAULT_CACHE, n=(8, 8, 8), steps=3, force=False):
+def tune(pairs, path=DEFAULT_CACHE, sizes=DEFAULT_SIZES, steps=3, force=False):
     """Tile table for the (N, precision) pairs, tuning the ones not cached."""
     table = {} if force else load(path)
     changed = False
     for N, prec in pairs:
         k = _key(N, prec)
         if k not in table:
-            best, times = tune_one(N, prec, n, steps)
-            table[k] = {"threads": best, "ms_per_step": times}
+            best, times, equal = tune_one(N, prec, sizes, steps)
+            table[k] = {"threads": best, "ms_per_step": times, "bitwise_equal": equal,
+                        "sizes": [list(n) for n in sizes]}
             changed = True
     if changed and path:
         try:

@@ -15,6 +15,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # packed FP32 instructions are disabled for all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fused multiply-adds only where one source expression multiplies and
+    # adds: every kernel instance (tile size, batched or not) then rounds
+    # the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-result",
 ]
 

@@ -358,7 +358,7 @@ template <typename T> struct Inst {
     T *Ck;                     // compensation of the state update (FP32 Kahan), or null
     T *Q, *TH;                 // grad(rho,u,c) [15] and T, for the API outputs only
     T *G2;                     // grad T + lap c [4]
-    T *T2, *TF, *TU;           // face traces: grad c . n and T (+ grad c on walls) [kT2],
+    T *T2, *TF, *TU;           // face traces: grad c . n and T (+ grad c on walls) [kT2<T>()],
                                // flux + wave speed [7],
                                // conserved state [3 buffers][6]; within an array
                                // (a buffer) face-major: [face][field][point]
@@ -407,7 +407,12 @@ __device__ __forceinline__ double stage_time(double t0, int n, double dt, double
 // (the tangential gradient of a Navier-slip wall). Interior faces need only
 // the first two: the divergence lifting of grad c takes the central normal
 // component, and the neighbour's outward normal is minus the own one.
-constexpr int kT2 = 5;
+// FP32 instances store the FP64 face temperature as two floats, the rounded
+// value (the BR1 face value of the FP32 lifting) and the rounding error in
+// the field after it, so that the pressure and sound speed at the face are
+// formed from the temperature as recovered in FP64 (about 48 bits).
+template <typename T> constexpr int kT2() { return sizeof(T) == 4 ? 6 : 5; }
+template <typename T> constexpr int kT2gc() { return sizeof(T) == 4 ? 3 : 2; }  // first wall grad c field
 
 template <int N2> struct FaceIx {
     size_t face;
@@ -782,16 +787,17 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 // Lifted grad c, and the own-face traces of grad c and of the face
 // temperature.  FULL: also every lifted gradient and the nodal temperature
 // (Q, TH) for the API outputs.
-// FP32 per-stage instances on affine elements are latency-bound and keep at
-// least 7 waves per SIMD, which their register demand allows without spills
-// (8 does not).
-template <typename T, bool FULL, bool CV> constexpr int lift1_waves()
+// FP32 per-stage instances on affine elements in 256-thread workgroups are
+// latency-bound and keep at least 7 waves per SIMD, which their register
+// demand allows without spills (8 does not; neither does 7 in 448-thread
+// workgroups).
+template <typename T, int BS, bool FULL, bool CV> constexpr int lift1_waves()
 {
-    return (sizeof(T) == 4 && !FULL && !CV) ? 7 : 1;
+    return (sizeof(T) == 4 && BS == 256 && !FULL && !CV) ? 7 : 1;
 }
 
 template <int P, typename T, int BS, bool BATCH, bool FULL = false, bool CV = false>
-__global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Launch<T> L)
+__global__ __launch_bounds__(BS, (lift1_waves<T, BS, FULL, CV>())) void k_lift1(Launch<T> L)
 {
     using G = Tile<P, BS>;
     Inst<T> a;
@@ -988,8 +994,10 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
                                           (double)qf[s][2]);
             const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
             const T gn = qf[s][0] * nf[s][0] + qf[s][1] * nf[s][1] + qf[s][2] * nf[s][2];
-            a.T2[o.at(kT2, 0)] = gn;
-            a.T2[o.at(kT2, 1)] = Tf;
+            a.T2[o.at(kT2<T>(), 0)] = gn;
+            const T Th = T(Tf);
+            a.T2[o.at(kT2<T>(), 1)] = Th;
+            if constexpr (sizeof(T) == 4) a.T2[o.at(kT2<T>(), 2)] = T(Tf - (double)Th);
         }
         // wall faces also keep the vector grad c (Navier-slip traction), in
         // a loop of its own: inside the one above the branch costs ~40 VGPRs
@@ -997,9 +1005,9 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, FULL, CV>())) void k_lift1(Laun
         for (int s = 0; s < 2; ++s)
             if ((s ? nbp : nbm) < 0) {
                 const FaceIx<G::n2> o((size_t)el * 6 + 2 * lt.d + s, lt.fp);
-                a.T2[o.at(kT2, 2)] = qf[s][0];
-                a.T2[o.at(kT2, 3)] = qf[s][1];
-                a.T2[o.at(kT2, 4)] = qf[s][2];
+                a.T2[o.at(kT2<T>(), kT2gc<T>())] = qf[s][0];
+                a.T2[o.at(kT2<T>(), kT2gc<T>() + 1)] = qf[s][1];
+                a.T2[o.at(kT2<T>(), kT2gc<T>() + 2)] = qf[s][2];
             }
     }
 }
@@ -1053,7 +1061,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         if (el >= E) return;
         const FaceIx<G::n2> o((size_t)el * 6 + ft.f, ft.fp);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) r.own[k] = a.T2[o.at(kT2, k)];
+        for (int k = 0; k < 2; ++k) r.own[k] = a.T2[o.at(kT2<T>(), k)];
 #pragma unroll
         for (int v = 0; v < 6; ++v)
             if (v != 4) r.uo[v] = TU[o.at(6, v)];
@@ -1061,7 +1069,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         if (r.nb >= 0) {
             const FaceIx<G::n2> on(nbr_face<P>(r.nb), nbr_point<P>(r.nb, ft.fp));
 #pragma unroll
-            for (int k = 0; k < 2; ++k) r.oth[k] = a.T2[on.at(kT2, k)];
+            for (int k = 0; k < 2; ++k) r.oth[k] = a.T2[on.at(kT2<T>(), k)];
 #pragma unroll
             for (int v = 0; v < 6; ++v)
                 if (v != 4) r.wn[v] = TU[on.at(6, v)];
@@ -1355,7 +1363,9 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
             const T mn = m0 * n0 + m1 * n1 + m2 * n2;
             const T un = mn * ir;
-            const double Tf = (double)a.T2[o.at(kT2, 1)];
+            // the face temperature as recovered in FP64 (FP32: value + rounding error)
+            double Tf = (double)a.T2[o.at(kT2<T>(), 1)];
+            if constexpr (sizeof(T) == 4) Tf += (double)a.T2[o.at(kT2<T>(), 2)];
             double pd, cs2;
             eos<fast_fp64<T>()>(a.ph, (double)rho, Tf, pd, cs2);
             // model 2: p_alpha and its sound speed (ap = 0 for model 1)
@@ -1444,7 +1454,8 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
                     // Navier slip: tangential traction gamma_1 div u grad_G c -
                     // gamma_2 (u_t - u_w,t), and its work on u_t
                     const BcDev &bc = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1];
-                    const T gc0 = a.T2[o.at(kT2, 2)], gc1 = a.T2[o.at(kT2, 3)], gc2 = a.T2[o.at(kT2, 4)];
+                    const T gc0 = a.T2[o.at(kT2<T>(), kT2gc<T>())], gc1 = a.T2[o.at(kT2<T>(), kT2gc<T>() + 1)],
+                            gc2 = a.T2[o.at(kT2<T>(), kT2gc<T>() + 2)];
                     const T gcn = gc0 * n0 + gc1 * n1 + gc2 * n2;
                     const T w0 = T(bc.uw[0]), w1 = T(bc.uw[1]), w2 = T(bc.uw[2]);
                     const T wn = w0 * n0 + w1 * n1 + w2 * n2;
@@ -1478,7 +1489,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // order-parameter terms of j_e and F^V_c
             __builtin_amdgcn_sched_barrier(0);
             if (!wall) {
-                const T gcn = a.T2[o.at(kT2, 0)];
+                const T gcn = a.T2[o.at(kT2<T>(), 0)];
                 const T lapc = pro(sTs);
                 const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;

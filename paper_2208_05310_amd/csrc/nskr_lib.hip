@@ -882,36 +882,48 @@ template <int P, typename T, int BS, bool CV> struct Impl {
     }
 };
 
-// Valid block sizes per degree: the block must hold at least one element and
-// one line task per thread.
+// Workgroup sizes built for each degree: 256 and 512 threads, and one size
+// that packs whole elements into waves more tightly than 256 does (N = 2:
+// 7 elements of 27 nodes in 192 threads; N = 3, 4: one wave pair, 2 and 1
+// elements; N = 5: 2 elements of 216 nodes in 448 threads, against 1 in 256).
+static int tight_block(int N) { return N == 2 ? 192 : (N == 5 ? 448 : 128); }
+
+// Valid block sizes per degree: one of the built sizes, holding at least one
+// element and one line task per thread.
 static bool block_ok(int N, int bs)
 {
     const int P = N + 1, n3 = P * P * P;
-    if (bs != 256 && bs != 512) return false;
+    if (N < 2 || N > 5) return false;
+    if (bs != 256 && bs != 512 && bs != tight_block(N)) return false;
     const int epb = bs / n3;
     return epb >= 1 && epb * 3 * P * P <= bs;
 }
 
+template <int PP, int BS, typename F> static int impl_prec(bool dbl, F &&f)
+{
+    return dbl ? f(Impl<PP, double, BS, false>()) : f(Impl<PP, float, BS, false>());
+}
+
 // The kernel instance set of a (degree, precision, block size, curved) choice.
 // Curved meshes run 256-thread workgroups only (their per-node metrics do
-// not fit the LDS of 512-thread tiles at every degree).
+// not fit the LDS of larger tiles at every degree).
 template <typename F> static int impl_dispatch(int N, int prec, int bs, bool curved, F &&f)
 {
     const bool dbl = prec == 0;
-    const bool big = bs == 512;
-#define NSKR_CASE(NN, PP)                                                                               \
+#define NSKR_CASE(NN, PP, TB)                                                                           \
     case NN:                                                                                            \
         if (curved) {                                                                                   \
-            if (big) return NSKR_E_UNSUPPORTED;                                                         \
+            if (bs != 256) return NSKR_E_UNSUPPORTED;                                                   \
             return dbl ? f(Impl<PP, double, 256, true>()) : f(Impl<PP, float, 256, true>());            \
         }                                                                                               \
-        if (dbl) return big ? f(Impl<PP, double, 512, false>()) : f(Impl<PP, double, 256, false>());     \
-        return big ? f(Impl<PP, float, 512, false>()) : f(Impl<PP, float, 256, false>());
+        if (bs == 512) return impl_prec<PP, 512>(dbl, f);                                               \
+        if (bs == TB) return impl_prec<PP, TB>(dbl, f);                                                 \
+        return impl_prec<PP, 256>(dbl, f);
     switch (N) {
-        NSKR_CASE(2, 3)
-        NSKR_CASE(3, 4)
-        NSKR_CASE(4, 5)
-        NSKR_CASE(5, 6)
+        NSKR_CASE(2, 3, 192)
+        NSKR_CASE(3, 4, 128)
+        NSKR_CASE(4, 5, 128)
+        NSKR_CASE(5, 6, 448)
     }
 #undef NSKR_CASE
     return NSKR_E_ARG;
@@ -1570,7 +1582,7 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
         (curved && (rc = dalloc(c, (void **)&c->d_xnode, sizeof(double) * xnode.size()))) ||
         (rc = dalloc(c, (void **)&c->d_bcs, sizeof(BcDev) * bcs.size())) ||
         (rc = dalloc(c, &c->d_Q, ts * 15 * c->NN)) || (rc = dalloc(c, &c->d_TH, ts * c->NN)) ||
-        (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * kT2 * c->NF)) ||
+        (rc = dalloc(c, &c->d_G2, ts * 4 * c->NN)) || (rc = dalloc(c, &c->d_T2, ts * (ts == 4 ? kT2<float>() : kT2<double>()) * c->NF)) ||
         (rc = dalloc(c, &c->d_TF, ts * 7 * c->NF)) || (rc = dalloc(c, &c->d_TU, ts * 3 * 6 * c->NF)) ||
         (rc = dalloc(c, (void **)&c->d_part, sizeof(double) * NSKR_NSUMS * (size_t)nblk)) ||
         (rc = dalloc(c, (void **)&c->d_out, sizeof(double) * NSKR_NSUMS)) ||
@@ -1814,7 +1826,9 @@ int nskr_reduce(nskr_ctx *c, const void *U, double *out, nskr_stream sv)
 int nskr_set_block(nskr_ctx *c, int threads)
 {
     if (!c) return NSKR_E_ARG;
-    if (!block_ok(c->N, threads)) return fail(c, NSKR_E_ARG, "block size must be 256 or 512 and hold an element");
+    if (!block_ok(c->N, threads))
+        return fail(c, NSKR_E_ARG, "block size must be 256, 512 or the degree's tight size (N=2: 192, N=3, 4: 128, "
+                                   "N=5: 448) and hold an element");
     if (c->curved && threads != 256) return fail(c, NSKR_E_UNSUPPORTED, "meshes with curved elements run 256 threads");
     DeviceGuard guard(c->device);
     int maxlds = 0;
