@@ -1050,9 +1050,18 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     // traces are loaded before the node loads: both sides' conserved state
     // (rho, m, c; the own side's is the prolongation of the state, written by
     // the previous stage) and both sides' grad c and T
+    // The own side's traces of the first round's face point (the whole
+    // conserved state and (grad c) . n, T; in FP32 also T's rounding error)
+    // stay in registers from this load to the flux pass at the end, instead
+    // of being read again from memory there, where they mostly miss the L2
+    // (where the block has more face points than threads, the second
+    // round's are read again).  FP32 instances keep them only where one
+    // round covers the block: with two rounds the registers cost a wave per
+    // SIMD, which measured slower than the re-read.
+    constexpr bool kKeep = sizeof(T) == 8 || G::NF <= BS;
     struct Tr {
         int nb;
-        T own[2], oth[2], wn[6], uo[6];
+        T own[3], oth[2], wn[6], uo[6];
     };
     auto load_tr = [&](int task, Tr &r) {
         const FaceTask<P> ft(task);
@@ -1062,9 +1071,10 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         const FaceIx<G::n2> o((size_t)el * 6 + ft.f, ft.fp);
 #pragma unroll
         for (int k = 0; k < 2; ++k) r.own[k] = a.T2[o.at(kT2<T>(), k)];
+        if constexpr (kKeep && sizeof(T) == 4) r.own[2] = a.T2[o.at(kT2<T>(), 2)];
 #pragma unroll
         for (int v = 0; v < 6; ++v)
-            if (v != 4) r.uo[v] = TU[o.at(6, v)];
+            if (v != 4 || kKeep) r.uo[v] = TU[o.at(6, v)];
         r.nb = gld(a.mesh.nbr, el * 6 + ft.f);
         if (r.nb >= 0) {
             const FaceIx<G::n2> on(nbr_face<P>(r.nb), nbr_point<P>(r.nb, ft.fp));
@@ -1356,16 +1366,26 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // scheduling barriers keep each field group's LDS loads next to the
             // arithmetic that consumes them (otherwise all of them are hoisted
             // and the register demand limits occupancy)
-            const T rho = TU[o.at(6, 0)], m0 = TU[o.at(6, 1)], m1 = TU[o.at(6, 2)], m2 = TU[o.at(6, 3)];
-            const T E = TU[o.at(6, 4)], c = TU[o.at(6, 5)];
+            T rho, m0, m1, m2, E, c, gcn;
+            double Tf;
+            if (kKeep && task == t) {
+                rho = tr0.uo[0]; m0 = tr0.uo[1]; m1 = tr0.uo[2]; m2 = tr0.uo[3]; E = tr0.uo[4]; c = tr0.uo[5];
+                gcn = tr0.own[0];
+                Tf = (double)tr0.own[1];
+                if constexpr (sizeof(T) == 4) Tf += (double)tr0.own[2];
+            } else {
+                rho = TU[o.at(6, 0)]; m0 = TU[o.at(6, 1)]; m1 = TU[o.at(6, 2)]; m2 = TU[o.at(6, 3)];
+                E = TU[o.at(6, 4)]; c = TU[o.at(6, 5)];
+                gcn = a.T2[o.at(kT2<T>(), 0)];
+                // the face temperature as recovered in FP64 (FP32: value + rounding error)
+                Tf = (double)a.T2[o.at(kT2<T>(), 1)];
+                if constexpr (sizeof(T) == 4) Tf += (double)a.T2[o.at(kT2<T>(), 2)];
+            }
             __builtin_amdgcn_sched_barrier(0);
             const T ir = T(1) / rho;
             const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
             const T mn = m0 * n0 + m1 * n1 + m2 * n2;
             const T un = mn * ir;
-            // the face temperature as recovered in FP64 (FP32: value + rounding error)
-            double Tf = (double)a.T2[o.at(kT2<T>(), 1)];
-            if constexpr (sizeof(T) == 4) Tf += (double)a.T2[o.at(kT2<T>(), 2)];
             double pd, cs2;
             eos<fast_fp64<T>()>(a.ph, (double)rho, Tf, pd, cs2);
             // model 2: p_alpha and its sound speed (ap = 0 for model 1)
@@ -1489,7 +1509,6 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             // order-parameter terms of j_e and F^V_c
             __builtin_amdgcn_sched_barrier(0);
             if (!wall) {
-                const T gcn = a.T2[o.at(kT2<T>(), 0)];
                 const T lapc = pro(sTs);
                 const T zeta = T(a.ph.beta) * (T(a.ph.gam) * lapc + T(a.ph.alpha) * (rho - c));
                 G4 -= -T(a.ph.gam) * c * gcn * div + T(a.ph.gam) * gcn * zeta;

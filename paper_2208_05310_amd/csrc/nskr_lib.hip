@@ -1272,7 +1272,47 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
     lobatto_host(c->N, xl);
     std::vector<double> egeo((size_t)E * 12), fpos((size_t)E * 6 * n2 * 3), escale(E);
     bool curved = false;
-    for (int e = 0; e < E; ++e) {
+    // The common case first: elements given by their 8 corners that are all
+    // parallelepipeds.  Corner, edge vectors and face points then follow from
+    // the corners in FP64 (the map is affine), without interpolating the
+    // geometry; any other element sends the whole mesh through the general
+    // pass below.  (A trilinear map deviates most from the affine one at the
+    // corners, so the corner test is the general pass's test.)
+    bool affine_corners = ng == 1;
+    for (int e = 0; e < E && affine_corners; ++e) {
+        const double *v = m->xgeo + (size_t)e * 24;
+        for (int q = 0; q < 24; ++q)
+            if (!std::isfinite(v[q])) return fail(c, NSKR_E_ARG, "non-finite geometry node");
+        double a[3][3], scale = 0;
+        for (int mm = 0; mm < 3; ++mm) {
+            a[0][mm] = v[3 + mm] - v[mm];
+            a[1][mm] = v[6 + mm] - v[mm];
+            a[2][mm] = v[12 + mm] - v[mm];
+            for (int d = 0; d < 3; ++d) scale = fmax(scale, fabs(a[d][mm]));
+        }
+        if (!(scale > 0)) return fail(c, NSKR_E_ARG, "element " + std::to_string(e) + " is degenerate");
+        for (int cn = 0; cn < 8 && affine_corners; ++cn)
+            for (int mm = 0; mm < 3; ++mm) {
+                const double lin = v[mm] + (cn & 1) * a[0][mm] + ((cn >> 1) & 1) * a[1][mm] + (cn >> 2) * a[2][mm];
+                if (fabs(lin - v[3 * cn + mm]) > 1e-12 * scale) affine_corners = false;
+            }
+        escale[e] = scale;
+        for (int mm = 0; mm < 3; ++mm) egeo[(size_t)e * 12 + mm] = v[mm];
+        for (int d = 0; d < 3; ++d)
+            for (int mm = 0; mm < 3; ++mm) egeo[(size_t)e * 12 + 3 + 3 * d + mm] = a[d][mm];
+        for (int f = 0; f < 6; ++f) {
+            const int d = f >> 1;
+            const double xn = (f & 1) ? 1.0 : -1.0;
+            for (int fp = 0; fp < n2; ++fp) {
+                const double xa = c->bas.x[fp % P], xb = c->bas.x[fp / P];
+                const double r[3] = {d == 0 ? xn : xa, d == 1 ? xn : (d == 0 ? xa : xb), d == 2 ? xn : xb};
+                for (int mm = 0; mm < 3; ++mm)
+                    fpos[(((size_t)e * 6 + f) * n2 + fp) * 3 + mm] =
+                        v[mm] + 0.5 * ((r[0] + 1.0) * a[0][mm] + (r[1] + 1.0) * a[1][mm] + (r[2] + 1.0) * a[2][mm]);
+            }
+        }
+    }
+    for (int e = 0; e < E && !affine_corners; ++e) {
         const double *xe = m->xgeo + (size_t)e * g3 * 3;
         for (int q = 0; q < 3 * g3; ++q)
             if (!std::isfinite(xe[q])) return fail(c, NSKR_E_ARG, "non-finite geometry node");
