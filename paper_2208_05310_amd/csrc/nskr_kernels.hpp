@@ -378,6 +378,7 @@ template <typename T> struct Launch {
     Inst<T> one;
     const Inst<T> *tab;
     const int *blk_inst, *blk_e0;
+    const int *blk_map;  // single instance: first element of every block (null: block b, elements b EPB..)
     Basis bas;
     int mode;        // update: 0 write U_t; 1 RK stage (update U, R, write traces)
     int first;       // RK: assign R at the first stage
@@ -448,7 +449,7 @@ __device__ __forceinline__ void instance_of(const Launch<T> &L, Inst<T> &a, int 
         a = load_const(L.tab, k);
     } else {
         a = L.one;
-        e0 = blockIdx.x * epb;
+        e0 = L.blk_map ? load_const(L.blk_map, blockIdx.x) : blockIdx.x * epb;
     }
 }
 
@@ -523,16 +524,13 @@ template <int P> struct FaceTask {
 
 template <int P, int BS> __device__ __forceinline__ constexpr int n_lines() { return Tile<P, BS>::EPB * 3 * P * P; }
 
-// Line task of thread t, or -1.  Every wave (on its own SIMD) gets an equal,
-// contiguous chunk of lines, so the heavy face phases use all SIMDs of the
-// workgroup and each wave's trace accesses stay contiguous.
+// Line task of thread t, or -1.  The lines fill the first waves of the
+// workgroup lane by lane, so waves without lines issue no instructions for
+// the line phases (at N = 5, 108 lines take two waves, not 27 lanes in each
+// of four: lift1 9-10 % faster on the 32^3 case in both precisions).
 template <int P, int BS> __device__ __forceinline__ int line_of_thread(int t)
 {
-    constexpr int W = BS / 64;
-    constexpr int C = (n_lines<P, BS>() + W - 1) / W;
-    const int w = t >> 6, l = t & 63;
-    const int task = w * C + l;
-    return (l < C && task < n_lines<P, BS>()) ? task : -1;
+    return t < n_lines<P, BS>() ? t : -1;
 }
 
 // ------------------------------------------------------------ shared pieces

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <map>
 #include <mutex>
@@ -51,6 +52,9 @@ struct nskr_ctx {
     double *d_out = nullptr;     // final reduction values (device)
     double *d_noise = nullptr;   // init noise
     double *d_drop = nullptr;    // init droplets
+    std::vector<float> cent;     // element centroids (host), for the block order
+    int *d_bmap = nullptr;       // first element of every stage-kernel block, in XCD order
+    int bmap_bs = 0;             // block size d_bmap was built for
     size_t bytes = 0;
     Basis bas;
     Phys ph;
@@ -706,6 +710,7 @@ template <int P, typename T, int BS, bool CV> struct Impl {
         L.one = I;
         L.bas = c->bas;
         L.t = c->time;
+        L.blk_map = c->d_bmap;
         return L;
     }
     // every stage kernel's static LDS fits the device's per-block limit
@@ -938,6 +943,69 @@ static int elem_per_block(int N)
 {
     const int n3 = (N + 1) * (N + 1) * (N + 1);
     return kBlock / n3;
+}
+
+// Order of the stage kernels' blocks across the XCDs.  Workgroups go to the
+// 8 XCDs round robin (block b to XCD b mod 8), each with its own L2, and an
+// element's face traces are read by its own block and by its neighbours'.
+// The groups of elements that share a block are split into 8 slabs of equal
+// count along the longest extent of the mesh (by their centroids), slab k
+// going to the blocks b = k mod 8 in the elements' own order, so most
+// neighbours of an element are processed on the same XCD at about the same
+// time and read its traces from that L2.  Concurrent XCDs still work on
+// nearby addresses (neighbouring slabs at the same position in their own
+// order).
+constexpr int kXcds = 8;
+
+static int build_block_map(nskr_ctx *c)
+{
+    const int epb = c->bs / ((c->N + 1) * (c->N + 1) * (c->N + 1));
+    const int E = c->E, G = (E + epb - 1) / epb;
+    std::vector<double> gc((size_t)G * 3, 0.0);
+    for (int e = 0; e < E; ++e)
+        for (int m = 0; m < 3; ++m) gc[(size_t)(e / epb) * 3 + m] += c->cent[(size_t)e * 3 + m];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int g = 0; g < G; ++g) {
+        const int n = std::min(epb, E - g * epb);
+        for (int m = 0; m < 3; ++m) {
+            gc[(size_t)g * 3 + m] /= n;
+            lo[m] = std::min(lo[m], gc[(size_t)g * 3 + m]);
+            hi[m] = std::max(hi[m], gc[(size_t)g * 3 + m]);
+        }
+    }
+    int ax = 0;
+    for (int m = 1; m < 3; ++m)
+        if (hi[m] - lo[m] > (hi[ax] - lo[ax]) * (1 + 1e-12)) ax = m;
+    std::vector<int> by(G);
+    for (int g = 0; g < G; ++g) by[g] = g;
+    std::stable_sort(by.begin(), by.end(), [&](int a, int b) { return gc[(size_t)a * 3 + ax] < gc[(size_t)b * 3 + ax]; });
+    // slab k holds q + (k < r) groups; within a slab the groups keep their order
+    const int q = G / kXcds, r = G % kXcds;
+    std::vector<int> map(G);
+    int start = 0;
+    for (int k = 0; k < kXcds; ++k) {
+        const int cnt = q + (k < r ? 1 : 0);
+        std::vector<int> slab(by.begin() + start, by.begin() + start + cnt);
+        std::sort(slab.begin(), slab.end());
+        for (int j = 0; j < cnt; ++j) map[(size_t)j * kXcds + k] = slab[j] * epb;
+        start += cnt;
+    }
+    // every group exactly once
+    std::vector<char> seen(G, 0);
+    for (int b = 0; b < G; ++b) {
+        const int g = map[b] / epb;
+        if (map[b] % epb != 0 || g < 0 || g >= G || seen[g]) return fail(c, NSKR_E_STATE, "block order is not a permutation");
+        seen[g] = 1;
+    }
+    if (c->d_bmap) {
+        (void)hipFree(c->d_bmap);
+        c->d_bmap = nullptr;
+        c->bmap_bs = 0;
+    }
+    HIPCHK(c, hipMalloc((void **)&c->d_bmap, sizeof(int) * (size_t)G));
+    HIPCHK(c, hipMemcpy(c->d_bmap, map.data(), sizeof(int) * (size_t)G, hipMemcpyHostToDevice));
+    c->bmap_bs = c->bs;
+    return NSKR_OK;
 }
 
 // Reduction scratch of nskr_dt_noalloc, for callers that cannot allocate:
@@ -1173,7 +1241,7 @@ static void free_mesh(nskr_ctx *c)
 {
     void *ptrs[] = {c->d_nbr, c->d_bcid, c->d_emet, c->d_fmet, c->d_egeo, c->d_bcs, c->d_Q, c->d_TH,
                     c->d_G2, c->d_T2, c->d_TF, c->d_TU, c->d_part, c->d_out, c->d_noise, c->d_drop, c->d_Ck,
-                    c->d_stab, c->d_clk, c->d_nmet, c->d_fnrm, c->d_xnode};
+                    c->d_stab, c->d_clk, c->d_nmet, c->d_fnrm, c->d_xnode, c->d_bmap};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     c->d_nbr = c->d_bcid = nullptr;
@@ -1186,6 +1254,9 @@ static void free_mesh(nskr_ctx *c)
     c->d_clk = nullptr;
     c->d_Q = c->d_TH = c->d_G2 = c->d_T2 = c->d_TF = c->d_TU = c->d_Ck = nullptr;
     c->d_part = c->d_out = c->d_noise = c->d_drop = nullptr;
+    c->d_bmap = nullptr;
+    c->bmap_bs = 0;
+    std::vector<float>().swap(c->cent);
     c->E = 0;
     c->NN = c->NF = 0;
     c->bytes = 0;
@@ -1653,7 +1724,13 @@ int nskr_mesh_upload(nskr_ctx *c, const nskr_mesh *m, nskr_stream sv)
     HIPCHK(c, hipMemcpy(c->d_egeo, egeo.data(), sizeof(double) * egeo.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_bcs, bcs.data(), sizeof(BcDev) * bcs.size(), hipMemcpyHostToDevice));
     if (tab) HIPCHK(c, hipMemcpy(c->d_stab, tab->data(), sizeof(double) * tab->size(), hipMemcpyHostToDevice));
-    return NSKR_OK;
+    c->cent.resize((size_t)E * 3);
+    for (int e = 0; e < E; ++e)
+        for (int mm = 0; mm < 3; ++mm) {
+            const double *g = &egeo[(size_t)e * 12];
+            c->cent[(size_t)e * 3 + mm] = (float)(g[mm] + 0.5 * (g[3 + mm] + g[6 + mm] + g[9 + mm]));
+        }
+    return build_block_map(c);
 }
 
 int nskr_state_size(const nskr_ctx *c, size_t *n)
@@ -1881,6 +1958,7 @@ int nskr_set_block(nskr_ctx *c, int threads)
         c->bs = old;
         return fail(c, NSKR_E_UNSUPPORTED, "kernels of this block size exceed the device's LDS per block");
     }
+    if (c->E > 0 && c->bmap_bs != c->bs) return build_block_map(c);
     return NSKR_OK;
 }
 
