@@ -323,6 +323,44 @@ def test_rk_split_equals_joined(torch_cuda):
     assert torch.equal(U1, U2)
 
 
+@pytest.mark.parametrize("case,prec", [(0, "fp64"), (0, "fp32_mixed"), ("timed", "fp64"), (9, "fp32_mixed")],
+                         ids=["droplet_fp64", "droplet_fp32_mixed", "timed_walls_fp64", "sliding_fp32_mixed"])
+def test_checkpoint_restart_in_a_new_context(torch_cuda, tmp_path, case, prec):
+    """A run stopped after 10 steps, its state and time written to disk, and
+    continued for 10 steps in a new context (new mesh upload) ends bit for bit
+    where the same 10 + 10 steps end in one context: between rk_steps calls
+    the state U and the context time are all there is (the register is
+    assigned at stage 1, face traces are rebuilt and the FP32 compensation is
+    cleared at the start of every call)."""
+    torch = torch_cuda
+    from paper_2208_05310_amd.nskr import init_workload
+    w = timed_wall_case() if case == "timed" else CASES[case]
+    print(f"[case] checkpoint {w.name} {prec}", flush=True)
+    s = gpu_solver(w, prec)
+    U = init_workload(s, w)
+    dt = s.dt(U)
+    U0 = U.clone()
+    R = s.new_state()
+    s.rk_steps(U, R, dt, 10)
+    s.rk_steps(U, R, dt, 10)
+    torch.cuda.synchronize()
+    # the interrupted run
+    s2 = gpu_solver(w, prec)
+    V, R2 = U0.clone(), s2.new_state()
+    s2.rk_steps(V, R2, dt, 10)
+    path = tmp_path / "checkpoint.npz"
+    np.savez(path, U=V.cpu().numpy(), t=np.float64(s2.get_time()))
+    del s2, V, R2
+    ck = np.load(path)
+    s3 = gpu_solver(w, prec)
+    s3.set_time(float(ck["t"]))
+    W = torch.tensor(ck["U"], device="cuda:0")
+    s3.rk_steps(W, s3.new_state(), dt, 10)
+    torch.cuda.synchronize()
+    assert s3.get_time() == s.get_time()
+    assert torch.equal(W, U)
+
+
 def model2(w, name=None):
     return w.with_(name=name or f"{w.name}_model2", params=dict(w.params, model=2))
 
