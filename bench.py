@@ -725,7 +725,8 @@ def main():
         try:
             res = serving_bench(args.serving_requests, max_active_nodes=args.serving_max_nodes, log=progress)
             bt, sq = res["batched_fp32_mixed"], res.get("one_at_a_time_fp64", {})
-            out["serving"] = {"requests": bt["requests"], "p50_s": bt["p50_s"], "p99_s": bt["p99_s"],
+            out["serving"] = {"requests": bt["requests"], "errors": bt["errors"], "p50_s": bt["p50_s"],
+                              "p99_s": bt["p99_s"],
                               "aggregate_node_stage_updates_per_s": bt["node_stage_updates_per_s"],
                               "one_at_a_time_fp64": {k: sq.get(k) for k in ("p50_s", "p99_s",
                                                                              "node_stage_updates_per_s")},

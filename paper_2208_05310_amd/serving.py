@@ -19,7 +19,7 @@ import time
 import numpy as np
 
 from . import autotune
-from .nskr import Batch, init_workload, solver_for
+from .nskr import Batch, NskrError, init_workload, solver_for
 
 
 class Request:
@@ -31,6 +31,7 @@ class Request:
         self.t_done = None
         self.result = None
         self.dt = None
+        self.status = None   # "ok", or the health check's error at retirement
 
 
 def _setup(req, precision, table, setup_stream):
@@ -97,6 +98,14 @@ def serve(requests, budget_bytes, precision="fp32_mixed", table=None, keep_resul
                     req = active.pop(slot)
                     solver, U, R = batch.retire(slot)
                     req.t_done = tnow
+                    # health of the finished state (non-finite values, density
+                    # outside (0, 1/b), T <= 0): an instance that failed is
+                    # reported, the others are unaffected
+                    try:
+                        solver.reduce(U, stream=step_stream)
+                        req.status = "ok"
+                    except NskrError as e:
+                        req.status = f"error {e.code}: {e}"
                     node_stages += solver.nnodes * 5 * req.w.steps
                     if keep_results:
                         req.result = U.double().cpu().numpy()
@@ -118,6 +127,7 @@ def serve(requests, budget_bytes, precision="fp32_mixed", table=None, keep_resul
         "max_active": max_active,
         "graph": graph,
         "max_active_nodes": max_active_nodes,
+        "errors": sum(1 for r in reqs if r.status != "ok"),
     }, reqs
 
 

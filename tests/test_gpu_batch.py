@@ -202,6 +202,7 @@ def test_serving_loop_small_stream(torch_cuda):
     stats, done = serving.serve(reqs, budget_bytes=1 << 32, precision="fp32_mixed", keep_results=True)
     print(stats, flush=True)
     assert stats["requests"] == 8 and all(r.t_done is not None for r in done)
+    assert stats["errors"] == 0 and all(r.status == "ok" for r in done)
     assert stats["p99_s"] >= stats["p50_s"] > 0
     stream = torch.cuda.Stream()
     for r in done[:4]:

@@ -6,6 +6,10 @@
 * Invalid arguments (non-positive dt, aliasing state and register, wrong
   buffer sizes, an instance admitted twice) are rejected before any launch,
   and the context stays usable afterwards.
+* The same steps twice give the same bits (races would show as run-to-run
+  differences); an unstable time step is caught by the health check within
+  a few steps; a poisoned instance of a batch fails its own health check
+  and leaves the other instances bitwise unchanged.
 """
 import numpy as np
 import pytest
@@ -120,3 +124,104 @@ def test_invalid_walls_are_rejected(torch_cuda):
                          side_uwall=v.side_uwall, side_gamma=v.side_gamma, side_tgrad=v.side_tgrad)
         if isinstance(ei.value, NskrError):
             assert ei.value.code == NSKR_E_ARG
+
+
+RUN_TWICE = [
+    (wl.c1(), "fp64"),
+    (wl.c4(scale=12).with_(name="wall_4x4x2_N4", N=4), "fp32_mixed"),
+    (wl.c1().with_(name="curved_3x3x3_N5", N=5, n=(3, 3, 3), curve_amp=0.04), "fp64"),
+    (wl.c6(scale=10), "fp64"),
+]
+
+
+@pytest.mark.parametrize("w,precision", RUN_TWICE, ids=[f"{w.name}_{p}" for w, p in RUN_TWICE])
+def test_run_twice_is_bitwise_identical(torch_cuda, w, precision):
+    """The same steps from the same state give the same bits: no kernel reads
+    LDS or memory that another thread may still be writing (a race shows as
+    run-to-run differences)."""
+    torch = torch_cuda
+    from paper_2208_05310_amd.nskr import init_workload, solver_for
+    print(f"[case] run twice {w.name} {precision}", flush=True)
+    s = solver_for(w, precision)
+    U = init_workload(s, w)
+    dt = s.dt(U)
+    outs = []
+    for _ in range(2):
+        V, R = U.clone(), s.new_state()
+        s.rk_steps(V, R, dt, 5)
+        outs.append(V)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_unstable_time_step_is_detected(torch_cuda):
+    """At 100 times the stable step the relaxation source blows up; the health
+    check reports it within a few steps."""
+    torch = torch_cuda
+    from paper_2208_05310_amd.nskr import NSKR_E_NONFINITE, NskrError
+    print("[case] 100 x dt", flush=True)
+    w, s, U = setup()
+    dt = 100.0 * s.dt(U)
+    R = s.new_state()
+    found = None
+    for k in range(1, 11):
+        s.rk_steps(U, R, dt, 1)
+        try:
+            s.reduce(U)
+        except NskrError as e:
+            assert e.code == NSKR_E_NONFINITE
+            found = k
+            break
+    print("detected after", found, "steps", flush=True)
+    assert found is not None
+    sums = s.reduce(U, check=False)
+    print("counters", sums[CNT_NONFINITE:CNT_T_NONPOS + 1], flush=True)
+    assert sums[CNT_NONFINITE] + sums[CNT_RHO_RANGE] + sums[CNT_T_NONPOS] >= 1
+    # nskr_dt refuses a state once its rates are not finite (a density above
+    # 1/b alone still gives finite rates)
+    if sums[CNT_NONFINITE] > 0:
+        with pytest.raises(NskrError):
+            s.dt(U)
+
+
+def test_poisoned_instance_leaves_the_others_of_a_batch_unchanged(torch_cuda):
+    """A NaN written into one instance's state between batch steps: that
+    instance's health check fails at the end, the other instances end bit for
+    bit as in the same batch without the poison."""
+    torch = torch_cuda
+    from paper_2208_05310_amd.nskr import NSKR_E_NONFINITE, Batch, NskrError, init_workload, solver_for
+    cases = [(wl.c1().with_(name="p_periodic_3x3x3_N3", n=(3, 3, 3)), "fp64"),
+             (wl.c4(scale=12).with_(name="p_wall_4x4x2_N4", N=4), "fp64"),
+             (wl.c1().with_(name="p_periodic_4x4x4_N2", N=2), "fp32_mixed")]
+    stream = torch.cuda.Stream()
+
+    def run(poison):
+        b = Batch(1 << 34)
+        held = []
+        for w, prec in cases:
+            s = solver_for(w, prec)
+            U = init_workload(s, w)
+            R = s.new_state()
+            dt = s.dt(U)
+            assert b.admit(s, U, R, dt, 6) is not None
+            held.append((s, U, R))
+        for k in range(6):
+            if poison and k == 2:
+                stream.synchronize()
+                held[1][1][0, 17] = float("nan")
+                torch.cuda.synchronize()
+            b.step(stream)
+        stream.synchronize()
+        assert sorted(b.poll()) == [0, 1, 2]
+        for slot in range(3):
+            b.retire(slot)
+        return held
+
+    print("[case] poisoned batch instance", flush=True)
+    clean, bad = run(False), run(True)
+    for k in (0, 2):
+        assert torch.equal(clean[k][1], bad[k][1]), cases[k][0].name
+        bad[k][0].reduce(bad[k][1])
+    with pytest.raises(NskrError) as ei:
+        bad[1][0].reduce(bad[1][1])
+    assert ei.value.code == NSKR_E_NONFINITE
