@@ -1717,6 +1717,17 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         source(a.ph, s, grho, S);
         flux_tensor(a.ph, s, Fx);
     }
+    // the RK register (and the compensation of an FP32 instance) of this
+    // node, requested now so that the loads complete during the volume
+    // integral
+    T Rn[6], Cn[6];
+    if (L.mode == 1 && act) {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            Rn[v] = L.first ? T(0) : gld(a.R + (v) * a.NN, g32);
+            if constexpr (sizeof(T) == 4) Cn[v] = a.Ck ? gld(a.Ck + (v) * a.NN, g32) : T(0);
+        }
+    }
     // volume integral sum_d Dhat_d (Ja^d . F): the contravariant fluxes of
     // direction d go to buffer d & 1, so direction d+1 is written while
     // direction d is read, one barrier per direction
@@ -1789,13 +1800,13 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
         T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            const T r = L.first ? dt * Ut[v] : A * gld(a.R + (v) * a.NN, g32) + dt * Ut[v];
+            const T r = L.first ? dt * Ut[v] : A * Rn[v] + dt * Ut[v];
             gst(a.R + (v) * a.NN, g32, T(r));
             T u;
-            if (a.Ck) {
+            if (sizeof(T) == 4 && a.Ck) {
                 // compensated summation: the low-order part lost by u6 + B r is
                 // kept in Ck and fed into the next stage's increment
-                const T y = B * r - gld(a.Ck + (v) * a.NN, g32);
+                const T y = B * r - Cn[v];
                 u = u6[v] + y;
                 gst(a.Ck + (v) * a.NN, g32, T((u - u6[v]) - y));
             } else {
