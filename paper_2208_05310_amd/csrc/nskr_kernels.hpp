@@ -1057,9 +1057,15 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
     // round covers the block: with two rounds the registers cost a wave per
     // SIMD, which measured slower than the re-read.
     constexpr bool kKeep = sizeof(T) == 8 || G::NF <= BS;
+    // FP64, where one round covers the block: the face point's normal and
+    // surface element are loaded with its traces too (their loads otherwise
+    // stall both face phases; in FP32 the registers would cost a wave per
+    // SIMD)
+    constexpr bool kOne = G::NF <= BS && sizeof(T) == 8;
     struct Tr {
         int nb;
         T own[3], oth[2], wn[6], uo[6];
+        T n[3], dS;
     };
     auto load_tr = [&](int task, Tr &r) {
         const FaceTask<P> ft(task);
@@ -1074,6 +1080,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         for (int v = 0; v < 6; ++v)
             if (v != 4 || kKeep) r.uo[v] = TU[o.at(6, v)];
         r.nb = gld(a.mesh.nbr, el * 6 + ft.f);
+        if constexpr (kOne) face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + ft.f, ft.fp, r.n, r.dS);
         if (r.nb >= 0) {
             const FaceIx<G::n2> on(nbr_face<P>(r.nb), nbr_point<P>(r.nb, ft.fp));
 #pragma unroll
@@ -1107,10 +1114,16 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         // the surface element always; the normal where it is used (walls,
         // and the lifting's n dS on curved elements)
         T n[3] = {T(0), T(0), T(0)}, dS;
-        if (CV || tr.nb < 0)
+        if constexpr (kOne) {
+            n[0] = tr.n[0];
+            n[1] = tr.n[1];
+            n[2] = tr.n[2];
+            dS = tr.dS;
+        } else if (CV || tr.nb < 0) {
             face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, n, dS);
-        else
+        } else {
             dS = face_dS<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp);
+        }
         const T *uf = tr.uo;
         T w[5];
         primitives(uf, w);
@@ -1355,9 +1368,18 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             };
             const FaceIx<G::n2> o((size_t)el * 6 + f, ft.fp);
             T nrm[3], dSf;
-            face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, nrm, dSf);
+            bool wall;
+            if constexpr (kOne) {  // task == t: the values loaded with the traces
+                nrm[0] = tr0.n[0];
+                nrm[1] = tr0.n[1];
+                nrm[2] = tr0.n[2];
+                dSf = tr0.dS;
+                wall = tr0.nb < 0;
+            } else {
+                face_normal<P, T, CV>(a.mesh, (size_t)el * 6 + f, ft.fp, nrm, dSf);
+                wall = gld(a.mesh.nbr, el * 6 + f) < 0;
+            }
             const T n0 = nrm[0], n1 = nrm[1], n2 = nrm[2];
-            const bool wall = gld(a.mesh.nbr, el * 6 + f) < 0;
             int kind = 0;  // interior faces have no wall-table entry
             if (wall) kind = a.mesh.bcs[a.mesh.bcid[el * 6 + f] - 1].kind;
             // state and convective part
