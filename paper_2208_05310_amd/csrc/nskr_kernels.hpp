@@ -735,10 +735,17 @@ template <typename T> __device__ __forceinline__ void to_physical(const T Ja[9],
 }
 
 // The element whose per-element data (metrics, face normals) a node thread
-// reads: with one element per workgroup it is the workgroup's, a wave-uniform
-// index, so those loads become scalar loads into scalar registers, issued
-// at once and costing no vector registers; otherwise the thread's own.
-template <int EPB> __device__ __forceinline__ int metric_element(int e0, int e) { return EPB == 1 ? e0 : e; }
+// reads, as a wave-uniform index where it is one: with one element per
+// workgroup it is the workgroup's, and with 64 nodes per element (N = 3)
+// each wave holds exactly one element.  Those loads then become scalar
+// loads into scalar registers, issued at once and costing no vector
+// registers; otherwise the index is the thread's own.
+template <int EPB, int N3> __device__ __forceinline__ int metric_element(int e0, int e)
+{
+    if constexpr (EPB == 1) return e0;
+    if constexpr (N3 == 64) return __builtin_amdgcn_readfirstlane(e);
+    return e;
+}
 
 template <typename T> __device__ __forceinline__ void element_metrics(const MeshDev &m, int e, T Ja[9], T &iJ)
 {
@@ -938,7 +945,7 @@ __global__ __launch_bounds__(BS, (lift1_waves<T, BS, FULL, CV>())) void k_lift1(
         } else {
             T Ja[9], iJ;
             // (FP32: the scalar loads cost the one vector register that keeps 8 waves per SIMD)
-            element_metrics(a.mesh, sizeof(T) == 8 ? metric_element<G::EPB>(e0, e) : e, Ja, iJ);
+            element_metrics(a.mesh, sizeof(T) == 8 ? metric_element<G::EPB, G::n3>(e0, e) : e, Ja, iJ);
             if (full) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
@@ -1209,7 +1216,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
         } else {
             T gd[4][3];
             lifted_grads<P, 4>(sW, sS, le * G::n3, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
-            element_metrics(a.mesh, metric_element<G::EPB>(e0, e), Ja, iJ);
+            element_metrics(a.mesh, metric_element<G::EPB, G::n3>(e0, e), Ja, iJ);
 #pragma unroll
             for (int w = 0; w < 3; ++w) to_physical(Ja, iJ, gd[w], gu + 3 * w);
             to_physical(Ja, iJ, gd[3], gc);
@@ -1343,7 +1350,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
             const T td = T(2.0 / 3.0) * div, mu = T(a.ph.mu);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const uint32_t fq = ((uint32_t)metric_element<G::EPB>(e0, e) * 6 + 2 * d + 1) * 4;
+                const uint32_t fq = ((uint32_t)metric_element<G::EPB, G::n3>(e0, e) * 6 + 2 * d + 1) * 4;
                 const T n0 = T(gld(a.mesh.fmet, fq)), n1 = T(gld(a.mesh.fmet, fq + 1)), n2 = T(gld(a.mesh.fmet, fq + 2));
                 T *out = d == 0 ? &sA[0][0] : sX + (d - 1) * 4 * G::NV;
                 out[0 * G::NV + t] = mu * ((gg[0] + gg[0]) * n0 + (gg[1] + gg[3]) * n1 + (gg[2] + gg[6]) * n2 - td * n0);
@@ -1729,7 +1736,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
             T gd[5][3];
             lifted_grads<P, 5>(sF, sS, base, le * 6 * G::n2, i, j, k, sDh, sLh, gd);
             T Ja[9];
-            element_metrics(a.mesh, metric_element<G::EPB>(e0, e), Ja, iJ);
+            element_metrics(a.mesh, metric_element<G::EPB, G::n3>(e0, e), Ja, iJ);
             to_physical(Ja, iJ, gd[0], grho);
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) to_physical(Ja, iJ, gd[1 + jj], s.gu[jj]);
@@ -1768,7 +1775,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
             Jd[1] = sJa[3 * d + 1][t];
             Jd[2] = sJa[3 * d + 2][t];
         } else {
-            const uint32_t eq = (uint32_t)metric_element<G::EPB>(e0, e) * 10 + 3 * d;
+            const uint32_t eq = (uint32_t)metric_element<G::EPB, G::n3>(e0, e) * 10 + 3 * d;
             Jd[0] = T(gld(a.mesh.emet, eq));
             Jd[1] = T(gld(a.mesh.emet, eq + 1));
             Jd[2] = T(gld(a.mesh.emet, eq + 2));
