@@ -138,3 +138,28 @@ def rotated_box_mesh(w, seed=11):
             o = next(x for x in range(8) if all(_orient(P, fp, x) == target[fp] for fp in range(P * P)))
             nbr_n[e, f], nbf_n[e, f], nbo_n[e, f] = nb, nf, o
     return dict(xgeo=xgn, ngeo=ngeo, nbr=nbr_n, nbf=nbf_n, nbo=nbo_n, bc=bc_n, bcs=bcs, perm=perm)
+
+
+# ------------------------------------------------------------------ raw mesh upload
+def upload_rc(s, m, nbo=None, nbf=None, ngeo=1, nelems=None):
+    """nskr_mesh_upload through the C ABI with the host arrays of a mesh tuple
+    (geometry nodes, neighbours, neighbour faces, wall indices, wall table),
+    optionally with face orientations, other neighbour faces or another
+    element count; returns the status code."""
+    import ctypes
+    from paper_2208_05310_amd.nskr import Bc, Mesh
+    xgeo = np.ascontiguousarray(m[0], dtype=np.float64)
+    nbr = np.ascontiguousarray(m[1], dtype=np.int32)
+    nbf = np.ascontiguousarray(m[2] if nbf is None else nbf, dtype=np.int32)
+    bc = np.ascontiguousarray(m[3], dtype=np.int32)
+    ip = ctypes.POINTER(ctypes.c_int)
+    nbo_a = None if nbo is None else np.ascontiguousarray(nbo, dtype=np.int32)
+    bcs = m[4]
+    bc_arr = (Bc * max(1, len(bcs)))(*[Bc(b["kind"], b["twall"], b["theta"], (ctypes.c_double * 3)(*b["uwall"]),
+                                             *b["gamma"], (ctypes.c_double * 3)(*b.get("tgrad", (0, 0, 0))),
+                                             b.get("trate", 0.0)) for b in bcs])
+    mm = Mesh(int(nbr.shape[0]) if nelems is None else nelems, ngeo,
+              xgeo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nbr.ctypes.data_as(ip),
+              nbf.ctypes.data_as(ip), None if nbo_a is None else nbo_a.ctypes.data_as(ip), bc.ctypes.data_as(ip),
+              len(bcs), bc_arr)
+    return s.L.nskr_mesh_upload(s._h, ctypes.byref(mm), None)

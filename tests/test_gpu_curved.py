@@ -16,12 +16,11 @@ through the C ABI, against the FP64 CPU oracle.
   face that is not the same surface, walls with a varying temperature on
   curved elements, 512-thread tiles on curved elements.
 """
-import ctypes
 
 import numpy as np
 import pytest
 
-from helpers import oracle_for, oracle_init, rotated_box_mesh
+from helpers import oracle_for, oracle_init, rotated_box_mesh, upload_rc
 from paper_2208_05310_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -317,54 +316,36 @@ def test_rotated_elements_batched_equal_single(torch_cuda):
 
 
 # ---------------------------------------------------------------- refusals
-def _upload_rc(s, m, nbo=None, nbf=None, ngeo=1):
-    from paper_2208_05310_amd.nskr import Mesh, Bc
-    xgeo = np.ascontiguousarray(m[0], dtype=np.float64)
-    nbr = np.ascontiguousarray(m[1], dtype=np.int32)
-    nbf = np.ascontiguousarray(m[2] if nbf is None else nbf, dtype=np.int32)
-    bc = np.ascontiguousarray(m[3], dtype=np.int32)
-    ip = ctypes.POINTER(ctypes.c_int)
-    nbo_a = None if nbo is None else np.ascontiguousarray(nbo, dtype=np.int32)
-    bcs = m[4]
-    bc_arr = (Bc * max(1, len(bcs)))(*[Bc(b["kind"], b["twall"], b["theta"], (ctypes.c_double * 3)(*b["uwall"]),
-                                             *b["gamma"], (ctypes.c_double * 3)(*b.get("tgrad", (0, 0, 0))),
-                                             b.get("trate", 0.0)) for b in bcs])
-    mm = Mesh(int(nbr.shape[0]), ngeo, xgeo.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nbr.ctypes.data_as(ip),
-              nbf.ctypes.data_as(ip), None if nbo_a is None else nbo_a.ctypes.data_as(ip), bc.ctypes.data_as(ip),
-              len(bcs), bc_arr)
-    return s.L.nskr_mesh_upload(s._h, ctypes.byref(mm), None)
-
-
 def test_mesh_upload_refuses_mismatched_faces(torch_cuda):
     from paper_2208_05310_amd.nskr import NSKR_E_ARG, NSKR_E_UNSUPPORTED, Solver, box_mesh
     w = wl.c1().with_(n=(3, 3, 3))
     s = Solver(w.params, w.N)
     m = box_mesh(w.n)
-    assert _upload_rc(s, m) == 0
+    assert upload_rc(s, m) == 0
     # a flipped face: the orientation of one interior pair reversed on both sides
     nbo = np.zeros((w.nelems, 6), dtype=np.int32)
     nbo[0, 1] = 1
     nbo[int(m[1][0, 1]), 0] = 1
-    assert _upload_rc(s, m, nbo=nbo) == NSKR_E_ARG
+    assert upload_rc(s, m, nbo=nbo) == NSKR_E_ARG
     # a transposed face point order
     nbo[0, 1] = nbo[int(m[1][0, 1]), 0] = 4
-    assert _upload_rc(s, m, nbo=nbo) == NSKR_E_ARG
+    assert upload_rc(s, m, nbo=nbo) == NSKR_E_ARG
     # reciprocal but wrong pairs in the periodic row of elements 0, 1, 2: the
     # + faces of 0 and 1 paired (one translation apart, but facing the same
     # way), and the - faces of 1 and 2
     nbr, nbf = m[1].copy(), m[2].copy()
     nbr[0, 1], nbf[0, 1], nbr[1, 1], nbf[1, 1] = 1, 1, 0, 1
     nbr[1, 0], nbf[1, 0], nbr[2, 0], nbf[2, 0] = 2, 0, 1, 0
-    assert _upload_rc(s, (m[0], nbr, nbf, m[3], m[4])) == NSKR_E_ARG
+    assert upload_rc(s, (m[0], nbr, nbf, m[3], m[4])) == NSKR_E_ARG
     # and the library still takes the correct mesh afterwards
-    assert _upload_rc(s, m) == 0
+    assert upload_rc(s, m) == 0
     # a wall temperature varying along a curved wall
     wc = wl.c7(scale=12).with_(curve_amp=0.03)
     sc = Solver(wc.params, wc.N)
     mb = box_mesh(wc.n, wc.length, wc.periodic, wc.side_kind, wc.side_twall, wc.side_theta,
                   side_tgrad=wc.side_tgrad)
     xg = wl.box_geometry(wc.n, wc.length, wc.N, wc.curve_amp)
-    assert _upload_rc(sc, (xg,) + tuple(mb[1:]), ngeo=wc.N) == NSKR_E_UNSUPPORTED
+    assert upload_rc(sc, (xg,) + tuple(mb[1:]), ngeo=wc.N) == NSKR_E_UNSUPPORTED
     # 512-thread tiles on curved elements
     s2 = gpu_solver(CURVED[0])
     from paper_2208_05310_amd.nskr import NskrError
