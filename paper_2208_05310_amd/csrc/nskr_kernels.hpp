@@ -382,6 +382,8 @@ template <typename T> struct Launch {
     Basis bas;
     int mode;        // update: 0 write U_t; 1 RK stage (update U, R, write traces)
     int first;       // RK: assign R at the first stage
+    int last;        // RK: the step's last stage, which does not store R (the next
+                     // stage to read it is a first stage, which assigns it)
     int tb, tw;      // conserved-trace buffer read by this stage, written for the next
     int full;        // host side: launch the k_lift1 variant that also writes Q and TH
     double A, B;     // RK coefficients of this stage
@@ -1837,7 +1839,7 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             const T r = L.first ? dt * Ut[v] : A * Rn[v] + dt * Ut[v];
-            gst(a.R + (v) * a.NN, g32, T(r));
+            if (!L.last) gst(a.R + (v) * a.NN, g32, T(r));
             T u;
             if (sizeof(T) == 4 && a.Ck) {
                 // compensated summation: the low-order part lost by u6 + B r is

@@ -757,6 +757,7 @@ template <int P, typename T, int BS, bool CV> struct Impl {
         for (int st = 0; st < 5; ++st) {
             L.mode = 1;
             L.first = st == 0;
+            L.last = st == 4;
             L.A = kRkA[st];
             L.B = kRkB[st];
             L.tb = kTraceBuf[st];
@@ -804,6 +805,7 @@ template <int P, typename T, int BS, bool CV> struct Impl {
             for (int st = 0; st < 5; ++st) {
                 L.mode = 1;
                 L.first = st == 0;
+                L.last = st == 4;
                 L.A = kRkA[st];
                 L.B = kRkB[st];
                 L.tb = kTraceBuf[st];
