@@ -43,8 +43,9 @@ def kernel_words_per_node(N, curved=False, fp32=False):
         "lift1": 6 + 3 * F,               # U, neighbour c traces in; grad c . n + T traces (2) out
         "lift2": 10 + 15 * F,             # U, conserved traces (own and neighbour: 6), grad c . n + T traces (2)
                                           # in; grad T + lap c (4), flux + wave-speed traces (7) out
-        "update": 28 + 19 * F,            # U, R, grad T + lap c, neighbour conserved traces (6), flux traces (7)
-                                          # in; U, R, conserved traces (6) out
+        "update": 25.6 + 19 * F,          # U, R, grad T + lap c, neighbour conserved traces (6), flux traces (7)
+                                          # in; U, R, conserved traces (6) out; R (6) is read by stages 2-5 and
+                                          # written by stages 1-4, so 4/5 of its 12 words per launch of a step
     }
     if fp32:
         k["lift1"] += F
