@@ -306,8 +306,9 @@ int nskr_dt_noalloc(nskr_ctx *ctx, const void *U, double *dt, nskr_stream s);
  * R <- A_s R + dt L(U) (assigned at stage 1, so R needs no initialisation),
  * U <- U + B_s R.  R is the scheme's scratch register: its content after
  * the call is unspecified (the last stage of a step does not store it, as
- * the next stage to read it assigns it).  Asynchronous.  Errors: NSKR_E_ARG (dt not positive and
- * finite, nsteps < 0, null or aliasing buffers), NSKR_E_STATE, NSKR_E_HIP. */
+ * the next stage to read it assigns it).  Asynchronous.  Errors: NSKR_E_ARG
+ * (dt not positive and finite, nsteps < 0, null or aliasing buffers),
+ * NSKR_E_STATE, NSKR_E_HIP. */
 int nskr_rk_steps(nskr_ctx *ctx, void *U, void *R, double dt, int nsteps, nskr_stream s);
 
 /* Integrals and counters (the NSKR_SUM_* indices) into out[NSKR_NSUMS]:
