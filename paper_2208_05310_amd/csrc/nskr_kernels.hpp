@@ -68,6 +68,24 @@ template <typename T> __device__ __forceinline__ void gst(T *base, uint32_t i, T
     typedef __attribute__((address_space(1))) char gc;
     *(__attribute__((address_space(1))) T *)((gc *)uniform_ptr(base) + i * (uint32_t)sizeof(T)) = v;
 }
+// The same accesses with the non-temporal hint (NT), for the update
+// kernel's node arrays on meshes whose node data would fill much of the
+// last-level cache: they stream through it instead of displacing the face
+// traces that the next kernels read again.
+template <bool NT, typename T> __device__ __forceinline__ T gldn(const T *base, uint32_t i)
+{
+    typedef __attribute__((address_space(1))) const char gc;
+    const auto *p = (__attribute__((address_space(1))) const T *)((gc *)uniform_ptr(base) + i * (uint32_t)sizeof(T));
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T> __device__ __forceinline__ void gstn(T *base, uint32_t i, T v)
+{
+    typedef __attribute__((address_space(1))) char gc;
+    auto *p = (__attribute__((address_space(1))) T *)((gc *)uniform_ptr(base) + i * (uint32_t)sizeof(T));
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 struct Phys {
     double R, a, b, cv, mu, kappa, gam, alpha, beta;
@@ -1571,7 +1589,7 @@ __global__ __launch_bounds__(BS) void k_lift2(Launch<T> L)
 }
 
 // ------------------------------------------------------------ k_update
-template <int P, typename T, int BS, bool BATCH, bool CV = false>
+template <int P, typename T, int BS, bool BATCH, bool CV = false, bool NT = false>
 __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 {
     using G = Tile<P, BS>;
@@ -1639,12 +1657,12 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     T iJn = T(0);
     if (act) {
         if constexpr (CV) iJn = stage_node_metrics<T, NJV>(a.mesh, a.NN, g, t, sJa);
-        s.rho = gld(a.U + (0) * a.NN, g32);
-        s.m[0] = gld(a.U + (1) * a.NN, g32);
-        s.m[1] = gld(a.U + (2) * a.NN, g32);
-        s.m[2] = gld(a.U + (3) * a.NN, g32);
-        s.E = gld(a.U + (4) * a.NN, g32);
-        s.c = gld(a.U + (5) * a.NN, g32);
+        s.rho = gldn<NT>(a.U + (0) * a.NN, g32);
+        s.m[0] = gldn<NT>(a.U + (1) * a.NN, g32);
+        s.m[1] = gldn<NT>(a.U + (2) * a.NN, g32);
+        s.m[2] = gldn<NT>(a.U + (3) * a.NN, g32);
+        s.E = gldn<NT>(a.U + (4) * a.NN, g32);
+        s.c = gldn<NT>(a.U + (5) * a.NN, g32);
         const T u6[6] = {s.rho, s.m[0], s.m[1], s.m[2], s.E, s.c};
         T w[5];
         primitives(u6, w);
@@ -1719,8 +1737,8 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     const int base = le * G::n3;
     if (act) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) s.gT[m] = gld(a.G2 + (m) * a.NN, g32);
-        s.lapc = gld(a.G2 + (3) * a.NN, g32);
+        for (int m = 0; m < 3; ++m) s.gT[m] = gldn<NT>(a.G2 + (m) * a.NN, g32);
+        s.lapc = gldn<NT>(a.G2 + (3) * a.NN, g32);
         T grho[3];
         if constexpr (CV) {
             T q[5][3];
@@ -1762,8 +1780,8 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
     if (L.mode == 1 && act) {
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            Rn[v] = L.first ? T(0) : gld(a.R + (v) * a.NN, g32);
-            if constexpr (sizeof(T) == 4) Cn[v] = a.Ck ? gld(a.Ck + (v) * a.NN, g32) : T(0);
+            Rn[v] = L.first ? T(0) : gldn<NT>(a.R + (v) * a.NN, g32);
+            if constexpr (sizeof(T) == 4) Cn[v] = a.Ck ? gldn<NT>(a.Ck + (v) * a.NN, g32) : T(0);
         }
     }
     // volume integral sum_d Dhat_d (Ja^d . F): the contravariant fluxes of
@@ -1839,18 +1857,18 @@ __global__ __launch_bounds__(BS) void k_update(Launch<T> L)
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             const T r = L.first ? dt * Ut[v] : A * Rn[v] + dt * Ut[v];
-            if (!L.last) gst(a.R + (v) * a.NN, g32, T(r));
+            if (!L.last) gstn<NT>(a.R + (v) * a.NN, g32, T(r));
             T u;
             if (sizeof(T) == 4 && a.Ck) {
                 // compensated summation: the low-order part lost by u6 + B r is
                 // kept in Ck and fed into the next stage's increment
                 const T y = B * r - Cn[v];
                 u = u6[v] + y;
-                gst(a.Ck + (v) * a.NN, g32, T((u - u6[v]) - y));
+                gstn<NT>(a.Ck + (v) * a.NN, g32, T((u - u6[v]) - y));
             } else {
                 u = u6[v] + B * r;
             }
-            gst(a.U + (v) * a.NN, g32, T(u));
+            gstn<NT>(a.U + (v) * a.NN, g32, T(u));
             sF[v][t] = u;
         }
     }
