@@ -818,17 +818,20 @@ __global__ __launch_bounds__(BS) void k_prolong(Launch<T> L)
 // Lifted grad c, and the own-face traces of grad c and of the face
 // temperature.  FULL: also every lifted gradient and the nodal temperature
 // (Q, TH) for the API outputs.
-// FP32 per-stage instances on affine elements in 256-thread workgroups are
-// latency-bound and keep at least 7 waves per SIMD, which their register
-// demand allows without spills (8 does not; neither does 7 in 448-thread
-// workgroups).
-template <typename T, int BS, bool FULL, bool CV> constexpr int lift1_waves()
+// The per-stage instances on affine elements in 256-thread workgroups are
+// latency-bound and keep as many waves per SIMD as their LDS allows without
+// register spills: 7 in FP32 (8 spills; so does 7 in 448-thread
+// workgroups), and in FP64 8 at N = 5 (63 registers instead of 79) and 6 at
+// N = 3 (80 instead of 83).
+template <int P, typename T, int BS, bool FULL, bool CV> constexpr int lift1_waves()
 {
-    return (sizeof(T) == 4 && BS == 256 && !FULL && !CV) ? 7 : 1;
+    if (BS != 256 || FULL || CV) return 1;
+    if (sizeof(T) == 4) return 7;
+    return P == 6 ? 8 : (P == 4 ? 6 : 1);
 }
 
 template <int P, typename T, int BS, bool BATCH, bool FULL = false, bool CV = false>
-__global__ __launch_bounds__(BS, (lift1_waves<T, BS, FULL, CV>())) void k_lift1(Launch<T> L)
+__global__ __launch_bounds__(BS, (lift1_waves<P, T, BS, FULL, CV>())) void k_lift1(Launch<T> L)
 {
     using G = Tile<P, BS>;
     Inst<T> a;
