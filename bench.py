@@ -498,9 +498,10 @@ def main():
                          "c6: sliding droplet, 200 steps)")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--serving-max-nodes", type=int, default=4_000_000)
-    ap.add_argument("--threads", type=int, default=256, choices=[128, 192, 256, 448, 512],
+    ap.add_argument("--threads", type=int, default=None, choices=[128, 192, 256, 448, 512],
                     help="workgroup size of the stage kernels: 256, 512 or the degree's tight size "
-                         "(N=2: 192, N=3 and 4: 128, N=5: 448)")
+                         "(N=2: 192, N=3 and 4: 128, N=5: 448); default: the library's (128 at N=3, "
+                         "else 256)")
     ap.add_argument("--young-laplace", type=float, default=None, metavar="THETA",
                     help="static contact-angle validation: liquid pillar with this angle (degrees) to --t-end, "
                          "pressure jump against the Young-Laplace law")
@@ -573,7 +574,9 @@ def main():
         """Warm-up + K timed steps of workload wk; returns throughput,
         per-kernel data, final state."""
         s = solver_for(wk, precision)
-        s.set_block(args.threads)
+        if args.threads:
+            s.set_block(args.threads)
+        threads = s.get_block()
         U = U0.to(s.dtype).clone()
         R = s.new_state()
         s.rk_steps(U, R, dtk, args.warmup, stream)
@@ -609,7 +612,7 @@ def main():
         nn = s.nnodes
         del s, R
         return {"value": nn * 5 * args.steps / wall, "wall": wall, "gpu_ms": ev0.elapsed_time(ev1),
-                "kern": kern, "nnodes": nn, "U": U, "mass": sums[0], "word": word}
+                "kern": kern, "nnodes": nn, "U": U, "mass": sums[0], "word": word, "threads": threads}
 
     def initial(wk, precision):
         s = solver_for(wk, precision)
@@ -641,7 +644,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic: seeded droplet state (tanh profiles at Maxwell densities, uniform noise 1e-6)",
-        "config": {"workload": w.name, "elements": w.nelems, "N": w.N, "nodes": nn, "threads": args.threads,
+        "config": {"workload": w.name, "elements": w.nelems, "N": w.N, "nodes": nn, "threads": r["threads"],
                    "precision": args.precision, "relaxation_model": args.model,
                    "alpha": w.params["alpha"], "beta": w.params["beta"],
                    "T0": w.T0, "dt": dt, "rk": "5-stage 2N RK4(3)5"},

@@ -334,7 +334,8 @@ int nskr_profile(nskr_ctx *ctx, double *ms, long *count, nskr_stream s);
 
 /* Threads per workgroup of the stage kernels: 256, 512, or the degree's
  * tight size that packs whole elements into waves (N = 2: 192, N = 3 and 4:
- * 128, N = 5: 448); a block must hold at least one element.  This is the tile
+ * 128, N = 5: 448); a block must hold at least one element.  Default: 128 at
+ * N = 3, 256 otherwise.  This is the tile
  * shape (elements per workgroup) the autotuner chooses.  Results do not
  * depend on it (every element's arithmetic is the same in any tile).  A mesh
  * with curved elements runs 256 threads (its upload sets 256).

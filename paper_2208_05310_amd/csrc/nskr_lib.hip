@@ -899,6 +899,11 @@ template <int P, typename T, int BS, bool CV> struct Impl {
 // 7 elements of 27 nodes in 192 threads; N = 3, 4: one wave pair, 2 and 1
 // elements; N = 5: 2 elements of 216 nodes in 448 threads, against 1 in 256).
 static int tight_block(int N) { return N == 2 ? 192 : (N == 5 ? 448 : 128); }
+// Default threads per workgroup: 128 at N = 3 (two elements per workgroup,
+// the same occupancy in finer workgroups: 3.4 % faster in FP64 and 0.7 % in
+// FP32-mixed than 256 on the 48x48x24 and 50^3 meshes), else 256 (at N = 4
+// the two measure the same; at N = 5 and N = 2 the tight sizes are slower).
+static int default_block(int N) { return N == 3 ? 128 : 256; }
 
 // Valid block sizes per degree: one of the built sizes, holding at least one
 // element and one line task per thread.
@@ -1238,6 +1243,7 @@ int nskr_create(const nskr_params *p, int N, int device, nskr_ctx **out)
     c->p = *p;
     c->N = N;
     c->P = N + 1;
+    c->bs = default_block(N);
     c->device = device;
     make_basis(N, c->bas);
     c->ph.R = p->R; c->ph.a = p->a; c->ph.b = p->b; c->ph.cv = p->cv; c->ph.mu = p->mu;

@@ -81,6 +81,8 @@ def test_block_size_does_not_change_results(torch_cuda, N, prec):
     torch = torch_cuda
     from paper_2208_05310_amd.autotune import block_sizes
     w = wl.c1().with_(name=f"tiles_N{N}", N=N, n=(3, 3, 3))
+    from paper_2208_05310_amd.nskr import solver_for
+    assert solver_for(w, prec).get_block() == (128 if N == 3 else 256)   # the library's default
     s1, U1, R1, dt = setup(w, prec, 256)
     s1.rk_steps(U1, R1, dt, 3)
     for bs in block_sizes(N):
