@@ -24,23 +24,27 @@ FLAGS = [
 
 
 KERNELS = os.path.join(HERE, "csrc", "nskr_kernels.hpp")
+# the launch layer: which kernel instance runs, its tile and cache hints
+LAUNCH = os.path.join(HERE, "csrc", "nskr_lib.hip")
 
 
 def _code_only(src: str) -> str:
     """The source without comments, trailing blanks and empty lines (the
-    kernel header holds no string literal that contains a comment marker)."""
+    sources hold no string literal that contains a comment marker)."""
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     src = re.sub(r"//[^\n]*", "", src)
     return "\n".join(line.rstrip() for line in src.splitlines() if line.strip())
 
 
 def kernel_fingerprint() -> str:
-    """sha256 over the device-kernel code (comments excluded) and the compile
+    """sha256 over the device-kernel code and the launch layer that picks the
+    instances, tiles and cache hints (comments excluded), and the compile
     flags: hardware counters taken for one fingerprint say nothing about
-    kernels built from another."""
+    kernels built or launched from another."""
     h = hashlib.sha256()
-    with open(KERNELS, encoding="utf-8") as f:
-        h.update(_code_only(f.read()).encode())
+    for path in (KERNELS, LAUNCH):
+        with open(path, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     h.update(" ".join(FLAGS).encode())
     return h.hexdigest()
 
